@@ -1,0 +1,224 @@
+"""CPU oracle for the island-model GA generation step (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package. The GPU library
+never imports, links or calls it, and it imports nothing from the GPU library.
+
+The arithmetic lives in ``ga_oracle.c`` (plain single-threaded C). This module
+only marshals arguments. Every function cites the passage of the paper it
+follows in the C source (Sec. 2 Methods for the generation cycle, Sec. 3 for the
+genome layout, Fig. 1 for post hoc relatedness estimation).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libga_oracle.so")
+SOURCES = [os.path.join(_HERE, "ga_oracle.c")]
+DISCARD = 0xFFFFFFFF
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math) into oracle/libga_oracle.so."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+           "-fno-fast-math", "-ffp-contract=off", "-o", tmp] + SOURCES
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in (
+        "width", "height", "pop", "sites", "k", "selection", "p32", "migration",
+        "seed", "run_id")]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build()
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    u32, u64, sz = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    lib.orc_philox.argtypes = [P, P, P]
+    lib.orc_site_of.argtypes = [u64, u32]
+    lib.orc_site_of.restype = u32
+    lib.orc_epoch.argtypes = [u64, u32]
+    lib.orc_epoch.restype = u32
+    lib.orc_site_of_range.argtypes = [u64, sz, u32, P]
+    lib.orc_validate.argtypes = [ctypes.POINTER(_Config)]
+    lib.orc_validate.restype = ctypes.c_int
+    lib.orc_create.argtypes = [ctypes.POINTER(_Config), ctypes.c_int]
+    lib.orc_create.restype = P
+    lib.orc_free.argtypes = [P]
+    lib.orc_step.argtypes = [P, u64]
+    lib.orc_step.restype = ctypes.c_int
+    lib.orc_generation.argtypes = [P]
+    lib.orc_generation.restype = u64
+    lib.orc_agents.argtypes = [P]
+    lib.orc_agents.restype = u64
+    lib.orc_get_population.argtypes = [P, P, P, P]
+    lib.orc_set_population.argtypes = [P, P, P, P]
+    lib.orc_get_outbox.argtypes = [P, P, P, P, P, P]
+    lib.orc_set_outbox.argtypes = [P, P, P, P, P, P]
+    lib.orc_set_generation.argtypes = [P, u64]
+    lib.orc_set_generation.restype = ctypes.c_int
+    lib.orc_sample_one_per_island.argtypes = [P, P]
+    lib.orc_true_mrca.argtypes = [P, u64, u64]
+    lib.orc_true_mrca.restype = ctypes.c_int64
+    lib.orc_ancestry.argtypes = [P, u64, P, P, P, sz]
+    lib.orc_ancestry.restype = sz
+    lib.orc_mrca_interval.argtypes = [u32, P, u32, P, u32, u32, P, P]
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def philox(ctr, key) -> np.ndarray:
+    """One Philox4x32-10 block for a 4-word counter and 2-word key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def site_of(rank: int, sites: int) -> int:
+    """Surface site written by the deposit of stratum ``rank`` (DISCARD if none)."""
+    return int(_load().orc_site_of(rank, sites))
+
+
+def epoch(n: int, sites: int) -> int:
+    return int(_load().orc_epoch(n, sites))
+
+
+def site_of_range(first: int, count: int, sites: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint32)
+    _load().orc_site_of_range(first, count, sites, _ptr(out))
+    return out
+
+
+def mrca_interval(Ta: int, Da, Tb: int, Db, sites: int, kc: int = 5):
+    """(L, U) bounds on the MRCA's deposit counter from two surfaces."""
+    a = np.ascontiguousarray(Da, dtype=np.uint32)
+    b = np.ascontiguousarray(Db, dtype=np.uint32)
+    L = ctypes.c_uint32()
+    U = ctypes.c_uint32()
+    _load().orc_mrca_interval(Ta, _ptr(a), Tb, _ptr(b), sites, kc,
+                              ctypes.byref(L), ctypes.byref(U))
+    return int(L.value), int(U.value)
+
+
+CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32",
+                 "migration", "seed", "run_id")
+
+
+def validate(cfg: dict) -> bool:
+    c = _Config(**{f: int(cfg[f]) for f in CONFIG_FIELDS})
+    return _load().orc_validate(ctypes.byref(c)) == 0
+
+
+class OracleRun:
+    """One GA run on the CPU oracle. ``cfg`` holds the fields of CONFIG_FIELDS."""
+
+    def __init__(self, cfg: dict, lineage: bool = False):
+        lib = _load()
+        self.cfg = {f: int(cfg[f]) for f in CONFIG_FIELDS}
+        c = _Config(**self.cfg)
+        h = lib.orc_create(ctypes.byref(c), 1 if lineage else 0)
+        if not h:
+            raise ValueError(f"oracle rejected configuration {self.cfg}")
+        self._h = ctypes.c_void_p(h)
+        self.words = self.cfg["sites"] // 32
+        self.islands = self.cfg["width"] * self.cfg["height"]
+        self.agents = self.islands * self.cfg["pop"]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().orc_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def generation(self) -> int:
+        return int(_load().orc_generation(self._h))
+
+    def step(self, n: int):
+        if _load().orc_step(self._h, int(n)) != 0:
+            raise RuntimeError("oracle step failed (lineage buffer)")
+
+    def population(self):
+        f = np.empty(self.agents, dtype=np.float32)
+        T = np.empty(self.agents, dtype=np.uint32)
+        D = np.empty((self.agents, self.words), dtype=np.uint32)
+        _load().orc_get_population(self._h, _ptr(f), _ptr(T), _ptr(D))
+        return f, T, D
+
+    def set_population(self, f=None, T=None, D=None):
+        args = []
+        for a, dt in ((f, np.float32), (T, np.uint32), (D, np.uint32)):
+            if a is None:
+                args.append(None)
+            else:
+                args.append(np.ascontiguousarray(a, dtype=dt))
+        _load().orc_set_population(self._h, *[(_ptr(a) if a is not None else None) for a in args])
+
+    def outbox(self):
+        n = self.islands
+        valid = np.empty(n, dtype=np.uint8)
+        d = np.empty(n, dtype=np.uint8)
+        f = np.empty(n, dtype=np.float32)
+        T = np.empty(n, dtype=np.uint32)
+        D = np.empty((n, self.words), dtype=np.uint32)
+        _load().orc_get_outbox(self._h, _ptr(valid), _ptr(d), _ptr(f), _ptr(T), _ptr(D))
+        return {"valid": valid, "dir": d, "f": f, "T": T, "D": D}
+
+    def set_outbox(self, valid, d, f, T, D):
+        arrs = [np.ascontiguousarray(valid, dtype=np.uint8), np.ascontiguousarray(d, dtype=np.uint8),
+                np.ascontiguousarray(f, dtype=np.float32), np.ascontiguousarray(T, dtype=np.uint32),
+                np.ascontiguousarray(D, dtype=np.uint32)]
+        _load().orc_set_outbox(self._h, *[_ptr(a) for a in arrs])
+
+    def set_generation(self, t: int):
+        if _load().orc_set_generation(self._h, int(t)) != 0:
+            raise RuntimeError("cannot move the generation counter of a lineage-recording run")
+
+    def sample_one_per_island(self) -> np.ndarray:
+        ids = np.empty(self.islands, dtype=np.uint64)
+        _load().orc_sample_one_per_island(self._h, _ptr(ids))
+        return ids
+
+    def true_mrca(self, a: int, b: int) -> int:
+        g = int(_load().orc_true_mrca(self._h, int(a), int(b)))
+        if g == -2:
+            raise RuntimeError("lineage was not recorded from generation 0")
+        return g
+
+    def ancestry(self, agent: int):
+        cap = self.generation + 1
+        g = np.empty(cap, dtype=np.uint64)
+        i = np.empty(cap, dtype=np.uint32)
+        s = np.empty(cap, dtype=np.uint32)
+        n = _load().orc_ancestry(self._h, int(agent), _ptr(g), _ptr(i), _ptr(s), cap)
+        return g[:n], i[:n], s[:n]

@@ -1,0 +1,491 @@
+/*
+ * CPU oracle for the tracking-enabled island-model GA generation step.
+ *
+ * TEST INFRASTRUCTURE ONLY: plain, slow, single-threaded, written for reading
+ * against the paper, not for speed. Only the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg may use it. It shares no code with the GPU
+ * library.
+ *
+ * Paper: Moreno, Yang, Dolson, Zaman, "Trackable Island-model Genetic
+ * Algorithms at Wafer Scale" (GECCO '24 Companion).
+ *
+ * Readings taken where the paper is silent (the GPU library follows the same
+ * readings in its own code):
+ *   schedule   synchronous; every island finishes generation t before any
+ *              starts t+1; an emigrant sent in generation t is absorbed in
+ *              generation t+1 (Sec. 2: immigration consumes buffers filled
+ *              earlier, emigration refills them afterwards).
+ *   migration  one emigrant per island per generation, copied (the sender keeps
+ *              it), sent to one random cardinal neighbour; the receiver draws
+ *              the slot it overwrites; up to 4 arrivals are applied in
+ *              direction order N, E, S, W, the later one winning a slot clash.
+ *   selection  k entrants drawn with replacement; the first entrant (in draw
+ *              order) with the strictly greatest fitness wins, which breaks
+ *              ties uniformly at random as the paper asks (Sec. 2).
+ *   mutation   with probability p the fitness gains a delta drawn uniformly
+ *              from {-1, -1/2, 0, 1/2, 1}, added in binary32 with
+ *              round-to-nearest-even.
+ *   tracking   a hereditary-stratigraphy surface of S one-bit differentia plus
+ *              a deposit counter T; one deposit per generation (Sec. 2), at
+ *              the site chosen by the "doubling steady" policy below.
+ *   RNG        Philox4x32-10 keyed by (seed, run_id), counter
+ *              (slot or 0, island, generation low word,
+ *               generation high word * 4 + stream tag).
+ */
+#include "ga_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+/* ----------------------------------------------------------------------- */
+/* Philox4x32-10, from Salmon, Moraes, Dror and Shaw, "Parallel Random      */
+/* Numbers: As Easy as 1, 2, 3" (SC'11). Each round multiplies counter      */
+/* words 0 and 2 by fixed odd constants, keeps both halves of each 64-bit   */
+/* product, and mixes the high halves with the other two words and the key; */
+/* the key grows by the Weyl increments between rounds.                     */
+/* ----------------------------------------------------------------------- */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)PHILOX_M0 * c0;
+    uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    k0 += PHILOX_W0;
+    k1 += PHILOX_W1;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+enum { TAG_SELECT = 0, TAG_MIGRATE = 1, TAG_SAMPLE = 2 };
+
+static void draw(const orc_config* cfg, uint32_t slot, uint32_t island, uint64_t t,
+                 uint32_t tag, uint32_t out[4]) {
+  uint32_t ctr[4];
+  uint32_t key[2];
+  ctr[0] = slot;
+  ctr[1] = island;
+  ctr[2] = (uint32_t)t;
+  ctr[3] = (uint32_t)(t >> 32) * 4u + tag;
+  key[0] = cfg->seed;
+  key[1] = cfg->run_id;
+  orc_philox(ctr, key, out);
+}
+
+/* ----------------------------------------------------------------------- */
+/* Surface policy ("doubling steady").                                      */
+/* With S sites and n deposits made, the epoch is e(n) = max(0, ceil(log2 n) */
+/* - log2 S) and the retained ranks are the multiples of 2^e(n) below n.    */
+/* A deposit of rank r is written only if r is a multiple of 2^e(r+1);      */
+/* ranks below S get site r; the j-th rank written during epoch e >= 1     */
+/* reuses the site of the j-th smallest rank that left the retained set     */
+/* when epoch e began, i.e. rank (2j+1) * 2^(e-1).                          */
+/* ----------------------------------------------------------------------- */
+static uint32_t log2_exact(uint32_t v) {
+  uint32_t l = 0;
+  while ((1u << l) < v) ++l;
+  return l;
+}
+
+uint32_t orc_epoch(uint64_t n, uint32_t sites) {
+  uint32_t s = log2_exact(sites);
+  uint32_t c = 0; /* ceil(log2 n) for n >= 1; 0 for n <= 1 */
+  while (c < 64 && ((uint64_t)1 << c) < n) ++c;
+  return c > s ? c - s : 0;
+}
+
+uint32_t orc_site_of(uint64_t rank, uint32_t sites) {
+  uint64_t r = rank;
+  int first = 1;
+  for (;;) {
+    if (r < sites) return (uint32_t)r;
+    uint32_t e = orc_epoch(r + 1, sites);
+    if (r % ((uint64_t)1 << e) != 0) {
+      /* Only the deposit itself can be a discard: every rank reached by the
+       * recursion below was written in its own time. */
+      if (first) return ORC_DISCARD;
+      abort();
+    }
+    uint64_t m = r >> e;              /* in [S/2, S) */
+    uint64_t j = m - sites / 2;       /* j-th rank written in epoch e */
+    r = (2 * j + 1) << (e - 1);       /* j-th rank dropped when e began */
+    first = 0;
+  }
+}
+
+void orc_site_of_range(uint64_t first, size_t count, uint32_t sites, uint32_t* out) {
+  for (size_t i = 0; i < count; ++i) out[i] = orc_site_of(first + i, sites);
+}
+
+/* ----------------------------------------------------------------------- */
+/* Run state.                                                               */
+/* ----------------------------------------------------------------------- */
+typedef struct outbox_entry {
+  uint8_t valid;
+  uint8_t dir;
+  float f;
+  uint32_t T;
+  uint32_t D[2];
+} outbox_entry;
+
+struct orc_run {
+  orc_config cfg;
+  uint32_t log2pop;
+  uint32_t words;      /* surface words per agent */
+  uint64_t islands;
+  uint64_t agents;
+  uint64_t t;
+  float* f;            /* population at the start of generation t */
+  uint32_t* T;
+  uint32_t* D;
+  float* nf;           /* next population, built during a generation */
+  uint32_t* nT;
+  uint32_t* nD;
+  outbox_entry* prev;  /* emitted during t-1, absorbed during t */
+  outbox_entry* next;  /* emitted during t */
+  int lineage;
+  uint8_t* winners;    /* winners[g*agents + a]: tournament winner of child a in generation g */
+  uint64_t lineage_gens;
+};
+
+static int is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
+
+int orc_validate(const orc_config* cfg) {
+  if (!cfg) return -1;
+  if (cfg->width == 0 || cfg->height == 0) return -1;
+  if (!is_pow2(cfg->pop) || cfg->pop > 256) return -1;
+  if (cfg->sites != 32 && cfg->sites != 64) return -1;
+  if (cfg->k < 1 || cfg->k > 8) return -1;
+  if (cfg->selection > 1 || cfg->migration > 1) return -1;
+  return 0;
+}
+
+orc_run* orc_create(const orc_config* cfg, int record_lineage) {
+  if (orc_validate(cfg) != 0) return NULL;
+  orc_run* r = (orc_run*)calloc(1, sizeof(orc_run));
+  if (!r) return NULL;
+  r->cfg = *cfg;
+  r->log2pop = log2_exact(cfg->pop);
+  r->words = cfg->sites / 32;
+  r->islands = (uint64_t)cfg->width * cfg->height;
+  r->agents = r->islands * cfg->pop;
+  r->t = 0;
+  /* Founders: fitness +0, no deposits, blank surface (Sec. 2 leaves the
+   * initial genome to the model's initialize function). */
+  r->f = (float*)calloc(r->agents, sizeof(float));
+  r->T = (uint32_t*)calloc(r->agents, sizeof(uint32_t));
+  r->D = (uint32_t*)calloc(r->agents * r->words, sizeof(uint32_t));
+  r->nf = (float*)calloc(r->agents, sizeof(float));
+  r->nT = (uint32_t*)calloc(r->agents, sizeof(uint32_t));
+  r->nD = (uint32_t*)calloc(r->agents * r->words, sizeof(uint32_t));
+  r->prev = (outbox_entry*)calloc(r->islands, sizeof(outbox_entry));
+  r->next = (outbox_entry*)calloc(r->islands, sizeof(outbox_entry));
+  r->lineage = record_lineage != 0;
+  if (!r->f || !r->T || !r->D || !r->nf || !r->nT || !r->nD || !r->prev || !r->next) {
+    orc_free(r);
+    return NULL;
+  }
+  return r;
+}
+
+void orc_free(orc_run* r) {
+  if (!r) return;
+  free(r->f); free(r->T); free(r->D);
+  free(r->nf); free(r->nT); free(r->nD);
+  free(r->prev); free(r->next);
+  free(r->winners);
+  free(r);
+}
+
+uint64_t orc_generation(const orc_run* r) { return r->t; }
+uint64_t orc_agents(const orc_run* r) { return r->agents; }
+
+/* Torus neighbour of island i in direction d: 0 north (y-1), 1 east (x+1),
+ * 2 south (y+1), 3 west (x-1). The opposite direction is d ^ 2. */
+static uint64_t neighbour(const orc_config* cfg, uint64_t i, uint32_t d) {
+  uint64_t x = i % cfg->width, y = i / cfg->width;
+  uint64_t W = cfg->width, H = cfg->height;
+  switch (d) {
+    case 0: y = (y + H - 1) % H; break;
+    case 1: x = (x + 1) % W; break;
+    case 2: y = (y + 1) % H; break;
+    default: x = (x + W - 1) % W; break;
+  }
+  return y * W + x;
+}
+
+/* Index in [0, 2^bits) from the top bits of an 8-bit or 32-bit draw. */
+static uint32_t top_bits_of_byte(uint32_t byte, uint32_t bits) { return byte >> (8 - bits); }
+static uint32_t top_bits_of_word(uint32_t word, uint32_t bits) {
+  return (uint32_t)((uint64_t)word >> (32 - bits));
+}
+
+static uint32_t byte_of(const uint32_t w[4], uint32_t m) {
+  /* byte m of the little-endian 64-bit pair (w[0], w[1]) */
+  uint32_t word = m < 4 ? w[0] : w[1];
+  return (word >> (8 * (m & 3))) & 0xFFu;
+}
+
+static void copy_agent(const orc_run* r, const float* sf, const uint32_t* sT,
+                       const uint32_t* sD, uint64_t src, float* df, uint32_t* dT,
+                       uint32_t* dD, uint64_t dst) {
+  df[dst] = sf[src];
+  dT[dst] = sT[src];
+  for (uint32_t w = 0; w < r->words; ++w) dD[dst * r->words + w] = sD[src * r->words + w];
+}
+
+static int grow_lineage(orc_run* r, uint64_t gens) {
+  size_t bytes = (size_t)(gens * r->agents);
+  uint8_t* p = (uint8_t*)realloc(r->winners, bytes);
+  if (!p) return -1;
+  r->winners = p;
+  return 0;
+}
+
+static void one_generation(orc_run* r) {
+  const orc_config* cfg = &r->cfg;
+  const uint64_t N = cfg->pop;
+  const uint32_t L = r->log2pop;
+  const uint64_t t = r->t;
+  uint32_t w[4];
+
+  /* 1. Migration, immigration half (Sec. 2): arrivals overwrite receiver-drawn
+   *    slots, applied in direction order so the later direction wins a clash. */
+  for (uint64_t i = 0; i < r->islands; ++i) {
+    draw(cfg, 0, (uint32_t)i, t, TAG_MIGRATE, w);
+    for (uint32_t q = 0; q < 4; ++q) {
+      uint64_t j = neighbour(cfg, i, q);
+      const outbox_entry* in = &r->prev[j];
+      if (!in->valid || in->dir != (q ^ 2u)) continue;
+      uint32_t slot = top_bits_of_byte((w[2] >> (8 * q)) & 0xFFu, L);
+      uint64_t a = i * N + slot;
+      r->f[a] = in->f;
+      r->T[a] = in->T;
+      for (uint32_t k = 0; k < r->words; ++k) r->D[a * r->words + k] = in->D[k];
+    }
+  }
+
+  /* 2. Migration, emigration half (Sec. 2): a copy of one random member goes to
+   *    one random neighbour; it is absorbed in the next generation. */
+  for (uint64_t i = 0; i < r->islands; ++i) {
+    outbox_entry* out = &r->next[i];
+    memset(out, 0, sizeof(*out));
+    if (!cfg->migration) continue;
+    draw(cfg, 0, (uint32_t)i, t, TAG_MIGRATE, w);
+    uint32_t e = top_bits_of_word(w[0], L);
+    uint64_t a = i * N + e;
+    out->valid = 1;
+    out->dir = (uint8_t)(w[1] >> 30);
+    out->f = r->f[a];
+    out->T = r->T[a];
+    for (uint32_t k = 0; k < r->words; ++k) out->D[k] = r->D[a * r->words + k];
+  }
+
+  /* 3-7. Evaluation, tournament, copy, mutation, stratum deposit (Sec. 2). */
+  uint8_t* win_row = r->lineage ? r->winners + (size_t)(t * r->agents) : NULL;
+  for (uint64_t i = 0; i < r->islands; ++i) {
+    for (uint64_t s = 0; s < N; ++s) {
+      draw(cfg, (uint32_t)s, (uint32_t)i, t, TAG_SELECT, w);
+      /* Evaluation is reading the fitness word (Sec. 3 genome layout). */
+      uint32_t best = top_bits_of_byte(byte_of(w, 0), L);
+      if (cfg->selection) {
+        for (uint32_t m = 1; m < cfg->k; ++m) {
+          uint32_t cand = top_bits_of_byte(byte_of(w, m), L);
+          if (r->f[i * N + cand] > r->f[i * N + best]) best = cand;
+        }
+      }
+      uint64_t child = i * N + s;
+      copy_agent(r, r->f, r->T, r->D, i * N + best, r->nf, r->nT, r->nD, child);
+      if (win_row) win_row[child] = (uint8_t)best;
+
+      if (w[2] < cfg->p32) {
+        uint32_t idx = (uint32_t)(((uint64_t)(w[3] & 0x7FFFFFFFu) * 5u) >> 31);
+        float delta = 0.5f * (float)((int)idx - 2);
+        r->nf[child] = r->nf[child] + delta;
+      }
+
+      uint32_t site = orc_site_of(r->nT[child], cfg->sites);
+      if (site != ORC_DISCARD) {
+        uint32_t bit = w[3] >> 31;
+        uint32_t* word = &r->nD[child * r->words + (site >> 5)];
+        *word = (*word & ~(1u << (site & 31))) | (bit << (site & 31));
+      }
+      r->nT[child] = r->nT[child] + 1;
+    }
+  }
+
+  /* 8. Generational replacement; the fresh outbox becomes next generation's input. */
+  float* tf = r->f; r->f = r->nf; r->nf = tf;
+  uint32_t* tT = r->T; r->T = r->nT; r->nT = tT;
+  uint32_t* tD = r->D; r->D = r->nD; r->nD = tD;
+  outbox_entry* to = r->prev; r->prev = r->next; r->next = to;
+  r->t = t + 1;
+}
+
+int orc_step(orc_run* r, uint64_t n) {
+  if (r->lineage) {
+    if (r->lineage_gens != r->t) return -1; /* lineage must start at generation 0 */
+    if (grow_lineage(r, r->t + n) != 0) return -1;
+  }
+  for (uint64_t g = 0; g < n; ++g) {
+    one_generation(r);
+    if (r->lineage) r->lineage_gens = r->t;
+  }
+  return 0;
+}
+
+void orc_get_population(const orc_run* r, float* f, uint32_t* T, uint32_t* D) {
+  if (f) memcpy(f, r->f, r->agents * sizeof(float));
+  if (T) memcpy(T, r->T, r->agents * sizeof(uint32_t));
+  if (D) memcpy(D, r->D, r->agents * r->words * sizeof(uint32_t));
+}
+
+void orc_set_population(orc_run* r, const float* f, const uint32_t* T, const uint32_t* D) {
+  if (f) memcpy(r->f, f, r->agents * sizeof(float));
+  if (T) memcpy(r->T, T, r->agents * sizeof(uint32_t));
+  if (D) memcpy(r->D, D, r->agents * r->words * sizeof(uint32_t));
+}
+
+void orc_get_outbox(const orc_run* r, uint8_t* valid, uint8_t* dir, float* f,
+                    uint32_t* T, uint32_t* D) {
+  for (uint64_t i = 0; i < r->islands; ++i) {
+    const outbox_entry* e = &r->prev[i];
+    if (valid) valid[i] = e->valid;
+    if (dir) dir[i] = e->dir;
+    if (f) f[i] = e->f;
+    if (T) T[i] = e->T;
+    if (D) for (uint32_t k = 0; k < r->words; ++k) D[i * r->words + k] = e->D[k];
+  }
+}
+
+void orc_set_outbox(orc_run* r, const uint8_t* valid, const uint8_t* dir,
+                    const float* f, const uint32_t* T, const uint32_t* D) {
+  for (uint64_t i = 0; i < r->islands; ++i) {
+    outbox_entry* e = &r->prev[i];
+    if (valid) e->valid = valid[i] ? 1 : 0;
+    if (dir) e->dir = dir[i] & 3u;
+    if (f) e->f = f[i];
+    if (T) e->T = T[i];
+    if (D) for (uint32_t k = 0; k < r->words; ++k) e->D[k] = D[i * r->words + k];
+  }
+}
+
+int orc_set_generation(orc_run* r, uint64_t t) {
+  if (r->lineage) return -1;
+  r->t = t;
+  return 0;
+}
+
+void orc_sample_one_per_island(const orc_run* r, uint64_t* ids) {
+  uint32_t w[4];
+  for (uint64_t i = 0; i < r->islands; ++i) {
+    draw(&r->cfg, 0, (uint32_t)i, r->t, TAG_SAMPLE, w);
+    ids[i] = i * r->cfg.pop + top_bits_of_word(w[0], r->log2pop);
+  }
+}
+
+/* ----------------------------------------------------------------------- */
+/* True lineage. An individual is named by where it was born: generation b  */
+/* (it is a member of the population at the start of b; b = 0 for founders), */
+/* island and slot. Migration copies keep the name of what they copy.       */
+/* ----------------------------------------------------------------------- */
+
+/* Who occupies slot w of island i right after generation t's immigration. */
+static void post_absorb(const orc_run* r, uint64_t t, uint64_t i, uint32_t w,
+                        uint64_t* bt, uint64_t* bi, uint32_t* bs) {
+  const orc_config* cfg = &r->cfg;
+  uint32_t blk[4], nb[4];
+  for (;;) {
+    int moved = 0;
+    if (cfg->migration && t >= 1) {
+      draw(cfg, 0, (uint32_t)i, t, TAG_MIGRATE, blk);
+      for (int q = 3; q >= 0 && !moved; --q) {
+        uint32_t slot = top_bits_of_byte((blk[2] >> (8 * q)) & 0xFFu, r->log2pop);
+        if (slot != w) continue;
+        uint64_t j = neighbour(cfg, i, (uint32_t)q);
+        draw(cfg, 0, (uint32_t)j, t - 1, TAG_MIGRATE, nb);
+        if ((nb[1] >> 30) != ((uint32_t)q ^ 2u)) continue;
+        /* The arrival is the copy j emitted during t-1 of its own slot. */
+        i = j;
+        w = top_bits_of_word(nb[0], r->log2pop);
+        t = t - 1;
+        moved = 1;
+      }
+    }
+    if (!moved) break;
+  }
+  *bt = t; *bi = i; *bs = w;
+}
+
+size_t orc_ancestry(const orc_run* r, uint64_t agent, uint64_t* gen, uint32_t* island,
+                    uint32_t* slot, size_t max_len) {
+  uint64_t t = r->t, i = agent / r->cfg.pop;
+  uint32_t s = (uint32_t)(agent % r->cfg.pop);
+  size_t n = 0;
+  for (;;) {
+    if (n < max_len) { gen[n] = t; island[n] = (uint32_t)i; slot[n] = s; }
+    ++n;
+    if (t == 0) break;
+    uint32_t w = r->winners[(size_t)((t - 1) * r->agents + i * r->cfg.pop + s)];
+    post_absorb(r, t - 1, i, w, &t, &i, &s);
+  }
+  return n;
+}
+
+int64_t orc_true_mrca(const orc_run* r, uint64_t agent_a, uint64_t agent_b) {
+  if (!r->lineage || r->lineage_gens != r->t) return -2;
+  uint64_t ta = r->t, tb = r->t;
+  uint64_t ia = agent_a / r->cfg.pop, ib = agent_b / r->cfg.pop;
+  uint32_t sa = (uint32_t)(agent_a % r->cfg.pop), sb = (uint32_t)(agent_b % r->cfg.pop);
+  uint64_t steps_a = 0;
+  /* Walk both chains back in birth order until they name the same individual. */
+  for (;;) {
+    if (ta == tb && ia == ib && sa == sb) return (int64_t)r->T[agent_a] - (int64_t)steps_a;
+    if (ta == 0 && tb == 0) return -1;
+    if (ta >= tb) {
+      uint32_t w = r->winners[(size_t)((ta - 1) * r->agents + ia * r->cfg.pop + sa)];
+      post_absorb(r, ta - 1, ia, w, &ta, &ia, &sa);
+      ++steps_a;
+    } else {
+      uint32_t w = r->winners[(size_t)((tb - 1) * r->agents + ib * r->cfg.pop + sb)];
+      post_absorb(r, tb - 1, ib, w, &tb, &ib, &sb);
+    }
+  }
+}
+
+/* ----------------------------------------------------------------------- */
+/* MRCA interval from two surfaces (post hoc relatedness estimation,        */
+/* Fig. 1). Ranks retained by both are the multiples of 2^max(ea, eb)       */
+/* below min(Ta, Tb). Strata older than the MRCA are inherited identically, */
+/* so the first mismatching common rank bounds the MRCA's T from above;     */
+/* each common rank at or after the MRCA matches by chance with probability */
+/* 1/2, so kc matches in a row below that bound leave the MRCA earlier than */
+/* them with probability at most 2^-kc.                                     */
+/* ----------------------------------------------------------------------- */
+static uint32_t bit_at(const uint32_t* D, uint32_t site) { return (D[site >> 5] >> (site & 31)) & 1u; }
+
+void orc_mrca_interval(uint32_t Ta, const uint32_t* Da, uint32_t Tb, const uint32_t* Db,
+                       uint32_t sites, uint32_t kc, uint32_t* L, uint32_t* U) {
+  uint32_t ea = orc_epoch(Ta, sites), eb = orc_epoch(Tb, sites);
+  uint64_t step = (uint64_t)1 << (ea > eb ? ea : eb);
+  uint64_t n = Ta < Tb ? Ta : Tb;
+  uint64_t first_mismatch = n;
+  for (uint64_t r = 0; r < n; r += step) {
+    uint32_t site = orc_site_of(r, sites);
+    if (bit_at(Da, site) != bit_at(Db, site)) { first_mismatch = r; break; }
+  }
+  *U = (uint32_t)first_mismatch;
+  uint64_t below = (first_mismatch + step - 1) / step; /* common ranks below the bound */
+  *L = below < kc ? 0u : (uint32_t)((below - kc) * step + 1);
+}

@@ -1,0 +1,105 @@
+/*
+ * CPU oracle for the tracking-enabled island-model GA generation step.
+ *
+ * TEST INFRASTRUCTURE ONLY. This is the plain, slow, single-threaded reference
+ * that the GPU library is checked against. Only the test suite, the smoke check
+ * and the benchmark's CPU-baseline leg may load it. It shares no code, header,
+ * table or helper with the GPU library; the two meet only in the seeded run
+ * configuration they are both given.
+ *
+ * The method (paper: Moreno, Yang, Dolson, Zaman, "Trackable Island-model
+ * Genetic Algorithms at Wafer Scale", GECCO '24 Companion):
+ *   - islands on a 2D lattice each host an independent, fixed-size population
+ *     and exchange genomes with their cardinal neighbours (Sec. 2 Methods);
+ *   - each generation handles migration first, then evaluation, tournament
+ *     selection with random tie-breaks, mutation of the whole next population,
+ *     and one hereditary-stratigraphy update, until a generation count is met
+ *     (Sec. 2 Methods);
+ *   - the genome carries a float fitness first, the rest is tracking
+ *     annotation (Sec. 3 Results and Discussion).
+ * Where the paper is silent (schedule, RNG, surface policy, mutation law) the
+ * readings below are the project's conventions; the GPU library follows the
+ * same readings, written separately.
+ */
+#ifndef GA_ORACLE_H
+#define GA_ORACLE_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_DISCARD 0xFFFFFFFFu
+
+typedef struct orc_config {
+  uint32_t width;       /* islands per row (x extent) */
+  uint32_t height;      /* rows (y extent); island id = y*width + x */
+  uint32_t pop;         /* agents per island, power of two, 1..256 */
+  uint32_t sites;       /* surface sites S, 32 or 64 */
+  uint32_t k;           /* tournament size, 1..8 */
+  uint32_t selection;   /* 1 tournament, 0 neutral (uniform parent) */
+  uint32_t p32;         /* mutate iff a 32-bit draw is below this */
+  uint32_t migration;   /* 1 one emigrant per island per generation, 0 off */
+  uint32_t seed;        /* RNG key word 0 */
+  uint32_t run_id;      /* RNG key word 1 */
+} orc_config;
+
+typedef struct orc_run orc_run;
+
+/* Philox4x32 with 10 rounds (Salmon et al., SC'11): one 128-bit block. */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Surface policy: site written by the deposit of stratum rank r, or ORC_DISCARD. */
+uint32_t orc_site_of(uint64_t rank, uint32_t sites);
+/* Epoch after n deposits: max(0, ceil(log2 n) - log2 S). */
+uint32_t orc_epoch(uint64_t n, uint32_t sites);
+/* Bulk form for tests: out[i] = orc_site_of(first + i, sites). */
+void orc_site_of_range(uint64_t first, size_t count, uint32_t sites, uint32_t* out);
+
+/* 0 on success, -1 for an invalid configuration. */
+int orc_validate(const orc_config* cfg);
+/* record_lineage != 0 keeps every child's tournament winner (1 byte each). */
+orc_run* orc_create(const orc_config* cfg, int record_lineage);
+void orc_free(orc_run* run);
+/* Advance n generations. Returns 0, or -1 when the lineage buffer cannot grow. */
+int orc_step(orc_run* run, uint64_t n);
+uint64_t orc_generation(const orc_run* run);
+uint64_t orc_agents(const orc_run* run);
+
+/* Population at the start of the current generation. D is agent-major:
+ * D[a*W + w] with W = sites/32 words per agent. Any pointer may be NULL. */
+void orc_get_population(const orc_run* run, float* f, uint32_t* T, uint32_t* D);
+void orc_set_population(orc_run* run, const float* f, const uint32_t* T, const uint32_t* D);
+/* The outbox the next generation will absorb from (one entry per island). */
+void orc_get_outbox(const orc_run* run, uint8_t* valid, uint8_t* dir, float* f,
+                    uint32_t* T, uint32_t* D);
+void orc_set_outbox(orc_run* run, const uint8_t* valid, const uint8_t* dir,
+                    const float* f, const uint32_t* T, const uint32_t* D);
+/* Jump the generation counter (state is kept as is; lineage must be off). */
+int orc_set_generation(orc_run* run, uint64_t t);
+
+/* One agent per island, drawn from the SAMPLE stream at the current
+ * generation: ids[i] = i*pop + slot. */
+void orc_sample_one_per_island(const orc_run* run, uint64_t* ids);
+
+/* True lineage (needs record_lineage from generation 0). For two agents of
+ * the current population, the generation counter T of their most recent
+ * common ancestor, or -1 when they descend from different founders. */
+int64_t orc_true_mrca(const orc_run* run, uint64_t agent_a, uint64_t agent_b);
+/* Lineage walk: writes up to max_len (generation, island, slot) triples of
+ * the ancestors of one agent, newest first; returns the chain length. */
+size_t orc_ancestry(const orc_run* run, uint64_t agent, uint64_t* gen,
+                    uint32_t* island, uint32_t* slot, size_t max_len);
+
+/* MRCA interval from two surfaces: g (the MRCA's T) is always <= *U, and
+ * g < *L has probability at most 2^-kc. */
+void orc_mrca_interval(uint32_t Ta, const uint32_t* Da, uint32_t Tb,
+                       const uint32_t* Db, uint32_t sites, uint32_t kc,
+                       uint32_t* L, uint32_t* U);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
