@@ -1,0 +1,188 @@
+/*
+ * ga.h - C ABI of the MI355X island-model GA library (libga_hip.so).
+ *
+ * The library runs the generation step of a tracking-enabled island-model
+ * genetic algorithm (Moreno, Yang, Dolson, Zaman, "Trackable Island-model
+ * Genetic Algorithms at Wafer Scale", GECCO '24 Companion) as HIP kernels on
+ * one gfx950 GPU. Islands sit on a W x H torus, each holding N agents; every
+ * generation handles migration first, then evaluation, tournament selection,
+ * mutation of the whole next population and one hereditary-stratigraphy
+ * deposit per agent, and the run halts at a generation count (Sec. 2,
+ * Methods). The genome is a float32 fitness followed by tracking annotation
+ * (Sec. 3): here a uint32 deposit counter T and an S-site surface of 1-bit
+ * differentia.
+ *
+ * Semantics of one generation t (synchronous; every island finishes t before
+ * any island starts t+1):
+ *   1. absorb: for q = N, E, S, W (0..3), if the neighbour in direction q
+ *      emitted toward this island during t-1, its genome overwrites the slot
+ *      this island draws for q; a later q wins a clash (Sec. 2, immigration);
+ *   2. emit: a copy of one random member (post-absorb) is sent to one random
+ *      cardinal neighbour, delivered at t+1 (Sec. 2, emigration);
+ *   3-5. every child slot takes the fittest of k entrants drawn with
+ *      replacement, the first in draw order on ties (tournament with random
+ *      tie-break, Sec. 2), or entrant 0 under neutral selection;
+ *   6. with probability p the child's fitness gains a delta drawn uniformly
+ *      from {-1, -1/2, 0, 1/2, 1} (binary32, round to nearest even) (Sec. 2,
+ *      mutation operator);
+ *   7. the child writes one random differentia bit at the site the
+ *      "doubling steady" surface policy gives for rank T (or writes nothing),
+ *      then T += 1 (Sec. 2, stratigraphy update once per generation).
+ * Every random draw is one Philox4x32-10 block (Salmon et al., SC'11) keyed
+ * by (seed, run_id) with counter (slot or 0, island, generation low word,
+ * generation high word * 4 + stream), stream 0 selection, 1 migration,
+ * 2 sampling. Results are therefore bit-identical for any launch shape,
+ * batching or schedule.
+ *
+ * Conventions for every entry point:
+ *   - Return value: GA_OK (0) or a negative GA_E* code; ga_last_error()
+ *     gives a message for the calling thread's last failure. A call that
+ *     fails leaves the run's state unchanged. No C++ exception crosses the ABI.
+ *   - Device memory for a run's state is allocated by the caller and is never
+ *     freed by the library. Host buffers are owned by the caller.
+ *   - A run is bound to one HIP stream. Calls on one handle must not overlap
+ *     from several host threads.
+ *   - Agent a = island * N + slot, island = y * W + x.
+ */
+#ifndef GA_H
+#define GA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GA_OK 0
+#define GA_EINVAL (-1)   /* invalid argument or configuration */
+#define GA_ENOMEM (-2)   /* caller's device buffer smaller than ga_state_bytes */
+#define GA_EDEVICE (-3)  /* a HIP runtime call failed */
+#define GA_ESTATE (-4)   /* handle in the wrong state for this call */
+
+/* Run configuration. All fields are validated by ga_init. */
+typedef struct ga_config {
+  uint32_t struct_size;        /* sizeof(ga_config) */
+  uint32_t width;              /* islands per row, 1..65535 */
+  uint32_t height;             /* rows, 1..65535; width * height * N < 2^31 */
+  uint32_t pop_per_island;     /* N: power of two, 1..64 (Sec. 2 uses 32) */
+  uint32_t surface_sites;      /* S: 32 or 64 one-bit differentia */
+  uint32_t tournament_size;    /* k: 1..8 (Sec. 2 uses 5) */
+  uint32_t selection;          /* 1 tournament, 0 neutral (uniform parent) */
+  uint32_t mutation_threshold; /* p * 2^32: mutate iff a 32-bit draw < this */
+  uint32_t migration;          /* 1 one emigrant per island per generation, 0 none */
+  uint32_t seed;               /* RNG key word 0 */
+  uint32_t run_id;             /* RNG key word 1 */
+} ga_config;
+
+/* Outbox entry as exchanged with the host (ga_read/ga_write_population):
+ * the genome an island emitted in the last generation and its direction. */
+typedef struct ga_outbox_entry {
+  uint32_t valid;              /* 1 if the island emitted, else 0 */
+  uint32_t dir;                /* 0 N, 1 E, 2 S, 3 W */
+  float fitness;
+  uint32_t T;
+  uint32_t surface[2];         /* word 1 unused when S = 32 */
+} ga_outbox_entry;
+
+typedef struct ga_run ga_run;
+
+/* Device bytes a run needs (population planes, double-buffered outboxes,
+ * generation counter, extraction staging). 0 for an invalid configuration. */
+size_t ga_state_bytes(const ga_config* cfg);
+
+/* Create a run in caller-owned device memory dev_mem (>= ga_state_bytes(cfg),
+ * 256-byte aligned) on hip_stream (a hipStream_t; NULL = default stream).
+ * Founders: fitness +0, T = 0, blank surfaces, no emission pending,
+ * generation 0 (the paper leaves initialisation to the genome model, Sec. 2).
+ * Initialisation is enqueued on the stream. *out receives the handle. */
+int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
+            ga_run** out);
+
+/* Enqueue n_gens generations on the run's stream (asynchronous; Sec. 2
+ * generation cycle with a generation-count halt). n_gens = 0 is a no-op. */
+int ga_step(ga_run* run, uint64_t n_gens);
+
+/* Copy the population at the start of the current generation to the host,
+ * after waiting for the run's stream. fitness[agents], T[agents] and
+ * surface_words[agents * S/32] (agent-major) may each be NULL; outbox, if not
+ * NULL, receives one ga_outbox_entry per island (the emissions the next
+ * generation will absorb); generation, if not NULL, receives t. */
+int ga_read_population(ga_run* run, float* fitness, uint32_t* T,
+                       uint32_t* surface_words, ga_outbox_entry* outbox,
+                       uint64_t* generation);
+
+/* Overwrite the state (checkpoint resume). Same layouts as
+ * ga_read_population; NULL leaves that part unchanged. Synchronous. */
+int ga_write_population(ga_run* run, const float* fitness, const uint32_t* T,
+                        const uint32_t* surface_words,
+                        const ga_outbox_entry* outbox, uint64_t generation);
+
+/* Sample end-state genomes for post hoc reconstruction (Sec. 3: one genome
+ * sampled per island). agent_ids == NULL picks one agent per island from the
+ * sampling stream at the current generation (n must equal the island count);
+ * otherwise the n listed agents are gathered. Writes ids_out[n] (may be NULL),
+ * T_out[n] and surface_words_out[n * S/32]. Synchronous. */
+int ga_extract_surfaces(ga_run* run, const uint64_t* agent_ids, size_t n,
+                        uint64_t* ids_out, uint32_t* T_out,
+                        uint32_t* surface_words_out);
+
+/* Generation counter as enqueued so far (host mirror; no synchronisation). */
+uint64_t ga_generation(const ga_run* run);
+
+/* Release the handle (waits for the run's stream). Device memory stays with
+ * the caller. NULL is allowed. */
+void ga_destroy(ga_run* run);
+
+/* Launch forms for ga_step. */
+#define GA_FORM_AUTO 0       /* resident when the run fits one workgroup, else streaming */
+#define GA_FORM_STREAMING 1  /* one kernel per generation over all islands */
+#define GA_FORM_RESIDENT 2   /* one workgroup loops over generations (<= 16 wavefronts) */
+
+/* Launch tuning for one run: islands per wavefront (a multiple of 64/N, at
+ * most 64), wavefronts per workgroup (1..16) and the launch form. 0 keeps the
+ * current value of the first two. Results do not depend on any of these.
+ * GA_EINVAL if the resident form is asked for a run that needs more than 16
+ * wavefronts at the given islands per wavefront. */
+int ga_set_launch(ga_run* run, uint32_t islands_per_wave, uint32_t waves_per_group,
+                  uint32_t form);
+/* Generations per captured HIP graph replay (0 disables graphs). */
+int ga_set_graph_block(ga_run* run, uint32_t gens_per_block);
+
+/* ---------------------------------------------------------------------- */
+/* Batched form: many independent runs of uneven shape advanced together, */
+/* one kernel launch per generation covering every member's islands, with */
+/* blocks of generations captured in a HIP graph. Each member gives the   */
+/* bits it would give alone.                                              */
+/* ---------------------------------------------------------------------- */
+typedef struct ga_batch ga_batch;
+
+/* Create an empty batch bound to hip_stream. The batch allocates its own
+ * small descriptor tables in device memory. */
+int ga_batch_create(void* hip_stream, ga_batch** out);
+/* Add a run (created by ga_init, bound to any stream; from now on it is
+ * advanced only through the batch) with a generation budget: the batch stops
+ * advancing it after budget more generations. Returns GA_OK. */
+int ga_batch_add(ga_batch* batch, ga_run* run, uint64_t budget);
+/* Remove a member (after waiting for the batch's stream). */
+int ga_batch_remove(ga_batch* batch, ga_run* run);
+/* Enqueue up to n_gens generations for every member with budget left. */
+int ga_batch_step(ga_batch* batch, uint64_t n_gens);
+/* Generations still owed to a member (host mirror). */
+uint64_t ga_batch_remaining(const ga_batch* batch, const ga_run* run);
+/* Members; waits for nothing. */
+size_t ga_batch_size(const ga_batch* batch);
+/* Generations per graph replay for the batch (default 100; 0 disables). */
+int ga_batch_set_graph_block(ga_batch* batch, uint32_t gens_per_block);
+/* Islands per wavefront used for a member (0 = the autotuned default). */
+int ga_batch_set_islands_per_wave(ga_batch* batch, uint32_t islands_per_wave);
+void ga_batch_destroy(ga_batch* batch);
+
+/* Message for a return code, and the calling thread's last error message. */
+const char* ga_strerror(int code);
+const char* ga_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GA_H */

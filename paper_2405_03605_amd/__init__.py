@@ -1,0 +1,9 @@
+"""MI355X-native island-model GA generation step (HIP kernels behind a C ABI).
+
+Import is light: the HIP library is loaded on first use of GARun / GABatch.
+"""
+from ._lib import (FORM_AUTO, FORM_RESIDENT, FORM_STREAMING, GAError, build, load)
+from .run import CONFIG_FIELDS, GABatch, GARun, state_bytes
+
+__all__ = ["GARun", "GABatch", "GAError", "build", "load", "state_bytes", "CONFIG_FIELDS",
+           "FORM_AUTO", "FORM_STREAMING", "FORM_RESIDENT"]

@@ -1,0 +1,98 @@
+"""ctypes binding of libga_hip.so (include/ga.h). Argument marshalling only:
+every generation step runs in the library's HIP kernels. There is no CPU
+fallback; loading fails loudly when the library is missing."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(_HERE)
+LIB_PATH = os.path.join(_HERE, "libga_hip.so")
+HEADER = os.path.join(ROOT, "include", "ga.h")
+SOURCES = [os.path.join(_HERE, "csrc", "ga_kernels.hip"), os.path.join(_HERE, "csrc", "ga_api.hip")]
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_ESTATE = 0, -1, -2, -3, -4
+FORM_AUTO, FORM_STREAMING, FORM_RESIDENT = 0, 1, 2
+
+
+class GAError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def build(hipcc: str = "hipcc") -> str:
+    """Compile libga_hip.so for gfx950 in-tree."""
+    tmp = LIB_PATH + ".tmp"
+    subprocess.run([hipcc] + HIPCC_FLAGS + ["-o", tmp] + SOURCES, check=True,
+                   stderr=subprocess.DEVNULL if os.environ.get("GA_QUIET_BUILD") else None)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Config(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in (
+        "struct_size", "width", "height", "pop_per_island", "surface_sites",
+        "tournament_size", "selection", "mutation_threshold", "migration", "seed", "run_id")]
+
+
+class OutboxEntry(ctypes.Structure):
+    _fields_ = [("valid", ctypes.c_uint32), ("dir", ctypes.c_uint32), ("fitness", ctypes.c_float),
+                ("T", ctypes.c_uint32), ("surface", ctypes.c_uint32 * 2)]
+
+
+# name -> (restype, argtypes); every symbol declared in include/ga.h
+P = ctypes.c_void_p
+u32, u64, sz, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
+SIGNATURES = {
+    "ga_state_bytes": (sz, [P]),
+    "ga_init": (i32, [P, P, sz, P, ctypes.POINTER(P)]),
+    "ga_step": (i32, [P, u64]),
+    "ga_read_population": (i32, [P, P, P, P, P, P]),
+    "ga_write_population": (i32, [P, P, P, P, P, u64]),
+    "ga_extract_surfaces": (i32, [P, P, sz, P, P, P]),
+    "ga_generation": (u64, [P]),
+    "ga_destroy": (None, [P]),
+    "ga_set_launch": (i32, [P, u32, u32, u32]),
+    "ga_set_graph_block": (i32, [P, u32]),
+    "ga_batch_create": (i32, [P, ctypes.POINTER(P)]),
+    "ga_batch_add": (i32, [P, P, u64]),
+    "ga_batch_remove": (i32, [P, P]),
+    "ga_batch_step": (i32, [P, u64]),
+    "ga_batch_remaining": (u64, [P, P]),
+    "ga_batch_size": (sz, [P]),
+    "ga_batch_set_graph_block": (i32, [P, u32]),
+    "ga_batch_set_islands_per_wave": (i32, [P, u32]),
+    "ga_batch_destroy": (None, [P]),
+    "ga_strerror": (ctypes.c_char_p, [i32]),
+    "ga_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(code: int):
+    if code != GA_OK:
+        lib = load()
+        raise GAError(code, lib.ga_last_error().decode() or lib.ga_strerror(code).decode())

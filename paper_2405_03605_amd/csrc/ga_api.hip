@@ -1,0 +1,695 @@
+// C ABI of libga_hip: configuration checks, device layout, launch planning,
+// HIP-graph capture of generation blocks, state I/O and the batched form.
+// Declarations and semantics: include/ga.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ga.h"
+#include "ga_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return GA_EDEVICE;
+}
+
+#define GA_HIP(call, what)                      \
+  do {                                          \
+    hipError_t _e = (call);                     \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
+uint32_t log2u(uint32_t v) {
+  uint32_t l = 0;
+  while ((1u << l) < v) ++l;
+  return l;
+}
+
+bool config_ok(const ga_config* c, std::string* why) {
+  auto no = [&](const char* m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (!c) return no("config is NULL");
+  if (c->struct_size != sizeof(ga_config)) return no("struct_size != sizeof(ga_config)");
+  if (c->width < 1 || c->width > 65535) return no("width must be in [1, 65535]");
+  if (c->height < 1 || c->height > 65535) return no("height must be in [1, 65535]");
+  if (!is_pow2(c->pop_per_island) || c->pop_per_island > 64)
+    return no("pop_per_island must be a power of two in [1, 64]");
+  if (c->surface_sites != 32 && c->surface_sites != 64) return no("surface_sites must be 32 or 64");
+  if (c->tournament_size < 1 || c->tournament_size > 8) return no("tournament_size must be in [1, 8]");
+  if (c->selection > 1) return no("selection must be 0 or 1");
+  if (c->migration > 1) return no("migration must be 0 or 1");
+  const uint64_t agents = (uint64_t)c->width * c->height * c->pop_per_island;
+  if (agents >= (1ull << 31)) return no("width * height * pop_per_island must be < 2^31");
+  return true;
+}
+
+// Byte offsets of every plane inside a run's device buffer.
+struct Layout {
+  size_t pop_f, pop_T, pop_D;
+  size_t ob_meta[2], ob_f[2], ob_T[2], ob_D[2];
+  size_t counters;  // generation counter, batch budget
+  size_t st_ids, st_T, st_D;
+  size_t total;
+};
+
+Layout layout_of(const ga_config* c) {
+  const size_t islands = (size_t)c->width * c->height;
+  const size_t agents = islands * c->pop_per_island;
+  const size_t words = c->surface_sites / 32;
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  L.pop_f = take(agents * 4);
+  L.pop_T = take(agents * 4);
+  L.pop_D = take(agents * 4 * words);
+  for (int p = 0; p < 2; ++p) {
+    L.ob_meta[p] = take(islands * 4);
+    L.ob_f[p] = take(islands * 4);
+    L.ob_T[p] = take(islands * 4);
+    L.ob_D[p] = take(islands * 4 * words);
+  }
+  L.counters = take(16);
+  L.st_ids = take(islands * 4);
+  L.st_T = take(islands * 4);
+  L.st_D = take(islands * 4 * words);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct ga_run {
+  ga_config cfg{};
+  ga::RunView view{};
+  Layout lay{};
+  hipStream_t stream = nullptr;
+  uint8_t* base = nullptr;
+  uint64_t gen_host = 0;
+  uint32_t ipw = 64;
+  uint32_t wpg = 4;
+  uint32_t form = GA_FORM_AUTO;
+  uint32_t graph_block = 100;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  uint32_t graph_key_ipw = 0, graph_key_wpg = 0, graph_key_block = 0;
+  ga_batch* batch = nullptr;
+};
+
+struct ga_batch {
+  hipStream_t stream = nullptr;
+  std::vector<ga_run*> members;
+  std::vector<uint64_t> remaining;
+  ga::RunView* d_views = nullptr;
+  ga::Tile* d_tiles = nullptr;
+  size_t cap_views = 0, cap_tiles = 0;
+  uint32_t n_tiles = 0;
+  uint32_t wpg = 4;
+  uint32_t ipw_override = 0;
+  uint32_t graph_block = 100;
+  bool dirty = true;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+};
+
+namespace {
+
+uint32_t per_iter(const ga_run* r) { return 64u >> r->view.log2n; }
+
+uint32_t waves_for(const ga_run* r, uint32_t ipw) {
+  return (r->view.islands + ipw - 1) / ipw;
+}
+
+// Islands per wavefront for the resident form: spread the islands over as many
+// wavefronts as a workgroup can hold.
+uint32_t resident_ipw(const ga_run* r) {
+  const uint32_t g = per_iter(r);
+  uint32_t want = (r->view.islands + ga::kMaxWavesPerGroup - 1) / ga::kMaxWavesPerGroup;
+  want = (want + g - 1) / g * g;
+  return std::max(g, std::min(64u, want));
+}
+
+bool use_resident(const ga_run* r) {
+  if (r->form == GA_FORM_RESIDENT) return true;
+  if (r->form == GA_FORM_STREAMING) return false;
+  return r->view.agents <= 4096 && waves_for(r, resident_ipw(r)) <= (uint32_t)ga::kMaxWavesPerGroup;
+}
+
+void drop_graph(ga_run* r) {
+  if (r->graph) {
+    (void)hipGraphExecDestroy(r->graph);
+    r->graph = nullptr;
+  }
+}
+
+int enqueue_direct(ga_run* r, uint64_t n) {
+  // Streaming launches in slices whose generation offsets fit a 32-bit argument.
+  ga::RunView v = r->view;
+  v.ipw = r->ipw;
+  const uint32_t waves = waves_for(r, r->ipw);
+  while (n > 0) {
+    const uint64_t slice = std::min<uint64_t>(n, 1u << 20);
+    for (uint64_t g = 0; g < slice; ++g)
+      GA_HIP(ga::launch_generation(v, (uint32_t)g, waves, r->wpg, r->stream), "generation launch");
+    GA_HIP(ga::launch_advance(v.gen, slice, r->stream), "advance launch");
+    n -= slice;
+  }
+  return GA_OK;
+}
+
+int ensure_graph(ga_run* r) {
+  if (r->graph && r->graph_key_ipw == r->ipw && r->graph_key_wpg == r->wpg &&
+      r->graph_key_block == r->graph_block)
+    return GA_OK;
+  drop_graph(r);
+  if (!r->capture_stream)
+    GA_HIP(hipStreamCreateWithFlags(&r->capture_stream, hipStreamNonBlocking), "capture stream");
+  ga::RunView v = r->view;
+  v.ipw = r->ipw;
+  const uint32_t waves = waves_for(r, r->ipw);
+  GA_HIP(hipStreamBeginCapture(r->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  hipError_t err = hipSuccess;
+  for (uint32_t g = 0; g < r->graph_block && err == hipSuccess; ++g)
+    err = ga::launch_generation(v, g, waves, r->wpg, r->capture_stream);
+  if (err == hipSuccess) err = ga::launch_advance(v.gen, r->graph_block, r->capture_stream);
+  hipGraph_t graph = nullptr;
+  hipError_t end = hipStreamEndCapture(r->capture_stream, &graph);
+  if (err != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(err, "launch during capture");
+  }
+  if (end != hipSuccess) return hip_fail(end, "end capture");
+  hipGraphExec_t exec = nullptr;
+  err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (err != hipSuccess) return hip_fail(err, "graph instantiate");
+  r->graph = exec;
+  r->graph_key_ipw = r->ipw;
+  r->graph_key_wpg = r->wpg;
+  r->graph_key_block = r->graph_block;
+  return GA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ga_strerror(int code) {
+  switch (code) {
+    case GA_OK: return "success";
+    case GA_EINVAL: return "invalid argument";
+    case GA_ENOMEM: return "device buffer too small";
+    case GA_EDEVICE: return "HIP runtime error";
+    case GA_ESTATE: return "handle in the wrong state";
+    default: return "unknown error";
+  }
+}
+
+const char* ga_last_error(void) { return g_last_error.c_str(); }
+
+size_t ga_state_bytes(const ga_config* cfg) {
+  if (!config_ok(cfg, nullptr)) return 0;
+  return layout_of(cfg).total;
+}
+
+int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream, ga_run** out) {
+  std::string why;
+  if (!out) return fail(GA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!config_ok(cfg, &why)) return fail(GA_EINVAL, why);
+  if (!dev_mem) return fail(GA_EINVAL, "dev_mem is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_mem) % kAlign) return fail(GA_EINVAL, "dev_mem must be 256-byte aligned");
+  const Layout lay = layout_of(cfg);
+  if (bytes < lay.total) return fail(GA_ENOMEM, "dev_mem smaller than ga_state_bytes(cfg)");
+
+  ga_run* r = new (std::nothrow) ga_run();
+  if (!r) return fail(GA_EINVAL, "host allocation failed");
+  r->cfg = *cfg;
+  r->lay = lay;
+  r->stream = static_cast<hipStream_t>(hip_stream);
+  r->base = static_cast<uint8_t*>(dev_mem);
+  ga::RunView& v = r->view;
+  uint8_t* b = r->base;
+  v.pop_f = reinterpret_cast<float*>(b + lay.pop_f);
+  v.pop_T = reinterpret_cast<uint32_t*>(b + lay.pop_T);
+  v.pop_D = reinterpret_cast<uint32_t*>(b + lay.pop_D);
+  for (int p = 0; p < 2; ++p) {
+    v.ob_meta[p] = reinterpret_cast<uint32_t*>(b + lay.ob_meta[p]);
+    v.ob_f[p] = reinterpret_cast<float*>(b + lay.ob_f[p]);
+    v.ob_T[p] = reinterpret_cast<uint32_t*>(b + lay.ob_T[p]);
+    v.ob_D[p] = reinterpret_cast<uint32_t*>(b + lay.ob_D[p]);
+  }
+  v.gen = reinterpret_cast<unsigned long long*>(b + lay.counters);
+  v.left = v.gen + 1;
+  v.width = cfg->width;
+  v.height = cfg->height;
+  v.islands = cfg->width * cfg->height;
+  v.agents = v.islands * cfg->pop_per_island;
+  v.log2n = log2u(cfg->pop_per_island);
+  v.words = cfg->surface_sites / 32;
+  v.k = cfg->tournament_size;
+  v.selection = cfg->selection;
+  v.p32 = cfg->mutation_threshold;
+  v.migration = cfg->migration;
+  v.seed = cfg->seed;
+  v.run_id = cfg->run_id;
+  v.ipw = 64;
+  r->ipw = 64;
+
+  // Founders: all-zero bits are +0 fitness, T = 0, blank surfaces, invalid
+  // outbox headers, generation 0.
+  hipError_t e = ga::launch_fill(reinterpret_cast<uint32_t*>(b), 0u, lay.total / 4, r->stream);
+  if (e != hipSuccess) {
+    delete r;
+    return hip_fail(e, "init fill");
+  }
+  *out = r;
+  return GA_OK;
+}
+
+uint64_t ga_generation(const ga_run* r) { return r ? r->gen_host : 0; }
+
+int ga_set_launch(ga_run* r, uint32_t ipw, uint32_t wpg, uint32_t form) {
+  if (!r) return fail(GA_EINVAL, "run is NULL");
+  const uint32_t g = per_iter(r);
+  uint32_t new_ipw = ipw ? ipw : r->ipw;
+  uint32_t new_wpg = wpg ? wpg : r->wpg;
+  if (new_ipw < g || new_ipw > 64 || new_ipw % g)
+    return fail(GA_EINVAL, "islands_per_wave must be a multiple of 64/N in [64/N, 64]");
+  if (new_wpg < 1 || new_wpg > (uint32_t)ga::kMaxWavesPerGroup)
+    return fail(GA_EINVAL, "waves_per_group must be in [1, 16]");
+  if (form > GA_FORM_RESIDENT) return fail(GA_EINVAL, "unknown form");
+  if (form == GA_FORM_RESIDENT && waves_for(r, resident_ipw(r)) > (uint32_t)ga::kMaxWavesPerGroup)
+    return fail(GA_EINVAL, "run too large for the resident form");
+  r->ipw = new_ipw;
+  r->wpg = new_wpg;
+  r->form = form;
+  return GA_OK;
+}
+
+int ga_set_graph_block(ga_run* r, uint32_t gens) {
+  if (!r) return fail(GA_EINVAL, "run is NULL");
+  if (gens > 100000) return fail(GA_EINVAL, "graph block too long");
+  r->graph_block = gens;
+  return GA_OK;
+}
+
+int ga_step(ga_run* r, uint64_t n) {
+  if (!r) return fail(GA_EINVAL, "run is NULL");
+  if (r->batch) return fail(GA_ESTATE, "run is a batch member; advance it with ga_batch_step");
+  if (n == 0) return GA_OK;
+  if (use_resident(r)) {
+    ga::RunView v = r->view;
+    v.ipw = resident_ipw(r);
+    GA_HIP(ga::launch_resident(v, n, waves_for(r, v.ipw), r->stream), "resident launch");
+    r->gen_host += n;
+    return GA_OK;
+  }
+  uint64_t left = n;
+  if (r->graph_block > 0 && left >= r->graph_block) {
+    int rc = ensure_graph(r);
+    if (rc != GA_OK) return rc;
+    while (left >= r->graph_block) {
+      GA_HIP(hipGraphLaunch(r->graph, r->stream), "graph launch");
+      left -= r->graph_block;
+    }
+  }
+  int rc = enqueue_direct(r, left);
+  if (rc != GA_OK) return rc;
+  r->gen_host += n;
+  return GA_OK;
+}
+
+int ga_read_population(ga_run* r, float* fitness, uint32_t* T, uint32_t* surface_words,
+                       ga_outbox_entry* outbox, uint64_t* generation) {
+  if (!r) return fail(GA_EINVAL, "run is NULL");
+  hipStream_t s = r->batch ? r->batch->stream : r->stream;
+  GA_HIP(hipStreamSynchronize(s), "stream sync");
+  const ga::RunView& v = r->view;
+  const size_t A = v.agents, I = v.islands, W = v.words;
+  unsigned long long t = 0;
+  GA_HIP(hipMemcpy(&t, v.gen, sizeof(t), hipMemcpyDeviceToHost), "read generation");
+  if (fitness) GA_HIP(hipMemcpy(fitness, v.pop_f, A * 4, hipMemcpyDeviceToHost), "read fitness");
+  if (T) GA_HIP(hipMemcpy(T, v.pop_T, A * 4, hipMemcpyDeviceToHost), "read T");
+  if (surface_words) {
+    if (W == 1) {
+      GA_HIP(hipMemcpy(surface_words, v.pop_D, A * 4, hipMemcpyDeviceToHost), "read surfaces");
+    } else {
+      std::vector<uint32_t> planes(A * W);
+      GA_HIP(hipMemcpy(planes.data(), v.pop_D, A * W * 4, hipMemcpyDeviceToHost), "read surfaces");
+      for (size_t a = 0; a < A; ++a)
+        for (size_t w = 0; w < W; ++w) surface_words[a * W + w] = planes[w * A + a];
+    }
+  }
+  if (outbox) {
+    const int p = (int)((t & 1) ^ 1);
+    std::vector<uint32_t> meta(I), ot(I), od(I * W);
+    std::vector<float> of(I);
+    GA_HIP(hipMemcpy(meta.data(), v.ob_meta[p], I * 4, hipMemcpyDeviceToHost), "read outbox");
+    GA_HIP(hipMemcpy(of.data(), v.ob_f[p], I * 4, hipMemcpyDeviceToHost), "read outbox");
+    GA_HIP(hipMemcpy(ot.data(), v.ob_T[p], I * 4, hipMemcpyDeviceToHost), "read outbox");
+    GA_HIP(hipMemcpy(od.data(), v.ob_D[p], I * W * 4, hipMemcpyDeviceToHost), "read outbox");
+    for (size_t i = 0; i < I; ++i) {
+      ga_outbox_entry& e = outbox[i];
+      e.valid = (meta[i] & ga::kMetaValid) ? 1u : 0u;
+      e.dir = meta[i] & 3u;
+      e.fitness = of[i];
+      e.T = ot[i];
+      e.surface[0] = od[i];
+      e.surface[1] = W > 1 ? od[I + i] : 0u;
+    }
+  }
+  if (generation) *generation = t;
+  if (!r->batch) r->gen_host = t;
+  return GA_OK;
+}
+
+int ga_write_population(ga_run* r, const float* fitness, const uint32_t* T,
+                        const uint32_t* surface_words, const ga_outbox_entry* outbox,
+                        uint64_t generation) {
+  if (!r) return fail(GA_EINVAL, "run is NULL");
+  if (r->batch) return fail(GA_ESTATE, "run is a batch member");
+  if (outbox) {
+    for (size_t i = 0; i < r->view.islands; ++i)
+      if (outbox[i].valid > 1 || outbox[i].dir > 3) return fail(GA_EINVAL, "outbox entry out of range");
+  }
+  hipStream_t s = r->stream;
+  GA_HIP(hipStreamSynchronize(s), "stream sync");
+  const ga::RunView& v = r->view;
+  const size_t A = v.agents, I = v.islands, W = v.words;
+  unsigned long long t_old = 0;
+  GA_HIP(hipMemcpy(&t_old, v.gen, sizeof(t_old), hipMemcpyDeviceToHost), "read generation");
+  const hipMemcpyKind h2d = hipMemcpyHostToDevice, d2d = hipMemcpyDeviceToDevice;
+  if (fitness) GA_HIP(hipMemcpyAsync(v.pop_f, fitness, A * 4, h2d, s), "write fitness");
+  if (T) GA_HIP(hipMemcpyAsync(v.pop_T, T, A * 4, h2d, s), "write T");
+  std::vector<uint32_t> planes;
+  if (surface_words) {
+    planes.resize(A * W);
+    for (size_t a = 0; a < A; ++a)
+      for (size_t w = 0; w < W; ++w) planes[w * A + a] = surface_words[a * W + w];
+    GA_HIP(hipMemcpyAsync(v.pop_D, planes.data(), A * W * 4, h2d, s), "write surfaces");
+  }
+  const int p_old = (int)((t_old & 1) ^ 1);
+  const int p_new = (int)((generation & 1) ^ 1);
+  std::vector<uint32_t> meta, ot, od;
+  std::vector<float> of;
+  if (outbox) {
+    meta.resize(I);
+    ot.resize(I);
+    od.resize(I * W);
+    of.resize(I);
+    for (size_t i = 0; i < I; ++i) {
+      meta[i] = outbox[i].valid ? (ga::kMetaValid | outbox[i].dir) : 0u;
+      of[i] = outbox[i].fitness;
+      ot[i] = outbox[i].T;
+      for (size_t w = 0; w < W; ++w) od[w * I + i] = outbox[i].surface[w];
+    }
+    GA_HIP(hipMemcpyAsync(v.ob_meta[p_new], meta.data(), I * 4, h2d, s), "write outbox");
+    GA_HIP(hipMemcpyAsync(v.ob_f[p_new], of.data(), I * 4, h2d, s), "write outbox");
+    GA_HIP(hipMemcpyAsync(v.ob_T[p_new], ot.data(), I * 4, h2d, s), "write outbox");
+    GA_HIP(hipMemcpyAsync(v.ob_D[p_new], od.data(), I * W * 4, h2d, s), "write outbox");
+  } else if (p_new != p_old) {
+    // keep the pending emissions readable at the new generation's parity
+    GA_HIP(hipMemcpyAsync(v.ob_meta[p_new], v.ob_meta[p_old], I * 4, d2d, s), "move outbox");
+    GA_HIP(hipMemcpyAsync(v.ob_f[p_new], v.ob_f[p_old], I * 4, d2d, s), "move outbox");
+    GA_HIP(hipMemcpyAsync(v.ob_T[p_new], v.ob_T[p_old], I * 4, d2d, s), "move outbox");
+    GA_HIP(hipMemcpyAsync(v.ob_D[p_new], v.ob_D[p_old], I * W * 4, d2d, s), "move outbox");
+  }
+  unsigned long long t = generation;
+  GA_HIP(hipMemcpyAsync(v.gen, &t, sizeof(t), h2d, s), "write generation");
+  GA_HIP(hipStreamSynchronize(s), "stream sync");
+  r->gen_host = generation;
+  return GA_OK;
+}
+
+int ga_extract_surfaces(ga_run* r, const uint64_t* agent_ids, size_t n, uint64_t* ids_out,
+                        uint32_t* T_out, uint32_t* surface_words_out) {
+  if (!r) return fail(GA_EINVAL, "run is NULL");
+  const ga::RunView& v = r->view;
+  const size_t I = v.islands, W = v.words;
+  if (!agent_ids && n != I) return fail(GA_EINVAL, "n must equal the island count when agent_ids is NULL");
+  if (agent_ids)
+    for (size_t j = 0; j < n; ++j)
+      if (agent_ids[j] >= v.agents) return fail(GA_EINVAL, "agent id out of range");
+  if (n == 0) return GA_OK;
+  hipStream_t s = r->batch ? r->batch->stream : r->stream;
+  GA_HIP(hipStreamSynchronize(s), "stream sync");
+  uint32_t* st_ids = reinterpret_cast<uint32_t*>(r->base + r->lay.st_ids);
+  uint32_t* st_T = reinterpret_cast<uint32_t*>(r->base + r->lay.st_T);
+  uint32_t* st_D = reinterpret_cast<uint32_t*>(r->base + r->lay.st_D);
+  std::vector<uint32_t> ids32(std::min(n, I)), tT(std::min(n, I)), tD(std::min(n, I) * W);
+  for (size_t done = 0; done < n;) {
+    const size_t m = std::min(n - done, I);
+    if (agent_ids) {
+      for (size_t j = 0; j < m; ++j) ids32[j] = (uint32_t)agent_ids[done + j];
+      GA_HIP(hipMemcpyAsync(st_ids, ids32.data(), m * 4, hipMemcpyHostToDevice, s), "write ids");
+    } else {
+      GA_HIP(ga::launch_sample(v, st_ids, s), "sample launch");
+    }
+    GA_HIP(ga::launch_gather(v, st_ids, (uint32_t)m, st_T, st_D, s), "gather launch");
+    GA_HIP(hipMemcpyAsync(ids32.data(), st_ids, m * 4, hipMemcpyDeviceToHost, s), "read ids");
+    GA_HIP(hipMemcpyAsync(tT.data(), st_T, m * 4, hipMemcpyDeviceToHost, s), "read T");
+    GA_HIP(hipMemcpyAsync(tD.data(), st_D, m * W * 4, hipMemcpyDeviceToHost, s), "read surfaces");
+    GA_HIP(hipStreamSynchronize(s), "stream sync");
+    for (size_t j = 0; j < m; ++j) {
+      if (ids_out) ids_out[done + j] = ids32[j];
+      if (T_out) T_out[done + j] = tT[j];
+      if (surface_words_out)
+        for (size_t w = 0; w < W; ++w) surface_words_out[(done + j) * W + w] = tD[w * m + j];
+    }
+    done += m;
+  }
+  return GA_OK;
+}
+
+void ga_destroy(ga_run* r) {
+  if (!r) return;
+  if (r->batch) ga_batch_remove(r->batch, r);
+  (void)hipStreamSynchronize(r->stream);
+  drop_graph(r);
+  if (r->capture_stream) (void)hipStreamDestroy(r->capture_stream);
+  delete r;
+}
+
+// ---------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------
+
+int ga_batch_create(void* hip_stream, ga_batch** out) {
+  if (!out) return fail(GA_EINVAL, "out is NULL");
+  ga_batch* b = new (std::nothrow) ga_batch();
+  if (!b) return fail(GA_EINVAL, "host allocation failed");
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  *out = b;
+  return GA_OK;
+}
+
+size_t ga_batch_size(const ga_batch* b) { return b ? b->members.size() : 0; }
+
+int ga_batch_set_graph_block(ga_batch* b, uint32_t gens) {
+  if (!b) return fail(GA_EINVAL, "batch is NULL");
+  if (gens > 100000) return fail(GA_EINVAL, "graph block too long");
+  if (gens != b->graph_block) b->dirty = true;
+  b->graph_block = gens;
+  return GA_OK;
+}
+
+int ga_batch_set_islands_per_wave(ga_batch* b, uint32_t ipw) {
+  if (!b) return fail(GA_EINVAL, "batch is NULL");
+  if (ipw > 64) return fail(GA_EINVAL, "islands_per_wave must be <= 64");
+  b->ipw_override = ipw;
+  b->dirty = true;
+  return GA_OK;
+}
+
+int ga_batch_add(ga_batch* b, ga_run* r, uint64_t budget) {
+  if (!b || !r) return fail(GA_EINVAL, "batch or run is NULL");
+  if (r->batch) return fail(GA_ESTATE, "run is already in a batch");
+  GA_HIP(hipStreamSynchronize(r->stream), "stream sync");
+  unsigned long long left = budget;
+  GA_HIP(hipMemcpy(r->view.left, &left, sizeof(left), hipMemcpyHostToDevice), "write budget");
+  r->batch = b;
+  b->members.push_back(r);
+  b->remaining.push_back(budget);
+  b->dirty = true;
+  return GA_OK;
+}
+
+int ga_batch_remove(ga_batch* b, ga_run* r) {
+  if (!b || !r) return fail(GA_EINVAL, "batch or run is NULL");
+  auto it = std::find(b->members.begin(), b->members.end(), r);
+  if (it == b->members.end()) return fail(GA_EINVAL, "run is not a member");
+  GA_HIP(hipStreamSynchronize(b->stream), "stream sync");
+  const size_t idx = (size_t)(it - b->members.begin());
+  b->members.erase(it);
+  b->remaining.erase(b->remaining.begin() + (long)idx);
+  unsigned long long t = 0;
+  GA_HIP(hipMemcpy(&t, r->view.gen, sizeof(t), hipMemcpyDeviceToHost), "read generation");
+  r->gen_host = t;
+  r->batch = nullptr;
+  b->dirty = true;
+  return GA_OK;
+}
+
+uint64_t ga_batch_remaining(const ga_batch* b, const ga_run* r) {
+  if (!b) return 0;
+  for (size_t i = 0; i < b->members.size(); ++i)
+    if (b->members[i] == r) return b->remaining[i];
+  return 0;
+}
+
+namespace {
+
+uint32_t batch_ipw(const ga_batch* b, const ga_run* r) {
+  const uint32_t g = per_iter(r);
+  uint32_t ipw = b->ipw_override ? b->ipw_override : 64u;
+  ipw = std::max(g, ipw / g * g);
+  return std::min(64u, ipw);
+}
+
+int rebuild_tables(ga_batch* b) {
+  std::vector<ga::RunView> views;
+  std::vector<ga::Tile> tiles;
+  views.reserve(b->members.size());
+  for (uint32_t m = 0; m < b->members.size(); ++m) {
+    ga_run* r = b->members[m];
+    ga::RunView v = r->view;
+    v.ipw = batch_ipw(b, r);
+    views.push_back(v);
+    for (uint32_t first = 0; first < v.islands; first += v.ipw) tiles.push_back({m, first});
+  }
+  if (views.size() > b->cap_views) {
+    if (b->d_views) GA_HIP(hipFree(b->d_views), "free views");
+    b->d_views = nullptr;
+    b->cap_views = 0;
+    const size_t cap = std::max<size_t>(64, views.size() * 2);
+    GA_HIP(hipMalloc(&b->d_views, cap * sizeof(ga::RunView)), "alloc views");
+    b->cap_views = cap;
+  }
+  if (tiles.size() > b->cap_tiles) {
+    if (b->d_tiles) GA_HIP(hipFree(b->d_tiles), "free tiles");
+    b->d_tiles = nullptr;
+    b->cap_tiles = 0;
+    const size_t cap = std::max<size_t>(1024, tiles.size() * 2);
+    GA_HIP(hipMalloc(&b->d_tiles, cap * sizeof(ga::Tile)), "alloc tiles");
+    b->cap_tiles = cap;
+  }
+  if (!views.empty())
+    GA_HIP(hipMemcpyAsync(b->d_views, views.data(), views.size() * sizeof(ga::RunView),
+                          hipMemcpyHostToDevice, b->stream), "upload views");
+  if (!tiles.empty())
+    GA_HIP(hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(ga::Tile),
+                          hipMemcpyHostToDevice, b->stream), "upload tiles");
+  GA_HIP(hipStreamSynchronize(b->stream), "stream sync");
+  b->n_tiles = (uint32_t)tiles.size();
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  b->dirty = false;
+  return GA_OK;
+}
+
+int batch_direct(ga_batch* b, uint64_t n) {
+  const uint32_t runs = (uint32_t)b->members.size();
+  while (n > 0) {
+    const uint64_t slice = std::min<uint64_t>(n, 1u << 20);
+    for (uint64_t g = 0; g < slice; ++g)
+      GA_HIP(ga::launch_batch_generation(b->d_views, b->d_tiles, b->n_tiles, (uint32_t)g, b->wpg,
+                                         b->stream), "batch launch");
+    GA_HIP(ga::launch_batch_advance(b->d_views, runs, slice, b->stream), "batch advance");
+    n -= slice;
+  }
+  return GA_OK;
+}
+
+int batch_graph(ga_batch* b) {
+  if (b->graph) return GA_OK;
+  if (!b->capture_stream)
+    GA_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking), "capture stream");
+  GA_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  hipError_t err = hipSuccess;
+  for (uint32_t g = 0; g < b->graph_block && err == hipSuccess; ++g)
+    err = ga::launch_batch_generation(b->d_views, b->d_tiles, b->n_tiles, g, b->wpg, b->capture_stream);
+  if (err == hipSuccess)
+    err = ga::launch_batch_advance(b->d_views, (uint32_t)b->members.size(), b->graph_block,
+                                   b->capture_stream);
+  hipGraph_t graph = nullptr;
+  hipError_t end = hipStreamEndCapture(b->capture_stream, &graph);
+  if (err != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(err, "launch during capture");
+  }
+  if (end != hipSuccess) return hip_fail(end, "end capture");
+  hipGraphExec_t exec = nullptr;
+  err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (err != hipSuccess) return hip_fail(err, "graph instantiate");
+  b->graph = exec;
+  return GA_OK;
+}
+
+}  // namespace
+
+int ga_batch_step(ga_batch* b, uint64_t n) {
+  if (!b) return fail(GA_EINVAL, "batch is NULL");
+  if (n == 0 || b->members.empty()) return GA_OK;
+  if (b->dirty) {
+    int rc = rebuild_tables(b);
+    if (rc != GA_OK) return rc;
+  }
+  uint64_t left = n;
+  if (b->graph_block > 0 && left >= b->graph_block) {
+    int rc = batch_graph(b);
+    if (rc != GA_OK) return rc;
+    while (left >= b->graph_block) {
+      GA_HIP(hipGraphLaunch(b->graph, b->stream), "graph launch");
+      left -= b->graph_block;
+    }
+  }
+  int rc = batch_direct(b, left);
+  if (rc != GA_OK) return rc;
+  // host mirror of the budgets: however the n generations are split into
+  // blocks, each member advances by min(n, its remaining budget)
+  for (auto& rem : b->remaining) rem -= std::min<uint64_t>(rem, n);
+  return GA_OK;
+}
+
+void ga_batch_destroy(ga_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  for (ga_run* r : b->members) {
+    unsigned long long t = 0;
+    if (hipMemcpy(&t, r->view.gen, sizeof(t), hipMemcpyDeviceToHost) == hipSuccess) r->gen_host = t;
+    r->batch = nullptr;
+  }
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  if (b->d_views) (void)hipFree(b->d_views);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  delete b;
+}
+
+}  // extern "C"

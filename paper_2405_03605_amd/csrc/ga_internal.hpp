@@ -1,0 +1,56 @@
+// Internal definitions shared by the kernels and the C ABI of libga_hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ga {
+
+// Device view of one run's state. Population and outbox are SoA planes so a
+// wavefront touches 256 contiguous bytes per field:
+//   pop_f[a], pop_T[a], pop_D[w * agents + a]            a = island * N + slot
+//   ob_meta[p][i] (bit 2 valid, bits 0-1 direction), ob_f[p][i], ob_T[p][i],
+//   ob_D[p][w * islands + i]                             p = generation parity
+struct RunView {
+  float* pop_f;
+  uint32_t* pop_T;
+  uint32_t* pop_D;
+  uint32_t* ob_meta[2];
+  float* ob_f[2];
+  uint32_t* ob_T[2];
+  uint32_t* ob_D[2];
+  unsigned long long* gen;   // generation counter t (device)
+  unsigned long long* left;  // generations still owed in the current batch block (batch only)
+  uint32_t width, height, islands, agents;
+  uint32_t log2n, words, k, selection;
+  uint32_t p32, migration, seed, run_id;
+  uint32_t ipw;              // islands per wavefront
+  uint32_t pad;
+};
+
+// One wavefront's share of a batched launch: islands [first, first + ipw) of run `run`.
+struct Tile {
+  uint32_t run;
+  uint32_t first;
+};
+
+constexpr uint32_t kMetaValid = 4u;
+constexpr uint32_t kDiscard = 0xFFFFFFFFu;
+constexpr int kMaxWavesPerGroup = 16;
+
+// Launch wrappers (defined in ga_kernels.hip). All enqueue on `stream`.
+hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t waves,
+                             uint32_t waves_per_group, hipStream_t stream);
+hipError_t launch_resident(const RunView& v, uint64_t n_gens, uint32_t waves, hipStream_t stream);
+hipError_t launch_advance(unsigned long long* gen, uint64_t n, hipStream_t stream);
+hipError_t launch_fill(uint32_t* p, uint32_t value, size_t words, hipStream_t stream);
+hipError_t launch_sample(const RunView& v, uint32_t* ids, hipStream_t stream);
+hipError_t launch_gather(const RunView& v, const uint32_t* ids, uint32_t n, uint32_t* T_out,
+                         uint32_t* D_out, hipStream_t stream);
+hipError_t launch_batch_generation(const RunView* views, const Tile* tiles, uint32_t n_tiles,
+                                   uint32_t gen_offset, uint32_t waves_per_group,
+                                   hipStream_t stream);
+hipError_t launch_batch_advance(const RunView* views, uint32_t n_runs, uint64_t block,
+                                hipStream_t stream);
+
+}  // namespace ga

@@ -1,0 +1,185 @@
+"""Python handles over the C ABI: GARun (one GA run) and GABatch (many runs
+advanced together). PyTorch provides the device memory and the stream; every
+generation runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import (FORM_AUTO, GA_EINVAL, Config, GAError, OutboxEntry, check, load)
+
+CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32", "migration",
+                 "seed", "run_id")
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_config(cfg: dict) -> Config:
+    return Config(struct_size=ctypes.sizeof(Config), width=cfg["width"], height=cfg["height"],
+                  pop_per_island=cfg["pop"], surface_sites=cfg["sites"],
+                  tournament_size=cfg["k"], selection=cfg["selection"],
+                  mutation_threshold=cfg["p32"], migration=cfg["migration"],
+                  seed=cfg["seed"], run_id=cfg["run_id"])
+
+
+def state_bytes(cfg: dict) -> int:
+    """Device footprint of a run (0 if the configuration is invalid)."""
+    c = make_config(cfg)
+    return int(load().ga_state_bytes(ctypes.byref(c)))
+
+
+class GARun:
+    """One island-model GA run whose state lives in a torch uint8 CUDA tensor."""
+
+    def __init__(self, cfg: dict, device=None, stream=None):
+        import torch
+        lib = load()
+        self.cfg = {f: int(cfg[f]) for f in CONFIG_FIELDS}
+        self._c = make_config(self.cfg)
+        nbytes = int(lib.ga_state_bytes(ctypes.byref(self._c)))
+        if nbytes == 0:
+            raise GAError(GA_EINVAL, f"invalid configuration {self.cfg}")
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        check(lib.ga_init(ctypes.byref(self._c), ctypes.c_void_p(self.mem.data_ptr()), nbytes,
+                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.state_bytes = nbytes
+        self.islands = self.cfg["width"] * self.cfg["height"]
+        self.agents = self.islands * self.cfg["pop"]
+        self.words = self.cfg["sites"] // 32
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ga_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int):
+        check(load().ga_step(self._h, int(n)))
+
+    @property
+    def generation(self) -> int:
+        return int(load().ga_generation(self._h))
+
+    def set_launch(self, islands_per_wave: int = 0, waves_per_group: int = 0, form: int = FORM_AUTO):
+        check(load().ga_set_launch(self._h, islands_per_wave, waves_per_group, form))
+
+    def set_graph_block(self, gens: int):
+        check(load().ga_set_graph_block(self._h, gens))
+
+    def read(self, outbox: bool = True) -> dict:
+        A, I, W = self.agents, self.islands, self.words
+        f = np.empty(A, dtype=np.float32)
+        T = np.empty(A, dtype=np.uint32)
+        D = np.empty((A, W), dtype=np.uint32)
+        ob = (OutboxEntry * I)() if outbox else None
+        gen = ctypes.c_uint64()
+        obp = ctypes.cast(ob, ctypes.c_void_p) if ob is not None else None
+        check(load().ga_read_population(self._h, _ptr(f), _ptr(T), _ptr(D), obp, ctypes.byref(gen)))
+        out = {"f": f, "T": T, "D": D, "generation": int(gen.value)}
+        if ob is not None:
+            raw = np.frombuffer(ob, dtype=np.uint32).reshape(I, 6)
+            out["outbox"] = {
+                "valid": raw[:, 0].astype(np.uint8), "dir": raw[:, 1].astype(np.uint8),
+                "f": raw[:, 2].copy().view(np.float32), "T": raw[:, 3].copy(),
+                "D": raw[:, 4:4 + W].copy()}
+        return out
+
+    def write(self, f=None, T=None, D=None, outbox: dict | None = None, generation: int = 0):
+        A, I, W = self.agents, self.islands, self.words
+        fa = None if f is None else np.ascontiguousarray(f, dtype=np.float32)
+        Ta = None if T is None else np.ascontiguousarray(T, dtype=np.uint32)
+        Da = None if D is None else np.ascontiguousarray(np.asarray(D, dtype=np.uint32).reshape(A, W))
+        for a, n in ((fa, A), (Ta, A)):
+            if a is not None and a.size != n:
+                raise ValueError("population array has the wrong size")
+        ob = None
+        if outbox is not None:
+            raw = np.zeros((I, 6), dtype=np.uint32)
+            raw[:, 0] = outbox["valid"]
+            raw[:, 1] = outbox["dir"]
+            raw[:, 2] = np.asarray(outbox["f"], dtype=np.float32).view(np.uint32)
+            raw[:, 3] = outbox["T"]
+            raw[:, 4:4 + W] = np.asarray(outbox["D"], dtype=np.uint32).reshape(I, W)
+            ob = (OutboxEntry * I).from_buffer_copy(raw.tobytes())
+        obp = ctypes.cast(ob, ctypes.c_void_p) if ob is not None else None
+        check(load().ga_write_population(self._h, _ptr(fa), _ptr(Ta), _ptr(Da), obp, int(generation)))
+
+    def extract(self, agent_ids=None):
+        """(ids, T, D) for one agent per island (agent_ids None) or the listed agents."""
+        W = self.words
+        if agent_ids is None:
+            n = self.islands
+            ids_in = None
+        else:
+            ids_in = np.ascontiguousarray(agent_ids, dtype=np.uint64)
+            n = ids_in.size
+        ids = np.empty(n, dtype=np.uint64)
+        T = np.empty(n, dtype=np.uint32)
+        D = np.empty((n, W), dtype=np.uint32)
+        check(load().ga_extract_surfaces(self._h, _ptr(ids_in), n, _ptr(ids), _ptr(T), _ptr(D)))
+        return ids, T, D
+
+
+class GABatch:
+    """Many runs advanced together: one launch per generation over every
+    member's islands, blocks of generations replayed from a HIP graph."""
+
+    def __init__(self, stream=None):
+        import torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        check(load().ga_batch_create(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.members = []
+
+    def add(self, run: GARun, budget: int):
+        check(load().ga_batch_add(self._h, run.handle, int(budget)))
+        self.members.append(run)
+
+    def remove(self, run: GARun):
+        check(load().ga_batch_remove(self._h, run.handle))
+        self.members.remove(run)
+
+    def step(self, n: int):
+        check(load().ga_batch_step(self._h, int(n)))
+
+    def remaining(self, run: GARun) -> int:
+        return int(load().ga_batch_remaining(self._h, run.handle))
+
+    def __len__(self):
+        return int(load().ga_batch_size(self._h))
+
+    def set_graph_block(self, gens: int):
+        check(load().ga_batch_set_graph_block(self._h, gens))
+
+    def set_islands_per_wave(self, ipw: int):
+        check(load().ga_batch_set_islands_per_wave(self._h, ipw))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ga_batch_destroy(self._h)
+            self._h = None
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

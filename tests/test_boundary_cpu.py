@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/ga.h declares, and rejects bad configurations and
+buffers before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2405_03605_amd as ga
+from paper_2405_03605_amd import _lib
+from paper_2405_03605_amd.run import make_config
+from paper_2405_03605_amd.workloads import MID, PAPER, TINY, run_config
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libga_hip.so not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def _declared_functions():
+    text = open(_lib.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(ga_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_state_bytes_layout(lib):
+    # SoA planes: fitness, T, surface words per agent; 2 outboxes of
+    # (header, fitness, T, surface words) per island; counters; extraction staging.
+    def expect(c):
+        I = c["width"] * c["height"]
+        A = I * c["pop"]
+        W = c["sites"] // 32
+        al = lambda b: (b + 255) // 256 * 256
+        return (al(4 * A) * 2 + al(4 * A * W) + 2 * (3 * al(4 * I) + al(4 * I * W)) + 256
+                + 2 * al(4 * I) + al(4 * I * W))
+    for c in (TINY, MID, PAPER, run_config(width=3, height=5, pop=1, sites=32)):
+        assert ga.state_bytes(c) == expect(c)
+    # paper-scale run: 16.8M agents, 12 B each
+    assert 200e6 < ga.state_bytes(PAPER) < 230e6
+
+
+@pytest.mark.parametrize("bad", [
+    dict(pop=24), dict(pop=128), dict(pop=0), dict(sites=48), dict(sites=16), dict(k=0),
+    dict(k=9), dict(width=0), dict(height=0), dict(width=70000), dict(selection=2),
+    dict(migration=3), dict(width=65535, height=65535, pop=64)])
+def test_invalid_configs_rejected(lib, bad):
+    c = make_config(run_config(**bad))
+    assert lib.ga_state_bytes(ctypes.byref(c)) == 0
+    h = ctypes.c_void_p()
+    rc = lib.ga_init(ctypes.byref(c), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(h))
+    assert rc == _lib.GA_EINVAL
+    assert h.value is None
+    assert lib.ga_last_error()
+
+
+def test_init_argument_checks(lib):
+    c = make_config(TINY)
+    need = lib.ga_state_bytes(ctypes.byref(c))
+    h = ctypes.c_void_p()
+    assert lib.ga_init(ctypes.byref(c), None, need, None, ctypes.byref(h)) == _lib.GA_EINVAL
+    assert lib.ga_init(ctypes.byref(c), ctypes.c_void_p(4096 + 8), need, None,
+                       ctypes.byref(h)) == _lib.GA_EINVAL
+    assert lib.ga_init(ctypes.byref(c), ctypes.c_void_p(4096), need - 1, None,
+                       ctypes.byref(h)) == _lib.GA_ENOMEM
+    c.struct_size = 8
+    assert lib.ga_init(ctypes.byref(c), ctypes.c_void_p(4096), need, None,
+                       ctypes.byref(h)) == _lib.GA_EINVAL
+
+
+def test_null_handles_rejected(lib):
+    assert lib.ga_step(None, 5) == _lib.GA_EINVAL
+    assert lib.ga_read_population(None, None, None, None, None, None) == _lib.GA_EINVAL
+    assert lib.ga_extract_surfaces(None, None, 0, None, None, None) == _lib.GA_EINVAL
+    assert lib.ga_batch_step(None, 1) == _lib.GA_EINVAL
+    assert lib.ga_generation(None) == 0
+    lib.ga_destroy(None)
+    lib.ga_batch_destroy(None)
+    for code in (0, -1, -2, -3, -4, -99):
+        assert lib.ga_strerror(code)
