@@ -1,0 +1,197 @@
+"""Benchmark: agent-generations per second of the island-model GA generation
+step on one MI355X, at 16.8M agents (1024 x 512 islands x 32 agents, 32-site
+surfaces, tournament 2, mutation p = 0.1), plus batched vs plain throughput on
+64 uneven runs.
+
+A step is one generation of the whole population: absorb, emit, evaluate,
+tournament, copy, mutate and deposit for every island and agent. The state is
+resident in HBM before timing starts. Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--batched-gens G]
+                  [--no-cpu-baseline] [--no-batched]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0          # MI355X HBM3E
+CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
+PEAK_LANE_OPS = CUS * LANES_PER_CU * CLOCK_HZ   # full-rate 32-bit VALU lane-ops/s
+KERNEL_SRC = os.path.join(ROOT, "paper_2405_03605_amd", "csrc", "ga_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_generation_kernel_paper.json")
+
+
+def algorithmic_bytes_per_generation(cfg: dict) -> int:
+    """HBM bytes one generation must move: every agent's genome read and
+    written once (fitness, T, S/32 surface words), and per island one outbox
+    entry written and one read (header, fitness, T, surface words)."""
+    I = cfg["width"] * cfg["height"]
+    A = I * cfg["pop"]
+    genome = 8 + cfg["sites"] // 8
+    return 2 * genome * A + 2 * (4 + genome) * I
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
+    if the kernel source has changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def bench_single(args, torch):
+    from paper_2405_03605_amd import GARun
+    from paper_2405_03605_amd.workloads import PAPER
+
+    cfg = dict(PAPER)
+    run = GARun(cfg)
+    if args.ipw or args.wpg:
+        run.set_launch(args.ipw, args.wpg)
+    if args.graph_block is not None:
+        run.set_graph_block(args.graph_block)
+    stream = torch.cuda.current_stream()
+    run.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    run.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    gen = run.read(outbox=False)["generation"]
+    assert gen == args.warmup + args.steps, (gen, args.warmup, args.steps)
+    run.close()
+    return cfg, wall, ev_ms
+
+
+def bench_batched(gens: int, torch):
+    from paper_2405_03605_amd import GABatch, GARun
+    from paper_2405_03605_amd.workloads import batched_configs
+
+    cfgs = batched_configs()
+    agents = sum(c["width"] * c["height"] * c["pop"] for c in cfgs)
+    # plain: one run per launch sequence, runs one after another
+    runs = [GARun(c) for c in cfgs]
+    for r in runs:
+        r.step(100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in runs:
+        r.step(gens)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    for r in runs:
+        r.close()
+    # batched: every run in one launch per generation, 100-generation graph blocks
+    runs = [GARun(c) for c in cfgs]
+    batch = GABatch()
+    for r in runs:
+        batch.add(r, gens + 100)
+    batch.step(100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(gens)
+    torch.cuda.synchronize()
+    batched = time.perf_counter() - t0
+    batch.close()
+    for r in runs:
+        r.close()
+    return {"runs": len(cfgs), "agents": agents, "generations": gens,
+            "batched_agent_gens_per_s": agents * gens / batched,
+            "plain_agent_gens_per_s": agents * gens / plain,
+            "speedup": plain / batched}
+
+
+def cpu_baseline(cfg: dict, budget_s: float = 12.0):
+    import oracle
+    run = oracle.OracleRun(cfg)
+    t0 = time.perf_counter()
+    run.step(1)
+    first = time.perf_counter() - t0
+    gens = max(1, min(40, int(budget_s / max(first, 1e-3))))
+    t0 = time.perf_counter()
+    run.step(gens)
+    dt = time.perf_counter() - t0
+    agents = cfg["width"] * cfg["height"] * cfg["pop"]
+    return {"value": agents * gens / dt, "unit": "agent-generations/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"single-threaded CPU oracle, generations 1..{gens + 1} of the "
+                      f"{cfg['width']}x{cfg['height']}x{cfg['pop']} run ({agents} agents), "
+                      f"generation loop only, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--batched-gens", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--ipw", type=int, default=0, help="islands per wavefront (0: library default)")
+    ap.add_argument("--wpg", type=int, default=0, help="wavefronts per workgroup (0: default)")
+    ap.add_argument("--graph-block", type=int, default=None,
+                    help="generations per HIP graph replay (default 100; 0 disables)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the island grid "
+              "would shard as 2D tiles with a per-generation halo exchange, which this "
+              "build does not run.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    cfg, wall, ev_ms = bench_single(args, torch)
+    agents = cfg["width"] * cfg["height"] * cfg["pop"]
+    value = agents * args.steps / wall
+    kernel_s = ev_ms * 1e-3 / args.steps
+    bytes_gen = algorithmic_bytes_per_generation(cfg)
+    achieved = bytes_gen / kernel_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                "traffic": measured_traffic(),
+                "kernel": "generation_kernel<5,1>", "bytes_per_launch": bytes_gen,
+                "launch_us": round(kernel_s * 1e6, 2)}
+    out = {"metric": "agent-generations/sec at 16.8M agents; batched vs plain throughput",
+           "value": value, "unit": "agent-generations/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "island GA 1024x512 islands x 32 agents (16.8M), 32-site "
+                                  "surface, tournament 2, mutation p=0.1, migration 1/island/gen",
+                      "islands": cfg["width"] * cfg["height"], "agents": agents,
+                      "step": "one generation"},
+           "roofline": roofline}
+    if not args.no_batched:
+        out["batched"] = bench_batched(args.batched_gens, torch)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

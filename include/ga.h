@@ -140,8 +140,9 @@ void ga_destroy(ga_run* run);
 #define GA_FORM_RESIDENT 2   /* one workgroup loops over generations (<= 16 wavefronts) */
 
 /* Launch tuning for one run: islands per wavefront (a multiple of 64/N, at
- * most 64), wavefronts per workgroup (1..16) and the launch form. 0 keeps the
- * current value of the first two. Results do not depend on any of these.
+ * most 64; default 16, or fewer for small grids), wavefronts per workgroup
+ * (1..16; default 4) and the launch form. 0 keeps the current value of the
+ * first two. Results do not depend on any of these.
  * GA_EINVAL if the resident form is asked for a run that needs more than 16
  * wavefronts at the given islands per wavefront. */
 int ga_set_launch(ga_run* run, uint32_t islands_per_wave, uint32_t waves_per_group,

@@ -58,21 +58,29 @@ bool config_ok(const ga_config* c, std::string* why) {
   if (c->selection > 1) return no("selection must be 0 or 1");
   if (c->migration > 1) return no("migration must be 0 or 1");
   const uint64_t agents = (uint64_t)c->width * c->height * c->pop_per_island;
-  if (agents >= (1ull << 31)) return no("width * height * pop_per_island must be < 2^31");
+  if (agents >= (1ull << 30)) return no("width * height * pop_per_island must be < 2^30");
   return true;
 }
 
 // Byte offsets of every plane inside a run's device buffer.
 struct Layout {
   size_t pop_f, pop_T, pop_D;
-  size_t ob_meta[2], ob_f[2], ob_T[2], ob_D[2];
+  size_t ob[2];
   size_t counters;  // generation counter, batch budget
   size_t st_ids, st_T, st_D;
   size_t total;
 };
 
-Layout layout_of(const ga_config* c) {
+// words per AoS outbox entry: fitness, T, surface words, header, padding to 16 B
+size_t outbox_stride(const ga_config* c) { return c->surface_sites == 32 ? 4 : 8; }
+
+size_t padded_islands(const ga_config* c) {
   const size_t islands = (size_t)c->width * c->height;
+  return (islands + 63) / 64 * 64 + 64;
+}
+
+Layout layout_of(const ga_config* c) {
+  const size_t islands = padded_islands(c);
   const size_t agents = islands * c->pop_per_island;
   const size_t words = c->surface_sites / 32;
   Layout L{};
@@ -85,12 +93,7 @@ Layout layout_of(const ga_config* c) {
   L.pop_f = take(agents * 4);
   L.pop_T = take(agents * 4);
   L.pop_D = take(agents * 4 * words);
-  for (int p = 0; p < 2; ++p) {
-    L.ob_meta[p] = take(islands * 4);
-    L.ob_f[p] = take(islands * 4);
-    L.ob_T[p] = take(islands * 4);
-    L.ob_D[p] = take(islands * 4 * words);
-  }
+  for (int p = 0; p < 2; ++p) L.ob[p] = take(islands * 4 * outbox_stride(c));
   L.counters = take(16);
   L.st_ids = take(islands * 4);
   L.st_T = take(islands * 4);
@@ -137,6 +140,16 @@ struct ga_batch {
 namespace {
 
 uint32_t per_iter(const ga_run* r) { return 64u >> r->view.log2n; }
+
+// Default islands per wavefront: 16 (measured best for large grids on
+// MI355X), fewer when that leaves under 4 wavefronts per SIMD (1024 SIMDs),
+// never fewer than one iteration's worth (64/N islands).
+uint32_t default_ipw(const ga::RunView& v) {
+  const uint32_t g = 64u >> v.log2n;
+  uint32_t ipw = 16;
+  while (ipw > g && (v.islands + ipw - 1) / ipw < 4096) ipw >>= 1;
+  return std::max(g, std::min(64u, ipw));
+}
 
 uint32_t waves_for(const ga_run* r, uint32_t ipw) {
   return (r->view.islands + ipw - 1) / ipw;
@@ -255,18 +268,16 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   v.pop_f = reinterpret_cast<float*>(b + lay.pop_f);
   v.pop_T = reinterpret_cast<uint32_t*>(b + lay.pop_T);
   v.pop_D = reinterpret_cast<uint32_t*>(b + lay.pop_D);
-  for (int p = 0; p < 2; ++p) {
-    v.ob_meta[p] = reinterpret_cast<uint32_t*>(b + lay.ob_meta[p]);
-    v.ob_f[p] = reinterpret_cast<float*>(b + lay.ob_f[p]);
-    v.ob_T[p] = reinterpret_cast<uint32_t*>(b + lay.ob_T[p]);
-    v.ob_D[p] = reinterpret_cast<uint32_t*>(b + lay.ob_D[p]);
-  }
+  for (int p = 0; p < 2; ++p) v.ob[p] = reinterpret_cast<uint32_t*>(b + lay.ob[p]);
+  v.ob_stride = (uint32_t)outbox_stride(cfg);
   v.gen = reinterpret_cast<unsigned long long*>(b + lay.counters);
   v.left = v.gen + 1;
   v.width = cfg->width;
   v.height = cfg->height;
   v.islands = cfg->width * cfg->height;
   v.agents = v.islands * cfg->pop_per_island;
+  v.island_stride = (uint32_t)padded_islands(cfg);
+  v.agent_stride = v.island_stride * cfg->pop_per_island;
   v.log2n = log2u(cfg->pop_per_island);
   v.words = cfg->surface_sites / 32;
   v.k = cfg->tournament_size;
@@ -275,8 +286,8 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   v.migration = cfg->migration;
   v.seed = cfg->seed;
   v.run_id = cfg->run_id;
-  v.ipw = 64;
-  r->ipw = 64;
+  r->ipw = default_ipw(v);
+  v.ipw = r->ipw;
 
   // Founders: all-zero bits are +0 fitness, T = 0, blank surfaces, invalid
   // outbox headers, generation 0.
@@ -358,27 +369,28 @@ int ga_read_population(ga_run* r, float* fitness, uint32_t* T, uint32_t* surface
       GA_HIP(hipMemcpy(surface_words, v.pop_D, A * 4, hipMemcpyDeviceToHost), "read surfaces");
     } else {
       std::vector<uint32_t> planes(A * W);
-      GA_HIP(hipMemcpy(planes.data(), v.pop_D, A * W * 4, hipMemcpyDeviceToHost), "read surfaces");
+      for (size_t w = 0; w < W; ++w)
+        GA_HIP(hipMemcpy(planes.data() + w * A, v.pop_D + w * v.agent_stride, A * 4,
+                         hipMemcpyDeviceToHost), "read surfaces");
       for (size_t a = 0; a < A; ++a)
         for (size_t w = 0; w < W; ++w) surface_words[a * W + w] = planes[w * A + a];
     }
   }
   if (outbox) {
     const int p = (int)((t & 1) ^ 1);
-    std::vector<uint32_t> meta(I), ot(I), od(I * W);
-    std::vector<float> of(I);
-    GA_HIP(hipMemcpy(meta.data(), v.ob_meta[p], I * 4, hipMemcpyDeviceToHost), "read outbox");
-    GA_HIP(hipMemcpy(of.data(), v.ob_f[p], I * 4, hipMemcpyDeviceToHost), "read outbox");
-    GA_HIP(hipMemcpy(ot.data(), v.ob_T[p], I * 4, hipMemcpyDeviceToHost), "read outbox");
-    GA_HIP(hipMemcpy(od.data(), v.ob_D[p], I * W * 4, hipMemcpyDeviceToHost), "read outbox");
+    const size_t st = v.ob_stride;
+    std::vector<uint32_t> ob(I * st);
+    GA_HIP(hipMemcpy(ob.data(), v.ob[p], I * st * 4, hipMemcpyDeviceToHost), "read outbox");
     for (size_t i = 0; i < I; ++i) {
+      const uint32_t* src = &ob[i * st];
+      const uint32_t hdr = src[2 + W];
       ga_outbox_entry& e = outbox[i];
-      e.valid = (meta[i] & ga::kMetaValid) ? 1u : 0u;
-      e.dir = meta[i] & 3u;
-      e.fitness = of[i];
-      e.T = ot[i];
-      e.surface[0] = od[i];
-      e.surface[1] = W > 1 ? od[I + i] : 0u;
+      e.valid = (hdr & ga::kMetaValid) ? 1u : 0u;
+      e.dir = hdr & 3u;
+      std::memcpy(&e.fitness, &src[0], 4);
+      e.T = src[1];
+      e.surface[0] = src[2];
+      e.surface[1] = W > 1 ? src[3] : 0u;
     }
   }
   if (generation) *generation = t;
@@ -409,33 +421,28 @@ int ga_write_population(ga_run* r, const float* fitness, const uint32_t* T,
     planes.resize(A * W);
     for (size_t a = 0; a < A; ++a)
       for (size_t w = 0; w < W; ++w) planes[w * A + a] = surface_words[a * W + w];
-    GA_HIP(hipMemcpyAsync(v.pop_D, planes.data(), A * W * 4, h2d, s), "write surfaces");
+    for (size_t w = 0; w < W; ++w)
+      GA_HIP(hipMemcpyAsync(v.pop_D + w * v.agent_stride, planes.data() + w * A, A * 4, h2d, s),
+             "write surfaces");
   }
   const int p_old = (int)((t_old & 1) ^ 1);
   const int p_new = (int)((generation & 1) ^ 1);
-  std::vector<uint32_t> meta, ot, od;
-  std::vector<float> of;
+  const size_t st = v.ob_stride;
+  std::vector<uint32_t> ob;
   if (outbox) {
-    meta.resize(I);
-    ot.resize(I);
-    od.resize(I * W);
-    of.resize(I);
+    ob.assign(I * st, 0u);
     for (size_t i = 0; i < I; ++i) {
-      meta[i] = outbox[i].valid ? (ga::kMetaValid | outbox[i].dir) : 0u;
-      of[i] = outbox[i].fitness;
-      ot[i] = outbox[i].T;
-      for (size_t w = 0; w < W; ++w) od[w * I + i] = outbox[i].surface[w];
+      uint32_t* dst = &ob[i * st];
+      std::memcpy(&dst[0], &outbox[i].fitness, 4);
+      dst[1] = outbox[i].T;
+      for (size_t w = 0; w < W; ++w) dst[2 + w] = outbox[i].surface[w];
+      dst[2 + W] = outbox[i].valid ? (ga::kMetaValid | outbox[i].dir) : 0u;
     }
-    GA_HIP(hipMemcpyAsync(v.ob_meta[p_new], meta.data(), I * 4, h2d, s), "write outbox");
-    GA_HIP(hipMemcpyAsync(v.ob_f[p_new], of.data(), I * 4, h2d, s), "write outbox");
-    GA_HIP(hipMemcpyAsync(v.ob_T[p_new], ot.data(), I * 4, h2d, s), "write outbox");
-    GA_HIP(hipMemcpyAsync(v.ob_D[p_new], od.data(), I * W * 4, h2d, s), "write outbox");
+    GA_HIP(hipMemcpyAsync(v.ob[p_new], ob.data(), I * st * 4, h2d, s), "write outbox");
   } else if (p_new != p_old) {
     // keep the pending emissions readable at the new generation's parity
-    GA_HIP(hipMemcpyAsync(v.ob_meta[p_new], v.ob_meta[p_old], I * 4, d2d, s), "move outbox");
-    GA_HIP(hipMemcpyAsync(v.ob_f[p_new], v.ob_f[p_old], I * 4, d2d, s), "move outbox");
-    GA_HIP(hipMemcpyAsync(v.ob_T[p_new], v.ob_T[p_old], I * 4, d2d, s), "move outbox");
-    GA_HIP(hipMemcpyAsync(v.ob_D[p_new], v.ob_D[p_old], I * W * 4, d2d, s), "move outbox");
+    GA_HIP(hipMemcpyAsync(v.ob[p_new], v.ob[p_old], (size_t)v.island_stride * st * 4, d2d, s),
+           "move outbox");
   }
   unsigned long long t = generation;
   GA_HIP(hipMemcpyAsync(v.gen, &t, sizeof(t), h2d, s), "write generation");
@@ -564,7 +571,7 @@ namespace {
 
 uint32_t batch_ipw(const ga_batch* b, const ga_run* r) {
   const uint32_t g = per_iter(r);
-  uint32_t ipw = b->ipw_override ? b->ipw_override : 64u;
+  uint32_t ipw = b->ipw_override ? b->ipw_override : r->ipw;
   ipw = std::max(g, ipw / g * g);
   return std::min(64u, ipw);
 }

@@ -6,26 +6,30 @@
 
 namespace ga {
 
-// Device view of one run's state. Population and outbox are SoA planes so a
-// wavefront touches 256 contiguous bytes per field:
-//   pop_f[a], pop_T[a], pop_D[w * agents + a]            a = island * N + slot
-//   ob_meta[p][i] (bit 2 valid, bits 0-1 direction), ob_f[p][i], ob_T[p][i],
-//   ob_D[p][w * islands + i]                             p = generation parity
+// Device view of one run's state. The population is SoA planes so a
+// wavefront touches 256 contiguous bytes per field; outbox entries are AoS so
+// one 16-byte load brings an arrival's genome (and, for 32-site surfaces, its
+// header):
+//   pop_f[a], pop_T[a], pop_D[w * agent_stride + a]      a = island * N + slot
+//   ob[p][i * ob_stride + k], k = 0 fitness, 1 T, 2.. surface words,
+//   2 + words header (bit 2 valid, bits 0-1 direction); ob_stride = 4 or 8
+//   words; p = generation parity.
+// Planes are padded to island_stride = roundup(islands, 64) + 64 islands
+// (agent_stride = island_stride * N agents): a wavefront's last chunk may run
+// past the last island and then only touches padding.
 struct RunView {
   float* pop_f;
   uint32_t* pop_T;
   uint32_t* pop_D;
-  uint32_t* ob_meta[2];
-  float* ob_f[2];
-  uint32_t* ob_T[2];
-  uint32_t* ob_D[2];
+  uint32_t* ob[2];
   unsigned long long* gen;   // generation counter t (device)
   unsigned long long* left;  // generations still owed in the current batch block (batch only)
   uint32_t width, height, islands, agents;
+  uint32_t island_stride, agent_stride;
   uint32_t log2n, words, k, selection;
   uint32_t p32, migration, seed, run_id;
   uint32_t ipw;              // islands per wavefront
-  uint32_t pad;
+  uint32_t ob_stride;        // words per outbox entry
 };
 
 // One wavefront's share of a batched launch: islands [first, first + ipw) of run `run`.

@@ -1,20 +1,25 @@
 // HIP kernels for the island-model GA generation step on gfx950 (CDNA4).
 //
-// Mapping: one wavefront owns a chunk of `ipw` consecutive islands. Lanes map
-// to agent slots; with N agents per island a wavefront covers 64/N islands per
-// iteration, so the tournament gathers and the parent copy are cross-lane
-// permutes (ds_bpermute) inside the wavefront and never touch LDS storage or
-// HBM twice. Before its iterations a wavefront draws the migration block of
-// each of its islands in one pass (lane l -> island first + l), reads the four
-// neighbour outbox headers of each, and keeps the result in two registers that
-// later iterations fetch by permute; the migration stream thus costs one
-// Philox block per island, not per agent.
+// Mapping. One wavefront owns a chunk of `ipw` consecutive islands and works
+// through it in iterations of 64 agents: lanes are agent slots, an iteration
+// covers 64/N islands, the tournament gathers and the parent copy are
+// cross-lane permutes (ds_bpermute) inside the wavefront, and every genome is
+// read from and written back to HBM exactly once per generation.
+//
+// Island pass. Before its iterations a wavefront handles the per-island work
+// of its whole chunk at once, one island per lane: the migration draw (one
+// Philox block per island), the four neighbour outbox headers, the arrivals
+// (genomes loaded into a small LDS table, their slots packed into one
+// register), and the emission, written to the outbox as consecutive entries.
+// The iterations then only compare their slot against the packed arrival
+// slots and read the LDS table in the rare case of a hit.
 //
 // Generation t (paper Sec. 2): absorb arrivals emitted during t-1 (outbox
 // parity (t-1)&1), emit into parity t&1, then tournament, copy, mutation and
 // one stratum deposit for every child. Islands are updated in place: a
 // wavefront reads all of an island's agents before it writes any child, and no
-// other wavefront reads them.
+// other wavefront reads them. Population and outbox planes are padded past the
+// last island, so iterations never need a tail predicate.
 #include "ga_internal.hpp"
 
 namespace ga {
@@ -33,38 +38,96 @@ struct Block {
   uint32_t x, y, z, w;
 };
 
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each takes
-// both halves of two 32x32->64 products and mixes the high halves with the
-// other two counter words and the round key.
-__device__ __forceinline__ Block philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                          uint32_t k0, uint32_t k1) {
+// a ^ b ^ c in one gfx950 three-input bitwise op (truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), rounds FIRST..9 applied
+// to counter state (c0..c3) with the round-0 key (k0, k1): each round takes both
+// halves of two 32x32->64 products and mixes the high halves with the other
+// two words and the round key (k + round * Weyl increment).
+template <int FIRST>
+__device__ __forceinline__ Block philox_rounds(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
 #pragma unroll
-  for (int round = 0; round < 10; ++round) {
-    const uint64_t pa = (uint64_t)kMulA * c0;  // one v_mad_u64_u32 each
+  for (int round = FIRST; round < 10; ++round) {
+    const uint64_t pa = (uint64_t)kMulA * c0;
     const uint64_t pb = (uint64_t)kMulB * c2;
-    const uint32_t a_hi = (uint32_t)(pa >> 32), a_lo = (uint32_t)pa;
-    const uint32_t b_hi = (uint32_t)(pb >> 32), b_lo = (uint32_t)pb;
-    c0 = b_hi ^ c1 ^ k0;
-    c2 = a_hi ^ c3 ^ k1;
-    c1 = b_lo;
-    c3 = a_lo;
-    k0 += kWeylA;
-    k1 += kWeylB;
+    const uint32_t n0 = xor3(hi32(pb), c1, k0 + (uint32_t)round * kWeylA);
+    const uint32_t n2 = xor3(hi32(pa), c3, k1 + (uint32_t)round * kWeylB);
+    c1 = (uint32_t)pb;
+    c3 = (uint32_t)pa;
+    c0 = n0;
+    c2 = n2;
   }
   return {c0, c1, c2, c3};
 }
 
-// Site written by the deposit of stratum rank r on S = 2^s sites, or kDiscard
-// ("doubling steady" surface): ranks below S keep site r; a rank r >= S is
-// written only when its low e bits are clear, e = bitlen(r) - s, and the j-th
-// rank written in epoch e takes over the site of rank (2j+1) << (e-1), which
-// left the retained set when epoch e began. Written ranks are odd multiples
-// odd << shift, so the walk only renormalises the odd part.
-__device__ __forceinline__ uint32_t surface_site(uint32_t r, uint32_t s) {
+__device__ __forceinline__ Block philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+  return philox_rounds<0>(c0, c1, c2, c3, k0, k1);
+}
+
+// Selection-stream blocks for one lane across a chunk. The counter is
+// (slot, island, t_lo, t_hi*4): only the island word changes between a lane's
+// iterations, so everything of rounds 0-2 that does not depend on it is
+// computed once. The remaining per-block cost is 2 + 7*2 products and 3 + 7*2
+// three-input ops.
+struct SelectStream {
+  uint32_t x0;      // round 0: c0' = x0 ^ island
+  uint32_t inv_a;   // round 1: c2'' = hi(M0*c0') ^ inv_a
+  uint32_t inv_b;   // round 2: c0''' = hi(M1*c2'') ^ inv_b
+  uint32_t inv_c;   // round 2: c2''' = inv_c ^ lo(M0*c0')
+  uint32_t inv_d;   // round 2: c3''' = inv_d
+  uint32_t k0, k1;
+
+  __device__ __forceinline__ void init(uint32_t slot, uint32_t t_lo, uint32_t t_hi4, uint32_t key0,
+                                       uint32_t key1) {
+    k0 = key0;
+    k1 = key1;
+    // round 0 on (slot, island, t_lo, t_hi4)
+    const uint64_t pa0 = (uint64_t)kMulA * slot;
+    const uint64_t pb0 = (uint64_t)kMulB * t_lo;
+    x0 = hi32(pb0) ^ key0;                       // c0' = hi(pb0) ^ island ^ k0
+    const uint32_t c1_1 = (uint32_t)pb0;
+    const uint32_t c2_1 = hi32(pa0) ^ t_hi4 ^ key1;
+    const uint32_t c3_1 = (uint32_t)pa0;
+    // round 1: pb1 from c2_1 is invariant; pa1 from c0' is not
+    const uint64_t pb1 = (uint64_t)kMulB * c2_1;
+    const uint32_t c0_2 = hi32(pb1) ^ c1_1 ^ (key0 + kWeylA);
+    const uint32_t c1_2 = (uint32_t)pb1;
+    inv_a = c3_1 ^ (key1 + kWeylB);              // c2_2 = hi(pa1) ^ inv_a, c3_2 = lo(pa1)
+    // round 2: pa2 from c0_2 is invariant; pb2 from c2_2 is not
+    const uint64_t pa2 = (uint64_t)kMulA * c0_2;
+    inv_b = c1_2 ^ (key0 + 2u * kWeylA);         // c0_3 = hi(pb2) ^ inv_b
+    inv_c = hi32(pa2) ^ (key1 + 2u * kWeylB);    // c2_3 = inv_c ^ c3_2
+    inv_d = (uint32_t)pa2;                       // c3_3
+  }
+
+  __device__ __forceinline__ Block block(uint32_t island) const {
+    const uint32_t c0_1 = x0 ^ island;
+    const uint64_t pa1 = (uint64_t)kMulA * c0_1;
+    const uint32_t c2_2 = hi32(pa1) ^ inv_a;
+    const uint32_t c3_2 = (uint32_t)pa1;
+    const uint64_t pb2 = (uint64_t)kMulB * c2_2;
+    const uint32_t c0_3 = hi32(pb2) ^ inv_b;
+    const uint32_t c1_3 = (uint32_t)pb2;
+    const uint32_t c2_3 = inv_c ^ c3_2;
+    return philox_rounds<3>(c0_3, c1_3, c2_3, inv_d, k0, k1);
+  }
+};
+
+// Site written by the deposit of stratum rank r on S = 2^s sites when r >= S
+// and r is a multiple of 2^e, e = bitlen(r) - s ("doubling steady" surface):
+// the j-th rank written in epoch e takes over the site of rank (2j+1) << (e-1),
+// which left the retained set when epoch e began. Written ranks have the form
+// odd << shift, so the walk only renormalises the odd part until the rank
+// falls below S.
+__device__ __noinline__ uint32_t surface_site_walk(uint32_t r, uint32_t e, uint32_t s) {
   const uint32_t half = 1u << (s - 1u);
-  if (r < (half << 1)) return r;
-  const uint32_t e = (32u - __clz(r)) - s;
-  if (r & ((1u << e) - 1u)) return kDiscard;
   uint32_t odd = (((r >> e) - half) << 1) | 1u;
   uint32_t shift = e - 1u;
   for (;;) {
@@ -76,11 +139,11 @@ __device__ __forceinline__ uint32_t surface_site(uint32_t r, uint32_t s) {
   }
 }
 
-__device__ __forceinline__ uint32_t permute(uint32_t value, uint32_t src_lane) {
-  return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src_lane << 2), (int)value);
+__device__ __forceinline__ uint32_t permute(uint32_t value, uint32_t byte_addr) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute((int)byte_addr, (int)value);
 }
-__device__ __forceinline__ float permute(float value, uint32_t src_lane) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute((int)(src_lane << 2), __float_as_int(value)));
+__device__ __forceinline__ float permute(float value, uint32_t byte_addr) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute((int)byte_addr, __float_as_int(value)));
 }
 
 // Island next to (x, y) in direction q on the W x H torus:
@@ -96,114 +159,164 @@ __device__ __forceinline__ uint32_t torus_step(uint32_t x, uint32_t y, uint32_t 
   return ny * W + nx;
 }
 
+template <typename P>
+__device__ __forceinline__ P* at_byte(P* base, uint32_t byte_off) {
+  return reinterpret_cast<P*>(reinterpret_cast<char*>(base) + byte_off);
+}
+template <typename P>
+__device__ __forceinline__ const P* at_byte(const P* base, uint32_t byte_off) {
+  return reinterpret_cast<const P*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+#ifndef GA_PREFETCH_DEPTH
+#define GA_PREFETCH_DEPTH 2
+#endif
+// Iterations of genomes a wavefront keeps in flight ahead of its compute.
+constexpr int kPrefetch = GA_PREFETCH_DEPTH;
+
+struct Genome {
+  float f = 0.f;
+  uint32_t T = 0, D0 = 0, D1 = 0;
+};
+
+__device__ __forceinline__ Genome load_genome(const float* pf, const uint32_t* pT,
+                                              const uint32_t* pD0, const uint32_t* pD1,
+                                              uint32_t off, uint32_t words) {
+  Genome g;
+  g.f = *at_byte(pf, off);
+  g.T = *at_byte(pT, off);
+  g.D0 = *at_byte(pD0, off);
+  if (words > 1) g.D1 = *at_byte(pD1, off);
+  return g;
+}
+
 // One generation for islands [base, base + v.ipw) of a run, by one wavefront.
 // LC / SWC: log2 N and surface words fixed at compile time, or -1 to read them
-// from the view.
+// from the view. `arrivals` is this wavefront's LDS table (64 x 4 entries).
 template <int LC, int SWC>
-__device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base, uint64_t t) {
+__device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base, uint64_t t,
+                                                 uint4* arrivals) {
   const uint32_t L = LC >= 0 ? (uint32_t)LC : v.log2n;
   const uint32_t SW = SWC >= 0 ? (uint32_t)SWC : v.words;
   const uint32_t s_log = 4u + SW;  // log2 S: 5 for 32 sites, 6 for 64
+  const uint32_t S = 1u << s_log;
   const uint32_t lane = __lane_id();
   const uint32_t N = 1u << L;
   const uint32_t per_iter = 64u >> L;  // islands per wavefront iteration
   const uint32_t t_lo = (uint32_t)t;
   const uint32_t t_hi4 = (uint32_t)(t >> 32) << 2;
-  const uint32_t rp = ((uint32_t)t & 1u) ^ 1u;  // parity absorbed from
-  const uint32_t wp = (uint32_t)t & 1u;         // parity emitted into
+  const bool odd_gen = ((uint32_t)t & 1u) != 0u;  // emit into parity t&1, absorb the other
   const uint32_t W = v.width, H = v.height;
-  // parity-selected outbox planes (selects, not indexing, so views held in
-  // registers never spill to scratch)
-  const uint32_t* __restrict__ in_meta = rp ? v.ob_meta[1] : v.ob_meta[0];
-  const float* __restrict__ in_f = rp ? v.ob_f[1] : v.ob_f[0];
-  const uint32_t* __restrict__ in_T = rp ? v.ob_T[1] : v.ob_T[0];
-  const uint32_t* __restrict__ in_D = rp ? v.ob_D[1] : v.ob_D[0];
-  uint32_t* __restrict__ out_meta = wp ? v.ob_meta[1] : v.ob_meta[0];
-  float* __restrict__ out_f = wp ? v.ob_f[1] : v.ob_f[0];
-  uint32_t* __restrict__ out_T = wp ? v.ob_T[1] : v.ob_T[0];
-  uint32_t* __restrict__ out_D = wp ? v.ob_D[1] : v.ob_D[0];
+  const uint32_t* __restrict__ in_ob = odd_gen ? v.ob[0] : v.ob[1];
+  uint32_t* __restrict__ out_ob = odd_gen ? v.ob[1] : v.ob[0];
+  const uint32_t ob_stride = SW == 1 ? 4u : 8u;  // words per outbox entry
+  const uint32_t ob_hdr = 2u + SW;               // header word
 
-  // ---- per-island pass: lane l handles island base + l ---------------------
-  uint32_t own = base + lane;
-  if (lane >= v.ipw || own >= v.islands) own = base;
+  // chunk base pointers (uniform) and this lane's byte offset in the chunk
+  const uint32_t first_agent = base << L;
+  float* __restrict__ pf = v.pop_f + first_agent;
+  uint32_t* __restrict__ pT = v.pop_T + first_agent;
+  uint32_t* __restrict__ pD0 = v.pop_D + first_agent;
+  uint32_t* __restrict__ pD1 = v.pop_D + v.agent_stride + first_agent;
+  const uint32_t n_iter = v.ipw >> (6u - L);
+  uint32_t off = lane << 2;
+
+  // genomes of the first kPrefetch iterations go in flight before the island
+  // pass, whose own loads and draws then hide their latency
+  Genome ring[kPrefetch];
+#pragma unroll
+  for (int p = 0; p < kPrefetch; ++p)
+    ring[p] = (uint32_t)p < n_iter ? load_genome(pf, pT, pD0, pD1, off + 256u * p, SW) : Genome{};
+
+  // ---- island pass: lane l handles island base + l ---------------------------
+  const bool own_ok = lane < v.ipw && base + lane < v.islands;
+  const uint32_t own = own_ok ? base + lane : base;
   const uint32_t ox = own % W, oy = own / W;
   const Block mig = philox10(0u, own, t_lo, t_hi4 | kStreamMigrate, v.seed, v.run_id);
-  const uint32_t emig_slot = L ? (mig.x >> (32u - L)) : 0u;
-  const uint32_t emig_dir = mig.y >> 30;
-  uint32_t arrive = 0;
+  const uint32_t emig = L ? (mig.x >> (32u - L)) : 0u;
+  uint32_t desc = 0xFFFFFFFFu;  // byte q: slot taken by the arrival from direction q, or 0xFF
 #pragma unroll
   for (uint32_t q = 0; q < 4; ++q) {
     const uint32_t j = torus_step(ox, oy, q, W, H);
-    if (in_meta[j] == (kMetaValid | (q ^ 2u))) arrive |= 1u << q;
+    if (own_ok && in_ob[j * ob_stride + ob_hdr] == (kMetaValid | (q ^ 2u))) {
+      const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
+      desc = (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q));
+      // f, T, D0 and the header (32 sites) or D1 (64 sites)
+      arrivals[lane * 4u + q] = *reinterpret_cast<const uint4*>(in_ob + j * ob_stride);
+    }
   }
-  const uint32_t info = emig_slot | (emig_dir << 8) | (arrive << 12);
-  const uint32_t slots4 = mig.z;          // byte q: replacement slot draw for direction q
-  const uint32_t xy = ox | (oy << 16);
+  // emission: slot and header of what this island sends; the lane holding the
+  // post-absorb member in that slot writes the outbox entry during its iteration
+  const uint32_t emit = own_ok ? (emig | ((v.migration ? (kMetaValid | (mig.y >> 30)) : 0u) << 8))
+                               : 0xFFu;
+  // hand the arrival table to the other lanes of this wavefront
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 
+  // ---- iterations: lanes are agent slots ------------------------------------
   const uint32_t slot = lane & (N - 1u);
-  const uint32_t lane0 = lane & ~(N - 1u);  // first lane of this lane's island
-  const uint32_t A = v.agents;
-  float* __restrict__ pf = v.pop_f;
-  uint32_t* __restrict__ pT = v.pop_T;
-  uint32_t* __restrict__ pD = v.pop_D;
+  const uint32_t slot_bytes = slot * 0x01010101u;
+  const uint32_t lane0_addr = (lane & ~(N - 1u)) << 2;  // permute address of slot 0 of my island
+  SelectStream sel;
+  sel.init(slot, t_lo, t_hi4, v.seed, v.run_id);
 
-  for (uint32_t it = 0; it * per_iter < v.ipw; ++it) {
+  for (uint32_t it = 0; it < n_iter; ++it) {
+    // this iteration's genomes; keep kPrefetch iterations in flight
+    Genome g = ring[0];
+#pragma unroll
+    for (int p = 0; p + 1 < kPrefetch; ++p) ring[p] = ring[p + 1];
+    ring[kPrefetch - 1] = it + kPrefetch < n_iter
+                              ? load_genome(pf, pT, pD0, pD1, off + 256u * kPrefetch, SW)
+                              : Genome{};
+    float f = g.f;
+    uint32_t T = g.T, D0 = g.D0, D1 = g.D1;
     const uint32_t local = it * per_iter + (lane >> L);
     const uint32_t island = base + local;
-    const bool active = island < v.islands;
-    const uint32_t a = island * N + slot;
 
-    float f = 0.f;
-    uint32_t T = 0, D0 = 0, D1 = 0;
-    if (active) {
-      f = pf[a];
-      T = pT[a];
-      D0 = pD[a];
-      if (SW > 1) D1 = pD[A + a];
-    }
-    const uint32_t my_info = permute(info, local);
-    const uint32_t my_slots = permute(slots4, local);
-    const uint32_t my_xy = permute(xy, local);
-
-    // 1. absorb: the last arriving direction whose drawn slot is mine wins
-    int from = -1;
-#pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
-      const uint32_t want = ((my_slots >> (8u * q)) & 0xFFu) >> (8u - L);
-      if (((my_info >> (12u + q)) & 1u) && want == slot) from = (int)q;
-    }
-    if (active && from >= 0) {
-      const uint32_t j = torus_step(my_xy & 0xFFFFu, my_xy >> 16, (uint32_t)from, W, H);
-      f = in_f[j];
-      T = in_T[j];
-      D0 = in_D[j];
-      if (SW > 1) D1 = in_D[v.islands + j];
+    // 1. absorb: the last arriving direction whose drawn slot is mine wins.
+    //    Bytes of x are zero exactly where the descriptor names my slot; z
+    //    keeps the top bit of each such byte, and its highest set bit is the
+    //    last direction.
+    const uint32_t x = permute(desc, local << 2) ^ slot_bytes;
+    const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+    if (z != 0u) {
+      const uint32_t q = (31u - __clz(z)) >> 3;
+      const uint4 a = arrivals[local * 4u + q];
+      f = __uint_as_float(a.x);
+      T = a.y;
+      D0 = a.z;
+      D1 = a.w;
     }
 
-    // 2. emit a copy of the drawn member (post-absorb) toward the drawn neighbour
-    if (active && slot == (my_info & 0xFFu)) {
-      if (v.migration) {
-        out_meta[island] = kMetaValid | ((my_info >> 8) & 3u);
-        out_f[island] = f;
-        out_T[island] = T;
-        out_D[island] = D0;
-        if (SW > 1) out_D[v.islands + island] = D1;
+    // 2. emit the post-absorb member in the drawn slot (one lane per island)
+    const uint32_t my_emit = permute(emit, local << 2);
+    if ((my_emit & 0xFFu) == slot) {
+      uint32_t* e = out_ob + island * ob_stride;
+      const uint32_t hdr = my_emit >> 8;
+      if (hdr) {
+        if (SW == 1) {
+          *reinterpret_cast<uint4*>(e) = make_uint4(__float_as_uint(f), T, D0, hdr);
+        } else {
+          *reinterpret_cast<uint4*>(e) = make_uint4(__float_as_uint(f), T, D0, D1);
+          e[ob_hdr] = hdr;
+        }
       } else {
-        out_meta[island] = 0u;
+        e[ob_hdr] = 0u;
       }
     }
 
     // 3-5. evaluate (read fitness) and run the tournament over permuted entrants
-    const Block r = philox10(slot, island, t_lo, t_hi4 | kStreamSelect, v.seed, v.run_id);
-    uint32_t best = (r.x & 0xFFu) >> (8u - L);
-    float fbest = permute(f, lane0 + best);
+    const Block r = sel.block(island);
+    uint32_t best = lane0_addr + (((r.x & 0xFFu) >> (8u - L)) << 2);
+    float fbest = permute(f, best);
     if (v.selection) {
 #pragma unroll
       for (uint32_t m = 1; m < 8; ++m) {
         if (m < v.k) {
           const uint32_t byte = ((m < 4 ? r.x : r.y) >> (8u * (m & 3u))) & 0xFFu;
-          const uint32_t cand = byte >> (8u - L);
-          const float fc = permute(f, lane0 + cand);
+          const uint32_t cand = lane0_addr + ((byte >> (8u - L)) << 2);
+          const float fc = permute(f, cand);
           if (fc > fbest) {
             best = cand;
             fbest = fc;
@@ -211,57 +324,71 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
         }
       }
     }
-    uint32_t cT = permute(T, lane0 + best);
-    uint32_t cD0 = permute(D0, lane0 + best);
-    uint32_t cD1 = SW > 1 ? permute(D1, lane0 + best) : 0u;
-    float cf = fbest;
+    uint32_t cT = permute(T, best);
+    uint32_t cD0 = permute(D0, best);
+    uint32_t cD1 = SW > 1 ? permute(D1, best) : 0u;
+    float cfit = fbest;
 
-    // 6. mutation: delta index (w & 0x7FFFFFFF) * 5 >> 31 maps to {-1,-1/2,0,1/2,1}
+    // 6. mutation: delta index (w & 0x7FFFFFFF) * 5 >> 31 = hi32((w & 0x7FFFFFFF) * 10)
+    //    maps 0..4 to {-1, -1/2, 0, 1/2, 1}
     if (r.z < v.p32) {
-      const uint32_t di = (uint32_t)(((uint64_t)(r.w & 0x7FFFFFFFu) * 5u) >> 31);
-      cf = __fadd_rn(cf, 0.5f * (float)((int)di - 2));
+      const int di = (int)__umulhi(r.w & 0x7FFFFFFFu, 10u) - 2;  // -2..2
+      cfit = __fadd_rn(cfit, (float)di * 0.5f);
     }
 
     // 7. stratum deposit at rank T, then T + 1
-    const uint32_t site = surface_site(cT, s_log);
-    if (site != kDiscard) {
-      const uint32_t bit = r.w >> 31;
-      const uint32_t sh = site & 31u;
+    uint32_t site = cT;
+    bool write = true;
+    if (cT >= S) {
+      const uint32_t e = (32u - __clz(cT)) - s_log;
+      write = (cT & ((1u << e) - 1u)) == 0u;
+      if (write) site = surface_site_walk(cT, e, s_log);
+    }
+    if (write) {
+      const uint32_t mask = 1u << (site & 31u);
+      const uint32_t bit = (r.w >> 31) ? mask : 0u;
       if (SW == 1 || site < 32u) {
-        cD0 = (cD0 & ~(1u << sh)) | (bit << sh);
+        cD0 = (cD0 & ~mask) | bit;
       } else {
-        cD1 = (cD1 & ~(1u << sh)) | (bit << sh);
+        cD1 = (cD1 & ~mask) | bit;
       }
     }
     cT += 1u;
 
-    if (active) {
-      pf[a] = cf;
-      pT[a] = cT;
-      pD[a] = cD0;
-      if (SW > 1) pD[A + a] = cD1;
-    }
+    *at_byte(pf, off) = cfit;
+    *at_byte(pT, off) = cT;
+    *at_byte(pD0, off) = cD0;
+    if (SW > 1) *at_byte(pD1, off) = cD1;
+
+    off += 256u;
   }
+}
+
+// Dynamic LDS: one 64 x 4 arrival table (4 KiB) per wavefront of the group.
+extern __shared__ uint4 ga_lds[];
+
+__device__ __forceinline__ uint4* wave_arrivals(uint32_t wave_in_group) {
+  return ga_lds + wave_in_group * 256u;
 }
 
 template <int LC, int SWC>
 __global__ __launch_bounds__(1024) void generation_kernel(RunView v, uint32_t gen_offset) {
-  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) +
-                        (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wig;
   const uint32_t base = wave * v.ipw;
   if (base >= v.islands) return;
-  chunk_generation<LC, SWC>(v, base, *v.gen + gen_offset);
+  chunk_generation<LC, SWC>(v, base, *v.gen + gen_offset, wave_arrivals(wig));
 }
 
 // Whole run in one workgroup: the generation loop stays on the GPU, with a
 // workgroup barrier between generations (the outbox hand-over).
 template <int LC, int SWC>
 __global__ __launch_bounds__(1024) void resident_kernel(RunView v, uint64_t n_gens) {
-  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t base = wave * v.ipw;
+  const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t base = wig * v.ipw;
   const uint64_t t0 = *v.gen;
   for (uint64_t g = 0; g < n_gens; ++g) {
-    if (base < v.islands) chunk_generation<LC, SWC>(v, base, t0 + g);
+    if (base < v.islands) chunk_generation<LC, SWC>(v, base, t0 + g, wave_arrivals(wig));
     __syncthreads();
   }
   if (threadIdx.x == 0) *v.gen = t0 + n_gens;
@@ -293,7 +420,8 @@ __global__ void gather_kernel(RunView v, const uint32_t* ids, uint32_t n, uint32
   if (j >= n) return;
   const uint32_t a = ids[j];
   T_out[j] = v.pop_T[a];
-  for (uint32_t w = 0; w < v.words; ++w) D_out[(size_t)w * n + j] = v.pop_D[(size_t)w * v.agents + a];
+  for (uint32_t w = 0; w < v.words; ++w)
+    D_out[(size_t)w * n + j] = v.pop_D[(size_t)w * v.agent_stride + a];
 }
 
 // Batched form: wavefront i works on tiles[i]; members whose budget for this
@@ -302,13 +430,13 @@ __global__ __launch_bounds__(1024) void batch_generation_kernel(const RunView* _
                                                                 const Tile* __restrict__ tiles,
                                                                 uint32_t n_tiles,
                                                                 uint32_t gen_offset) {
-  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) +
-                        (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wig;
   if (wave >= n_tiles) return;
   const Tile tile = tiles[wave];
   const RunView v = views[tile.run];
   if (*v.left <= gen_offset) return;
-  chunk_generation<-1, -1>(v, tile.first, *v.gen + gen_offset);
+  chunk_generation<-1, -1>(v, tile.first, *v.gen + gen_offset, wave_arrivals(wig));
 }
 
 __global__ void batch_advance_kernel(const RunView* views, uint32_t n_runs, uint64_t block) {
@@ -320,6 +448,8 @@ __global__ void batch_advance_kernel(const RunView* views, uint32_t n_runs, uint
   *v.gen = *v.gen + done;
   *v.left = left - done;
 }
+
+constexpr size_t kLdsPerWave = 256 * sizeof(uint4);
 
 }  // namespace
 
@@ -349,15 +479,17 @@ hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t wav
   if (waves == 0) return hipSuccess;
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
   const dim3 grid(groups), block(64 * waves_per_group);
+  const size_t lds = kLdsPerWave * waves_per_group;
   GA_DISPATCH(generation_kernel, v.log2n, v.words,
-              <<<grid, block, 0, stream>>>(v, gen_offset));
+              <<<grid, block, lds, stream>>>(v, gen_offset));
   return hipGetLastError();
 }
 
 hipError_t launch_resident(const RunView& v, uint64_t n_gens, uint32_t waves, hipStream_t stream) {
   if (waves == 0 || waves > (uint32_t)kMaxWavesPerGroup) return hipErrorInvalidValue;
   const dim3 grid(1), block(64 * waves);
-  GA_DISPATCH(resident_kernel, v.log2n, v.words, <<<grid, block, 0, stream>>>(v, n_gens));
+  const size_t lds = kLdsPerWave * waves;
+  GA_DISPATCH(resident_kernel, v.log2n, v.words, <<<grid, block, lds, stream>>>(v, n_gens));
   return hipGetLastError();
 }
 
@@ -392,7 +524,8 @@ hipError_t launch_batch_generation(const RunView* views, const Tile* tiles, uint
                                    hipStream_t stream) {
   if (n_tiles == 0) return hipSuccess;
   const uint32_t groups = (n_tiles + waves_per_group - 1) / waves_per_group;
-  batch_generation_kernel<<<dim3(groups), dim3(64 * waves_per_group), 0, stream>>>(
+  const size_t lds = kLdsPerWave * waves_per_group;
+  batch_generation_kernel<<<dim3(groups), dim3(64 * waves_per_group), lds, stream>>>(
       views, tiles, n_tiles, gen_offset);
   return hipGetLastError();
 }

@@ -36,14 +36,16 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_state_bytes_layout(lib):
-    # SoA planes: fitness, T, surface words per agent; 2 outboxes of
-    # (header, fitness, T, surface words) per island; counters; extraction staging.
+    # SoA planes: fitness, T, surface words per agent; 2 AoS outboxes of
+    # (fitness, T, surface words, header) per island; counters; extraction staging.
+    # Planes are padded to roundup(islands, 64) + 64 islands.
     def expect(c):
-        I = c["width"] * c["height"]
+        I = (c["width"] * c["height"] + 63) // 64 * 64 + 64
         A = I * c["pop"]
         W = c["sites"] // 32
         al = lambda b: (b + 255) // 256 * 256
-        return (al(4 * A) * 2 + al(4 * A * W) + 2 * (3 * al(4 * I) + al(4 * I * W)) + 256
+        ob = 4 if W == 1 else 8   # AoS outbox entry words
+        return (al(4 * A) * 2 + al(4 * A * W) + 2 * al(4 * I * ob) + 256
                 + 2 * al(4 * I) + al(4 * I * W))
     for c in (TINY, MID, PAPER, run_config(width=3, height=5, pop=1, sites=32)):
         assert ga.state_bytes(c) == expect(c)
@@ -54,7 +56,7 @@ def test_state_bytes_layout(lib):
 @pytest.mark.parametrize("bad", [
     dict(pop=24), dict(pop=128), dict(pop=0), dict(sites=48), dict(sites=16), dict(k=0),
     dict(k=9), dict(width=0), dict(height=0), dict(width=70000), dict(selection=2),
-    dict(migration=3), dict(width=65535, height=65535, pop=64)])
+    dict(migration=3), dict(width=65535, height=65535, pop=64), dict(width=65535, height=8193, pop=2)])
 def test_invalid_configs_rejected(lib, bad):
     c = make_config(run_config(**bad))
     assert lib.ga_state_bytes(ctypes.byref(c)) == 0
