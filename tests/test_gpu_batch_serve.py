@@ -1,0 +1,140 @@
+"""GPU parity of the batched and served forms: every member of a batch, and
+every served request, must give the bits it gives alone and the oracle's bits."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import assert_same_state, oracle_after, say
+from paper_2405_03605_amd import FORM_STREAMING, GABatch, GARun
+from paper_2405_03605_amd.autotune import autotune, candidates
+from paper_2405_03605_amd.serve import Server
+from paper_2405_03605_amd.workloads import batched_configs, run_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+UNEVEN = [
+    run_config(width=5, height=3, pop=8, sites=32, k=3, selection=1, run_id=11),
+    run_config(width=17, height=9, pop=16, sites=64, k=8, selection=0, run_id=12),
+    run_config(width=12, height=12, pop=32, sites=32, k=2, run_id=13),
+    run_config(width=3, height=40, pop=64, sites=64, k=5, run_id=14),
+    run_config(width=33, height=2, pop=4, sites=32, k=2, run_id=15),
+    run_config(width=1, height=1, pop=1, sites=64, k=1, run_id=16),
+    run_config(width=20, height=20, pop=8, sites=64, k=7, selection=0, run_id=17),
+    run_config(width=9, height=11, pop=32, sites=64, migration=0, run_id=18),
+]
+BUDGETS = [150, 230, 100, 99, 305, 1, 320, 200]
+
+
+@pytest.mark.parametrize("graph_block,ipw", [(100, 0), (0, 0), (64, 8)])
+def test_batch_members_match_oracle(graph_block, ipw):
+    say(f"batch of {len(UNEVEN)} uneven runs, graph block {graph_block}, ipw {ipw}")
+    runs = [GARun(c) for c in UNEVEN]
+    batch = GABatch()
+    batch.set_graph_block(graph_block)
+    if ipw:
+        batch.set_islands_per_wave(ipw)
+    for r, b in zip(runs, BUDGETS):
+        batch.add(r, b)
+    batch.step(120)
+    batch.step(200)
+    for r, b in zip(runs, BUDGETS):
+        assert batch.remaining(r) == 0
+    for r, c, b in zip(runs, UNEVEN, BUDGETS):
+        assert_same_state(r.read(), oracle_after(c, b), f"member {c['run_id']}")
+    batch.close()
+
+
+def test_membership_changes_between_blocks():
+    a, b, c = (GARun(cfg) for cfg in UNEVEN[:3])
+    batch = GABatch()
+    batch.add(a, 500)
+    batch.add(b, 500)
+    batch.step(100)
+    batch.remove(b)          # b continues alone
+    b.set_launch(form=FORM_STREAMING)
+    b.step(37)
+    batch.add(c, 80)         # c joins late
+    batch.step(150)
+    batch.add(b, 13)         # b rejoins
+    batch.step(100)
+    batch.close()
+    assert_same_state(a.read(), oracle_after(UNEVEN[0], 350), "a")
+    assert_same_state(b.read(), oracle_after(UNEVEN[1], 150), "b")
+    assert_same_state(c.read(), oracle_after(UNEVEN[2], 80), "c")
+
+
+def test_batched_workload_equals_alone():
+    cfgs = batched_configs()
+    gens = 130
+    say(f"64-run batched workload, {gens} generations, batch vs alone")
+    alone = []
+    for c in cfgs:
+        r = GARun(c)
+        r.step(gens)
+        alone.append(r.read(outbox=False))
+        r.close()
+    runs = [GARun(c) for c in cfgs]
+    batch = GABatch()
+    for r in runs:
+        batch.add(r, gens)
+    batch.step(gens)
+    for r, c, ref in zip(runs, cfgs, alone):
+        got = r.read(outbox=False)
+        for key in ("f", "T", "D"):
+            assert np.array_equal(got[key], ref[key]), (c, key)
+    # the smallest members against the oracle as well
+    order = np.argsort([c["width"] * c["height"] * c["pop"] for c in cfgs])
+    for i in order[:4]:
+        assert_same_state(runs[i].read(), oracle_after(cfgs[i], gens), f"batched {i}")
+    batch.close()
+
+
+def test_autotune_candidates_are_bit_identical():
+    cfg = run_config(width=40, height=30, pop=16, sites=64, k=3, seed=2)
+    ref = oracle_after(cfg, 60)
+    cands = candidates(cfg)
+    assert len(cands) >= 8
+    for cand in cands:
+        run = GARun(cfg)
+        run.set_launch(*cand)
+        run.step(60)
+        assert_same_state(run.read(), ref, f"candidate {cand}")
+        run.close()
+    best = autotune(cfg, gens=10, use_cache=False)
+    assert best in cands
+
+
+def test_served_results_equal_alone_and_oracle():
+    rng = np.random.default_rng(5)
+    stream = []
+    for i in range(10):
+        cfg = run_config(width=int(rng.integers(3, 30)), height=int(rng.integers(3, 20)),
+                         pop=int(rng.choice([8, 16, 32])), sites=int(rng.choice([32, 64])),
+                         k=int(rng.integers(2, 9)), selection=int(rng.integers(0, 2)),
+                         seed=1, run_id=500 + i)
+        stream.append((0.002 * i, cfg, int(rng.integers(50, 400))))
+    import paper_2405_03605_amd as ga
+    biggest = max(ga.state_bytes(c) for _, c, _ in stream)
+    srv = Server(budget_bytes=3 * biggest, max_slots=4, block=64)
+    done = srv.drain(stream)
+    srv.close()
+    assert len(done) == len(stream)
+    assert max(srv.used, 0) == 0
+    for req in done:
+        ids, T, D = req.result
+        ref = oracle_after(req.cfg, req.gens)
+        f0, T0, D0 = ref.population()
+        assert np.array_equal(ids, ref.sample_one_per_island())
+        assert np.array_equal(T, T0[ids.astype(np.int64)])
+        assert np.array_equal(D, D0[ids.astype(np.int64)])
