@@ -123,6 +123,32 @@ def bench_batched(gens: int, torch):
             "speedup": plain / batched}
 
 
+def bench_served(n_requests: int, capacity: float, torch):
+    """The served workload's Poisson stream (its first n_requests requests) at
+    80% of the measured batched capacity, full free HBM as budget."""
+    import numpy as np
+
+    from paper_2405_03605_amd.serve import Server
+    from paper_2405_03605_amd.workloads import served_requests
+
+    reqs = served_requests(n_requests, rate=1.0)
+    mean_work = float(np.mean([c["width"] * c["height"] * c["pop"] * g for _, c, g in reqs]))
+    rate = 0.8 * capacity / mean_work
+    arrivals = [(t / rate, c, g) for t, c, g in reqs]
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free - 8e9)
+    srv = Server(budget, max_slots=256, block=100)
+    t0 = time.perf_counter()
+    srv.drain(arrivals)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rep = srv.report(wall)
+    srv.close()
+    rep.update({"requests": n_requests, "rate_per_s": rate, "budget_bytes": budget,
+                "mean_work_agent_gens": mean_work})
+    return rep
+
+
 def cpu_baseline(cfg: dict, budget_s: float = 12.0):
     import oracle
     run = oracle.OracleRun(cfg)
@@ -149,6 +175,8 @@ def main():
     ap.add_argument("--batched-gens", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=150,
+                    help="requests of the served stream to run (0 skips the served leg)")
     ap.add_argument("--ipw", type=int, default=0, help="islands per wavefront (0: library default)")
     ap.add_argument("--wpg", type=int, default=0, help="wavefronts per workgroup (0: default)")
     ap.add_argument("--graph-block", type=int, default=None,
@@ -188,6 +216,9 @@ def main():
            "roofline": roofline}
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_gens, torch)
+        if args.served_requests > 0:
+            out["served"] = bench_served(args.served_requests,
+                                         out["batched"]["batched_agent_gens_per_s"], torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)

@@ -66,7 +66,7 @@ SIGNATURES = {
     "ga_batch_remaining": (u64, [P, P]),
     "ga_batch_size": (sz, [P]),
     "ga_batch_set_graph_block": (i32, [P, u32]),
-    "ga_batch_set_islands_per_wave": (i32, [P, u32]),
+    "ga_batch_set_launch": (i32, [P, u32, u32]),
     "ga_batch_destroy": (None, [P]),
     "ga_strerror": (ctypes.c_char_p, [i32]),
     "ga_last_error": (ctypes.c_char_p, []),

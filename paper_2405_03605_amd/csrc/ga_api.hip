@@ -523,10 +523,12 @@ int ga_batch_set_graph_block(ga_batch* b, uint32_t gens) {
   return GA_OK;
 }
 
-int ga_batch_set_islands_per_wave(ga_batch* b, uint32_t ipw) {
+int ga_batch_set_launch(ga_batch* b, uint32_t ipw, uint32_t wpg) {
   if (!b) return fail(GA_EINVAL, "batch is NULL");
   if (ipw > 64) return fail(GA_EINVAL, "islands_per_wave must be <= 64");
+  if (wpg > (uint32_t)ga::kMaxWavesPerGroup) return fail(GA_EINVAL, "waves_per_group must be in [1, 16]");
   b->ipw_override = ipw;
+  if (wpg) b->wpg = wpg;
   b->dirty = true;
   return GA_OK;
 }
@@ -569,9 +571,11 @@ uint64_t ga_batch_remaining(const ga_batch* b, const ga_run* r) {
 
 namespace {
 
+// Islands per wavefront for a member: the batch setting, 16 by default (a
+// batch has wavefronts enough, so small members need no finer chunks).
 uint32_t batch_ipw(const ga_batch* b, const ga_run* r) {
   const uint32_t g = per_iter(r);
-  uint32_t ipw = b->ipw_override ? b->ipw_override : r->ipw;
+  uint32_t ipw = b->ipw_override ? b->ipw_override : 16u;
   ipw = std::max(g, ipw / g * g);
   return std::min(64u, ipw);
 }

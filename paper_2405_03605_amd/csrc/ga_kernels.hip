@@ -436,7 +436,29 @@ __global__ __launch_bounds__(1024) void batch_generation_kernel(const RunView* _
   const Tile tile = tiles[wave];
   const RunView v = views[tile.run];
   if (*v.left <= gen_offset) return;
-  chunk_generation<-1, -1>(v, tile.first, *v.gen + gen_offset, wave_arrivals(wig));
+  const uint64_t t = *v.gen + gen_offset;
+  uint4* arr = wave_arrivals(wig);
+#ifndef GA_BATCH_GENERIC
+  // wavefront-uniform dispatch to the specialised bodies
+  switch (v.log2n * 2u + v.words - 1u) {
+    case 0: chunk_generation<0, 1>(v, tile.first, t, arr); break;
+    case 1: chunk_generation<0, 2>(v, tile.first, t, arr); break;
+    case 2: chunk_generation<1, 1>(v, tile.first, t, arr); break;
+    case 3: chunk_generation<1, 2>(v, tile.first, t, arr); break;
+    case 4: chunk_generation<2, 1>(v, tile.first, t, arr); break;
+    case 5: chunk_generation<2, 2>(v, tile.first, t, arr); break;
+    case 6: chunk_generation<3, 1>(v, tile.first, t, arr); break;
+    case 7: chunk_generation<3, 2>(v, tile.first, t, arr); break;
+    case 8: chunk_generation<4, 1>(v, tile.first, t, arr); break;
+    case 9: chunk_generation<4, 2>(v, tile.first, t, arr); break;
+    case 10: chunk_generation<5, 1>(v, tile.first, t, arr); break;
+    case 11: chunk_generation<5, 2>(v, tile.first, t, arr); break;
+    case 12: chunk_generation<6, 1>(v, tile.first, t, arr); break;
+    default: chunk_generation<6, 2>(v, tile.first, t, arr); break;
+  }
+#else
+  chunk_generation<-1, -1>(v, tile.first, t, arr);
+#endif
 }
 
 __global__ void batch_advance_kernel(const RunView* views, uint32_t n_runs, uint64_t block) {

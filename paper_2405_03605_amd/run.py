@@ -169,8 +169,8 @@ class GABatch:
     def set_graph_block(self, gens: int):
         check(load().ga_batch_set_graph_block(self._h, gens))
 
-    def set_islands_per_wave(self, ipw: int):
-        check(load().ga_batch_set_islands_per_wave(self._h, ipw))
+    def set_launch(self, islands_per_wave: int = 0, waves_per_group: int = 0):
+        check(load().ga_batch_set_launch(self._h, islands_per_wave, waves_per_group))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -36,14 +36,14 @@ UNEVEN = [
 BUDGETS = [150, 230, 100, 99, 305, 1, 320, 200]
 
 
-@pytest.mark.parametrize("graph_block,ipw", [(100, 0), (0, 0), (64, 8)])
-def test_batch_members_match_oracle(graph_block, ipw):
+@pytest.mark.parametrize("graph_block,ipw,wpg", [(100, 0, 0), (0, 0, 1), (64, 8, 8), (100, 64, 2)])
+def test_batch_members_match_oracle(graph_block, ipw, wpg):
     say(f"batch of {len(UNEVEN)} uneven runs, graph block {graph_block}, ipw {ipw}")
     runs = [GARun(c) for c in UNEVEN]
     batch = GABatch()
     batch.set_graph_block(graph_block)
-    if ipw:
-        batch.set_islands_per_wave(ipw)
+    if ipw or wpg:
+        batch.set_launch(ipw, wpg)
     for r, b in zip(runs, BUDGETS):
         batch.add(r, b)
     batch.step(120)
