@@ -64,6 +64,8 @@ def _load():
     lib.orc_create.argtypes = [ctypes.POINTER(_Config), ctypes.c_int]
     lib.orc_create.restype = P
     lib.orc_free.argtypes = [P]
+    lib.orc_reserve_lineage.argtypes = [P, u64]
+    lib.orc_reserve_lineage.restype = ctypes.c_int
     lib.orc_step.argtypes = [P, u64]
     lib.orc_step.restype = ctypes.c_int
     lib.orc_generation.argtypes = [P]
@@ -82,6 +84,9 @@ def _load():
     lib.orc_ancestry.argtypes = [P, u64, P, P, P, sz]
     lib.orc_ancestry.restype = sz
     lib.orc_mrca_interval.argtypes = [u32, P, u32, P, u32, u32, P, P]
+    lib.orc_true_mrca_matrix.argtypes = [P, P, sz, P]
+    lib.orc_true_mrca_matrix.restype = ctypes.c_int
+    lib.orc_mrca_interval_matrix.argtypes = [P, P, sz, u32, u32, P, P]
     _lib = lib
     return lib
 
@@ -125,6 +130,17 @@ def mrca_interval(Ta: int, Da, Tb: int, Db, sites: int, kc: int = 5):
     return int(L.value), int(U.value)
 
 
+def mrca_interval_matrix(T, D, sites: int, kc: int = 5):
+    """(L, U) matrices for every pair of the n surfaces (T[n], D[n, S/32])."""
+    Ta = np.ascontiguousarray(T, dtype=np.uint32)
+    Da = np.ascontiguousarray(D, dtype=np.uint32)
+    n = Ta.size
+    L = np.empty((n, n), dtype=np.uint32)
+    U = np.empty((n, n), dtype=np.uint32)
+    _load().orc_mrca_interval_matrix(_ptr(Ta), _ptr(Da), n, sites, kc, _ptr(L), _ptr(U))
+    return L, U
+
+
 CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32",
                  "migration", "seed", "run_id")
 
@@ -163,6 +179,10 @@ class OracleRun:
     @property
     def generation(self) -> int:
         return int(_load().orc_generation(self._h))
+
+    def reserve_lineage(self, gens: int):
+        if _load().orc_reserve_lineage(self._h, int(gens)) != 0:
+            raise MemoryError("cannot reserve lineage storage")
 
     def step(self, n: int):
         if _load().orc_step(self._h, int(n)) != 0:
@@ -214,6 +234,14 @@ class OracleRun:
         if g == -2:
             raise RuntimeError("lineage was not recorded from generation 0")
         return g
+
+    def true_mrca_matrix(self, ids) -> np.ndarray:
+        """T of the MRCA for every pair of the listed agents (-1: different founders)."""
+        a = np.ascontiguousarray(ids, dtype=np.uint64)
+        out = np.empty((a.size, a.size), dtype=np.int32)
+        if _load().orc_true_mrca_matrix(self._h, _ptr(a), a.size, _ptr(out)) != 0:
+            raise RuntimeError("lineage not recorded from generation 0, or out of memory")
+        return out
 
     def ancestry(self, agent: int):
         cap = self.generation + 1

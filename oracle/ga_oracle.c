@@ -157,6 +157,7 @@ struct orc_run {
   int lineage;
   uint8_t* winners;    /* winners[g*agents + a]: tournament winner of child a in generation g */
   uint64_t lineage_gens;
+  uint64_t lineage_cap;  /* generations the winners buffer can hold */
 };
 
 static int is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
@@ -246,11 +247,18 @@ static void copy_agent(const orc_run* r, const float* sf, const uint32_t* sT,
 }
 
 static int grow_lineage(orc_run* r, uint64_t gens) {
+  if (gens <= r->lineage_cap) return 0;
   size_t bytes = (size_t)(gens * r->agents);
   uint8_t* p = (uint8_t*)realloc(r->winners, bytes);
   if (!p) return -1;
   r->winners = p;
+  r->lineage_cap = gens;
   return 0;
+}
+
+int orc_reserve_lineage(orc_run* r, uint64_t gens) {
+  if (!r->lineage) return -1;
+  return grow_lineage(r, gens);
 }
 
 static void one_generation(orc_run* r) {
@@ -488,4 +496,58 @@ void orc_mrca_interval(uint32_t Ta, const uint32_t* Da, uint32_t Tb, const uint3
   *U = (uint32_t)first_mismatch;
   uint64_t below = (first_mismatch + step - 1) / step; /* common ranks below the bound */
   *L = below < kc ? 0u : (uint32_t)((below - kc) * step + 1);
+}
+
+int orc_true_mrca_matrix(const orc_run* r, const uint64_t* ids, size_t n, int32_t* out) {
+  if (!r->lineage || r->lineage_gens != r->t) return -1;
+  const size_t cap = (size_t)r->t + 1;
+  uint64_t* gen = (uint64_t*)malloc(n * cap * sizeof(uint64_t));
+  uint32_t* isl = (uint32_t*)malloc(n * cap * sizeof(uint32_t));
+  uint32_t* slt = (uint32_t*)malloc(n * cap * sizeof(uint32_t));
+  size_t* len = (size_t*)malloc(n * sizeof(size_t));
+  if (!gen || !isl || !slt || !len) {
+    free(gen); free(isl); free(slt); free(len);
+    return -1;
+  }
+  for (size_t x = 0; x < n; ++x)
+    len[x] = orc_ancestry(r, ids[x], gen + x * cap, isl + x * cap, slt + x * cap, cap);
+  for (size_t x = 0; x < n; ++x) {
+    out[x * n + x] = (int32_t)r->T[ids[x]];
+    for (size_t y = x + 1; y < n; ++y) {
+      /* Both chains list ancestors newest first with strictly decreasing
+       * birth generations: walk them together until they name one individual. */
+      const uint64_t* ga = gen + x * cap; const uint64_t* gb = gen + y * cap;
+      const uint32_t* ia = isl + x * cap; const uint32_t* ib = isl + y * cap;
+      const uint32_t* sa = slt + x * cap; const uint32_t* sb = slt + y * cap;
+      size_t pa = 0, pb = 0;
+      int32_t g = -1;
+      while (pa < len[x] && pb < len[y]) {
+        if (ga[pa] == gb[pb]) {
+          if (ia[pa] == ib[pb] && sa[pa] == sb[pb]) {
+            g = (int32_t)r->T[ids[x]] - (int32_t)pa;
+            break;
+          }
+          ++pa;
+          ++pb;
+        } else if (ga[pa] > gb[pb]) {
+          ++pa;
+        } else {
+          ++pb;
+        }
+      }
+      out[x * n + y] = g;
+      out[y * n + x] = g;
+    }
+  }
+  free(gen); free(isl); free(slt); free(len);
+  return 0;
+}
+
+void orc_mrca_interval_matrix(const uint32_t* T, const uint32_t* D, size_t n, uint32_t sites,
+                              uint32_t kc, uint32_t* L, uint32_t* U) {
+  const uint32_t words = sites / 32;
+  for (size_t x = 0; x < n; ++x)
+    for (size_t y = 0; y < n; ++y)
+      orc_mrca_interval(T[x], D + x * words, T[y], D + y * words, sites, kc, &L[x * n + y],
+                        &U[x * n + y]);
 }

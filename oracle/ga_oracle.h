@@ -63,6 +63,8 @@ int orc_validate(const orc_config* cfg);
 /* record_lineage != 0 keeps every child's tournament winner (1 byte each). */
 orc_run* orc_create(const orc_config* cfg, int record_lineage);
 void orc_free(orc_run* run);
+/* Reserve lineage storage for gens generations in one allocation. */
+int orc_reserve_lineage(orc_run* run, uint64_t gens);
 /* Advance n generations. Returns 0, or -1 when the lineage buffer cannot grow. */
 int orc_step(orc_run* run, uint64_t n);
 uint64_t orc_generation(const orc_run* run);
@@ -92,6 +94,17 @@ int64_t orc_true_mrca(const orc_run* run, uint64_t agent_a, uint64_t agent_b);
  * the ancestors of one agent, newest first; returns the chain length. */
 size_t orc_ancestry(const orc_run* run, uint64_t agent, uint64_t* gen,
                     uint32_t* island, uint32_t* slot, size_t max_len);
+
+/* Pairwise true MRCA for n agents of the current population:
+ * out[x*n + y] = T of the MRCA of ids[x] and ids[y], or -1 for different
+ * founders. Each agent's ancestor chain is walked once; pairs merge chains.
+ * Returns 0, or -1 if lineage was not recorded or memory ran out. */
+int orc_true_mrca_matrix(const orc_run* run, const uint64_t* ids, size_t n, int32_t* out);
+
+/* MRCA intervals for all pairs of n surfaces (T[n], D[n * S/32]):
+ * L[x*n + y], U[x*n + y] as orc_mrca_interval gives them. */
+void orc_mrca_interval_matrix(const uint32_t* T, const uint32_t* D, size_t n, uint32_t sites,
+                              uint32_t kc, uint32_t* L, uint32_t* U);
 
 /* MRCA interval from two surfaces: g (the MRCA's T) is always <= *U, and
  * g < *L has probability at most 2^-kc. */

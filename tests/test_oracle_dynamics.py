@@ -383,3 +383,22 @@ def test_validation():
     assert not oracle.validate(cfg(k=9))
     assert not oracle.validate(cfg(k=0))
     assert not oracle.validate(cfg(width=0))
+
+
+def test_bulk_mrca_functions_match_pairwise():
+    S = 32
+    c = cfg(width=6, height=5, pop=16, sites=S, seed=44)
+    run = oracle.OracleRun(c, lineage=True)
+    run.step(300)
+    f, T, D = run.population()
+    ids = np.array([0, 3, 17, 100, 101, 250, 479, 333], dtype=np.uint64)
+    G = run.true_mrca_matrix(ids)
+    Lm, Um = oracle.mrca_interval_matrix(T[ids.astype(int)], D[ids.astype(int)], S, 5)
+    for x in range(len(ids)):
+        for y in range(len(ids)):
+            a, b = int(ids[x]), int(ids[y])
+            if x != y:
+                assert G[x, y] == run.true_mrca(a, b)
+            else:
+                assert G[x, x] == T[a]
+            assert (Lm[x, y], Um[x, y]) == oracle.mrca_interval(int(T[a]), D[a], int(T[b]), D[b], S, 5)
