@@ -31,7 +31,7 @@
  * Every random draw is one Philox4x32-10 block (Salmon et al., SC'11) keyed
  * by (seed, run_id) with counter (slot or 0, island, generation low word,
  * generation high word * 4 + stream), stream 0 selection, 1 migration,
- * 2 sampling. Results are therefore bit-identical for any launch shape,
+ * 2 sampling, 3 mutation sizes (law 1). Results are therefore bit-identical for any launch shape,
  * batching or schedule.
  *
  * Conventions for every entry point:
@@ -73,6 +73,15 @@ typedef struct ga_config {
   uint32_t migration;          /* 1 one emigrant per island per generation, 0 none */
   uint32_t seed;               /* RNG key word 0 */
   uint32_t run_id;             /* RNG key word 1 */
+  /* Fields below were added after the first release; a caller passing
+   * struct_size = offsetof(ga_config, mutation_law) gets law 0. */
+  uint32_t mutation_law;       /* 0: with probability p the delta above;
+                                * 1: the paper's treatments (Sec. 3): with
+                                * probability b fitness gains |Z|, else with
+                                * probability p it loses |Z|; Z ~ N(0,1)
+                                * approximated by the variance-matched sum of
+                                * eight uniform 16-bit draws (stream 3) */
+  uint32_t beneficial_threshold; /* b * 2^32 (law 1); b + p <= 1 */
 } ga_config;
 
 /* Outbox entry as exchanged with the host (ga_read/ga_write_population):
@@ -181,6 +190,29 @@ int ga_batch_set_graph_block(ga_batch* batch, uint32_t gens_per_block);
  * Results do not depend on either. */
 int ga_batch_set_launch(ga_batch* batch, uint32_t islands_per_wave, uint32_t waves_per_group);
 void ga_batch_destroy(ga_batch* batch);
+
+/* ---------------------------------------------------------------------- */
+/* Post hoc relatedness (Fig. 1: markers on genomes support estimating how */
+/* related two lineages are after the run; Sec. 3 reconstructs phylogenies */
+/* from 10k sampled end-state genomes).                                    */
+/* ---------------------------------------------------------------------- */
+
+/* Device bytes of the workspace ga_mrca_matrix needs for n surfaces. */
+size_t ga_mrca_workspace_bytes(size_t n);
+
+/* MRCA intervals for every pair of n sampled surfaces, on the GPU. All
+ * pointers are DEVICE pointers owned by the caller: T[n] deposit counters,
+ * surface_words[n * S/32] (agent-major, as ga_extract_surfaces returns them),
+ * workspace of at least ga_mrca_workspace_bytes(n) bytes, and outputs
+ * L[n * n], U[n * n] (row x, column y). For the pair (x, y), the counter g of
+ * the most recent common ancestor satisfies g <= U[x*n+y] always, and
+ * g < L[x*n+y] with probability at most 2^-kc: the ranks both surfaces
+ * retain are compared oldest first, U is the first whose bits differ (or
+ * min(Tx, Ty)), and L sits kc common ranks below U (0 if there are fewer).
+ * n <= 65535, kc >= 1, surface_sites 32 or 64. Enqueued on hip_stream. */
+int ga_mrca_matrix(const uint32_t* T, const uint32_t* surface_words, size_t n,
+                   uint32_t surface_sites, uint32_t kc, void* workspace,
+                   size_t workspace_bytes, uint32_t* L, uint32_t* U, void* hip_stream);
 
 /* Message for a return code, and the calling thread's last error message. */
 const char* ga_strerror(int code);

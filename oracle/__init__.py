@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
         return LIB_PATH
     tmp = LIB_PATH + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-           "-fno-fast-math", "-ffp-contract=off", "-o", tmp] + SOURCES
+           "-fno-fast-math", "-ffp-contract=off", "-o", tmp] + SOURCES + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
 class _Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "width", "height", "pop", "sites", "k", "selection", "p32", "migration",
-        "seed", "run_id")]
+        "seed", "run_id", "law", "p_ben32")]
 
 
 _lib = None
@@ -142,11 +142,17 @@ def mrca_interval_matrix(T, D, sites: int, kc: int = 5):
 
 
 CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32",
-                 "migration", "seed", "run_id")
+                 "migration", "seed", "run_id", "law", "p_ben32")
+OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0}
+
+
+def _fields(cfg: dict) -> dict:
+    return {f: int(cfg.get(f, OPTIONAL_FIELDS.get(f, 0)) if f in OPTIONAL_FIELDS else cfg[f])
+            for f in CONFIG_FIELDS}
 
 
 def validate(cfg: dict) -> bool:
-    c = _Config(**{f: int(cfg[f]) for f in CONFIG_FIELDS})
+    c = _Config(**_fields(cfg))
     return _load().orc_validate(ctypes.byref(c)) == 0
 
 
@@ -155,7 +161,7 @@ class OracleRun:
 
     def __init__(self, cfg: dict, lineage: bool = False):
         lib = _load()
-        self.cfg = {f: int(cfg[f]) for f in CONFIG_FIELDS}
+        self.cfg = _fields(cfg)
         c = _Config(**self.cfg)
         h = lib.orc_create(ctypes.byref(c), 1 if lineage else 0)
         if not h:

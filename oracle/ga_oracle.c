@@ -34,6 +34,7 @@
  */
 #include "ga_oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -68,7 +69,7 @@ void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-enum { TAG_SELECT = 0, TAG_MIGRATE = 1, TAG_SAMPLE = 2 };
+enum { TAG_SELECT = 0, TAG_MIGRATE = 1, TAG_SAMPLE = 2, TAG_MUTATE = 3 };
 
 static void draw(const orc_config* cfg, uint32_t slot, uint32_t island, uint64_t t,
                  uint32_t tag, uint32_t out[4]) {
@@ -169,7 +170,25 @@ int orc_validate(const orc_config* cfg) {
   if (cfg->sites != 32 && cfg->sites != 64) return -1;
   if (cfg->k < 1 || cfg->k > 8) return -1;
   if (cfg->selection > 1 || cfg->migration > 1) return -1;
+  if (cfg->law > 1) return -1;
+  if (cfg->law == 1 && (uint64_t)cfg->p_ben32 + cfg->p32 > 0xFFFFFFFFull) return -1;
   return 0;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Normally distributed mutation sizes for the paper's two treatments       */
+/* (Sec. 3: deleterious Normal decrements in 33% of replications; beneficial */
+/* Normal increments in 0.3%). Z is the variance-matched sum of eight       */
+/* uniform 16-bit draws (Irwin-Hall, n = 8): mean 0, variance 1 - 2^-32,     */
+/* excess kurtosis -0.15, |Z| < 4.9. Only integer sums and one rounded      */
+/* binary32 product are involved, so the value is exactly reproducible.     */
+/* ----------------------------------------------------------------------- */
+static float normal_draw(const uint32_t m[4]) {
+  uint32_t sum = 0;
+  for (int j = 0; j < 8; ++j) sum += (m[j / 2] >> (16 * (j % 2))) & 0xFFFFu;
+  /* E[sum] = 8 * 65535 / 2; Var[sum] = 8 * (65536^2 - 1) / 12 */
+  const float scale = (float)(sqrt(1.5) / 65536.0);
+  return (float)((int32_t)sum - 262140) * scale;
 }
 
 orc_run* orc_create(const orc_config* cfg, int record_lineage) {
@@ -317,10 +336,21 @@ static void one_generation(orc_run* r) {
       copy_agent(r, r->f, r->T, r->D, i * N + best, r->nf, r->nT, r->nD, child);
       if (win_row) win_row[child] = (uint8_t)best;
 
-      if (w[2] < cfg->p32) {
-        uint32_t idx = (uint32_t)(((uint64_t)(w[3] & 0x7FFFFFFFu) * 5u) >> 31);
-        float delta = 0.5f * (float)((int)idx - 2);
-        r->nf[child] = r->nf[child] + delta;
+      if (cfg->law == 0) {
+        if (w[2] < cfg->p32) {
+          uint32_t idx = (uint32_t)(((uint64_t)(w[3] & 0x7FFFFFFFu) * 5u) >> 31);
+          float delta = 0.5f * (float)((int)idx - 2);
+          r->nf[child] = r->nf[child] + delta;
+        }
+      } else {
+        int beneficial = w[2] < cfg->p_ben32;
+        int deleterious = !beneficial && (uint64_t)w[2] < (uint64_t)cfg->p_ben32 + cfg->p32;
+        if (beneficial || deleterious) {
+          uint32_t m[4];
+          draw(cfg, (uint32_t)s, (uint32_t)i, t, TAG_MUTATE, m);
+          float size = fabsf(normal_draw(m));
+          r->nf[child] = beneficial ? r->nf[child] + size : r->nf[child] - size;
+        }
       }
 
       uint32_t site = orc_site_of(r->nT[child], cfg->sites);

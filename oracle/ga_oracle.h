@@ -44,6 +44,10 @@ typedef struct orc_config {
   uint32_t migration;   /* 1 one emigrant per island per generation, 0 off */
   uint32_t seed;        /* RNG key word 0 */
   uint32_t run_id;      /* RNG key word 1 */
+  uint32_t law;         /* 0 discrete delta with probability p32;
+                           1 treatments: beneficial (+|Z|) if draw < p_ben32,
+                           else deleterious (-|Z|) if draw < p_ben32 + p32 */
+  uint32_t p_ben32;     /* beneficial probability times 2^32 (law 1) */
 } orc_config;
 
 typedef struct orc_run orc_run;

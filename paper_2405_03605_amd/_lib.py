@@ -11,7 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libga_hip.so")
 HEADER = os.path.join(ROOT, "include", "ga.h")
-SOURCES = [os.path.join(_HERE, "csrc", "ga_kernels.hip"), os.path.join(_HERE, "csrc", "ga_api.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", n) for n in ("ga_kernels.hip", "ga_mrca.hip", "ga_api.hip")]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -37,7 +37,8 @@ def build(hipcc: str = "hipcc") -> str:
 class Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "struct_size", "width", "height", "pop_per_island", "surface_sites",
-        "tournament_size", "selection", "mutation_threshold", "migration", "seed", "run_id")]
+        "tournament_size", "selection", "mutation_threshold", "migration", "seed", "run_id",
+        "mutation_law", "beneficial_threshold")]
 
 
 class OutboxEntry(ctypes.Structure):
@@ -68,6 +69,8 @@ SIGNATURES = {
     "ga_batch_set_graph_block": (i32, [P, u32]),
     "ga_batch_set_launch": (i32, [P, u32, u32]),
     "ga_batch_destroy": (None, [P]),
+    "ga_mrca_workspace_bytes": (sz, [sz]),
+    "ga_mrca_matrix": (i32, [P, P, sz, u32, u32, P, sz, P, P, P]),
     "ga_strerror": (ctypes.c_char_p, [i32]),
     "ga_last_error": (ctypes.c_char_p, []),
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <string>
@@ -35,6 +36,9 @@ int hip_fail(hipError_t e, const char* what) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Size of the configuration before mutation_law / beneficial_threshold.
+constexpr uint32_t kConfigV1Size = (uint32_t)offsetof(ga_config, mutation_law);
+
 bool is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
 uint32_t log2u(uint32_t v) {
   uint32_t l = 0;
@@ -48,7 +52,8 @@ bool config_ok(const ga_config* c, std::string* why) {
     return false;
   };
   if (!c) return no("config is NULL");
-  if (c->struct_size != sizeof(ga_config)) return no("struct_size != sizeof(ga_config)");
+  if (c->struct_size != sizeof(ga_config) && c->struct_size != kConfigV1Size)
+    return no("struct_size must be sizeof(ga_config)");
   if (c->width < 1 || c->width > 65535) return no("width must be in [1, 65535]");
   if (c->height < 1 || c->height > 65535) return no("height must be in [1, 65535]");
   if (!is_pow2(c->pop_per_island) || c->pop_per_island > 64)
@@ -57,6 +62,12 @@ bool config_ok(const ga_config* c, std::string* why) {
   if (c->tournament_size < 1 || c->tournament_size > 8) return no("tournament_size must be in [1, 8]");
   if (c->selection > 1) return no("selection must be 0 or 1");
   if (c->migration > 1) return no("migration must be 0 or 1");
+  if (c->struct_size == sizeof(ga_config)) {
+    if (c->mutation_law > 1) return no("mutation_law must be 0 or 1");
+    if (c->mutation_law == 1 &&
+        (uint64_t)c->beneficial_threshold + c->mutation_threshold > 0xFFFFFFFFull)
+      return no("beneficial_threshold + mutation_threshold must be < 2^32");
+  }
   const uint64_t agents = (uint64_t)c->width * c->height * c->pop_per_island;
   if (agents >= (1ull << 30)) return no("width * height * pop_per_island must be < 2^30");
   return true;
@@ -74,9 +85,12 @@ struct Layout {
 // words per AoS outbox entry: fitness, T, surface words, header, padding to 16 B
 size_t outbox_stride(const ga_config* c) { return c->surface_sites == 32 ? 4 : 8; }
 
+// Planes run 128 islands past the last 64-island boundary: a wavefront's last
+// chunk may end up to 63 islands past the last island, and its one-iteration
+// prefetch reads up to 64 more.
 size_t padded_islands(const ga_config* c) {
   const size_t islands = (size_t)c->width * c->height;
-  return (islands + 63) / 64 * 64 + 64;
+  return (islands + 63) / 64 * 64 + 128;
 }
 
 Layout layout_of(const ga_config* c) {
@@ -129,6 +143,7 @@ struct ga_batch {
   ga::Tile* d_tiles = nullptr;
   size_t cap_views = 0, cap_tiles = 0;
   uint32_t n_tiles = 0;
+  uint32_t max_ipw = 1;
   uint32_t wpg = 4;
   uint32_t ipw_override = 0;
   uint32_t graph_block = 100;
@@ -259,7 +274,8 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
 
   ga_run* r = new (std::nothrow) ga_run();
   if (!r) return fail(GA_EINVAL, "host allocation failed");
-  r->cfg = *cfg;
+  std::memcpy(&r->cfg, cfg, cfg->struct_size);
+  r->cfg.struct_size = sizeof(ga_config);
   r->lay = lay;
   r->stream = static_cast<hipStream_t>(hip_stream);
   r->base = static_cast<uint8_t*>(dev_mem);
@@ -286,6 +302,9 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   v.migration = cfg->migration;
   v.seed = cfg->seed;
   v.run_id = cfg->run_id;
+  v.law = r->cfg.mutation_law;
+  v.p_ben = v.law ? r->cfg.beneficial_threshold : 0u;
+  v.p_any = v.law ? r->cfg.beneficial_threshold + r->cfg.mutation_threshold : 0u;
   r->ipw = default_ipw(v);
   v.ipw = r->ipw;
 
@@ -615,6 +634,8 @@ int rebuild_tables(ga_batch* b) {
                           hipMemcpyHostToDevice, b->stream), "upload tiles");
   GA_HIP(hipStreamSynchronize(b->stream), "stream sync");
   b->n_tiles = (uint32_t)tiles.size();
+  b->max_ipw = 1;
+  for (const ga::RunView& v : views) b->max_ipw = std::max(b->max_ipw, v.ipw);
   if (b->graph) {
     (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
@@ -629,7 +650,7 @@ int batch_direct(ga_batch* b, uint64_t n) {
     const uint64_t slice = std::min<uint64_t>(n, 1u << 20);
     for (uint64_t g = 0; g < slice; ++g)
       GA_HIP(ga::launch_batch_generation(b->d_views, b->d_tiles, b->n_tiles, (uint32_t)g, b->wpg,
-                                         b->stream), "batch launch");
+                                         b->max_ipw, b->stream), "batch launch");
     GA_HIP(ga::launch_batch_advance(b->d_views, runs, slice, b->stream), "batch advance");
     n -= slice;
   }
@@ -643,7 +664,8 @@ int batch_graph(ga_batch* b) {
   GA_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
   hipError_t err = hipSuccess;
   for (uint32_t g = 0; g < b->graph_block && err == hipSuccess; ++g)
-    err = ga::launch_batch_generation(b->d_views, b->d_tiles, b->n_tiles, g, b->wpg, b->capture_stream);
+    err = ga::launch_batch_generation(b->d_views, b->d_tiles, b->n_tiles, g, b->wpg, b->max_ipw,
+                                      b->capture_stream);
   if (err == hipSuccess)
     err = ga::launch_batch_advance(b->d_views, (uint32_t)b->members.size(), b->graph_block,
                                    b->capture_stream);
@@ -701,6 +723,27 @@ void ga_batch_destroy(ga_batch* b) {
   if (b->d_views) (void)hipFree(b->d_views);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   delete b;
+}
+
+// ---------------------------------------------------------------------------
+// Post hoc relatedness
+// ---------------------------------------------------------------------------
+
+size_t ga_mrca_workspace_bytes(size_t n) { return ga::mrca_workspace_bytes(n); }
+
+int ga_mrca_matrix(const uint32_t* T, const uint32_t* surface_words, size_t n,
+                   uint32_t surface_sites, uint32_t kc, void* workspace, size_t workspace_bytes,
+                   uint32_t* L, uint32_t* U, void* hip_stream) {
+  if (n == 0) return GA_OK;
+  if (n > 65535) return fail(GA_EINVAL, "n must be <= 65535");
+  if (surface_sites != 32 && surface_sites != 64) return fail(GA_EINVAL, "surface_sites must be 32 or 64");
+  if (kc < 1) return fail(GA_EINVAL, "kc must be >= 1");
+  if (!T || !surface_words || !workspace || !L || !U) return fail(GA_EINVAL, "NULL pointer");
+  if (workspace_bytes < ga::mrca_workspace_bytes(n)) return fail(GA_ENOMEM, "workspace too small");
+  GA_HIP(ga::launch_mrca_matrix(T, surface_words, (uint32_t)n, surface_sites / 32, kc, workspace,
+                                L, U, static_cast<hipStream_t>(hip_stream)),
+         "mrca launch");
+  return GA_OK;
 }
 
 }  // extern "C"

@@ -14,9 +14,10 @@ namespace ga {
 //   ob[p][i * ob_stride + k], k = 0 fitness, 1 T, 2.. surface words,
 //   2 + words header (bit 2 valid, bits 0-1 direction); ob_stride = 4 or 8
 //   words; p = generation parity.
-// Planes are padded to island_stride = roundup(islands, 64) + 64 islands
-// (agent_stride = island_stride * N agents): a wavefront's last chunk may run
-// past the last island and then only touches padding.
+// Planes are padded to island_stride = roundup(islands, 64) + 128 islands
+// (agent_stride = island_stride * N agents): a wavefront's last chunk, and its
+// one-iteration prefetch, may run past the last island and then only touch
+// padding.
 struct RunView {
   float* pop_f;
   uint32_t* pop_T;
@@ -30,6 +31,10 @@ struct RunView {
   uint32_t p32, migration, seed, run_id;
   uint32_t ipw;              // islands per wavefront
   uint32_t ob_stride;        // words per outbox entry
+  uint32_t law;              // 0 discrete delta, 1 treatments (normal sizes)
+  uint32_t p_ben;            // law 1: beneficial iff draw < p_ben
+  uint32_t p_any;            // law 1: deleterious iff p_ben <= draw < p_any
+  uint32_t pad;
 };
 
 // One wavefront's share of a batched launch: islands [first, first + ipw) of run `run`.
@@ -53,8 +58,13 @@ hipError_t launch_gather(const RunView& v, const uint32_t* ids, uint32_t n, uint
                          uint32_t* D_out, hipStream_t stream);
 hipError_t launch_batch_generation(const RunView* views, const Tile* tiles, uint32_t n_tiles,
                                    uint32_t gen_offset, uint32_t waves_per_group,
-                                   hipStream_t stream);
+                                   uint32_t max_ipw, hipStream_t stream);
 hipError_t launch_batch_advance(const RunView* views, uint32_t n_runs, uint64_t block,
                                 hipStream_t stream);
+
+size_t mrca_workspace_bytes(size_t n);
+hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, uint32_t words,
+                              uint32_t kc, void* workspace, uint32_t* L, uint32_t* U,
+                              hipStream_t stream);
 
 }  // namespace ga

@@ -33,6 +33,7 @@ constexpr uint32_t kWeylB = 0xBB67AE85u;
 constexpr uint32_t kStreamSelect = 0u;
 constexpr uint32_t kStreamMigrate = 1u;
 constexpr uint32_t kStreamSample = 2u;
+constexpr uint32_t kStreamMutate = 3u;
 
 struct Block {
   uint32_t x, y, z, w;
@@ -71,8 +72,8 @@ __device__ __forceinline__ Block philox10(uint32_t c0, uint32_t c1, uint32_t c2,
   return philox_rounds<0>(c0, c1, c2, c3, k0, k1);
 }
 
-// Selection-stream blocks for one lane across a chunk. The counter is
-// (slot, island, t_lo, t_hi*4): only the island word changes between a lane's
+// Per-child stream blocks for one lane across a chunk. The counter is
+// (slot, island, t_lo, t_hi*4 + stream): only the island word changes between a lane's
 // iterations, so everything of rounds 0-2 that does not depend on it is
 // computed once. The remaining per-block cost is 2 + 7*2 products and 3 + 7*2
 // three-input ops.
@@ -85,7 +86,7 @@ struct SelectStream {
   uint32_t k0, k1;
 
   __device__ __forceinline__ void init(uint32_t slot, uint32_t t_lo, uint32_t t_hi4, uint32_t key0,
-                                       uint32_t key1) {
+                                       uint32_t key1, uint32_t stream) {
     k0 = key0;
     k1 = key1;
     // round 0 on (slot, island, t_lo, t_hi4)
@@ -93,7 +94,7 @@ struct SelectStream {
     const uint64_t pb0 = (uint64_t)kMulB * t_lo;
     x0 = hi32(pb0) ^ key0;                       // c0' = hi(pb0) ^ island ^ k0
     const uint32_t c1_1 = (uint32_t)pb0;
-    const uint32_t c2_1 = hi32(pa0) ^ t_hi4 ^ key1;
+    const uint32_t c2_1 = hi32(pa0) ^ (t_hi4 | stream) ^ key1;
     const uint32_t c3_1 = (uint32_t)pa0;
     // round 1: pb1 from c2_1 is invariant; pa1 from c0' is not
     const uint64_t pb1 = (uint64_t)kMulB * c2_1;
@@ -168,12 +169,6 @@ __device__ __forceinline__ const P* at_byte(const P* base, uint32_t byte_off) {
   return reinterpret_cast<const P*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
-#ifndef GA_PREFETCH_DEPTH
-#define GA_PREFETCH_DEPTH 2
-#endif
-// Iterations of genomes a wavefront keeps in flight ahead of its compute.
-constexpr int kPrefetch = GA_PREFETCH_DEPTH;
-
 struct Genome {
   float f = 0.f;
   uint32_t T = 0, D0 = 0, D1 = 0;
@@ -192,10 +187,12 @@ __device__ __forceinline__ Genome load_genome(const float* pf, const uint32_t* p
 
 // One generation for islands [base, base + v.ipw) of a run, by one wavefront.
 // LC / SWC: log2 N and surface words fixed at compile time, or -1 to read them
-// from the view. `arrivals` is this wavefront's LDS table (64 x 4 entries).
+// from the view. `lds` is this wavefront's table of 5 * ipw + 1 16-byte
+// entries: arrivals [4 * local + q], emissions [4 * ipw + local], and one
+// scratch entry read when a lane has no arrival.
 template <int LC, int SWC>
 __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base, uint64_t t,
-                                                 uint4* arrivals) {
+                                                 uint4* lds) {
   const uint32_t L = LC >= 0 ? (uint32_t)LC : v.log2n;
   const uint32_t SW = SWC >= 0 ? (uint32_t)SWC : v.words;
   const uint32_t s_log = 4u + SW;  // log2 S: 5 for 32 sites, 6 for 64
@@ -221,12 +218,9 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   const uint32_t n_iter = v.ipw >> (6u - L);
   uint32_t off = lane << 2;
 
-  // genomes of the first kPrefetch iterations go in flight before the island
-  // pass, whose own loads and draws then hide their latency
-  Genome ring[kPrefetch];
-#pragma unroll
-  for (int p = 0; p < kPrefetch; ++p)
-    ring[p] = (uint32_t)p < n_iter ? load_genome(pf, pT, pD0, pD1, off + 256u * p, SW) : Genome{};
+  // the first iteration's genomes go in flight before the island pass, whose
+  // own loads and draws then hide their latency
+  Genome g = load_genome(pf, pT, pD0, pD1, off, SW);
 
   // ---- island pass: lane l handles island base + l ---------------------------
   const bool own_ok = lane < v.ipw && base + lane < v.islands;
@@ -242,11 +236,12 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
       const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
       desc = (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q));
       // f, T, D0 and the header (32 sites) or D1 (64 sites)
-      arrivals[lane * 4u + q] = *reinterpret_cast<const uint4*>(in_ob + j * ob_stride);
+      lds[lane * 4u + q] = *reinterpret_cast<const uint4*>(in_ob + j * ob_stride);
     }
   }
   // emission: slot and header of what this island sends; the lane holding the
-  // post-absorb member in that slot writes the outbox entry during its iteration
+  // post-absorb member in that slot parks it in the LDS table during its
+  // iteration, and the island's lane writes the outbox entry after the loop
   const uint32_t emit = own_ok ? (emig | ((v.migration ? (kMetaValid | (mig.y >> 30)) : 0u) << 8))
                                : 0xFFu;
   // hand the arrival table to the other lanes of this wavefront
@@ -258,17 +253,21 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   const uint32_t slot = lane & (N - 1u);
   const uint32_t slot_bytes = slot * 0x01010101u;
   const uint32_t lane0_addr = (lane & ~(N - 1u)) << 2;  // permute address of slot 0 of my island
-  SelectStream sel;
-  sel.init(slot, t_lo, t_hi4, v.seed, v.run_id);
+  const uint32_t emit_base = 4u * v.ipw;
+  const uint32_t scratch = 5u * v.ipw;
+  SelectStream sel, mut;
+  sel.init(slot, t_lo, t_hi4, v.seed, v.run_id, kStreamSelect);
+  if (v.law) mut.init(slot, t_lo, t_hi4, v.seed, v.run_id, kStreamMutate);
 
+  // One iteration of loads stays in flight ahead of the compute. The wait
+  // below settles the prologue loads once, so the loop body has no pending
+  // load on its working registers and no divergent memory access: its only
+  // wait is for the prefetched genomes, at the end of the iteration.
+  __builtin_amdgcn_s_waitcnt(0);
   for (uint32_t it = 0; it < n_iter; ++it) {
-    // this iteration's genomes; keep kPrefetch iterations in flight
-    Genome g = ring[0];
-#pragma unroll
-    for (int p = 0; p + 1 < kPrefetch; ++p) ring[p] = ring[p + 1];
-    ring[kPrefetch - 1] = it + kPrefetch < n_iter
-                              ? load_genome(pf, pT, pD0, pD1, off + 256u * kPrefetch, SW)
-                              : Genome{};
+    // next iteration's genomes (past the chunk's end this reads padding or the
+    // next chunk's first genomes, and the values go unused)
+    const Genome next = load_genome(pf, pT, pD0, pD1, off + 256u, SW);
     float f = g.f;
     uint32_t T = g.T, D0 = g.D0, D1 = g.D1;
     const uint32_t local = it * per_iter + (lane >> L);
@@ -280,31 +279,20 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     //    last direction.
     const uint32_t x = permute(desc, local << 2) ^ slot_bytes;
     const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
-    if (z != 0u) {
-      const uint32_t q = (31u - __clz(z)) >> 3;
-      const uint4 a = arrivals[local * 4u + q];
-      f = __uint_as_float(a.x);
-      T = a.y;
-      D0 = a.z;
-      D1 = a.w;
+    {
+      // no branch: lanes without an arrival read the scratch entry and keep
+      // their genome, so the loop carries no memory access under divergence
+      const uint32_t q = (31u - __clz(z | 1u)) >> 3;
+      const uint4 a = lds[z ? local * 4u + q : scratch];
+      f = z ? __uint_as_float(a.x) : f;
+      T = z ? a.y : T;
+      D0 = z ? a.z : D0;
+      D1 = z ? a.w : D1;
     }
 
-    // 2. emit the post-absorb member in the drawn slot (one lane per island)
-    const uint32_t my_emit = permute(emit, local << 2);
-    if ((my_emit & 0xFFu) == slot) {
-      uint32_t* e = out_ob + island * ob_stride;
-      const uint32_t hdr = my_emit >> 8;
-      if (hdr) {
-        if (SW == 1) {
-          *reinterpret_cast<uint4*>(e) = make_uint4(__float_as_uint(f), T, D0, hdr);
-        } else {
-          *reinterpret_cast<uint4*>(e) = make_uint4(__float_as_uint(f), T, D0, D1);
-          e[ob_hdr] = hdr;
-        }
-      } else {
-        e[ob_hdr] = 0u;
-      }
-    }
+    // 2. the lane holding the island's drawn emigrant parks it in LDS
+    if ((permute(emit, local << 2) & 0xFFu) == slot)
+      lds[emit_base + local] = make_uint4(__float_as_uint(f), T, D0, D1);
 
     // 3-5. evaluate (read fitness) and run the tournament over permuted entrants
     const Block r = sel.block(island);
@@ -331,9 +319,24 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
 
     // 6. mutation: delta index (w & 0x7FFFFFFF) * 5 >> 31 = hi32((w & 0x7FFFFFFF) * 10)
     //    maps 0..4 to {-1, -1/2, 0, 1/2, 1}
-    if (r.z < v.p32) {
-      const int di = (int)__umulhi(r.w & 0x7FFFFFFFu, 10u) - 2;  // -2..2
-      cfit = __fadd_rn(cfit, (float)di * 0.5f);
+    if (v.law == 0) {
+      if (r.z < v.p32) {
+        // di * 0.5 is exact, so a fused multiply-add rounds like the plain add
+        const int di = (int)__umulhi(r.w & 0x7FFFFFFFu, 10u) - 2;  // -2..2
+        cfit = __fadd_rn(cfit, (float)di * 0.5f);
+      }
+    } else {
+      // treatments: beneficial iff draw < p_ben, deleterious iff below p_any;
+      // size |Z|, Z the variance-matched sum of eight uniform 16-bit halves
+      const bool ben = r.z < v.p_ben;
+      const bool del = !ben && r.z < v.p_any;
+      if (ben || del) {
+        const Block m = mut.block(island);
+        const uint32_t sum = (m.x & 0xFFFFu) + (m.x >> 16) + (m.y & 0xFFFFu) + (m.y >> 16) +
+                             (m.z & 0xFFFFu) + (m.z >> 16) + (m.w & 0xFFFFu) + (m.w >> 16);
+        const float size = fabsf(__fmul_rn((float)((int)sum - 262140), 0x1.3988e2p-16f));
+        cfit = ben ? __fadd_rn(cfit, size) : __fsub_rn(cfit, size);
+      }
     }
 
     // 7. stratum deposit at rank T, then T + 1
@@ -361,14 +364,37 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     if (SW > 1) *at_byte(pD1, off) = cD1;
 
     off += 256u;
+    g = next;
+  }
+
+  // emissions: one 16-byte entry per island, consecutive across lanes
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  if (own_ok) {
+    uint32_t* e = out_ob + own * ob_stride;
+    const uint32_t hdr = emit >> 8;
+    if (hdr) {
+      const uint4 g = lds[emit_base + lane];
+      if (SW == 1) {
+        *reinterpret_cast<uint4*>(e) = make_uint4(g.x, g.y, g.z, hdr);
+      } else {
+        *reinterpret_cast<uint4*>(e) = g;
+        e[ob_hdr] = hdr;
+      }
+    } else {
+      e[ob_hdr] = 0u;
+    }
   }
 }
 
-// Dynamic LDS: one 64 x 4 arrival table (4 KiB) per wavefront of the group.
+// Dynamic LDS: a table of 5 * ipw + 1 16-byte entries per wavefront.
 extern __shared__ uint4 ga_lds[];
 
-__device__ __forceinline__ uint4* wave_arrivals(uint32_t wave_in_group) {
-  return ga_lds + wave_in_group * 256u;
+__device__ __forceinline__ uint32_t lds_entries(uint32_t ipw) { return 5u * ipw + 1u; }
+
+__device__ __forceinline__ uint4* wave_lds(uint32_t wave_in_group, uint32_t ipw) {
+  return ga_lds + wave_in_group * lds_entries(ipw);
 }
 
 template <int LC, int SWC>
@@ -377,7 +403,7 @@ __global__ __launch_bounds__(1024) void generation_kernel(RunView v, uint32_t ge
   const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wig;
   const uint32_t base = wave * v.ipw;
   if (base >= v.islands) return;
-  chunk_generation<LC, SWC>(v, base, *v.gen + gen_offset, wave_arrivals(wig));
+  chunk_generation<LC, SWC>(v, base, *v.gen + gen_offset, wave_lds(wig, v.ipw));
 }
 
 // Whole run in one workgroup: the generation loop stays on the GPU, with a
@@ -388,7 +414,7 @@ __global__ __launch_bounds__(1024) void resident_kernel(RunView v, uint64_t n_ge
   const uint32_t base = wig * v.ipw;
   const uint64_t t0 = *v.gen;
   for (uint64_t g = 0; g < n_gens; ++g) {
-    if (base < v.islands) chunk_generation<LC, SWC>(v, base, t0 + g, wave_arrivals(wig));
+    if (base < v.islands) chunk_generation<LC, SWC>(v, base, t0 + g, wave_lds(wig, v.ipw));
     __syncthreads();
   }
   if (threadIdx.x == 0) *v.gen = t0 + n_gens;
@@ -429,7 +455,8 @@ __global__ void gather_kernel(RunView v, const uint32_t* ids, uint32_t n, uint32
 __global__ __launch_bounds__(1024) void batch_generation_kernel(const RunView* __restrict__ views,
                                                                 const Tile* __restrict__ tiles,
                                                                 uint32_t n_tiles,
-                                                                uint32_t gen_offset) {
+                                                                uint32_t gen_offset,
+                                                                uint32_t max_ipw) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wig;
   if (wave >= n_tiles) return;
@@ -437,7 +464,7 @@ __global__ __launch_bounds__(1024) void batch_generation_kernel(const RunView* _
   const RunView v = views[tile.run];
   if (*v.left <= gen_offset) return;
   const uint64_t t = *v.gen + gen_offset;
-  uint4* arr = wave_arrivals(wig);
+  uint4* arr = wave_lds(wig, max_ipw);
 #ifndef GA_BATCH_GENERIC
   // wavefront-uniform dispatch to the specialised bodies
   switch (v.log2n * 2u + v.words - 1u) {
@@ -471,7 +498,7 @@ __global__ void batch_advance_kernel(const RunView* views, uint32_t n_runs, uint
   *v.left = left - done;
 }
 
-constexpr size_t kLdsPerWave = 256 * sizeof(uint4);
+size_t lds_bytes(uint32_t ipw, uint32_t waves) { return (5u * ipw + 1u) * sizeof(uint4) * waves; }
 
 }  // namespace
 
@@ -501,7 +528,7 @@ hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t wav
   if (waves == 0) return hipSuccess;
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
   const dim3 grid(groups), block(64 * waves_per_group);
-  const size_t lds = kLdsPerWave * waves_per_group;
+  const size_t lds = lds_bytes(v.ipw, waves_per_group);
   GA_DISPATCH(generation_kernel, v.log2n, v.words,
               <<<grid, block, lds, stream>>>(v, gen_offset));
   return hipGetLastError();
@@ -510,7 +537,7 @@ hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t wav
 hipError_t launch_resident(const RunView& v, uint64_t n_gens, uint32_t waves, hipStream_t stream) {
   if (waves == 0 || waves > (uint32_t)kMaxWavesPerGroup) return hipErrorInvalidValue;
   const dim3 grid(1), block(64 * waves);
-  const size_t lds = kLdsPerWave * waves;
+  const size_t lds = lds_bytes(v.ipw, waves);
   GA_DISPATCH(resident_kernel, v.log2n, v.words, <<<grid, block, lds, stream>>>(v, n_gens));
   return hipGetLastError();
 }
@@ -543,12 +570,12 @@ hipError_t launch_gather(const RunView& v, const uint32_t* ids, uint32_t n, uint
 
 hipError_t launch_batch_generation(const RunView* views, const Tile* tiles, uint32_t n_tiles,
                                    uint32_t gen_offset, uint32_t waves_per_group,
-                                   hipStream_t stream) {
+                                   uint32_t max_ipw, hipStream_t stream) {
   if (n_tiles == 0) return hipSuccess;
   const uint32_t groups = (n_tiles + waves_per_group - 1) / waves_per_group;
-  const size_t lds = kLdsPerWave * waves_per_group;
+  const size_t lds = lds_bytes(max_ipw, waves_per_group);
   batch_generation_kernel<<<dim3(groups), dim3(64 * waves_per_group), lds, stream>>>(
-      views, tiles, n_tiles, gen_offset);
+      views, tiles, n_tiles, gen_offset, max_ipw);
   return hipGetLastError();
 }
 

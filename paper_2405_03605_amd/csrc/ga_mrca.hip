@@ -1,0 +1,131 @@
+// All-pairs MRCA-interval estimation from hereditary-stratigraphy surfaces on
+// gfx950: the primitive under post hoc phylogenetic reconstruction (paper
+// Fig. 1: markers on genomes let relatedness be estimated after the run; Sec. 3
+// reconstructs from 10k sampled end-state genomes).
+//
+// For two surfaces with deposit counters Ta, Tb on S sites, the ranks both
+// retain are the multiples of 2^e, e = max(e(Ta), e(Tb)), below min(Ta, Tb)
+// (e(n) = max(0, ceil(log2 n) - log2 S), "doubling steady" surface). Ranks
+// older than the MRCA hold identical bits, so the first common rank whose bits
+// differ bounds the MRCA's counter from above (U); kc matching common ranks in
+// a row below U make an MRCA earlier than them a 2^-kc event (L).
+//
+// Layout of the work: `normalize_kernel` turns each surface into its retained
+// bits in rank order (bit j = rank j * 2^e(T)), a 64-bit string; the pair
+// kernel keeps every 2^(e - e(T))-th bit of each string (stride compaction),
+// XORs them and takes the lowest set bit: O(1) per pair, integer only.
+#include "ga_internal.hpp"
+
+namespace ga {
+namespace {
+
+struct Normalized {
+  unsigned long long bits;  // retained differentia in rank order
+  uint32_t T;
+  uint32_t epoch;
+};
+
+__device__ __forceinline__ uint32_t epoch_of(uint32_t n, uint32_t s) {
+  // max(0, ceil(log2 n) - s); ceil(log2 n) = bitlen(n - 1) for n >= 1
+  const uint32_t c = n <= 1u ? 0u : 32u - __clz(n - 1u);
+  return c > s ? c - s : 0u;
+}
+
+// Site of rank r (a retained rank, so never a discard): ranks below S keep
+// site r; otherwise walk to the rank whose site the j-th rank of its epoch
+// took over, as in the generation step's deposit.
+__device__ uint32_t site_of_retained(uint32_t r, uint32_t s) {
+  const uint32_t half = 1u << (s - 1u);
+  if (r < (half << 1)) return r;
+  const uint32_t e = (32u - __clz(r)) - s;
+  uint32_t odd = (((r >> e) - half) << 1) | 1u;
+  uint32_t shift = e - 1u;
+  for (;;) {
+    const uint32_t len = 32u - __clz(odd);
+    if (len + shift <= s) return odd << shift;
+    const uint32_t lead = odd << (s - len);
+    shift = len + shift - s - 1u;
+    odd = ((lead - half) << 1) | 1u;
+  }
+}
+
+__global__ void normalize_kernel(const uint32_t* __restrict__ T, const uint32_t* __restrict__ D,
+                                 uint32_t n, uint32_t words, uint32_t s, Normalized* out) {
+  const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const uint32_t t = T[a];
+  const uint32_t e = epoch_of(t, s);
+  const uint32_t count = t == 0u ? 0u : ((t - 1u) >> e) + 1u;  // ceil(t / 2^e) <= S
+  const uint32_t w0 = D[(size_t)a * words];
+  const uint32_t w1 = words > 1 ? D[(size_t)a * words + 1] : 0u;
+  unsigned long long bits = 0ull;
+  for (uint32_t j = 0; j < count; ++j) {
+    const uint32_t site = site_of_retained(j << e, s);
+    const uint32_t word = site < 32u ? w0 : w1;
+    bits |= (unsigned long long)((word >> (site & 31u)) & 1u) << j;
+  }
+  out[a] = Normalized{bits, t, e};
+}
+
+// keep bits 0, 2^d, 2*2^d, ... of x, packed to the bottom
+__device__ __forceinline__ unsigned long long compact_stride(unsigned long long x, uint32_t d) {
+  for (uint32_t i = 0; i < d; ++i) {
+    x &= 0x5555555555555555ull;
+    x = (x | (x >> 1)) & 0x3333333333333333ull;
+    x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+  }
+  return x;
+}
+
+// One thread per pair (x, y); rows of the grid are x, 64 consecutive y per
+// wavefront so the two output rows are written coalesced.
+__global__ __launch_bounds__(256) void pairs_kernel(const Normalized* __restrict__ nz, uint32_t n,
+                                                    uint32_t kc, uint32_t* __restrict__ L,
+                                                    uint32_t* __restrict__ U) {
+  const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t x = blockIdx.y;
+  if (y >= n) return;
+  const Normalized a = nz[x];
+  const Normalized b = nz[y];
+  const uint32_t e = a.epoch > b.epoch ? a.epoch : b.epoch;
+  const uint32_t tmin = a.T < b.T ? a.T : b.T;
+  const uint32_t common = tmin == 0u ? 0u : ((tmin - 1u) >> e) + 1u;  // ranks j*2^e < tmin
+  const unsigned long long diff =
+      compact_stride(a.bits, e - a.epoch) ^ compact_stride(b.bits, e - b.epoch);
+  const unsigned long long mask = common >= 64u ? ~0ull : ((1ull << common) - 1ull);
+  const unsigned long long hit = diff & mask;
+  uint32_t upper, below;
+  if (hit) {
+    const uint32_t j = (uint32_t)__ffsll((long long)hit) - 1u;  // first mismatching common rank
+    upper = j << e;
+    below = j;
+  } else {
+    upper = tmin;
+    below = common;
+  }
+  const size_t at = (size_t)x * n + y;
+  U[at] = upper;
+  L[at] = below < kc ? 0u : ((below - kc) << e) + 1u;
+}
+
+}  // namespace
+
+size_t mrca_workspace_bytes(size_t n) { return n * sizeof(Normalized); }
+
+hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, uint32_t words,
+                              uint32_t kc, void* workspace, uint32_t* L, uint32_t* U,
+                              hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  Normalized* nz = static_cast<Normalized*>(workspace);
+  const uint32_t s = 4u + words;  // log2 S
+  normalize_kernel<<<dim3((n + 255) / 256), dim3(256), 0, stream>>>(T, D, n, words, s, nz);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  pairs_kernel<<<dim3((n + 255) / 256, n), dim3(256), 0, stream>>>(nz, n, kc, L, U);
+  return hipGetLastError();
+}
+
+}  // namespace ga

@@ -10,7 +10,13 @@ import numpy as np
 from ._lib import (FORM_AUTO, GA_EINVAL, Config, GAError, OutboxEntry, check, load)
 
 CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32", "migration",
-                 "seed", "run_id")
+                 "seed", "run_id", "law", "p_ben32")
+OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0}
+
+
+def _fields(cfg: dict) -> dict:
+    return {f: int(cfg.get(f, OPTIONAL_FIELDS[f]) if f in OPTIONAL_FIELDS else cfg[f])
+            for f in CONFIG_FIELDS}
 
 
 def _ptr(a):
@@ -22,7 +28,8 @@ def make_config(cfg: dict) -> Config:
                   pop_per_island=cfg["pop"], surface_sites=cfg["sites"],
                   tournament_size=cfg["k"], selection=cfg["selection"],
                   mutation_threshold=cfg["p32"], migration=cfg["migration"],
-                  seed=cfg["seed"], run_id=cfg["run_id"])
+                  seed=cfg["seed"], run_id=cfg["run_id"],
+                  mutation_law=cfg.get("law", 0), beneficial_threshold=cfg.get("p_ben32", 0))
 
 
 def state_bytes(cfg: dict) -> int:
@@ -37,7 +44,7 @@ class GARun:
     def __init__(self, cfg: dict, device=None, stream=None):
         import torch
         lib = load()
-        self.cfg = {f: int(cfg[f]) for f in CONFIG_FIELDS}
+        self.cfg = _fields(cfg)
         self._c = make_config(self.cfg)
         nbytes = int(lib.ga_state_bytes(ctypes.byref(self._c)))
         if nbytes == 0:

@@ -34,6 +34,15 @@ PAPER = run_config(width=1024, height=512, pop=32, sites=32)
 PAPER_GENS = 100000
 
 
+# The paper's two treatments (Sec. 3), tournament size 5: purifying-only (33%
+# of replications lose a normally distributed amount) and adaptation-enabled
+# (additionally 0.3% gain one).
+P33 = 1417339207   # floor(0.33 * 2^32)
+P003 = 12884901    # floor(0.003 * 2^32)
+PURIFYING = dict(k=5, law=1, p32=P33, p_ben32=0)
+ADAPTIVE = dict(k=5, law=1, p32=P33, p_ben32=P003)
+
+
 def batched_configs(n_runs: int = 64, seed: int = 20240503) -> list[dict]:
     """64 uneven runs: grids log-uniform 16..256 x 16..128, agents per island
     uniform over {8,16,32,64}, 32 or 64 sites, tournament 2..8, selection on or

@@ -38,9 +38,9 @@ def test_every_declared_symbol_is_exported(lib):
 def test_state_bytes_layout(lib):
     # SoA planes: fitness, T, surface words per agent; 2 AoS outboxes of
     # (fitness, T, surface words, header) per island; counters; extraction staging.
-    # Planes are padded to roundup(islands, 64) + 64 islands.
+    # Planes are padded to roundup(islands, 64) + 128 islands.
     def expect(c):
-        I = (c["width"] * c["height"] + 63) // 64 * 64 + 64
+        I = (c["width"] * c["height"] + 63) // 64 * 64 + 128
         A = I * c["pop"]
         W = c["sites"] // 32
         al = lambda b: (b + 255) // 256 * 256
@@ -56,7 +56,8 @@ def test_state_bytes_layout(lib):
 @pytest.mark.parametrize("bad", [
     dict(pop=24), dict(pop=128), dict(pop=0), dict(sites=48), dict(sites=16), dict(k=0),
     dict(k=9), dict(width=0), dict(height=0), dict(width=70000), dict(selection=2),
-    dict(migration=3), dict(width=65535, height=65535, pop=64), dict(width=65535, height=8193, pop=2)])
+    dict(migration=3), dict(width=65535, height=65535, pop=64), dict(width=65535, height=8193, pop=2),
+    dict(law=2), dict(law=1, p32=2 ** 32 - 10, p_ben32=100)])
 def test_invalid_configs_rejected(lib, bad):
     c = make_config(run_config(**bad))
     assert lib.ga_state_bytes(ctypes.byref(c)) == 0
@@ -91,3 +92,11 @@ def test_null_handles_rejected(lib):
     lib.ga_batch_destroy(None)
     for code in (0, -1, -2, -3, -4, -99):
         assert lib.ga_strerror(code)
+
+
+def test_first_release_config_size_accepted(lib):
+    import ctypes as ct
+    c = make_config(run_config(law=1, p_ben32=5))
+    full = lib.ga_state_bytes(ct.byref(c))
+    c.struct_size = _lib.Config.mutation_law.offset     # size before the treatment fields
+    assert lib.ga_state_bytes(ct.byref(c)) == full

@@ -32,8 +32,10 @@ UNEVEN = [
     run_config(width=1, height=1, pop=1, sites=64, k=1, run_id=16),
     run_config(width=20, height=20, pop=8, sites=64, k=7, selection=0, run_id=17),
     run_config(width=9, height=11, pop=32, sites=64, migration=0, run_id=18),
+    run_config(width=14, height=6, pop=16, sites=32, k=5, law=1, p32=1417339207,
+               p_ben32=12884901, run_id=19),
 ]
-BUDGETS = [150, 230, 100, 99, 305, 1, 320, 200]
+BUDGETS = [150, 230, 100, 99, 305, 1, 320, 200, 175]
 
 
 @pytest.mark.parametrize("graph_block,ipw,wpg", [(100, 0, 0), (0, 0, 1), (64, 8, 8), (100, 64, 2)])

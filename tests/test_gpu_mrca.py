@@ -41,7 +41,7 @@ def test_gpu_surfaces_bracket_true_mrca(sample):
     got_ids, T, D = run.extract(ids)
     f0, T0, D0 = ref.population()
     assert np.array_equal(T, T0[ids]) and np.array_equal(D, D0[ids])
-    hi_viol = lo_viol = eligible = related = 0
+    hi_viol = lo_viol = pairs = related = 0
     for x in range(len(ids)):
         for y in range(x + 1, len(ids)):
             a, b = int(ids[x]), int(ids[y])
@@ -49,9 +49,45 @@ def test_gpu_surfaces_bracket_true_mrca(sample):
             L, U = oracle.mrca_interval(int(T[x]), D[x], int(T[y]), D[y], S, kc)
             hi_viol += g > U
             lo_viol += g < L
-            eligible += L > 0
+            pairs += 1
             related += g > 0
     assert hi_viol == 0
     assert related > 0
+    # P(g < L) <= 2^-kc for each pair; pairs are correlated, so allow slack
     bound = 2.0 ** -kc
-    assert lo_viol <= bound * eligible + 4 * np.sqrt(bound * max(eligible, 1)) + 1
+    assert lo_viol <= 1.25 * bound * pairs + 4 * np.sqrt(bound * pairs) + 1
+
+
+@pytest.mark.parametrize("sites,kc", [(32, 5), (64, 5), (32, 1), (64, 3)])
+def test_gpu_mrca_matrix_equals_oracle_on_random_surfaces(sites, kc):
+    from paper_2405_03605_amd import phylo
+    rng = np.random.default_rng(sites * 10 + kc)
+    special = [0, 1, 2, sites - 1, sites, sites + 1, 2 * sites, 2 * sites + 1, 100, 1000,
+               100000, (1 << 31) - 1, 1 << 31, 4000000000]
+    n = 300
+    T = np.concatenate([special, rng.integers(0, 1 << 20, size=n // 2),
+                        rng.integers(0, 1 << 32, size=n - n // 2 - len(special), dtype=np.uint64)])
+    T = T.astype(np.uint32)
+    D = rng.integers(0, 1 << 32, size=(n, sites // 32), dtype=np.uint64).astype(np.uint32)
+    # make many pairs share long prefixes: copy surfaces between random pairs
+    for _ in range(200):
+        a, b = rng.integers(0, n, size=2)
+        D[b] = D[a]
+    L, U = phylo.mrca_matrix(T, D, sites, kc)
+    L0, U0 = oracle.mrca_interval_matrix(T, D, sites, kc)
+    assert np.array_equal(U, U0)
+    assert np.array_equal(L, L0)
+
+
+def test_gpu_mrca_matrix_on_run_surfaces():
+    from paper_2405_03605_amd import phylo
+    cfg = run_config(width=32, height=16, pop=32, sites=64, seed=5)
+    run = GARun(cfg)
+    run.step(700)
+    ids = np.arange(0, run.agents, 29)[:520]
+    _, T, D = run.extract(ids)
+    L, U = phylo.mrca_matrix(T, D, 64, 5)
+    L0, U0 = oracle.mrca_interval_matrix(T, D, 64, 5)
+    assert np.array_equal(U, U0) and np.array_equal(L, L0)
+    Z, m = phylo.reconstruct(T, D, 64)
+    assert m["tips"] == len(ids) and m["sum_branch_length"] > 0

@@ -57,6 +57,10 @@ EDGE = [
     dict(pop=32, width=6, height=6, p32=0xFFFFFFFF),
     dict(pop=8, width=33, height=3, k=3, seed=12345, run_id=77),
     dict(pop=32, width=1, height=1),
+    dict(pop=32, width=7, height=5, sites=32, k=5, law=1, p32=1417339207, p_ben32=0),
+    dict(pop=32, width=7, height=5, sites=32, k=5, law=1, p32=1417339207, p_ben32=12884901),
+    dict(pop=16, width=5, height=9, sites=64, k=3, law=1, p32=1417339207, p_ben32=1288490188),
+    dict(pop=8, width=9, height=4, sites=32, k=8, law=1, p32=0xFFFFFFFF - 1288490188, p_ben32=1288490188),
 ]
 
 
