@@ -228,16 +228,20 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   const uint32_t ox = own % W, oy = own / W;
   const Block mig = philox10(0u, own, t_lo, t_hi4 | kStreamMigrate, v.seed, v.run_id);
   const uint32_t emig = L ? (mig.x >> (32u - L)) : 0u;
+  // All four neighbour entries are loaded and parked in LDS whether they are
+  // arrivals or not (for 32 sites the header rides in the same 16 bytes as the
+  // genome; for 64 sites it is the next word), so the pass pays one memory
+  // round trip; only the packed slots say which entries are arrivals.
   uint32_t desc = 0xFFFFFFFFu;  // byte q: slot taken by the arrival from direction q, or 0xFF
 #pragma unroll
   for (uint32_t q = 0; q < 4; ++q) {
-    const uint32_t j = torus_step(ox, oy, q, W, H);
-    if (own_ok && in_ob[j * ob_stride + ob_hdr] == (kMetaValid | (q ^ 2u))) {
-      const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
-      desc = (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q));
-      // f, T, D0 and the header (32 sites) or D1 (64 sites)
-      lds[lane * 4u + q] = *reinterpret_cast<const uint4*>(in_ob + j * ob_stride);
-    }
+    const uint32_t* e = in_ob + torus_step(ox, oy, q, W, H) * ob_stride;
+    const uint4 entry = *reinterpret_cast<const uint4*>(e);  // f, T, D0, header or D1
+    const uint32_t header = SW == 1 ? entry.w : e[ob_hdr];
+    const bool hit = own_ok && header == (kMetaValid | (q ^ 2u));
+    const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
+    desc = hit ? (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q)) : desc;
+    if (lane < v.ipw) lds[lane * 4u + q] = entry;  // the table holds ipw islands
   }
   // emission: slot and header of what this island sends; the lane holding the
   // post-absorb member in that slot parks it in the LDS table during its
