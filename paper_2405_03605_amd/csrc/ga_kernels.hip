@@ -456,7 +456,9 @@ __global__ void gather_kernel(RunView v, const uint32_t* ids, uint32_t n, uint32
 
 // Batched form: wavefront i works on tiles[i]; members whose budget for this
 // block is spent sit the generation out.
-__global__ __launch_bounds__(1024) void batch_generation_kernel(const RunView* __restrict__ views,
+// eight wavefronts per SIMD: the specialised bodies must fit 64 registers
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+void batch_generation_kernel(const RunView* __restrict__ views,
                                                                 const Tile* __restrict__ tiles,
                                                                 uint32_t n_tiles,
                                                                 uint32_t gen_offset,

@@ -114,13 +114,19 @@ class Server:
                 req.cfg["width"] * req.cfg["height"] * req.cfg["pop"])
         self.batch.step(self.block)
 
-    def drain(self, arrivals=None, time_limit: float | None = None):
+    def drain(self, arrivals=None, time_limit: float | None = None, progress=None,
+              progress_every: float = 10.0):
         """Serve until every request is done. `arrivals` is an optional list of
-        (arrival_offset_s, cfg, gens) submitted when the clock reaches them."""
+        (arrival_offset_s, cfg, gens) submitted when the clock reaches them;
+        `progress(server, elapsed_s)` is called about every progress_every s."""
         start = self.clock()
+        next_report = progress_every
         pending = deque(sorted(arrivals or [], key=lambda a: a[0]))
         while pending or self.waiting or self.live:
             now = self.clock() - start
+            if progress is not None and now >= next_report:
+                progress(self, now)
+                next_report = now + progress_every
             if time_limit is not None and now > time_limit:
                 break
             while pending and pending[0][0] <= now:
@@ -179,8 +185,14 @@ def main():
     free, _ = torch.cuda.mem_get_info()
     budget = int(args.budget_gb * 1e9) if args.budget_gb else int(free - 8e9)
     srv = Server(budget, max_slots=args.slots, block=args.block)
+
+    def progress(server, elapsed):
+        print(f"[serve] {elapsed:.0f} s: done {len(server.done)}, live {len(server.live)}, "
+              f"waiting {len(server.waiting)}, used {server.used / 1e9:.2f} GB", file=sys.stderr,
+              flush=True)
+
     t0 = time.perf_counter()
-    srv.drain(arrivals, time_limit=args.time_limit)
+    srv.drain(arrivals, time_limit=args.time_limit, progress=progress)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     rep = srv.report(wall)
