@@ -68,6 +68,10 @@ def _load():
     lib.orc_reserve_lineage.restype = ctypes.c_int
     lib.orc_step.argtypes = [P, u64]
     lib.orc_step.restype = ctypes.c_int
+    lib.orc_step_async.argtypes = [P, u64, u64]
+    lib.orc_step_async.restype = ctypes.c_int
+    lib.orc_clear_mailboxes.argtypes = [P]
+    lib.orc_get_mailboxes.argtypes = [P, P, P, P, P, P]
     lib.orc_generation.argtypes = [P]
     lib.orc_generation.restype = u64
     lib.orc_agents.argtypes = [P]
@@ -193,6 +197,29 @@ class OracleRun:
     def step(self, n: int):
         if _load().orc_step(self._h, int(n)) != 0:
             raise RuntimeError("oracle step failed (lineage buffer)")
+
+    def step_async(self, n: int, group: int):
+        """n generations of the asynchronous schedule, islands in consecutive
+        groups of ``group`` taken one after another (a sequential interleaving)."""
+        if _load().orc_step_async(self._h, int(n), int(group)) != 0:
+            raise RuntimeError("oracle async step failed (lineage on, group 0, or memory)")
+
+    def clear_mailboxes(self):
+        _load().orc_clear_mailboxes(self._h)
+
+    def mailboxes(self):
+        """Asynchronous buffers, shape (islands, 4) per field: stamp (sending
+        generation + 1, 0 empty), seen, f, T and D (islands, 4, words)."""
+        n = self.islands * 4
+        stamp = np.empty(n, dtype=np.uint64)
+        seen = np.empty(n, dtype=np.uint64)
+        f = np.empty(n, dtype=np.float32)
+        T = np.empty(n, dtype=np.uint32)
+        D = np.empty((n, self.words), dtype=np.uint32)
+        _load().orc_get_mailboxes(self._h, _ptr(stamp), _ptr(seen), _ptr(f), _ptr(T), _ptr(D))
+        sh = (self.islands, 4)
+        return {"stamp": stamp.reshape(sh), "seen": seen.reshape(sh), "f": f.reshape(sh),
+                "T": T.reshape(sh), "D": D.reshape(sh + (self.words,))}
 
     def population(self):
         f = np.empty(self.agents, dtype=np.float32)

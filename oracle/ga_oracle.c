@@ -140,6 +140,15 @@ typedef struct outbox_entry {
   uint32_t D[2];
 } outbox_entry;
 
+/* One emigration buffer of the asynchronous schedule: the latest genome an
+ * island sent toward one neighbour, stamped with its generation + 1 (0: none). */
+typedef struct mail_entry {
+  uint64_t stamp;
+  float f;
+  uint32_t T;
+  uint32_t D[2];
+} mail_entry;
+
 struct orc_run {
   orc_config cfg;
   uint32_t log2pop;
@@ -155,6 +164,8 @@ struct orc_run {
   uint32_t* nD;
   outbox_entry* prev;  /* emitted during t-1, absorbed during t */
   outbox_entry* next;  /* emitted during t */
+  mail_entry* mail;    /* asynchronous schedule: mail[i*4 + d], island i's buffer toward d */
+  uint64_t* seen;      /* seen[i*4 + q]: stamp of the last arrival island i took from q */
   int lineage;
   uint8_t* winners;    /* winners[g*agents + a]: tournament winner of child a in generation g */
   uint64_t lineage_gens;
@@ -224,6 +235,7 @@ void orc_free(orc_run* r) {
   free(r->f); free(r->T); free(r->D);
   free(r->nf); free(r->nT); free(r->nD);
   free(r->prev); free(r->next);
+  free(r->mail); free(r->seen);
   free(r->winners);
   free(r);
 }
@@ -280,6 +292,55 @@ int orc_reserve_lineage(orc_run* r, uint64_t gens) {
   return grow_lineage(r, gens);
 }
 
+/* Steps 3-7 of generation t for island i (Sec. 2): evaluation (reading the
+ * fitness word), tournament, copy, mutation and one stratum deposit for every
+ * child, read from the current population and written to the next one. */
+static void reproduce_island(orc_run* r, uint64_t i, uint64_t t, uint8_t* win_row) {
+  const orc_config* cfg = &r->cfg;
+  const uint64_t N = cfg->pop;
+  const uint32_t L = r->log2pop;
+  uint32_t w[4];
+  for (uint64_t s = 0; s < N; ++s) {
+    draw(cfg, (uint32_t)s, (uint32_t)i, t, TAG_SELECT, w);
+    /* Evaluation is reading the fitness word (Sec. 3 genome layout). */
+    uint32_t best = top_bits_of_byte(byte_of(w, 0), L);
+    if (cfg->selection) {
+      for (uint32_t m = 1; m < cfg->k; ++m) {
+        uint32_t cand = top_bits_of_byte(byte_of(w, m), L);
+        if (r->f[i * N + cand] > r->f[i * N + best]) best = cand;
+      }
+    }
+    uint64_t child = i * N + s;
+    copy_agent(r, r->f, r->T, r->D, i * N + best, r->nf, r->nT, r->nD, child);
+    if (win_row) win_row[child] = (uint8_t)best;
+
+    if (cfg->law == 0) {
+      if (w[2] < cfg->p32) {
+        uint32_t idx = (uint32_t)(((uint64_t)(w[3] & 0x7FFFFFFFu) * 5u) >> 31);
+        float delta = 0.5f * (float)((int)idx - 2);
+        r->nf[child] = r->nf[child] + delta;
+      }
+    } else {
+      int beneficial = w[2] < cfg->p_ben32;
+      int deleterious = !beneficial && (uint64_t)w[2] < (uint64_t)cfg->p_ben32 + cfg->p32;
+      if (beneficial || deleterious) {
+        uint32_t m[4];
+        draw(cfg, (uint32_t)s, (uint32_t)i, t, TAG_MUTATE, m);
+        float size = fabsf(normal_draw(m));
+        r->nf[child] = beneficial ? r->nf[child] + size : r->nf[child] - size;
+      }
+    }
+
+    uint32_t site = orc_site_of(r->nT[child], cfg->sites);
+    if (site != ORC_DISCARD) {
+      uint32_t bit = w[3] >> 31;
+      uint32_t* word = &r->nD[child * r->words + (site >> 5)];
+      *word = (*word & ~(1u << (site & 31))) | (bit << (site & 31));
+    }
+    r->nT[child] = r->nT[child] + 1;
+  }
+}
+
 static void one_generation(orc_run* r) {
   const orc_config* cfg = &r->cfg;
   const uint64_t N = cfg->pop;
@@ -321,47 +382,7 @@ static void one_generation(orc_run* r) {
 
   /* 3-7. Evaluation, tournament, copy, mutation, stratum deposit (Sec. 2). */
   uint8_t* win_row = r->lineage ? r->winners + (size_t)(t * r->agents) : NULL;
-  for (uint64_t i = 0; i < r->islands; ++i) {
-    for (uint64_t s = 0; s < N; ++s) {
-      draw(cfg, (uint32_t)s, (uint32_t)i, t, TAG_SELECT, w);
-      /* Evaluation is reading the fitness word (Sec. 3 genome layout). */
-      uint32_t best = top_bits_of_byte(byte_of(w, 0), L);
-      if (cfg->selection) {
-        for (uint32_t m = 1; m < cfg->k; ++m) {
-          uint32_t cand = top_bits_of_byte(byte_of(w, m), L);
-          if (r->f[i * N + cand] > r->f[i * N + best]) best = cand;
-        }
-      }
-      uint64_t child = i * N + s;
-      copy_agent(r, r->f, r->T, r->D, i * N + best, r->nf, r->nT, r->nD, child);
-      if (win_row) win_row[child] = (uint8_t)best;
-
-      if (cfg->law == 0) {
-        if (w[2] < cfg->p32) {
-          uint32_t idx = (uint32_t)(((uint64_t)(w[3] & 0x7FFFFFFFu) * 5u) >> 31);
-          float delta = 0.5f * (float)((int)idx - 2);
-          r->nf[child] = r->nf[child] + delta;
-        }
-      } else {
-        int beneficial = w[2] < cfg->p_ben32;
-        int deleterious = !beneficial && (uint64_t)w[2] < (uint64_t)cfg->p_ben32 + cfg->p32;
-        if (beneficial || deleterious) {
-          uint32_t m[4];
-          draw(cfg, (uint32_t)s, (uint32_t)i, t, TAG_MUTATE, m);
-          float size = fabsf(normal_draw(m));
-          r->nf[child] = beneficial ? r->nf[child] + size : r->nf[child] - size;
-        }
-      }
-
-      uint32_t site = orc_site_of(r->nT[child], cfg->sites);
-      if (site != ORC_DISCARD) {
-        uint32_t bit = w[3] >> 31;
-        uint32_t* word = &r->nD[child * r->words + (site >> 5)];
-        *word = (*word & ~(1u << (site & 31))) | (bit << (site & 31));
-      }
-      r->nT[child] = r->nT[child] + 1;
-    }
-  }
+  for (uint64_t i = 0; i < r->islands; ++i) reproduce_island(r, i, t, win_row);
 
   /* 8. Generational replacement; the fresh outbox becomes next generation's input. */
   float* tf = r->f; r->f = r->nf; r->nf = tf;
@@ -381,6 +402,119 @@ int orc_step(orc_run* r, uint64_t n) {
     if (r->lineage) r->lineage_gens = r->t;
   }
   return 0;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Asynchronous schedule (Sec. 2 Methods): every island keeps an            */
+/* immigration and an emigration buffer per cardinal neighbour and, at the  */
+/* start of each pass of its update loop, takes in whatever has arrived     */
+/* since it last looked and refills the buffers it sends from. Here a       */
+/* buffer holds the latest genome its island sent toward that neighbour,    */
+/* stamped with the sending generation + 1; the receiver absorbs a buffer   */
+/* once, when its stamp is newer than the last one it took from there, so a */
+/* genome overwritten before it was read is lost, as a send that never      */
+/* completed would be. Arrivals go to the receiver-drawn slots in direction */
+/* order N, E, S, W and the emission is drawn from the post-absorb          */
+/* population, exactly as in the synchronous schedule; only the moment a    */
+/* genome is read differs.                                                  */
+/*                                                                          */
+/* On hardware the islands interleave freely. This function is the one      */
+/* interleaving that is sequential: in generation t the islands go in       */
+/* consecutive groups of `group`, one group after another; a group reads    */
+/* all of its arrivals, then updates, then publishes its emissions. A group */
+/* therefore sees generation t's emissions of the groups before it and      */
+/* generation t-1's of the groups after it (or of itself), and a single     */
+/* group holding every island is the synchronous schedule.                  */
+/* ----------------------------------------------------------------------- */
+static int ensure_mail(orc_run* r) {
+  if (r->mail) return 0;
+  r->mail = (mail_entry*)calloc(r->islands * 4, sizeof(mail_entry));
+  r->seen = (uint64_t*)calloc(r->islands * 4, sizeof(uint64_t));
+  if (!r->mail || !r->seen) {
+    free(r->mail); free(r->seen);
+    r->mail = NULL; r->seen = NULL;
+    return -1;
+  }
+  return 0;
+}
+
+void orc_clear_mailboxes(orc_run* r) {
+  if (!r->mail) return;
+  memset(r->mail, 0, r->islands * 4 * sizeof(mail_entry));
+  memset(r->seen, 0, r->islands * 4 * sizeof(uint64_t));
+}
+
+static void one_generation_async(orc_run* r, uint64_t group) {
+  const orc_config* cfg = &r->cfg;
+  const uint64_t N = cfg->pop;
+  const uint32_t L = r->log2pop;
+  const uint64_t t = r->t;
+  uint32_t w[4];
+  for (uint64_t lo = 0; lo < r->islands; lo += group) {
+    const uint64_t hi = lo + group < r->islands ? lo + group : r->islands;
+    /* immigration: the buffer neighbour j keeps toward i is j's buffer in
+     * direction q ^ 2 */
+    for (uint64_t i = lo; i < hi; ++i) {
+      draw(cfg, 0, (uint32_t)i, t, TAG_MIGRATE, w);
+      for (uint32_t q = 0; q < 4; ++q) {
+        const mail_entry* in = &r->mail[neighbour(cfg, i, q) * 4 + (q ^ 2u)];
+        if (in->stamp <= r->seen[i * 4 + q]) continue;
+        r->seen[i * 4 + q] = in->stamp;
+        uint32_t slot = top_bits_of_byte((w[2] >> (8 * q)) & 0xFFu, L);
+        uint64_t a = i * N + slot;
+        r->f[a] = in->f;
+        r->T[a] = in->T;
+        for (uint32_t k = 0; k < r->words; ++k) r->D[a * r->words + k] = in->D[k];
+      }
+    }
+    /* emigration choice from the post-absorb population, held back until the
+     * group is done */
+    for (uint64_t i = lo; i < hi; ++i) {
+      outbox_entry* out = &r->next[i];
+      memset(out, 0, sizeof(*out));
+      if (!cfg->migration) continue;
+      draw(cfg, 0, (uint32_t)i, t, TAG_MIGRATE, w);
+      uint64_t a = i * N + top_bits_of_word(w[0], L);
+      out->valid = 1;
+      out->dir = (uint8_t)(w[1] >> 30);
+      out->f = r->f[a];
+      out->T = r->T[a];
+      for (uint32_t k = 0; k < r->words; ++k) out->D[k] = r->D[a * r->words + k];
+    }
+    for (uint64_t i = lo; i < hi; ++i) reproduce_island(r, i, t, NULL);
+    for (uint64_t i = lo; i < hi; ++i) {
+      const outbox_entry* out = &r->next[i];
+      if (!out->valid) continue;
+      mail_entry* m = &r->mail[i * 4 + out->dir];
+      m->stamp = t + 1;
+      m->f = out->f;
+      m->T = out->T;
+      for (uint32_t k = 0; k < r->words; ++k) m->D[k] = out->D[k];
+    }
+  }
+  float* tf = r->f; r->f = r->nf; r->nf = tf;
+  uint32_t* tT = r->T; r->T = r->nT; r->nT = tT;
+  uint32_t* tD = r->D; r->D = r->nD; r->nD = tD;
+  r->t = t + 1;
+}
+
+int orc_step_async(orc_run* r, uint64_t n, uint64_t group) {
+  if (r->lineage || group == 0) return -1;
+  if (ensure_mail(r) != 0) return -1;
+  for (uint64_t g = 0; g < n; ++g) one_generation_async(r, group);
+  return 0;
+}
+
+void orc_get_mailboxes(const orc_run* r, uint64_t* stamp, uint64_t* seen, float* f,
+                       uint32_t* T, uint32_t* D) {
+  for (uint64_t b = 0; b < r->islands * 4; ++b) {
+    const mail_entry* m = r->mail ? &r->mail[b] : NULL;
+    if (stamp) stamp[b] = m ? m->stamp : 0;
+    if (seen) seen[b] = r->seen ? r->seen[b] : 0;
+    if (f) f[b] = m ? m->f : 0.0f;
+    if (T) T[b] = m ? m->T : 0;
+    if (D) for (uint32_t k = 0; k < r->words; ++k) D[b * r->words + k] = m ? m->D[k] : 0;
+  }
 }
 
 void orc_get_population(const orc_run* r, float* f, uint32_t* T, uint32_t* D) {
