@@ -68,7 +68,7 @@ def _load():
     lib.orc_reserve_lineage.restype = ctypes.c_int
     lib.orc_step.argtypes = [P, u64]
     lib.orc_step.restype = ctypes.c_int
-    lib.orc_step_async.argtypes = [P, u64, u64]
+    lib.orc_step_async.argtypes = [P, u64, u64, u32]
     lib.orc_step_async.restype = ctypes.c_int
     lib.orc_clear_mailboxes.argtypes = [P]
     lib.orc_get_mailboxes.argtypes = [P, P, P, P, P, P]
@@ -198,28 +198,30 @@ class OracleRun:
         if _load().orc_step(self._h, int(n)) != 0:
             raise RuntimeError("oracle step failed (lineage buffer)")
 
-    def step_async(self, n: int, group: int):
-        """n generations of the asynchronous schedule, islands in consecutive
-        groups of ``group`` taken one after another (a sequential interleaving)."""
-        if _load().orc_step_async(self._h, int(n), int(group)) != 0:
+    def step_async(self, n: int, group: int, skew: int = 0):
+        """n generations of the asynchronous schedule in the reproducible
+        interleaving: groups of ``group`` islands, group c running generation t
+        at step t + (c mod (skew + 1)); skew 0 equals the synchronous schedule."""
+        if _load().orc_step_async(self._h, int(n), int(group), int(skew)) != 0:
             raise RuntimeError("oracle async step failed (lineage on, group 0, or memory)")
 
     def clear_mailboxes(self):
         _load().orc_clear_mailboxes(self._h)
 
     def mailboxes(self):
-        """Asynchronous buffers, shape (islands, 4) per field: stamp (sending
-        generation + 1, 0 empty), seen, f, T and D (islands, 4, words)."""
-        n = self.islands * 4
+        """Asynchronous buffers: stamp, f, T with shape (islands, 4, 2) (sender,
+        direction, parity of the sending generation), D (islands, 4, 2, words),
+        and seen (islands, 4)."""
+        n = self.islands * 8
         stamp = np.empty(n, dtype=np.uint64)
-        seen = np.empty(n, dtype=np.uint64)
+        seen = np.empty(self.islands * 4, dtype=np.uint64)
         f = np.empty(n, dtype=np.float32)
         T = np.empty(n, dtype=np.uint32)
         D = np.empty((n, self.words), dtype=np.uint32)
         _load().orc_get_mailboxes(self._h, _ptr(stamp), _ptr(seen), _ptr(f), _ptr(T), _ptr(D))
-        sh = (self.islands, 4)
-        return {"stamp": stamp.reshape(sh), "seen": seen.reshape(sh), "f": f.reshape(sh),
-                "T": T.reshape(sh), "D": D.reshape(sh + (self.words,))}
+        sh = (self.islands, 4, 2)
+        return {"stamp": stamp.reshape(sh), "seen": seen.reshape(self.islands, 4),
+                "f": f.reshape(sh), "T": T.reshape(sh), "D": D.reshape(sh + (self.words,))}
 
     def population(self):
         f = np.empty(self.agents, dtype=np.float32)

@@ -141,7 +141,8 @@ typedef struct outbox_entry {
 } outbox_entry;
 
 /* One emigration buffer of the asynchronous schedule: the latest genome an
- * island sent toward one neighbour, stamped with its generation + 1 (0: none). */
+ * island sent toward one neighbour in a generation of one parity, stamped with
+ * that generation + 1 (0: none). */
 typedef struct mail_entry {
   uint64_t stamp;
   float f;
@@ -164,7 +165,8 @@ struct orc_run {
   uint32_t* nD;
   outbox_entry* prev;  /* emitted during t-1, absorbed during t */
   outbox_entry* next;  /* emitted during t */
-  mail_entry* mail;    /* asynchronous schedule: mail[i*4 + d], island i's buffer toward d */
+  mail_entry* mail;    /* asynchronous schedule: mail[(i*4 + d)*2 + p], island i's buffer
+                          toward d for sending generations of parity p */
   uint64_t* seen;      /* seen[i*4 + q]: stamp of the last arrival island i took from q */
   int lineage;
   uint8_t* winners;    /* winners[g*agents + a]: tournament winner of child a in generation g */
@@ -407,28 +409,33 @@ int orc_step(orc_run* r, uint64_t n) {
 /* ----------------------------------------------------------------------- */
 /* Asynchronous schedule (Sec. 2 Methods): every island keeps an            */
 /* immigration and an emigration buffer per cardinal neighbour and, at the  */
-/* start of each pass of its update loop, takes in whatever has arrived     */
-/* since it last looked and refills the buffers it sends from. Here a       */
-/* buffer holds the latest genome its island sent toward that neighbour,    */
-/* stamped with the sending generation + 1; the receiver absorbs a buffer   */
-/* once, when its stamp is newer than the last one it took from there, so a */
-/* genome overwritten before it was read is lost, as a send that never      */
-/* completed would be. Arrivals go to the receiver-drawn slots in direction */
-/* order N, E, S, W and the emission is drawn from the post-absorb          */
-/* population, exactly as in the synchronous schedule; only the moment a    */
-/* genome is read differs.                                                  */
+/* start of each pass of its update loop, takes in whatever has arrived and */
+/* refills the buffers it sends from. Here each island keeps, per           */
+/* direction, two buffers told apart by the parity of the sending           */
+/* generation; a buffer holds the latest genome sent that way in a          */
+/* generation of its parity, stamped with that generation + 1. A send       */
+/* starts as its sender's pass begins and is read when the receiver begins  */
+/* a pass, so a genome is still in flight during the generation it was     */
+/* sent in: in generation t a receiver takes, from each side, the newest    */
+/* buffer sent before t that is newer than the last one it took from there  */
+/* (if any). A genome overwritten before it was taken is lost, as a send    */
+/* that never completed would be. Arrivals go to the receiver-drawn slots   */
+/* in direction order N, E, S, W and the emission is drawn from the         */
+/* post-absorb population, exactly as in the synchronous schedule; only the */
+/* moment a genome is read differs.                                         */
 /*                                                                          */
-/* On hardware the islands interleave freely. This function is the one      */
-/* interleaving that is sequential: in generation t the islands go in       */
-/* consecutive groups of `group`, one group after another; a group reads    */
-/* all of its arrivals, then updates, then publishes its emissions. A group */
-/* therefore sees generation t's emissions of the groups before it and      */
-/* generation t-1's of the groups after it (or of itself), and a single     */
-/* group holding every island is the synchronous schedule.                  */
+/* On hardware the islands interleave freely. This function runs one        */
+/* reproducible interleaving: islands go in consecutive groups of `group`;  */
+/* group c runs its generation t at step t + (c mod (skew + 1)), and within */
+/* a step the groups go in order, each reading all of its arrivals, then    */
+/* updating, then publishing. While every island's neighbours are between   */
+/* the end of its previous generation and the start of its next one (skew   */
+/* 0), this is exactly the synchronous schedule; larger skews put           */
+/* neighbours generations apart, so genomes arrive late or are overwritten. */
 /* ----------------------------------------------------------------------- */
 static int ensure_mail(orc_run* r) {
   if (r->mail) return 0;
-  r->mail = (mail_entry*)calloc(r->islands * 4, sizeof(mail_entry));
+  r->mail = (mail_entry*)calloc(r->islands * 8, sizeof(mail_entry));
   r->seen = (uint64_t*)calloc(r->islands * 4, sizeof(uint64_t));
   if (!r->mail || !r->seen) {
     free(r->mail); free(r->seen);
@@ -440,81 +447,93 @@ static int ensure_mail(orc_run* r) {
 
 void orc_clear_mailboxes(orc_run* r) {
   if (!r->mail) return;
-  memset(r->mail, 0, r->islands * 4 * sizeof(mail_entry));
+  memset(r->mail, 0, r->islands * 8 * sizeof(mail_entry));
   memset(r->seen, 0, r->islands * 4 * sizeof(uint64_t));
 }
 
-static void one_generation_async(orc_run* r, uint64_t group) {
+/* Generation t for the islands [lo, hi), as one group of the interleaving. */
+static void group_generation_async(orc_run* r, uint64_t lo, uint64_t hi, uint64_t t) {
   const orc_config* cfg = &r->cfg;
   const uint64_t N = cfg->pop;
   const uint32_t L = r->log2pop;
-  const uint64_t t = r->t;
   uint32_t w[4];
-  for (uint64_t lo = 0; lo < r->islands; lo += group) {
-    const uint64_t hi = lo + group < r->islands ? lo + group : r->islands;
-    /* immigration: the buffer neighbour j keeps toward i is j's buffer in
-     * direction q ^ 2 */
-    for (uint64_t i = lo; i < hi; ++i) {
-      draw(cfg, 0, (uint32_t)i, t, TAG_MIGRATE, w);
-      for (uint32_t q = 0; q < 4; ++q) {
-        const mail_entry* in = &r->mail[neighbour(cfg, i, q) * 4 + (q ^ 2u)];
-        if (in->stamp <= r->seen[i * 4 + q]) continue;
-        r->seen[i * 4 + q] = in->stamp;
-        uint32_t slot = top_bits_of_byte((w[2] >> (8 * q)) & 0xFFu, L);
-        uint64_t a = i * N + slot;
-        r->f[a] = in->f;
-        r->T[a] = in->T;
-        for (uint32_t k = 0; k < r->words; ++k) r->D[a * r->words + k] = in->D[k];
+  /* immigration: the buffers neighbour j keeps toward i are j's buffers in
+   * direction q ^ 2 */
+  for (uint64_t i = lo; i < hi; ++i) {
+    draw(cfg, 0, (uint32_t)i, t, TAG_MIGRATE, w);
+    for (uint32_t q = 0; q < 4; ++q) {
+      const mail_entry* pick = NULL;
+      for (uint32_t p = 0; p < 2; ++p) {
+        const mail_entry* in = &r->mail[(neighbour(cfg, i, q) * 4 + (q ^ 2u)) * 2 + p];
+        if (in->stamp > t || in->stamp <= r->seen[i * 4 + q]) continue;
+        if (!pick || in->stamp > pick->stamp) pick = in;
       }
-    }
-    /* emigration choice from the post-absorb population, held back until the
-     * group is done */
-    for (uint64_t i = lo; i < hi; ++i) {
-      outbox_entry* out = &r->next[i];
-      memset(out, 0, sizeof(*out));
-      if (!cfg->migration) continue;
-      draw(cfg, 0, (uint32_t)i, t, TAG_MIGRATE, w);
-      uint64_t a = i * N + top_bits_of_word(w[0], L);
-      out->valid = 1;
-      out->dir = (uint8_t)(w[1] >> 30);
-      out->f = r->f[a];
-      out->T = r->T[a];
-      for (uint32_t k = 0; k < r->words; ++k) out->D[k] = r->D[a * r->words + k];
-    }
-    for (uint64_t i = lo; i < hi; ++i) reproduce_island(r, i, t, NULL);
-    for (uint64_t i = lo; i < hi; ++i) {
-      const outbox_entry* out = &r->next[i];
-      if (!out->valid) continue;
-      mail_entry* m = &r->mail[i * 4 + out->dir];
-      m->stamp = t + 1;
-      m->f = out->f;
-      m->T = out->T;
-      for (uint32_t k = 0; k < r->words; ++k) m->D[k] = out->D[k];
+      if (!pick) continue;
+      r->seen[i * 4 + q] = pick->stamp;
+      uint64_t a = i * N + top_bits_of_byte((w[2] >> (8 * q)) & 0xFFu, L);
+      r->f[a] = pick->f;
+      r->T[a] = pick->T;
+      for (uint32_t k = 0; k < r->words; ++k) r->D[a * r->words + k] = pick->D[k];
     }
   }
-  float* tf = r->f; r->f = r->nf; r->nf = tf;
-  uint32_t* tT = r->T; r->T = r->nT; r->nT = tT;
-  uint32_t* tD = r->D; r->D = r->nD; r->nD = tD;
-  r->t = t + 1;
+  /* emigration choice from the post-absorb population, held back until the
+   * group is done */
+  for (uint64_t i = lo; i < hi; ++i) {
+    outbox_entry* out = &r->next[i];
+    memset(out, 0, sizeof(*out));
+    if (!cfg->migration) continue;
+    draw(cfg, 0, (uint32_t)i, t, TAG_MIGRATE, w);
+    uint64_t a = i * N + top_bits_of_word(w[0], L);
+    out->valid = 1;
+    out->dir = (uint8_t)(w[1] >> 30);
+    out->f = r->f[a];
+    out->T = r->T[a];
+    for (uint32_t k = 0; k < r->words; ++k) out->D[k] = r->D[a * r->words + k];
+  }
+  /* update: the group's next population replaces its current one */
+  for (uint64_t i = lo; i < hi; ++i) {
+    reproduce_island(r, i, t, NULL);
+    for (uint64_t s = 0; s < N; ++s) copy_agent(r, r->nf, r->nT, r->nD, i * N + s, r->f, r->T, r->D, i * N + s);
+  }
+  for (uint64_t i = lo; i < hi; ++i) {
+    const outbox_entry* out = &r->next[i];
+    if (!out->valid) continue;
+    mail_entry* m = &r->mail[(i * 4 + out->dir) * 2 + (t & 1)];
+    m->stamp = t + 1;
+    m->f = out->f;
+    m->T = out->T;
+    for (uint32_t k = 0; k < r->words; ++k) m->D[k] = out->D[k];
+  }
 }
 
-int orc_step_async(orc_run* r, uint64_t n, uint64_t group) {
+int orc_step_async(orc_run* r, uint64_t n, uint64_t group, uint32_t skew) {
   if (r->lineage || group == 0) return -1;
   if (ensure_mail(r) != 0) return -1;
-  for (uint64_t g = 0; g < n; ++g) one_generation_async(r, group);
+  const uint64_t t0 = r->t;
+  for (uint64_t step = 0; step < n + skew; ++step) {
+    uint64_t c = 0;
+    for (uint64_t lo = 0; lo < r->islands; lo += group, ++c) {
+      const uint64_t lag = c % ((uint64_t)skew + 1);
+      if (step < lag || step - lag >= n) continue;
+      const uint64_t hi = lo + group < r->islands ? lo + group : r->islands;
+      group_generation_async(r, lo, hi, t0 + step - lag);
+    }
+  }
+  r->t = t0 + n;
   return 0;
 }
 
 void orc_get_mailboxes(const orc_run* r, uint64_t* stamp, uint64_t* seen, float* f,
                        uint32_t* T, uint32_t* D) {
-  for (uint64_t b = 0; b < r->islands * 4; ++b) {
+  for (uint64_t b = 0; b < r->islands * 8; ++b) {
     const mail_entry* m = r->mail ? &r->mail[b] : NULL;
     if (stamp) stamp[b] = m ? m->stamp : 0;
-    if (seen) seen[b] = r->seen ? r->seen[b] : 0;
     if (f) f[b] = m ? m->f : 0.0f;
     if (T) T[b] = m ? m->T : 0;
     if (D) for (uint32_t k = 0; k < r->words; ++k) D[b * r->words + k] = m ? m->D[k] : 0;
   }
+  if (seen)
+    for (uint64_t b = 0; b < r->islands * 4; ++b) seen[b] = r->seen ? r->seen[b] : 0;
 }
 
 void orc_get_population(const orc_run* r, float* f, uint32_t* T, uint32_t* D) {

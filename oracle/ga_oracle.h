@@ -72,19 +72,22 @@ int orc_reserve_lineage(orc_run* run, uint64_t gens);
 /* Advance n generations. Returns 0, or -1 when the lineage buffer cannot grow. */
 int orc_step(orc_run* run, uint64_t n);
 uint64_t orc_generation(const orc_run* run);
-/* Asynchronous schedule, sequential interleaving: n generations in which
- * islands go in consecutive groups of `group` (each group reads its arrivals,
- * updates, then publishes its emissions). Per-neighbour buffers hold the latest
- * genome sent that way; a receiver takes each once. group >= islands gives the
- * synchronous schedule's results. Buffers start empty and are separate from the
- * synchronous outbox. Returns -1 with lineage on, group == 0, or no memory. */
-int orc_step_async(orc_run* run, uint64_t n, uint64_t group);
+/* Asynchronous schedule in a reproducible interleaving: n generations in
+ * which islands go in consecutive groups of `group`; group c runs its
+ * generation t at step t + (c mod (skew + 1)), groups in order within a step,
+ * each reading its arrivals, updating, then publishing. Per neighbour and per
+ * parity of the sending generation a buffer holds the latest genome sent; in
+ * generation t a receiver takes, from each side, the newest buffer sent before
+ * t and not taken yet. skew 0 gives the synchronous schedule's results.
+ * Buffers start empty and are separate from the synchronous outbox. Returns
+ * -1 with lineage on, group == 0, or no memory. */
+int orc_step_async(orc_run* run, uint64_t n, uint64_t group, uint32_t skew);
 /* Empty every asynchronous buffer and forget what was taken from them. */
 void orc_clear_mailboxes(orc_run* run);
-/* Asynchronous buffers, entry b = i*4 + d (island i's buffer toward d):
- * stamp[b] (sending generation + 1, 0 if empty), seen[b] (for island i and
- * direction d: the stamp of the last arrival it took from its neighbour
- * there), and the genome. Any pointer may be NULL. */
+/* Asynchronous buffers, entry b = (i*4 + d)*2 + p (island i's buffer toward
+ * d for sending generations of parity p): stamp[b] (sending generation + 1,
+ * 0 if empty) and the genome; seen[i*4 + q] is the stamp of the last arrival
+ * island i took from its neighbour in direction q. Any pointer may be NULL. */
 void orc_get_mailboxes(const orc_run* run, uint64_t* stamp, uint64_t* seen, float* f,
                        uint32_t* T, uint32_t* D);
 
