@@ -82,7 +82,35 @@ typedef struct ga_config {
                                 * approximated by the variance-matched sum of
                                 * eight uniform 16-bit draws (stream 3) */
   uint32_t beneficial_threshold; /* b * 2^32 (law 1); b + p <= 1 */
+  /* Added later still; struct_size = offsetof(ga_config, schedule) gets the
+   * synchronous schedule. */
+  uint32_t schedule;           /* GA_SCHEDULE_SYNC or GA_SCHEDULE_ASYNC */
 } ga_config;
+
+/* Schedules (ga_config.schedule).
+ *
+ * GA_SCHEDULE_SYNC: the deterministic schedule described at the top of this
+ * file; results do not depend on the launch shape.
+ *
+ * GA_SCHEDULE_ASYNC: the paper's asynchronous exchange (Sec. 2 Methods): each
+ * island keeps emigration buffers per cardinal neighbour (two, by parity of
+ * the sending generation); at the start of each generation it takes from each
+ * side the newest genome sent before this generation that it has not taken
+ * yet (a genome is in flight during the generation it was sent in), and after
+ * updating it writes its emigrant into the buffer toward the drawn direction.
+ * There is no barrier across the grid: wavefronts of one persistent launch
+ * each own a range of islands and run the generations, an island waiting only
+ * while a neighbour is more than a set number of generations behind (see
+ * ga_set_async). Every random draw is the same as in the synchronous schedule;
+ * only the moment a genome is read differs. With the default pacing, or
+ * migration off, the results equal the synchronous schedule's unless a wait
+ * gave up; looser pacing lets genomes arrive late or be overwritten unread,
+ * and the results then depend on timing, except in the reproducible skewed
+ * interleaving of ga_set_async. An asynchronous run has no synchronous outbox:
+ * the outbox arguments of ga_read_population and ga_write_population must be
+ * NULL, ga_write_population empties the buffers, and it cannot join a batch. */
+#define GA_SCHEDULE_SYNC 0
+#define GA_SCHEDULE_ASYNC 1
 
 /* Outbox entry as exchanged with the host (ga_read/ga_write_population):
  * the genome an island emitted in the last generation and its direction. */
@@ -96,7 +124,8 @@ typedef struct ga_outbox_entry {
 
 typedef struct ga_run ga_run;
 
-/* Device bytes a run needs (population planes, double-buffered outboxes,
+/* Device bytes a run needs (population planes, double-buffered outboxes or,
+ * for the asynchronous schedule, four buffers and four stamps per island,
  * generation counter, extraction staging). 0 for an invalid configuration. */
 size_t ga_state_bytes(const ga_config* cfg);
 
@@ -156,6 +185,30 @@ void ga_destroy(ga_run* run);
  * wavefronts at the given islands per wavefront. */
 int ga_set_launch(ga_run* run, uint32_t islands_per_wave, uint32_t waves_per_group,
                   uint32_t form);
+/* Asynchronous runs only (GA_EINVAL for a synchronous run).
+ *
+ * max_wavefronts caps the wavefronts of a launch (0, the default: as many as
+ * the GPU holds at once, from the occupancy of the kernel).
+ *
+ * max_lead bounds how many generations an island may run ahead of a
+ * neighbour: before generation t an island waits until each neighbour has
+ * completed t - max_lead generations, checking a bounded number of times and
+ * then going on regardless (ga_async_waits counts those). Default 0: each
+ * island waits for its neighbours to finish the previous generation, which
+ * makes the results equal to the synchronous schedule's whenever no wait gave
+ * up, with no barrier across the grid. GA_ASYNC_UNPACED: no waiting at all.
+ *
+ * skew > 0 (needs max_wavefronts 1 and GA_ASYNC_UNPACED): the reproducible
+ * interleaving in which chunk c (islands c*ipw ...) runs its generation g of a
+ * ga_step call at step g + (c mod (skew + 1)), the chunks in order within a
+ * step; neighbours are then up to skew generations apart, so genomes arrive
+ * late or are overwritten unread. skew <= 1024. */
+#define GA_ASYNC_UNPACED 0xFFFFFFFFu
+int ga_set_async(ga_run* run, uint32_t max_wavefronts, uint32_t max_lead, uint32_t skew);
+/* Asynchronous runs: how many times so far an island stopped waiting for a
+ * neighbour and went on (0 means every pacing wait was met). Synchronous. */
+int ga_async_waits(ga_run* run, uint64_t* gave_up);
+
 /* Generations per captured HIP graph replay (0 disables graphs). */
 int ga_set_graph_block(ga_run* run, uint32_t gens_per_block);
 

@@ -17,6 +17,8 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_ESTATE = 0, -1, -2, -3, -4
 FORM_AUTO, FORM_STREAMING, FORM_RESIDENT = 0, 1, 2
+SCHEDULE_SYNC, SCHEDULE_ASYNC = 0, 1
+ASYNC_UNPACED = 0xFFFFFFFF
 
 
 class GAError(RuntimeError):
@@ -38,7 +40,7 @@ class Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "struct_size", "width", "height", "pop_per_island", "surface_sites",
         "tournament_size", "selection", "mutation_threshold", "migration", "seed", "run_id",
-        "mutation_law", "beneficial_threshold")]
+        "mutation_law", "beneficial_threshold", "schedule")]
 
 
 class OutboxEntry(ctypes.Structure):
@@ -60,6 +62,8 @@ SIGNATURES = {
     "ga_destroy": (None, [P]),
     "ga_set_launch": (i32, [P, u32, u32, u32]),
     "ga_set_graph_block": (i32, [P, u32]),
+    "ga_set_async": (i32, [P, u32, u32, u32]),
+    "ga_async_waits": (i32, [P, ctypes.POINTER(u64)]),
     "ga_batch_create": (i32, [P, ctypes.POINTER(P)]),
     "ga_batch_add": (i32, [P, P, u64]),
     "ga_batch_remove": (i32, [P, P]),

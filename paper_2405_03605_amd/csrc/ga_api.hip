@@ -36,8 +36,10 @@ int hip_fail(hipError_t e, const char* what) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Size of the configuration before mutation_law / beneficial_threshold.
+// Sizes of earlier configuration layouts: before mutation_law /
+// beneficial_threshold, and before schedule.
 constexpr uint32_t kConfigV1Size = (uint32_t)offsetof(ga_config, mutation_law);
+constexpr uint32_t kConfigV2Size = (uint32_t)offsetof(ga_config, schedule);
 
 bool is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
 uint32_t log2u(uint32_t v) {
@@ -52,7 +54,8 @@ bool config_ok(const ga_config* c, std::string* why) {
     return false;
   };
   if (!c) return no("config is NULL");
-  if (c->struct_size != sizeof(ga_config) && c->struct_size != kConfigV1Size)
+  if (c->struct_size != sizeof(ga_config) && c->struct_size != kConfigV1Size &&
+      c->struct_size != kConfigV2Size)
     return no("struct_size must be sizeof(ga_config)");
   if (c->width < 1 || c->width > 65535) return no("width must be in [1, 65535]");
   if (c->height < 1 || c->height > 65535) return no("height must be in [1, 65535]");
@@ -62,7 +65,9 @@ bool config_ok(const ga_config* c, std::string* why) {
   if (c->tournament_size < 1 || c->tournament_size > 8) return no("tournament_size must be in [1, 8]");
   if (c->selection > 1) return no("selection must be 0 or 1");
   if (c->migration > 1) return no("migration must be 0 or 1");
-  if (c->struct_size == sizeof(ga_config)) {
+  if (c->struct_size == sizeof(ga_config) && c->schedule > GA_SCHEDULE_ASYNC)
+    return no("schedule must be 0 (synchronous) or 1 (asynchronous)");
+  if (c->struct_size >= kConfigV2Size) {
     if (c->mutation_law > 1) return no("mutation_law must be 0 or 1");
     if (c->mutation_law == 1 &&
         (uint64_t)c->beneficial_threshold + c->mutation_threshold > 0xFFFFFFFFull)
@@ -76,7 +81,8 @@ bool config_ok(const ga_config* c, std::string* why) {
 // Byte offsets of every plane inside a run's device buffer.
 struct Layout {
   size_t pop_f, pop_T, pop_D;
-  size_t ob[2];
+  size_t ob[2];     // synchronous schedule
+  size_t mail, seen, prog;  // asynchronous schedule
   size_t counters;  // generation counter, batch budget
   size_t st_ids, st_T, st_D;
   size_t total;
@@ -93,6 +99,10 @@ size_t padded_islands(const ga_config* c) {
   return (islands + 63) / 64 * 64 + 128;
 }
 
+bool is_async(const ga_config* c) {
+  return c->struct_size == sizeof(ga_config) && c->schedule == GA_SCHEDULE_ASYNC;
+}
+
 Layout layout_of(const ga_config* c) {
   const size_t islands = padded_islands(c);
   const size_t agents = islands * c->pop_per_island;
@@ -107,8 +117,16 @@ Layout layout_of(const ga_config* c) {
   L.pop_f = take(agents * 4);
   L.pop_T = take(agents * 4);
   L.pop_D = take(agents * 4 * words);
-  for (int p = 0; p < 2; ++p) L.ob[p] = take(islands * 4 * outbox_stride(c));
-  L.counters = take(16);
+  if (is_async(c)) {
+    // eight buffers per island (direction x parity), four stamps, and one
+    // progress word per possible chunk
+    L.mail = take(islands * 8 * 4 * outbox_stride(c));
+    L.seen = take(islands * 4 * 4);
+    L.prog = take(islands * 4);
+  } else {
+    for (int p = 0; p < 2; ++p) L.ob[p] = take(islands * 4 * outbox_stride(c));
+  }
+  L.counters = take(24);  // generation, batch budget, async give-ups
   L.st_ids = take(islands * 4);
   L.st_T = take(islands * 4);
   L.st_D = take(islands * 4 * words);
@@ -133,6 +151,9 @@ struct ga_run {
   hipGraphExec_t graph = nullptr;
   uint32_t graph_key_ipw = 0, graph_key_wpg = 0, graph_key_block = 0;
   ga_batch* batch = nullptr;
+  uint32_t async_max_waves = 0;  // 0: as many as the GPU holds at once
+  uint32_t async_lead = 0;       // pacing bound (ga::kUnpaced: none)
+  uint32_t async_skew = 0;       // reproducible skewed interleaving (one wavefront)
 };
 
 struct ga_batch {
@@ -240,6 +261,39 @@ int ensure_graph(ga_run* r) {
   return GA_OK;
 }
 
+// Asynchronous schedule: one persistent launch per slice of generations, the
+// chunks spread over as many wavefronts as the GPU holds at once (or over the
+// caller's cap), each wavefront owning consecutive chunks.
+int step_async(ga_run* r, uint64_t n) {
+  ga::RunView v = r->view;
+  v.ipw = r->ipw;
+  const uint32_t chunks = waves_for(r, r->ipw);
+  uint32_t cap = 0;
+  GA_HIP(ga::async_capacity(v, r->wpg, &cap), "occupancy query");
+  uint32_t waves = std::max(1u, std::min(chunks, cap));
+  if (r->async_max_waves) waves = std::min(waves, r->async_max_waves);
+  const uint32_t per_wave = (chunks + waves - 1) / waves;
+  waves = (chunks + per_wave - 1) / per_wave;
+  // bound one launch to about 2^34 agent-generations; with a skew, one call
+  // is one interleaving block, so it is never split
+  const uint64_t slice_max =
+      r->async_skew ? n
+                    : std::max<uint64_t>(1, std::min<uint64_t>(1u << 16,
+                                                               (1ull << 34) / std::max(1u, v.agents)));
+  uint64_t left = n;
+  while (left > 0) {
+    const uint64_t slice = std::min(left, slice_max);
+    // every chunk starts the launch having completed the current generation
+    GA_HIP(ga::launch_fill(v.prog, (uint32_t)r->gen_host, v.island_stride, r->stream), "progress reset");
+    GA_HIP(ga::launch_async(v, slice, waves, per_wave, r->wpg, r->async_lead, r->async_skew,
+                            r->stream), "async launch");
+    GA_HIP(ga::launch_advance(v.gen, slice, r->stream), "advance launch");
+    left -= slice;
+    r->gen_host += slice;
+  }
+  return GA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -275,6 +329,7 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   ga_run* r = new (std::nothrow) ga_run();
   if (!r) return fail(GA_EINVAL, "host allocation failed");
   std::memcpy(&r->cfg, cfg, cfg->struct_size);
+  const bool async = is_async(cfg);
   r->cfg.struct_size = sizeof(ga_config);
   r->lay = lay;
   r->stream = static_cast<hipStream_t>(hip_stream);
@@ -284,10 +339,14 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   v.pop_f = reinterpret_cast<float*>(b + lay.pop_f);
   v.pop_T = reinterpret_cast<uint32_t*>(b + lay.pop_T);
   v.pop_D = reinterpret_cast<uint32_t*>(b + lay.pop_D);
-  for (int p = 0; p < 2; ++p) v.ob[p] = reinterpret_cast<uint32_t*>(b + lay.ob[p]);
+  for (int p = 0; p < 2; ++p) v.ob[p] = async ? nullptr : reinterpret_cast<uint32_t*>(b + lay.ob[p]);
+  v.mail = async ? reinterpret_cast<uint32_t*>(b + lay.mail) : nullptr;
+  v.seen = async ? reinterpret_cast<uint32_t*>(b + lay.seen) : nullptr;
+  v.prog = async ? reinterpret_cast<uint32_t*>(b + lay.prog) : nullptr;
   v.ob_stride = (uint32_t)outbox_stride(cfg);
   v.gen = reinterpret_cast<unsigned long long*>(b + lay.counters);
   v.left = v.gen + 1;
+  v.waits = v.gen + 2;
   v.width = cfg->width;
   v.height = cfg->height;
   v.islands = cfg->width * cfg->height;
@@ -331,11 +390,35 @@ int ga_set_launch(ga_run* r, uint32_t ipw, uint32_t wpg, uint32_t form) {
   if (new_wpg < 1 || new_wpg > (uint32_t)ga::kMaxWavesPerGroup)
     return fail(GA_EINVAL, "waves_per_group must be in [1, 16]");
   if (form > GA_FORM_RESIDENT) return fail(GA_EINVAL, "unknown form");
+  if (form == GA_FORM_RESIDENT && r->cfg.schedule == GA_SCHEDULE_ASYNC)
+    return fail(GA_EINVAL, "the resident form is synchronous");
   if (form == GA_FORM_RESIDENT && waves_for(r, resident_ipw(r)) > (uint32_t)ga::kMaxWavesPerGroup)
     return fail(GA_EINVAL, "run too large for the resident form");
   r->ipw = new_ipw;
   r->wpg = new_wpg;
   r->form = form;
+  return GA_OK;
+}
+
+int ga_set_async(ga_run* r, uint32_t max_wavefronts, uint32_t max_lead, uint32_t skew) {
+  if (!r) return fail(GA_EINVAL, "run is NULL");
+  if (r->cfg.schedule != GA_SCHEDULE_ASYNC) return fail(GA_EINVAL, "run is not asynchronous");
+  if (skew && (max_wavefronts != 1 || max_lead != GA_ASYNC_UNPACED))
+    return fail(GA_EINVAL, "a skewed interleaving needs one wavefront and no pacing");
+  if (skew > 1024) return fail(GA_EINVAL, "skew must be <= 1024");
+  r->async_max_waves = max_wavefronts;
+  r->async_lead = max_lead;
+  r->async_skew = skew;
+  return GA_OK;
+}
+
+int ga_async_waits(ga_run* r, uint64_t* gave_up) {
+  if (!r || !gave_up) return fail(GA_EINVAL, "run or gave_up is NULL");
+  if (r->cfg.schedule != GA_SCHEDULE_ASYNC) return fail(GA_EINVAL, "run is not asynchronous");
+  GA_HIP(hipStreamSynchronize(r->stream), "stream sync");
+  unsigned long long n = 0;
+  GA_HIP(hipMemcpy(&n, r->view.waits, sizeof(n), hipMemcpyDeviceToHost), "read waits");
+  *gave_up = n;
   return GA_OK;
 }
 
@@ -350,6 +433,7 @@ int ga_step(ga_run* r, uint64_t n) {
   if (!r) return fail(GA_EINVAL, "run is NULL");
   if (r->batch) return fail(GA_ESTATE, "run is a batch member; advance it with ga_batch_step");
   if (n == 0) return GA_OK;
+  if (r->cfg.schedule == GA_SCHEDULE_ASYNC) return step_async(r, n);
   if (use_resident(r)) {
     ga::RunView v = r->view;
     v.ipw = resident_ipw(r);
@@ -375,6 +459,8 @@ int ga_step(ga_run* r, uint64_t n) {
 int ga_read_population(ga_run* r, float* fitness, uint32_t* T, uint32_t* surface_words,
                        ga_outbox_entry* outbox, uint64_t* generation) {
   if (!r) return fail(GA_EINVAL, "run is NULL");
+  if (outbox && r->cfg.schedule == GA_SCHEDULE_ASYNC)
+    return fail(GA_EINVAL, "an asynchronous run has no synchronous outbox");
   hipStream_t s = r->batch ? r->batch->stream : r->stream;
   GA_HIP(hipStreamSynchronize(s), "stream sync");
   const ga::RunView& v = r->view;
@@ -422,6 +508,8 @@ int ga_write_population(ga_run* r, const float* fitness, const uint32_t* T,
                         uint64_t generation) {
   if (!r) return fail(GA_EINVAL, "run is NULL");
   if (r->batch) return fail(GA_ESTATE, "run is a batch member");
+  const bool async = r->cfg.schedule == GA_SCHEDULE_ASYNC;
+  if (outbox && async) return fail(GA_EINVAL, "an asynchronous run has no synchronous outbox");
   if (outbox) {
     for (size_t i = 0; i < r->view.islands; ++i)
       if (outbox[i].valid > 1 || outbox[i].dir > 3) return fail(GA_EINVAL, "outbox entry out of range");
@@ -458,6 +546,11 @@ int ga_write_population(ga_run* r, const float* fitness, const uint32_t* T,
       dst[2 + W] = outbox[i].valid ? (ga::kMetaValid | outbox[i].dir) : 0u;
     }
     GA_HIP(hipMemcpyAsync(v.ob[p_new], ob.data(), I * st * 4, h2d, s), "write outbox");
+  } else if (async) {
+    // empty buffers: every stamp reads as already taken at the new generation
+    const uint32_t taken = (uint32_t)(2u * (uint32_t)generation);
+    GA_HIP(ga::launch_fill(v.mail, taken, (size_t)v.island_stride * 8 * st, s), "reset buffers");
+    GA_HIP(ga::launch_fill(v.seen, taken, (size_t)v.island_stride * 4, s), "reset stamps");
   } else if (p_new != p_old) {
     // keep the pending emissions readable at the new generation's parity
     GA_HIP(hipMemcpyAsync(v.ob[p_new], v.ob[p_old], (size_t)v.island_stride * st * 4, d2d, s),
@@ -554,6 +647,8 @@ int ga_batch_set_launch(ga_batch* b, uint32_t ipw, uint32_t wpg) {
 
 int ga_batch_add(ga_batch* b, ga_run* r, uint64_t budget) {
   if (!b || !r) return fail(GA_EINVAL, "batch or run is NULL");
+  if (r->cfg.schedule == GA_SCHEDULE_ASYNC)
+    return fail(GA_EINVAL, "a batch advances synchronous runs only");
   if (r->batch) return fail(GA_ESTATE, "run is already in a batch");
   GA_HIP(hipStreamSynchronize(r->stream), "stream sync");
   unsigned long long left = budget;

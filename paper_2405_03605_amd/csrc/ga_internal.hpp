@@ -35,7 +35,24 @@ struct RunView {
   uint32_t p_ben;            // law 1: beneficial iff draw < p_ben
   uint32_t p_any;            // law 1: deleterious iff p_ben <= draw < p_any
   uint32_t pad;
+  // asynchronous schedule only (NULL otherwise):
+  //   mail[((i * 4 + d) * 2 + p) * ob_stride + k]: island i's buffer toward
+  //     direction d for sending generations of parity p, k as in an outbox
+  //     entry, the header word holding the stamp 2 * (sending generation + 1),
+  //     odd while being rewritten;
+  //   seen[i * 4 + q]: stamp of the last genome island i took from direction q;
+  //   prog[c]: generations chunk c (islands c * ipw ...) has completed, low word;
+  //   waits: how often a wavefront stopped waiting for a neighbour and went on.
+  uint32_t* mail;
+  uint32_t* seen;
+  uint32_t* prog;
+  unsigned long long* waits;
 };
+
+// Asynchronous pacing: no bound on how far an island may run ahead, and the
+// number of progress checks before an island goes on regardless.
+constexpr uint32_t kUnpaced = 0xFFFFFFFFu;
+constexpr uint32_t kPaceSpins = 2048;
 
 // One wavefront's share of a batched launch: islands [first, first + ipw) of run `run`.
 struct Tile {
@@ -51,6 +68,11 @@ constexpr int kMaxWavesPerGroup = 16;
 hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t waves,
                              uint32_t waves_per_group, hipStream_t stream);
 hipError_t launch_resident(const RunView& v, uint64_t n_gens, uint32_t waves, hipStream_t stream);
+hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint32_t chunks,
+                        uint32_t waves_per_group, uint32_t lead, uint32_t skew,
+                        hipStream_t stream);
+// Wavefronts of the async kernel the current device holds at once.
+hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, uint32_t* waves);
 hipError_t launch_advance(unsigned long long* gen, uint64_t n, hipStream_t stream);
 hipError_t launch_fill(uint32_t* p, uint32_t value, size_t words, hipStream_t stream);
 hipError_t launch_sample(const RunView& v, uint32_t* ids, hipStream_t stream);

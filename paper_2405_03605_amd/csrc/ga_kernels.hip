@@ -169,6 +169,26 @@ __device__ __forceinline__ const P* at_byte(const P* base, uint32_t byte_off) {
   return reinterpret_cast<const P*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
+// Word accesses to the asynchronous buffers, which other wavefronts (on any
+// XCD) read and write while this one runs: relaxed atomics at device scope.
+// Each such access is coherent across the XCDs by itself (its scope bits send
+// it past the per-XCD L2's non-coherent state), so ordering two of them only
+// needs the first to have completed before the second issues: drain_memory()
+// waits for every memory access this wavefront has in flight. A device-scope
+// fence would do the same but also write back and invalidate the whole L2 of
+// the XCD, which under thousands of wavefronts streaming the population costs
+// far more than the exchange itself.
+__device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint32_t* p, uint32_t value) {
+  __hip_atomic_store(p, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void drain_memory() {
+  // also a compiler barrier: no memory access moves across it
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 struct Genome {
   float f = 0.f;
   uint32_t T = 0, D0 = 0, D1 = 0;
@@ -190,9 +210,15 @@ __device__ __forceinline__ Genome load_genome(const float* pf, const uint32_t* p
 // from the view. `lds` is this wavefront's table of 5 * ipw + 1 16-byte
 // entries: arrivals [4 * local + q], emissions [4 * ipw + local], and one
 // scratch entry read when a lane has no arrival.
-template <int LC, int SWC>
+// Per-wavefront state of the asynchronous schedule.
+struct AsyncCtx {
+  uint32_t lead;     // how many generations an island may run ahead of a neighbour
+  uint32_t gave_up;  // waits for a neighbour that hit the spin limit
+};
+
+template <int LC, int SWC, bool ASYNC = false>
 __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base, uint64_t t,
-                                                 uint4* lds) {
+                                                 uint4* lds, AsyncCtx* ax = nullptr) {
   const uint32_t L = LC >= 0 ? (uint32_t)LC : v.log2n;
   const uint32_t SW = SWC >= 0 ? (uint32_t)SWC : v.words;
   const uint32_t s_log = 4u + SW;  // log2 S: 5 for 32 sites, 6 for 64
@@ -233,15 +259,99 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   // genome; for 64 sites it is the next word), so the pass pays one memory
   // round trip; only the packed slots say which entries are arrivals.
   uint32_t desc = 0xFFFFFFFFu;  // byte q: slot taken by the arrival from direction q, or 0xFF
+  if constexpr (!ASYNC) {
 #pragma unroll
-  for (uint32_t q = 0; q < 4; ++q) {
-    const uint32_t* e = in_ob + torus_step(ox, oy, q, W, H) * ob_stride;
-    const uint4 entry = *reinterpret_cast<const uint4*>(e);  // f, T, D0, header or D1
-    const uint32_t header = SW == 1 ? entry.w : e[ob_hdr];
-    const bool hit = own_ok && header == (kMetaValid | (q ^ 2u));
-    const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
-    desc = hit ? (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q)) : desc;
-    if (lane < v.ipw) lds[lane * 4u + q] = entry;  // the table holds ipw islands
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t* e = in_ob + torus_step(ox, oy, q, W, H) * ob_stride;
+      const uint4 entry = *reinterpret_cast<const uint4*>(e);  // f, T, D0, header or D1
+      const uint32_t header = SW == 1 ? entry.w : e[ob_hdr];
+      const bool hit = own_ok && header == (kMetaValid | (q ^ 2u));
+      const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
+      desc = hit ? (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q)) : desc;
+      if (lane < v.ipw) lds[lane * 4u + q] = entry;  // the table holds ipw islands
+    }
+  } else {
+    // Asynchronous schedule. The neighbour in direction q keeps two buffers
+    // toward this island (its buffers in direction q ^ 2), one per parity of
+    // the sending generation, each with a stamp word 2 * (sending generation
+    // + 1), odd while being rewritten. A genome is in flight during the
+    // generation it was sent in, so in generation t a buffer is eligible if
+    // its stamp is even, at most 2t, and newer than the last one taken from
+    // that side; the newest eligible buffer is read, and its stamp read again
+    // after the genome: the genome is taken if the two reads agree.
+    uint32_t nb[4];
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) nb[q] = torus_step(ox, oy, q, W, H);
+
+    // Pacing: wait until every neighbouring chunk has completed at least
+    // t - lead generations, checking at most kPaceSpins times, then go on
+    // regardless (the exchange stays valid at any distance, only looser).
+    if (ax->lead != kUnpaced) {
+      uint32_t nbc[4];
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) nbc[q] = nb[q] / v.ipw;
+      for (uint32_t spin = 0;; ++spin) {
+        bool behind = false;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q)
+          behind |= (int32_t)(t_lo - ax->lead - load_agent(v.prog + nbc[q])) > 0;
+        if (__ballot(own_ok && behind) == 0ull) break;
+        if (spin == kPaceSpins) {
+          ++ax->gave_up;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+
+    uint32_t* seen_at = v.seen + own * 4u;
+    const uint4 seen4 = *reinterpret_cast<const uint4*>(seen_at);
+    uint32_t seen_q[4] = {seen4.x, seen4.y, seen4.z, seen4.w};
+    const uint32_t newest_ok = 2u * t_lo;  // stamp of a genome sent in t-1
+    uint32_t* box[4];
+    uint32_t stamp[4];
+    bool ok[4];
+    {
+      uint32_t s0[4], s1[4];
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        box[q] = v.mail + (nb[q] * 4u + (q ^ 2u)) * 2u * ob_stride;
+        s0[q] = load_agent(box[q] + ob_hdr);
+        s1[q] = load_agent(box[q] + ob_stride + ob_hdr);
+      }
+      drain_memory();
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        const bool e0 = (s0[q] & 1u) == 0u && (int32_t)(newest_ok - s0[q]) >= 0 &&
+                        (int32_t)(s0[q] - seen_q[q]) > 0;
+        const bool e1 = (s1[q] & 1u) == 0u && (int32_t)(newest_ok - s1[q]) >= 0 &&
+                        (int32_t)(s1[q] - seen_q[q]) > 0;
+        const bool take1 = e1 && (!e0 || (int32_t)(s1[q] - s0[q]) > 0);
+        ok[q] = e0 || e1;
+        stamp[q] = take1 ? s1[q] : s0[q];
+        box[q] += take1 ? ob_stride : 0u;
+      }
+    }
+    uint4 pay[4];
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      pay[q].x = load_agent(box[q]);
+      pay[q].y = load_agent(box[q] + 1);
+      pay[q].z = load_agent(box[q] + 2);
+      pay[q].w = SW > 1 ? load_agent(box[q] + 3) : 0u;
+    }
+    drain_memory();
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t again = load_agent(box[q] + ob_hdr);
+      const bool hit = own_ok && ok[q] && again == stamp[q];
+      seen_q[q] = hit ? stamp[q] : seen_q[q];
+      const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
+      desc = hit ? (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q)) : desc;
+      if (lane < v.ipw) lds[lane * 4u + q] = pay[q];
+    }
+    if (own_ok)
+      *reinterpret_cast<uint4*>(seen_at) = make_uint4(seen_q[0], seen_q[1], seen_q[2], seen_q[3]);
   }
   // emission: slot and header of what this island sends; the lane holding the
   // post-absorb member in that slot parks it in the LDS table during its
@@ -375,7 +485,30 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  if (own_ok) {
+  if constexpr (ASYNC) {
+    // publish into this island's buffer toward the drawn direction for this
+    // generation's parity: odd stamp, genome, even stamp, each step complete
+    // before the next issues; then the chunk's progress
+    const uint32_t hdr = emit >> 8;
+    const bool sending = own_ok && hdr != 0u;
+    uint32_t* box = v.mail + ((own * 4u + (hdr & 3u)) * 2u + (t_lo & 1u)) * ob_stride;
+    const uint32_t stamp = 2u * (t_lo + 1u);
+    if (sending) store_agent(box + ob_hdr, stamp - 1u);
+    drain_memory();
+    if (sending) {
+      const uint4 g = lds[emit_base + lane];
+      store_agent(box, g.x);
+      store_agent(box + 1, g.y);
+      store_agent(box + 2, g.z);
+      if (SW > 1) store_agent(box + 3, g.w);
+    }
+    drain_memory();
+    if (sending) store_agent(box + ob_hdr, stamp);
+    // complete before this wavefront's next chunk reads the buffers, and
+    // before the progress word says the generation is done
+    drain_memory();
+    if (lane == 0u) store_agent(v.prog + base / v.ipw, t_lo + 1u);
+  } else if (own_ok) {
     uint32_t* e = out_ob + own * ob_stride;
     const uint32_t hdr = emit >> 8;
     if (hdr) {
@@ -422,6 +555,46 @@ __global__ __launch_bounds__(1024) void resident_kernel(RunView v, uint64_t n_ge
     __syncthreads();
   }
   if (threadIdx.x == 0) *v.gen = t0 + n_gens;
+}
+
+// Asynchronous schedule: each wavefront owns `chunks` consecutive chunks and
+// runs n_gens generations over them with no barrier with any other wavefront;
+// islands exchange genomes only through the stamped per-neighbour buffers,
+// and an island waits (a bounded number of times) only while a neighbour is
+// more than `lead` generations behind. Every wait ends, so the kernel ends
+// however the wavefronts are scheduled; the grid is sized to the wavefronts
+// the GPU holds at once, so all islands advance together.
+// skew > 0 (one wavefront only): chunk c runs its generation g at step
+// g + (c mod (skew + 1)), a reproducible interleaving with neighbours up to
+// skew generations apart.
+// eight wavefronts per SIMD: registers (scalar ones included) must fit, or the
+// occupancy query would promise more resident wavefronts than the GPU holds
+template <int LC, int SWC>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, uint32_t skew) {
+  const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wig;
+  const uint32_t first = wave * chunks * v.ipw;
+  if (first >= v.islands) return;
+  const uint32_t end = min(first + chunks * v.ipw, v.islands);
+  const uint64_t t0 = *v.gen;
+  uint4* lds = wave_lds(wig, v.ipw);
+  AsyncCtx ax{lead, 0u};
+  for (uint64_t step = 0; step < n_gens + skew; ++step) {
+    for (uint32_t base = first; base < end; base += v.ipw) {
+      const uint64_t lag = skew ? (base / v.ipw) % (skew + 1u) : 0u;
+      if (step < lag || step - lag >= n_gens) continue;
+      chunk_generation<LC, SWC, true>(v, base, t0 + step - lag, lds, &ax);
+    }
+  }
+  if (__lane_id() == 0u && ax.gave_up)
+    __hip_atomic_fetch_add(v.waits, (unsigned long long)ax.gave_up, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int LC, int SWC>
+hipError_t async_occupancy(int* groups, int block, size_t lds) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, async_kernel<LC, SWC>, block, lds);
 }
 
 __global__ void advance_kernel(unsigned long long* gen, uint64_t n) {
@@ -546,6 +719,31 @@ hipError_t launch_resident(const RunView& v, uint64_t n_gens, uint32_t waves, hi
   const size_t lds = lds_bytes(v.ipw, waves);
   GA_DISPATCH(resident_kernel, v.log2n, v.words, <<<grid, block, lds, stream>>>(v, n_gens));
   return hipGetLastError();
+}
+
+hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint32_t chunks,
+                        uint32_t waves_per_group, uint32_t lead, uint32_t skew,
+                        hipStream_t stream) {
+  if (waves == 0 || n_gens == 0) return hipSuccess;
+  const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
+  const dim3 grid(groups), block(64 * waves_per_group);
+  const size_t lds = lds_bytes(v.ipw, waves_per_group);
+  GA_DISPATCH(async_kernel, v.log2n, v.words,
+              <<<grid, block, lds, stream>>>(v, chunks, n_gens, lead, skew));
+  return hipGetLastError();
+}
+
+hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, uint32_t* waves) {
+  int device = 0, cus = 0, groups = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return e;
+  const int block = 64 * (int)waves_per_group;
+  const size_t lds = lds_bytes(v.ipw, waves_per_group);
+  GA_DISPATCH(e = async_occupancy, v.log2n, v.words, (&groups, block, lds));
+  if (e != hipSuccess) return e;
+  *waves = (uint32_t)groups * (uint32_t)cus * waves_per_group;
+  return hipSuccess;
 }
 
 hipError_t launch_advance(unsigned long long* gen, uint64_t n, hipStream_t stream) {

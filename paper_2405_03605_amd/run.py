@@ -10,8 +10,8 @@ import numpy as np
 from ._lib import (FORM_AUTO, GA_EINVAL, Config, GAError, OutboxEntry, check, load)
 
 CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32", "migration",
-                 "seed", "run_id", "law", "p_ben32")
-OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0}
+                 "seed", "run_id", "law", "p_ben32", "schedule")
+OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "schedule": 0}
 
 
 def _fields(cfg: dict) -> dict:
@@ -29,7 +29,8 @@ def make_config(cfg: dict) -> Config:
                   tournament_size=cfg["k"], selection=cfg["selection"],
                   mutation_threshold=cfg["p32"], migration=cfg["migration"],
                   seed=cfg["seed"], run_id=cfg["run_id"],
-                  mutation_law=cfg.get("law", 0), beneficial_threshold=cfg.get("p_ben32", 0))
+                  mutation_law=cfg.get("law", 0), beneficial_threshold=cfg.get("p_ben32", 0),
+                  schedule=cfg.get("schedule", 0))
 
 
 def state_bytes(cfg: dict) -> int:
@@ -90,7 +91,25 @@ class GARun:
     def set_graph_block(self, gens: int):
         check(load().ga_set_graph_block(self._h, gens))
 
+    def set_async(self, max_wavefronts: int = 0, max_lead: int = 0, skew: int = 0):
+        """Asynchronous runs: cap on wavefronts (0 = fill the GPU), how many
+        generations an island may lead a neighbour (ASYNC_UNPACED = no bound),
+        and a reproducible skewed interleaving (one wavefront, unpaced)."""
+        check(load().ga_set_async(self._h, int(max_wavefronts), int(max_lead), int(skew)))
+
+    def async_waits(self) -> int:
+        """How many pacing waits gave up so far (0: every wait was met)."""
+        n = ctypes.c_uint64()
+        check(load().ga_async_waits(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    @property
+    def asynchronous(self) -> bool:
+        return self.cfg["schedule"] == 1
+
     def read(self, outbox: bool = True) -> dict:
+        """Population, generation and (synchronous runs) the pending outbox."""
+        outbox = outbox and not self.asynchronous
         A, I, W = self.agents, self.islands, self.words
         f = np.empty(A, dtype=np.float32)
         T = np.empty(A, dtype=np.uint32)

@@ -39,16 +39,22 @@ def test_state_bytes_layout(lib):
     # SoA planes: fitness, T, surface words per agent; 2 AoS outboxes of
     # (fitness, T, surface words, header) per island; counters; extraction staging.
     # Planes are padded to roundup(islands, 64) + 128 islands.
+    # The asynchronous schedule has eight buffers (direction x parity), four
+    # stamps and a progress word per island instead of the two outboxes.
     def expect(c):
         I = (c["width"] * c["height"] + 63) // 64 * 64 + 128
         A = I * c["pop"]
         W = c["sites"] // 32
         al = lambda b: (b + 255) // 256 * 256
         ob = 4 if W == 1 else 8   # AoS outbox entry words
-        return (al(4 * A) * 2 + al(4 * A * W) + 2 * al(4 * I * ob) + 256
+        exchange = ((al(4 * 8 * I * ob) + al(4 * 4 * I) + al(4 * I)) if c.get("schedule")
+                    else 2 * al(4 * I * ob))
+        return (al(4 * A) * 2 + al(4 * A * W) + exchange + 256
                 + 2 * al(4 * I) + al(4 * I * W))
     for c in (TINY, MID, PAPER, run_config(width=3, height=5, pop=1, sites=32)):
         assert ga.state_bytes(c) == expect(c)
+        a = dict(c, schedule=1)
+        assert ga.state_bytes(a) == expect(a) > ga.state_bytes(c)
     # paper-scale run: 16.8M agents, 12 B each
     assert 200e6 < ga.state_bytes(PAPER) < 230e6
 
@@ -57,7 +63,7 @@ def test_state_bytes_layout(lib):
     dict(pop=24), dict(pop=128), dict(pop=0), dict(sites=48), dict(sites=16), dict(k=0),
     dict(k=9), dict(width=0), dict(height=0), dict(width=70000), dict(selection=2),
     dict(migration=3), dict(width=65535, height=65535, pop=64), dict(width=65535, height=8193, pop=2),
-    dict(law=2), dict(law=1, p32=2 ** 32 - 10, p_ben32=100)])
+    dict(law=2), dict(law=1, p32=2 ** 32 - 10, p_ben32=100), dict(schedule=2)])
 def test_invalid_configs_rejected(lib, bad):
     c = make_config(run_config(**bad))
     assert lib.ga_state_bytes(ctypes.byref(c)) == 0
@@ -99,4 +105,10 @@ def test_first_release_config_size_accepted(lib):
     c = make_config(run_config(law=1, p_ben32=5))
     full = lib.ga_state_bytes(ct.byref(c))
     c.struct_size = _lib.Config.mutation_law.offset     # size before the treatment fields
+    assert lib.ga_state_bytes(ct.byref(c)) == full
+    # size before the schedule field: synchronous, whatever the field would say
+    c = make_config(run_config(law=1, p_ben32=5, schedule=1))
+    c.struct_size = _lib.Config.schedule.offset
+    assert lib.ga_state_bytes(ct.byref(c)) == full
+    c.schedule = 7                                      # not read at that size
     assert lib.ga_state_bytes(ct.byref(c)) == full

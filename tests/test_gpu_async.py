@@ -1,0 +1,249 @@
+"""GPU checks of the asynchronous schedule (Sec. 2 Methods: per-neighbour
+buffers consumed and refilled without a global step).
+
+Bit for bit against the oracle: the one-wavefront launch (the sequential
+interleaving of chunks) for many shapes and chunk sizes, resume, and the cases
+that reduce to the synchronous schedule (migration off; every island in one
+chunk). The free-running launch is not reproducible; it is checked for
+invariants every interleaving keeps and, statistically, against the
+synchronous schedule and a no-migration control."""
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from gpu_helpers import assert_same_state, oracle_after, say
+from paper_2405_03605_amd import ASYNC_UNPACED, GABatch, GARun, GAError
+from paper_2405_03605_amd import phylo
+from paper_2405_03605_amd.workloads import run_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _async(**kw):
+    return run_config(schedule=1, **kw)
+
+
+def _oracle_cfg(cfg):
+    return {k: v for k, v in cfg.items() if k != "schedule"}
+
+
+ONE_WAVE = [
+    (dict(), 2, 0),
+    (dict(), 16, 3),
+    (dict(), 64, 0),
+    (dict(width=5, height=3, pop=8, sites=32, k=5), 8, 1),
+    (dict(width=13, height=11, pop=8, sites=32, k=5), 16, 2),
+    (dict(width=1, height=9, pop=4, selection=0), 16, 0),
+    (dict(width=33, height=1, pop=16, law=1, p_ben32=12884902, p32=1417339207, k=5), 4, 5),
+    (dict(width=20, height=10, pop=1, sites=32), 64, 1),
+    (dict(width=9, height=7, pop=64, k=8), 1, 7),
+    (dict(width=9, height=7, pop=64, k=8, sites=32), 3, 2),
+    (dict(width=2, height=2, pop=32, p32=0xFFFFFFFF), 2, 1),
+    (dict(width=17, height=9, pop=32, seed=777, run_id=5), 6, 4),
+]
+
+
+@pytest.mark.parametrize("kw,ipw,skew", ONE_WAVE)
+def test_one_wavefront_is_the_oracle_interleaving(kw, ipw, skew):
+    # One wavefront runs the chunks in order; with a skew it runs the
+    # oracle's skewed interleaving (genomes late or overwritten), without one
+    # (paced, as by default) the synchronous schedule.
+    cfg = _async(**kw)
+    say(f"async one wavefront {kw} ipw {ipw} skew {skew}")
+    run = GARun(cfg)
+    run.set_launch(ipw)
+    run.set_async(1, ASYNC_UNPACED if skew else 0, skew)
+    ref = oracle.OracleRun(_oracle_cfg(cfg))
+    for n in (1, 40, 59):
+        run.step(n)
+        ref.step_async(n, ipw, skew)
+    got = run.read()
+    assert run.async_waits() == 0
+    run.close()
+    assert "outbox" not in got
+    assert_same_state(got, ref, f"async one wavefront {kw} ipw {ipw} skew {skew}")
+    if not skew:
+        assert_same_state(got, oracle_after(_oracle_cfg(cfg), 100), "equals synchronous")
+
+
+def test_long_skewed_run_and_resume():
+    cfg = _async(width=12, height=8, pop=32, sites=64, k=5)
+    say("async skewed 12x8x32, 1500 generations with a resume")
+    run = GARun(cfg)
+    run.set_launch(16)
+    run.set_async(1, ASYNC_UNPACED, 2)
+    run.step(700)
+    mid = run.read()
+    ref = oracle.OracleRun(_oracle_cfg(cfg))
+    ref.step_async(700, 16, 2)
+    assert_same_state(mid, ref, "async at 700")
+    # resume into a fresh run from the population alone: buffers start empty
+    run2 = GARun(cfg)
+    run2.set_launch(16)
+    run2.set_async(1, ASYNC_UNPACED, 2)
+    run2.write(mid["f"], mid["T"], mid["D"], generation=700)
+    run2.step(800)
+    ref.clear_mailboxes()
+    ref.step_async(800, 16, 2)
+    assert_same_state(run2.read(), ref, "async resumed at 1500")
+    run.close()
+    run2.close()
+
+
+@pytest.mark.parametrize("kw,gens", [(dict(width=64, height=64, pop=32, sites=64, k=5), 1000),
+                                     (dict(width=100, height=37, pop=8, sites=32, k=3), 800),
+                                     (dict(width=256, height=256, pop=32, sites=32), 200)])
+def test_paced_free_running_is_synchronous(kw, gens):
+    # Default pacing: an island starts generation t only once its neighbours
+    # have finished t-1, and takes only genomes sent before t, so with no
+    # barrier across the grid the result is the synchronous schedule's.
+    cfg = _async(**kw)
+    say(f"async paced free-running {kw}, {gens} generations")
+    run = GARun(cfg)
+    run.step(gens // 2)
+    run.step(gens - gens // 2)
+    got = run.read()
+    waits = run.async_waits()
+    run.close()
+    assert waits == 0, f"{waits} pacing waits gave up"
+    assert_same_state(got, oracle_after(_oracle_cfg(cfg), gens), f"async paced {kw}")
+
+
+@pytest.mark.parametrize("kw", [dict(width=64, height=64, pop=32, sites=32),
+                                dict(width=100, height=37, pop=8, sites=64, k=5)])
+def test_unpaced_without_migration_is_synchronous(kw):
+    cfg = _async(migration=0, **kw)
+    say(f"async unpaced, no migration {kw}")
+    run = GARun(cfg)
+    run.set_async(0, ASYNC_UNPACED)
+    run.step(300)
+    got = run.read()
+    run.close()
+    assert_same_state(got, oracle_after(_oracle_cfg(cfg), 300), f"async no migration {kw}")
+
+
+@pytest.mark.parametrize("lead", [ASYNC_UNPACED, 3])
+def test_free_running_invariants(lead):
+    # Until T reaches S every deposit fills a fresh site (rank r at site r), so a
+    # genome with T deposits has no bit set at sites T..S-1: a genome read torn
+    # between two buffer contents would likely break that. Fitness under the
+    # discrete law stays a multiple of 1/2. A genome is taken only after the
+    # generation it was sent in, so T never exceeds the generation, even when
+    # it comes from a neighbour that is further along.
+    cfg = _async(width=256, height=128, pop=32, sites=64, p32=2 ** 31)
+    say(f"async free-running invariants 256x128x32, lead {lead}, 60 generations x 5")
+    run = GARun(cfg)
+    run.set_async(0, lead)
+    for rep in range(5):
+        run.step(12)
+        got = run.read()
+        t = got["generation"]
+        T = got["T"].astype(np.uint64)
+        assert (T >= 1).all() and (T <= t).all()
+        bits = got["D"][:, 0].astype(np.uint64) | (got["D"][:, 1].astype(np.uint64) << np.uint64(32))
+        above = np.where(T < 64, bits >> T, np.uint64(0))
+        assert (above == 0).all(), f"surface bits above T at {np.flatnonzero(above)[:5]}"
+        twice = got["f"] * 2
+        assert np.array_equal(twice, np.round(twice))
+    run.close()
+
+
+def test_async_errors():
+    cfg = _async(width=8, height=8)
+    run = GARun(cfg)
+    from paper_2405_03605_amd import _lib
+    import ctypes
+    lib = _lib.load()
+    box = (_lib.OutboxEntry * run.islands)()
+    assert lib.ga_read_population(run.handle, None, None, None,
+                                  ctypes.cast(box, ctypes.c_void_p), None) == _lib.GA_EINVAL
+    with pytest.raises(GAError):
+        run.set_launch(16, 4, 2)          # resident form is synchronous
+    batch = GABatch()
+    with pytest.raises(GAError):
+        batch.add(run, 10)
+    batch.close()
+    with pytest.raises(GAError):
+        run.set_async(2, ASYNC_UNPACED, 3)   # a skew needs one wavefront
+    with pytest.raises(GAError):
+        run.set_async(1, 0, 3)               # ... and no pacing
+    sync = GARun(run_config(width=8, height=8))
+    with pytest.raises(GAError):
+        sync.set_async(1)
+    with pytest.raises(GAError):
+        sync.async_waits()
+    sync.close()
+    run.close()
+
+
+# --------------------------------------------------------------------------
+# statistics of the free-running schedule
+# --------------------------------------------------------------------------
+STAT_CFG = dict(width=64, height=64, pop=32, sites=64, k=5, p32=429496729)
+STAT_GENS = 1500
+STAT_REPS = 10
+
+
+def _run_stats(schedule, migration, seed, lead=0):
+    cfg = run_config(schedule=schedule, migration=migration, seed=seed, run_id=seed * 7, **STAT_CFG)
+    run = GARun(cfg)
+    if schedule:
+        run.set_async(0, lead)
+    run.step(STAT_GENS)
+    f = run.read(outbox=False)["f"]
+    ids, T, D = run.extract()
+    run.close()
+    L, U = phylo.mrca_matrix(T, D, 64)
+    W = STAT_CFG["width"]
+    isl = np.arange(W * STAT_CFG["height"])
+    east = (isl // W) * W + (isl % W + 1) % W
+    far = (isl // W) * W + (isl % W + W // 2) % W
+
+    def depth(j):
+        mid = (L[isl, j].astype(np.float64) + U[isl, j]) / 2
+        return float(np.mean(np.minimum(T[isl], T[j]) - mid))
+    return {"mean_fitness": float(f.mean()), "depth_adjacent": depth(east),
+            "depth_far": depth(far)}
+
+
+def test_loosely_paced_statistics_match_synchronous():
+    # With islands allowed a few generations apart, genomes arrive late or are
+    # overwritten, so the run is a different random process; its statistics
+    # are compared by effect size: the shift from the synchronous schedule must
+    # be a small fraction of what migration itself changes (synchronous against
+    # a no-migration control), or within three standard errors where that
+    # effect is small next to the noise. KS p-values and the unpaced
+    # schedule's shift are reported.
+    say(f"async vs sync statistics, {STAT_REPS} replicates of 64x64x32 x {STAT_GENS} generations")
+    sync = [_run_stats(0, 1, 1000 + r) for r in range(STAT_REPS)]
+    loose = [_run_stats(1, 1, 2000 + r, lead=2) for r in range(STAT_REPS)]
+    unpaced = [_run_stats(1, 1, 3000 + r, lead=ASYNC_UNPACED) for r in range(STAT_REPS // 2)]
+    control = [_run_stats(0, 0, 900 + r) for r in range(2)]
+    for key in ("mean_fitness", "depth_adjacent", "depth_far"):
+        a = np.array([r[key] for r in sync])
+        b = np.array([r[key] for r in loose])
+        u = np.array([r[key] for r in unpaced])
+        c = np.mean([r[key] for r in control])
+        effect = abs(a.mean() - c)
+        rel = abs(b.mean() - a.mean()) / effect
+        say(f"{key}: sync {a.mean():.3f} +- {a.std():.3f}, lead 2 {b.mean():.3f} +- {b.std():.3f} "
+            f"(shift {rel:.3f} of the migration effect, KS p {stats.ks_2samp(a, b).pvalue:.3g}), "
+            f"unpaced {u.mean():.3f} (shift {abs(u.mean() - a.mean()) / effect:.3f}), "
+            f"no migration {c:.3f}")
+        se = np.sqrt(a.var(ddof=1) / a.size + b.var(ddof=1) / b.size)
+        assert rel < 0.25 or abs(b.mean() - a.mean()) < 3 * se, key
+    # the statistics have power: without migration, neighbouring islands share
+    # no recent ancestor at all
+    adj = np.array([r["depth_adjacent"] for r in sync + loose])
+    assert min(r["depth_adjacent"] for r in control) > adj.max() * 2
