@@ -9,6 +9,11 @@ resident in HBM before timing starts. Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--batched-gens G]
                   [--no-cpu-baseline] [--no-batched]
+                  [--schedule async [--max-lead N|unpaced]]
+
+The default is the synchronous schedule. --schedule async times the
+barrier-free asynchronous schedule on the same workload instead (and adds the
+freshness of the exchanged genomes to the line).
 """
 from __future__ import annotations
 
@@ -62,9 +67,13 @@ def bench_single(args, torch):
     from paper_2405_03605_amd.workloads import PAPER
 
     cfg = dict(PAPER)
+    if args.schedule == "async":
+        cfg["schedule"] = 1
     run = GARun(cfg)
     if args.ipw or args.wpg:
         run.set_launch(args.ipw, args.wpg)
+    if args.schedule == "async":
+        run.set_async(0, args.max_lead)
     if args.graph_block is not None:
         run.set_graph_block(args.graph_block)
     stream = torch.cuda.current_stream()
@@ -81,8 +90,16 @@ def bench_single(args, torch):
     ev_ms = ev0.elapsed_time(ev1)
     gen = run.read(outbox=False)["generation"]
     assert gen == args.warmup + args.steps, (gen, args.warmup, args.steps)
+    extra = None
+    if args.schedule == "async":
+        import numpy as np
+        age = gen - 1 - run.async_last_taken()
+        extra = {"max_lead": "unpaced" if args.max_lead == 0xFFFFFFFF else args.max_lead,
+                 "waits_given_up": run.async_waits(),
+                 "last_taken_age_p50_p99_max": [float(np.percentile(age, 50)),
+                                                float(np.percentile(age, 99)), int(age.max())]}
     run.close()
-    return cfg, wall, ev_ms
+    return cfg, wall, ev_ms, extra
 
 
 def bench_batched(gens: int, torch):
@@ -181,7 +198,11 @@ def main():
     ap.add_argument("--wpg", type=int, default=0, help="wavefronts per workgroup (0: default)")
     ap.add_argument("--graph-block", type=int, default=None,
                     help="generations per HIP graph replay (default 100; 0 disables)")
+    ap.add_argument("--schedule", choices=("sync", "async"), default="sync")
+    ap.add_argument("--max-lead", default="0",
+                    help="async: generations an island may lead a neighbour, or 'unpaced'")
     args = ap.parse_args()
+    args.max_lead = 0xFFFFFFFF if args.max_lead == "unpaced" else int(args.max_lead)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the island grid "
               "would shard as 2D tiles with a per-generation halo exchange, which this "
@@ -193,7 +214,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
 
-    cfg, wall, ev_ms = bench_single(args, torch)
+    cfg, wall, ev_ms, async_info = bench_single(args, torch)
     agents = cfg["width"] * cfg["height"] * cfg["pop"]
     value = agents * args.steps / wall
     kernel_s = ev_ms * 1e-3 / args.steps
@@ -204,6 +225,11 @@ def main():
                 "traffic": measured_traffic(),
                 "kernel": "generation_kernel<5,1>", "bytes_per_launch": bytes_gen,
                 "launch_us": round(kernel_s * 1e6, 2)}
+    if async_info is not None:
+        # one persistent launch covers many generations: per-generation figures
+        roofline.update({"kernel": "async_kernel<5,1>", "traffic": None,
+                         "bytes_per_launch": None, "bytes_per_generation": bytes_gen,
+                         "launch_us": None, "us_per_generation": round(kernel_s * 1e6, 2)})
     out = {"metric": "agent-generations/sec at 16.8M agents; batched vs plain throughput",
            "value": value, "unit": "agent-generations/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
@@ -212,8 +238,10 @@ def main():
            "config": {"workload": "island GA 1024x512 islands x 32 agents (16.8M), 32-site "
                                   "surface, tournament 2, mutation p=0.1, migration 1/island/gen",
                       "islands": cfg["width"] * cfg["height"], "agents": agents,
-                      "step": "one generation"},
+                      "step": "one generation", "schedule": args.schedule},
            "roofline": roofline}
+    if async_info is not None:
+        out["async"] = async_info
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_gens, torch)
         if args.served_requests > 0:

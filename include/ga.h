@@ -208,6 +208,12 @@ int ga_set_async(ga_run* run, uint32_t max_wavefronts, uint32_t max_lead, uint32
 /* Asynchronous runs: how many times so far an island stopped waiting for a
  * neighbour and went on (0 means every pacing wait was met). Synchronous. */
 int ga_async_waits(ga_run* run, uint64_t* gave_up);
+/* Asynchronous runs: for island i and direction q, sent[i*4 + q] receives the
+ * generation in which the last genome island i took from that side was sent
+ * (t - 1 where t is the generation of the run or of the last
+ * ga_write_population if it took none since; -1 at the start). The gap to
+ * the current generation shows how fresh the exchange is. Synchronous. */
+int ga_async_last_taken(ga_run* run, int64_t* sent);
 
 /* Generations per captured HIP graph replay (0 disables graphs). */
 int ga_set_graph_block(ga_run* run, uint32_t gens_per_block);

@@ -412,6 +412,24 @@ int ga_set_async(ga_run* r, uint32_t max_wavefronts, uint32_t max_lead, uint32_t
   return GA_OK;
 }
 
+int ga_async_last_taken(ga_run* r, int64_t* sent) {
+  if (!r || !sent) return fail(GA_EINVAL, "run or sent is NULL");
+  if (r->cfg.schedule != GA_SCHEDULE_ASYNC) return fail(GA_EINVAL, "run is not asynchronous");
+  GA_HIP(hipStreamSynchronize(r->stream), "stream sync");
+  const size_t I = r->view.islands;
+  std::vector<uint32_t> stamps(I * 4);
+  unsigned long long t = 0;
+  GA_HIP(hipMemcpy(&t, r->view.gen, sizeof(t), hipMemcpyDeviceToHost), "read generation");
+  GA_HIP(hipMemcpy(stamps.data(), r->view.seen, I * 16, hipMemcpyDeviceToHost), "read stamps");
+  // stamp = 2 * (sending generation + 1) mod 2^32; a taken genome was sent
+  // less than 2^31 generations before t
+  for (size_t k = 0; k < I * 4; ++k) {
+    const uint32_t back = (uint32_t)(2u * (uint32_t)t) - stamps[k];
+    sent[k] = (int64_t)t - 1 - (int64_t)(back / 2u);
+  }
+  return GA_OK;
+}
+
 int ga_async_waits(ga_run* r, uint64_t* gave_up) {
   if (!r || !gave_up) return fail(GA_EINVAL, "run or gave_up is NULL");
   if (r->cfg.schedule != GA_SCHEDULE_ASYNC) return fail(GA_EINVAL, "run is not asynchronous");

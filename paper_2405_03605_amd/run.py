@@ -97,6 +97,13 @@ class GARun:
         and a reproducible skewed interleaving (one wavefront, unpaced)."""
         check(load().ga_set_async(self._h, int(max_wavefronts), int(max_lead), int(skew)))
 
+    def async_last_taken(self) -> np.ndarray:
+        """(islands, 4): generation in which the last genome each island took
+        from each side was sent (-1: none yet)."""
+        out = np.empty((self.islands, 4), dtype=np.int64)
+        check(load().ga_async_last_taken(self._h, _ptr(out)))
+        return out
+
     def async_waits(self) -> int:
         """How many pacing waits gave up so far (0: every wait was met)."""
         n = ctypes.c_uint64()

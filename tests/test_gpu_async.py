@@ -120,6 +120,32 @@ def test_paced_free_running_is_synchronous(kw, gens):
     assert_same_state(got, oracle_after(_oracle_cfg(cfg), gens), f"async paced {kw}")
 
 
+def test_paced_last_taken_follows_the_migration_draws():
+    # Equal to the synchronous schedule, the last genome island i took from
+    # side q was sent in the last generation g <= t-2 in which the neighbour
+    # there drew the direction toward i (Philox MIGRATE stream, computed here).
+    cfg = _async(width=32, height=24, pop=16, sites=32)
+    t = 150
+    say("async paced last-taken generations 32x24x16")
+    run = GARun(cfg)
+    run.step(t)
+    got = run.async_last_taken()
+    assert run.async_waits() == 0
+    run.close()
+    W, H = cfg["width"], cfg["height"]
+    I = W * H
+    key = [cfg["seed"], cfg["run_id"]]
+    dirs = np.array([[int(oracle.philox([0, i, g, 1], key)[1] >> 30) for g in range(t - 1)]
+                     for i in range(I)])
+    for i in range(I):
+        x, y = i % W, i // W
+        nbrs = [((y - 1) % H) * W + x, y * W + (x + 1) % W, ((y + 1) % H) * W + x,
+                y * W + (x - 1) % W]
+        for q, j in enumerate(nbrs):
+            sent = np.nonzero(dirs[j] == (q ^ 2))[0]
+            assert got[i, q] == (sent[-1] if sent.size else -1), (i, q)
+
+
 @pytest.mark.parametrize("kw", [dict(width=64, height=64, pop=32, sites=32),
                                 dict(width=100, height=37, pop=8, sites=64, k=5)])
 def test_unpaced_without_migration_is_synchronous(kw):
