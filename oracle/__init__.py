@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
 class _Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "width", "height", "pop", "sites", "k", "selection", "p32", "migration",
-        "seed", "run_id", "law", "p_ben32")]
+        "seed", "run_id", "law", "p_ben32", "model")]
 
 
 _lib = None
@@ -91,6 +91,10 @@ def _load():
     lib.orc_true_mrca_matrix.argtypes = [P, P, sz, P]
     lib.orc_true_mrca_matrix.restype = ctypes.c_int
     lib.orc_mrca_interval_matrix.argtypes = [P, P, sz, u32, u32, P, P]
+    lib.orc_get_payload.argtypes = [P, P]
+    lib.orc_set_payload.argtypes = [P, P]
+    lib.orc_evaluate.argtypes = [u32, u32, u32]
+    lib.orc_evaluate.restype = ctypes.c_float
     _lib = lib
     return lib
 
@@ -106,6 +110,11 @@ def philox(ctr, key) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
     _load().orc_philox(_ptr(c), _ptr(k), _ptr(out))
     return out
+
+
+def evaluate(model: int, p0: int, p1: int) -> float:
+    """Fitness genome model 1 (OneMax) or 2 (Trap-4) gives the 64-bit string (p0, p1)."""
+    return float(_load().orc_evaluate(model, p0, p1))
 
 
 def site_of(rank: int, sites: int) -> int:
@@ -146,8 +155,8 @@ def mrca_interval_matrix(T, D, sites: int, kc: int = 5):
 
 
 CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32",
-                 "migration", "seed", "run_id", "law", "p_ben32")
-OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0}
+                 "migration", "seed", "run_id", "law", "p_ben32", "model")
+OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "model": 0}
 
 
 def _fields(cfg: dict) -> dict:
@@ -222,6 +231,16 @@ class OracleRun:
         sh = (self.islands, 4, 2)
         return {"stamp": stamp.reshape(sh), "seen": seen.reshape(self.islands, 4),
                 "f": f.reshape(sh), "T": T.reshape(sh), "D": D.reshape(sh + (self.words,))}
+
+    def payload(self) -> np.ndarray:
+        """Genome strings of models 1 and 2, shape (agents, 2) uint32."""
+        P = np.empty((self.agents, 2), dtype=np.uint32)
+        _load().orc_get_payload(self._h, _ptr(P))
+        return P
+
+    def set_payload(self, P):
+        a = np.ascontiguousarray(P, dtype=np.uint32).reshape(self.agents, 2)
+        _load().orc_set_payload(self._h, _ptr(a))
 
     def population(self):
         f = np.empty(self.agents, dtype=np.float32)

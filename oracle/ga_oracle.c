@@ -138,6 +138,7 @@ typedef struct outbox_entry {
   float f;
   uint32_t T;
   uint32_t D[2];
+  uint32_t P[2];       /* genome payload (bitstring models) */
 } outbox_entry;
 
 /* One emigration buffer of the asynchronous schedule: the latest genome an
@@ -148,6 +149,7 @@ typedef struct mail_entry {
   float f;
   uint32_t T;
   uint32_t D[2];
+  uint32_t P[2];
 } mail_entry;
 
 struct orc_run {
@@ -163,6 +165,8 @@ struct orc_run {
   float* nf;           /* next population, built during a generation */
   uint32_t* nT;
   uint32_t* nD;
+  uint32_t* P;         /* genome payload, 2 words per agent (zero for model 0) */
+  uint32_t* nP;
   outbox_entry* prev;  /* emitted during t-1, absorbed during t */
   outbox_entry* next;  /* emitted during t */
   mail_entry* mail;    /* asynchronous schedule: mail[(i*4 + d)*2 + p], island i's buffer
@@ -185,6 +189,8 @@ int orc_validate(const orc_config* cfg) {
   if (cfg->selection > 1 || cfg->migration > 1) return -1;
   if (cfg->law > 1) return -1;
   if (cfg->law == 1 && (uint64_t)cfg->p_ben32 + cfg->p32 > 0xFFFFFFFFull) return -1;
+  if (cfg->model > 2) return -1;
+  if (cfg->model != 0 && cfg->law != 0) return -1;
   return 0;
 }
 
@@ -202,6 +208,51 @@ static float normal_draw(const uint32_t m[4]) {
   /* E[sum] = 8 * 65535 / 2; Var[sum] = 8 * (65536^2 - 1) / 12 */
   const float scale = (float)(sqrt(1.5) / 65536.0);
   return (float)((int32_t)sum - 262140) * scale;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Genome models (Sec. 2 Methods: the kernel takes any fixed-length genome  */
+/* through three functions, initialize, mutate and evaluate).               */
+/*   model 0  the genome is its fitness value (the paper's own runs): no    */
+/*            payload; mutation changes the fitness (law 0 or 1 above).     */
+/*   model 1  OneMax on a 64-bit string (payload words P0, P1): fitness is  */
+/*            the number of one bits.                                       */
+/*   model 2  Trap-4 on a 64-bit string (Deb and Goldberg's deceptive trap  */
+/*            of order 4): the string is 16 four-bit blocks, block b with u  */
+/*            one bits scores 4 if u = 4, else 3 - u; fitness is the sum.   */
+/* For models 1 and 2: initialize draws the founder's string as words 0 and */
+/* 1 of one block of the sampling stream at the counter's last generation   */
+/* (2^64 - 1, never a real one); mutate, with the same probability p as     */
+/* model 0, flips bit (w3 mod 64) of the child's string, bit b of the       */
+/* string being bit b mod 32 of word b / 32; evaluate runs after every      */
+/* mutation, and the stored fitness always equals evaluate(string).         */
+/* ----------------------------------------------------------------------- */
+static uint32_t ones_in(uint32_t v) {
+  uint32_t n = 0;
+  for (int b = 0; b < 32; ++b) n += (v >> b) & 1u;
+  return n;
+}
+
+static float evaluate_model(uint32_t model, const uint32_t P[2]) {
+  if (model == 1) return (float)(ones_in(P[0]) + ones_in(P[1]));
+  uint32_t sum = 0;
+  for (int b = 0; b < 16; ++b) {
+    const uint32_t u = ones_in((P[b / 8] >> (4 * (b % 8))) & 0xFu);
+    sum += u == 4 ? 4u : 3u - u;
+  }
+  return (float)sum;
+}
+
+static void initialize_model(orc_run* r) {
+  uint32_t w[4];
+  for (uint64_t i = 0; i < r->islands; ++i)
+    for (uint64_t s = 0; s < r->cfg.pop; ++s) {
+      const uint64_t a = i * r->cfg.pop + s;
+      draw(&r->cfg, (uint32_t)s, (uint32_t)i, UINT64_MAX, TAG_SAMPLE, w);
+      r->P[a * 2] = w[0];
+      r->P[a * 2 + 1] = w[1];
+      r->f[a] = evaluate_model(r->cfg.model, &r->P[a * 2]);
+    }
 }
 
 orc_run* orc_create(const orc_config* cfg, int record_lineage) {
@@ -222,13 +273,17 @@ orc_run* orc_create(const orc_config* cfg, int record_lineage) {
   r->nf = (float*)calloc(r->agents, sizeof(float));
   r->nT = (uint32_t*)calloc(r->agents, sizeof(uint32_t));
   r->nD = (uint32_t*)calloc(r->agents * r->words, sizeof(uint32_t));
+  r->P = (uint32_t*)calloc(r->agents * 2, sizeof(uint32_t));
+  r->nP = (uint32_t*)calloc(r->agents * 2, sizeof(uint32_t));
   r->prev = (outbox_entry*)calloc(r->islands, sizeof(outbox_entry));
   r->next = (outbox_entry*)calloc(r->islands, sizeof(outbox_entry));
   r->lineage = record_lineage != 0;
-  if (!r->f || !r->T || !r->D || !r->nf || !r->nT || !r->nD || !r->prev || !r->next) {
+  if (!r->f || !r->T || !r->D || !r->nf || !r->nT || !r->nD || !r->P || !r->nP || !r->prev ||
+      !r->next) {
     orc_free(r);
     return NULL;
   }
+  if (cfg->model != 0) initialize_model(r);
   return r;
 }
 
@@ -236,6 +291,7 @@ void orc_free(orc_run* r) {
   if (!r) return;
   free(r->f); free(r->T); free(r->D);
   free(r->nf); free(r->nT); free(r->nD);
+  free(r->P); free(r->nP);
   free(r->prev); free(r->next);
   free(r->mail); free(r->seen);
   free(r->winners);
@@ -272,11 +328,13 @@ static uint32_t byte_of(const uint32_t w[4], uint32_t m) {
 }
 
 static void copy_agent(const orc_run* r, const float* sf, const uint32_t* sT,
-                       const uint32_t* sD, uint64_t src, float* df, uint32_t* dT,
-                       uint32_t* dD, uint64_t dst) {
+                       const uint32_t* sD, const uint32_t* sP, uint64_t src, float* df,
+                       uint32_t* dT, uint32_t* dD, uint32_t* dP, uint64_t dst) {
   df[dst] = sf[src];
   dT[dst] = sT[src];
   for (uint32_t w = 0; w < r->words; ++w) dD[dst * r->words + w] = sD[src * r->words + w];
+  dP[dst * 2] = sP[src * 2];
+  dP[dst * 2 + 1] = sP[src * 2 + 1];
 }
 
 static int grow_lineage(orc_run* r, uint64_t gens) {
@@ -313,10 +371,16 @@ static void reproduce_island(orc_run* r, uint64_t i, uint64_t t, uint8_t* win_ro
       }
     }
     uint64_t child = i * N + s;
-    copy_agent(r, r->f, r->T, r->D, i * N + best, r->nf, r->nT, r->nD, child);
+    copy_agent(r, r->f, r->T, r->D, r->P, i * N + best, r->nf, r->nT, r->nD, r->nP, child);
     if (win_row) win_row[child] = (uint8_t)best;
 
-    if (cfg->law == 0) {
+    if (cfg->model != 0) {
+      if (w[2] < cfg->p32) {
+        const uint32_t bit = w[3] & 63u;
+        r->nP[child * 2 + bit / 32] ^= 1u << (bit % 32);
+        r->nf[child] = evaluate_model(cfg->model, &r->nP[child * 2]);
+      }
+    } else if (cfg->law == 0) {
       if (w[2] < cfg->p32) {
         uint32_t idx = (uint32_t)(((uint64_t)(w[3] & 0x7FFFFFFFu) * 5u) >> 31);
         float delta = 0.5f * (float)((int)idx - 2);
@@ -363,6 +427,8 @@ static void one_generation(orc_run* r) {
       r->f[a] = in->f;
       r->T[a] = in->T;
       for (uint32_t k = 0; k < r->words; ++k) r->D[a * r->words + k] = in->D[k];
+      r->P[a * 2] = in->P[0];
+      r->P[a * 2 + 1] = in->P[1];
     }
   }
 
@@ -380,6 +446,8 @@ static void one_generation(orc_run* r) {
     out->f = r->f[a];
     out->T = r->T[a];
     for (uint32_t k = 0; k < r->words; ++k) out->D[k] = r->D[a * r->words + k];
+    out->P[0] = r->P[a * 2];
+    out->P[1] = r->P[a * 2 + 1];
   }
 
   /* 3-7. Evaluation, tournament, copy, mutation, stratum deposit (Sec. 2). */
@@ -390,6 +458,7 @@ static void one_generation(orc_run* r) {
   float* tf = r->f; r->f = r->nf; r->nf = tf;
   uint32_t* tT = r->T; r->T = r->nT; r->nT = tT;
   uint32_t* tD = r->D; r->D = r->nD; r->nD = tD;
+  uint32_t* tP = r->P; r->P = r->nP; r->nP = tP;
   outbox_entry* to = r->prev; r->prev = r->next; r->next = to;
   r->t = t + 1;
 }
@@ -474,6 +543,8 @@ static void group_generation_async(orc_run* r, uint64_t lo, uint64_t hi, uint64_
       r->f[a] = pick->f;
       r->T[a] = pick->T;
       for (uint32_t k = 0; k < r->words; ++k) r->D[a * r->words + k] = pick->D[k];
+      r->P[a * 2] = pick->P[0];
+      r->P[a * 2 + 1] = pick->P[1];
     }
   }
   /* emigration choice from the post-absorb population, held back until the
@@ -489,11 +560,14 @@ static void group_generation_async(orc_run* r, uint64_t lo, uint64_t hi, uint64_
     out->f = r->f[a];
     out->T = r->T[a];
     for (uint32_t k = 0; k < r->words; ++k) out->D[k] = r->D[a * r->words + k];
+    out->P[0] = r->P[a * 2];
+    out->P[1] = r->P[a * 2 + 1];
   }
   /* update: the group's next population replaces its current one */
   for (uint64_t i = lo; i < hi; ++i) {
     reproduce_island(r, i, t, NULL);
-    for (uint64_t s = 0; s < N; ++s) copy_agent(r, r->nf, r->nT, r->nD, i * N + s, r->f, r->T, r->D, i * N + s);
+    for (uint64_t s = 0; s < N; ++s)
+      copy_agent(r, r->nf, r->nT, r->nD, r->nP, i * N + s, r->f, r->T, r->D, r->P, i * N + s);
   }
   for (uint64_t i = lo; i < hi; ++i) {
     const outbox_entry* out = &r->next[i];
@@ -503,6 +577,8 @@ static void group_generation_async(orc_run* r, uint64_t lo, uint64_t hi, uint64_
     m->f = out->f;
     m->T = out->T;
     for (uint32_t k = 0; k < r->words; ++k) m->D[k] = out->D[k];
+    m->P[0] = out->P[0];
+    m->P[1] = out->P[1];
   }
 }
 
@@ -534,6 +610,19 @@ void orc_get_mailboxes(const orc_run* r, uint64_t* stamp, uint64_t* seen, float*
   }
   if (seen)
     for (uint64_t b = 0; b < r->islands * 4; ++b) seen[b] = r->seen ? r->seen[b] : 0;
+}
+
+void orc_get_payload(const orc_run* r, uint32_t* P) {
+  memcpy(P, r->P, r->agents * 2 * sizeof(uint32_t));
+}
+
+void orc_set_payload(orc_run* r, const uint32_t* P) {
+  memcpy(r->P, P, r->agents * 2 * sizeof(uint32_t));
+}
+
+float orc_evaluate(uint32_t model, uint32_t p0, uint32_t p1) {
+  const uint32_t P[2] = {p0, p1};
+  return model == 0 ? 0.0f : evaluate_model(model, P);
 }
 
 void orc_get_population(const orc_run* r, float* f, uint32_t* T, uint32_t* D) {

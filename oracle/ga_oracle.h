@@ -48,6 +48,9 @@ typedef struct orc_config {
                            1 treatments: beneficial (+|Z|) if draw < p_ben32,
                            else deleterious (-|Z|) if draw < p_ben32 + p32 */
   uint32_t p_ben32;     /* beneficial probability times 2^32 (law 1) */
+  uint32_t model;       /* genome model: 0 the genome is its fitness (law 0 or 1);
+                           1 OneMax, 2 Trap-4, both on a 64-bit string (law 0's
+                           probability p flips one bit) */
 } orc_config;
 
 typedef struct orc_run orc_run;
@@ -92,6 +95,13 @@ void orc_get_mailboxes(const orc_run* run, uint64_t* stamp, uint64_t* seen, floa
                        uint32_t* T, uint32_t* D);
 
 uint64_t orc_agents(const orc_run* run);
+
+/* Genome payload of models 1 and 2, two words per agent (agent-major); zero
+ * for model 0. */
+void orc_get_payload(const orc_run* run, uint32_t* P);
+void orc_set_payload(orc_run* run, const uint32_t* P);
+/* Fitness a model gives a 64-bit string (words p0, p1); 0 for model 0. */
+float orc_evaluate(uint32_t model, uint32_t p0, uint32_t p1);
 
 /* Population at the start of the current generation. D is agent-major:
  * D[a*W + w] with W = sites/32 words per agent. Any pointer may be NULL. */
