@@ -85,7 +85,31 @@ typedef struct ga_config {
   /* Added later still; struct_size = offsetof(ga_config, schedule) gets the
    * synchronous schedule. */
   uint32_t schedule;           /* GA_SCHEDULE_SYNC or GA_SCHEDULE_ASYNC */
+  /* Added last; struct_size = offsetof(ga_config, genome_model) gets model 0. */
+  uint32_t genome_model;       /* GA_MODEL_* below */
 } ga_config;
+
+/* Genome models (ga_config.genome_model). The paper's kernel serves any
+ * fixed-length genome through three functions, initialize, mutate and
+ * evaluate (Sec. 2 Methods); here a model is compiled into the generation
+ * kernels as one more template case.
+ *
+ * GA_MODEL_FITNESS: the genome is its fitness value (the paper's runs):
+ * founders +0, mutation as mutation_law says.
+ * GA_MODEL_ONEMAX, GA_MODEL_TRAP4: a 64-bit string carried with the genome
+ * (bit b is bit b % 32 of word b / 32). Founders take words 0 and 1 of the
+ * sampling stream's block for (slot, island) at generation 2^64 - 1; with
+ * probability p (mutation_threshold; mutation_law must be 0) a child's string
+ * has bit (draw mod 64) flipped, the draw being the one the fitness delta would
+ * use; the fitness is then re-evaluated: OneMax counts the one bits; Trap-4
+ * (Deb and Goldberg's deceptive trap of order 4) splits the string into 16
+ * four-bit blocks and scores a block with u one bits 4 if u = 4, else 3 - u.
+ * Strings travel with migrants. ga_read_strings / ga_write_strings move them;
+ * the outbox arguments of ga_read_population and ga_write_population must be
+ * NULL for such a run, and it cannot join a batch. */
+#define GA_MODEL_FITNESS 0
+#define GA_MODEL_ONEMAX 1
+#define GA_MODEL_TRAP4 2
 
 /* Schedules (ga_config.schedule).
  *
@@ -156,6 +180,13 @@ int ga_write_population(ga_run* run, const float* fitness, const uint32_t* T,
                         const uint32_t* surface_words,
                         const ga_outbox_entry* outbox, uint64_t generation);
 
+/* Genome models with a string: copy every agent's 64-bit string to the host
+ * (words[agents * 2], agent-major), after waiting for the run's stream, or
+ * overwrite them from the host (synchronous; the caller keeps fitness
+ * consistent with ga_write_population). GA_EINVAL for GA_MODEL_FITNESS. */
+int ga_read_strings(ga_run* run, uint32_t* words);
+int ga_write_strings(ga_run* run, const uint32_t* words);
+
 /* Sample end-state genomes for post hoc reconstruction (Sec. 3: one genome
  * sampled per island). agent_ids == NULL picks one agent per island from the
  * sampling stream at the current generation (n must equal the island count);
@@ -182,7 +213,9 @@ void ga_destroy(ga_run* run);
  * (1..16; default 4) and the launch form. 0 keeps the current value of the
  * first two. Results do not depend on any of these.
  * GA_EINVAL if the resident form is asked for a run that needs more than 16
- * wavefronts at the given islands per wavefront. */
+ * wavefronts at the given islands per wavefront, or if a workgroup's LDS table
+ * (5 * islands_per_wave + 1 entries of 16 bytes, 32 with a genome string, per
+ * wavefront) would exceed the 160 KiB of a CU. */
 int ga_set_launch(ga_run* run, uint32_t islands_per_wave, uint32_t waves_per_group,
                   uint32_t form);
 /* Asynchronous runs only (GA_EINVAL for a synchronous run).

@@ -19,6 +19,7 @@ GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_ESTATE = 0, -1, -2, -3, -4
 FORM_AUTO, FORM_STREAMING, FORM_RESIDENT = 0, 1, 2
 SCHEDULE_SYNC, SCHEDULE_ASYNC = 0, 1
 ASYNC_UNPACED = 0xFFFFFFFF
+MODEL_FITNESS, MODEL_ONEMAX, MODEL_TRAP4 = 0, 1, 2
 
 
 class GAError(RuntimeError):
@@ -40,7 +41,7 @@ class Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "struct_size", "width", "height", "pop_per_island", "surface_sites",
         "tournament_size", "selection", "mutation_threshold", "migration", "seed", "run_id",
-        "mutation_law", "beneficial_threshold", "schedule")]
+        "mutation_law", "beneficial_threshold", "schedule", "genome_model")]
 
 
 class OutboxEntry(ctypes.Structure):
@@ -58,6 +59,8 @@ SIGNATURES = {
     "ga_read_population": (i32, [P, P, P, P, P, P]),
     "ga_write_population": (i32, [P, P, P, P, P, u64]),
     "ga_extract_surfaces": (i32, [P, P, sz, P, P, P]),
+    "ga_read_strings": (i32, [P, P]),
+    "ga_write_strings": (i32, [P, P]),
     "ga_generation": (u64, [P]),
     "ga_destroy": (None, [P]),
     "ga_set_launch": (i32, [P, u32, u32, u32]),

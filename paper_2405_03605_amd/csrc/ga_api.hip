@@ -40,6 +40,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // beneficial_threshold, and before schedule.
 constexpr uint32_t kConfigV1Size = (uint32_t)offsetof(ga_config, mutation_law);
 constexpr uint32_t kConfigV2Size = (uint32_t)offsetof(ga_config, schedule);
+constexpr uint32_t kConfigV3Size = (uint32_t)offsetof(ga_config, genome_model);
 
 bool is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
 uint32_t log2u(uint32_t v) {
@@ -55,7 +56,7 @@ bool config_ok(const ga_config* c, std::string* why) {
   };
   if (!c) return no("config is NULL");
   if (c->struct_size != sizeof(ga_config) && c->struct_size != kConfigV1Size &&
-      c->struct_size != kConfigV2Size)
+      c->struct_size != kConfigV2Size && c->struct_size != kConfigV3Size)
     return no("struct_size must be sizeof(ga_config)");
   if (c->width < 1 || c->width > 65535) return no("width must be in [1, 65535]");
   if (c->height < 1 || c->height > 65535) return no("height must be in [1, 65535]");
@@ -65,8 +66,14 @@ bool config_ok(const ga_config* c, std::string* why) {
   if (c->tournament_size < 1 || c->tournament_size > 8) return no("tournament_size must be in [1, 8]");
   if (c->selection > 1) return no("selection must be 0 or 1");
   if (c->migration > 1) return no("migration must be 0 or 1");
-  if (c->struct_size == sizeof(ga_config) && c->schedule > GA_SCHEDULE_ASYNC)
+  if (c->struct_size > kConfigV2Size && c->schedule > GA_SCHEDULE_ASYNC)
     return no("schedule must be 0 (synchronous) or 1 (asynchronous)");
+  if (c->struct_size == sizeof(ga_config)) {
+    if (c->genome_model > GA_MODEL_TRAP4)
+      return no("genome_model must be 0 (fitness), 1 (OneMax) or 2 (Trap-4)");
+    if (c->genome_model != GA_MODEL_FITNESS && c->mutation_law != 0)
+      return no("a genome model with a string uses mutation_law 0");
+  }
   if (c->struct_size >= kConfigV2Size) {
     if (c->mutation_law > 1) return no("mutation_law must be 0 or 1");
     if (c->mutation_law == 1 &&
@@ -80,7 +87,7 @@ bool config_ok(const ga_config* c, std::string* why) {
 
 // Byte offsets of every plane inside a run's device buffer.
 struct Layout {
-  size_t pop_f, pop_T, pop_D;
+  size_t pop_f, pop_T, pop_D, pop_P;
   size_t ob[2];     // synchronous schedule
   size_t mail, seen, prog;  // asynchronous schedule
   size_t counters;  // generation counter, batch budget
@@ -88,8 +95,19 @@ struct Layout {
   size_t total;
 };
 
-// words per AoS outbox entry: fitness, T, surface words, header, padding to 16 B
-size_t outbox_stride(const ga_config* c) { return c->surface_sites == 32 ? 4 : 8; }
+bool is_async(const ga_config* c) {
+  return c->struct_size > kConfigV2Size && c->schedule == GA_SCHEDULE_ASYNC;
+}
+
+uint32_t model_of(const ga_config* c) {
+  return c->struct_size == sizeof(ga_config) ? c->genome_model : GA_MODEL_FITNESS;
+}
+
+// words per AoS outbox entry: fitness, T, surface words, header, padding to 16 B;
+// with a string: fitness, T, two surface words, two string words, header, pad
+size_t outbox_stride(const ga_config* c) {
+  return c->surface_sites == 32 && model_of(c) == GA_MODEL_FITNESS ? 4 : 8;
+}
 
 // Planes run 128 islands past the last 64-island boundary: a wavefront's last
 // chunk may end up to 63 islands past the last island, and its one-iteration
@@ -97,10 +115,6 @@ size_t outbox_stride(const ga_config* c) { return c->surface_sites == 32 ? 4 : 8
 size_t padded_islands(const ga_config* c) {
   const size_t islands = (size_t)c->width * c->height;
   return (islands + 63) / 64 * 64 + 128;
-}
-
-bool is_async(const ga_config* c) {
-  return c->struct_size == sizeof(ga_config) && c->schedule == GA_SCHEDULE_ASYNC;
 }
 
 Layout layout_of(const ga_config* c) {
@@ -117,6 +131,7 @@ Layout layout_of(const ga_config* c) {
   L.pop_f = take(agents * 4);
   L.pop_T = take(agents * 4);
   L.pop_D = take(agents * 4 * words);
+  if (model_of(c) != GA_MODEL_FITNESS) L.pop_P = take(agents * 4 * 2);
   if (is_async(c)) {
     // eight buffers per island (direction x parity), four stamps, and one
     // progress word per possible chunk
@@ -200,10 +215,23 @@ uint32_t resident_ipw(const ga_run* r) {
   return std::max(g, std::min(64u, want));
 }
 
+// LDS of one CU (gfx950), the most a workgroup can take.
+constexpr size_t kMaxGroupLds = 160 * 1024;
+
+// LDS one workgroup may take for the resident form.
+constexpr size_t kResidentLds = 64 * 1024;
+
+bool resident_fits(const ga_run* r) {
+  const uint32_t ipw = resident_ipw(r);
+  const uint32_t waves = waves_for(r, ipw);
+  return waves <= (uint32_t)ga::kMaxWavesPerGroup &&
+         ga::lds_bytes(ipw, waves, r->view.model) <= kResidentLds;
+}
+
 bool use_resident(const ga_run* r) {
   if (r->form == GA_FORM_RESIDENT) return true;
   if (r->form == GA_FORM_STREAMING) return false;
-  return r->view.agents <= 4096 && waves_for(r, resident_ipw(r)) <= (uint32_t)ga::kMaxWavesPerGroup;
+  return r->view.agents <= 4096 && resident_fits(r);
 }
 
 void drop_graph(ga_run* r) {
@@ -330,7 +358,8 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   if (!r) return fail(GA_EINVAL, "host allocation failed");
   std::memcpy(&r->cfg, cfg, cfg->struct_size);
   const bool async = is_async(cfg);
-  r->cfg.struct_size = sizeof(ga_config);
+  const uint32_t model = model_of(cfg);
+  r->cfg.struct_size = sizeof(ga_config);  // fields past the caller's size stay 0
   r->lay = lay;
   r->stream = static_cast<hipStream_t>(hip_stream);
   r->base = static_cast<uint8_t*>(dev_mem);
@@ -339,6 +368,8 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   v.pop_f = reinterpret_cast<float*>(b + lay.pop_f);
   v.pop_T = reinterpret_cast<uint32_t*>(b + lay.pop_T);
   v.pop_D = reinterpret_cast<uint32_t*>(b + lay.pop_D);
+  v.model = model;
+  v.pop_P = model ? reinterpret_cast<uint32_t*>(b + lay.pop_P) : nullptr;
   for (int p = 0; p < 2; ++p) v.ob[p] = async ? nullptr : reinterpret_cast<uint32_t*>(b + lay.ob[p]);
   v.mail = async ? reinterpret_cast<uint32_t*>(b + lay.mail) : nullptr;
   v.seen = async ? reinterpret_cast<uint32_t*>(b + lay.seen) : nullptr;
@@ -370,6 +401,7 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   // Founders: all-zero bits are +0 fitness, T = 0, blank surfaces, invalid
   // outbox headers, generation 0.
   hipError_t e = ga::launch_fill(reinterpret_cast<uint32_t*>(b), 0u, lay.total / 4, r->stream);
+  if (e == hipSuccess && model) e = ga::launch_init_strings(v, r->stream);
   if (e != hipSuccess) {
     delete r;
     return hip_fail(e, "init fill");
@@ -389,10 +421,12 @@ int ga_set_launch(ga_run* r, uint32_t ipw, uint32_t wpg, uint32_t form) {
     return fail(GA_EINVAL, "islands_per_wave must be a multiple of 64/N in [64/N, 64]");
   if (new_wpg < 1 || new_wpg > (uint32_t)ga::kMaxWavesPerGroup)
     return fail(GA_EINVAL, "waves_per_group must be in [1, 16]");
+  if (ga::lds_bytes(new_ipw, new_wpg, r->view.model) > kMaxGroupLds)
+    return fail(GA_EINVAL, "islands_per_wave x waves_per_group needs more LDS than a CU has");
   if (form > GA_FORM_RESIDENT) return fail(GA_EINVAL, "unknown form");
   if (form == GA_FORM_RESIDENT && r->cfg.schedule == GA_SCHEDULE_ASYNC)
     return fail(GA_EINVAL, "the resident form is synchronous");
-  if (form == GA_FORM_RESIDENT && waves_for(r, resident_ipw(r)) > (uint32_t)ga::kMaxWavesPerGroup)
+  if (form == GA_FORM_RESIDENT && !resident_fits(r))
     return fail(GA_EINVAL, "run too large for the resident form");
   r->ipw = new_ipw;
   r->wpg = new_wpg;
@@ -479,6 +513,8 @@ int ga_read_population(ga_run* r, float* fitness, uint32_t* T, uint32_t* surface
   if (!r) return fail(GA_EINVAL, "run is NULL");
   if (outbox && r->cfg.schedule == GA_SCHEDULE_ASYNC)
     return fail(GA_EINVAL, "an asynchronous run has no synchronous outbox");
+  if (outbox && r->view.model != GA_MODEL_FITNESS)
+    return fail(GA_EINVAL, "the outbox of a genome model with a string is not exchanged");
   hipStream_t s = r->batch ? r->batch->stream : r->stream;
   GA_HIP(hipStreamSynchronize(s), "stream sync");
   const ga::RunView& v = r->view;
@@ -528,6 +564,8 @@ int ga_write_population(ga_run* r, const float* fitness, const uint32_t* T,
   if (r->batch) return fail(GA_ESTATE, "run is a batch member");
   const bool async = r->cfg.schedule == GA_SCHEDULE_ASYNC;
   if (outbox && async) return fail(GA_EINVAL, "an asynchronous run has no synchronous outbox");
+  if (outbox && r->view.model != GA_MODEL_FITNESS)
+    return fail(GA_EINVAL, "the outbox of a genome model with a string is not exchanged");
   if (outbox) {
     for (size_t i = 0; i < r->view.islands; ++i)
       if (outbox[i].valid > 1 || outbox[i].dir > 3) return fail(GA_EINVAL, "outbox entry out of range");
@@ -578,6 +616,40 @@ int ga_write_population(ga_run* r, const float* fitness, const uint32_t* T,
   GA_HIP(hipMemcpyAsync(v.gen, &t, sizeof(t), h2d, s), "write generation");
   GA_HIP(hipStreamSynchronize(s), "stream sync");
   r->gen_host = generation;
+  return GA_OK;
+}
+
+int ga_read_strings(ga_run* r, uint32_t* words) {
+  if (!r || !words) return fail(GA_EINVAL, "run or words is NULL");
+  if (r->view.model == GA_MODEL_FITNESS) return fail(GA_EINVAL, "the genome model has no string");
+  hipStream_t s = r->batch ? r->batch->stream : r->stream;
+  GA_HIP(hipStreamSynchronize(s), "stream sync");
+  const size_t A = r->view.agents;
+  std::vector<uint32_t> planes(A * 2);
+  for (size_t w = 0; w < 2; ++w)
+    GA_HIP(hipMemcpy(planes.data() + w * A, r->view.pop_P + w * r->view.agent_stride, A * 4,
+                     hipMemcpyDeviceToHost), "read strings");
+  for (size_t a = 0; a < A; ++a) {
+    words[a * 2] = planes[a];
+    words[a * 2 + 1] = planes[A + a];
+  }
+  return GA_OK;
+}
+
+int ga_write_strings(ga_run* r, const uint32_t* words) {
+  if (!r || !words) return fail(GA_EINVAL, "run or words is NULL");
+  if (r->view.model == GA_MODEL_FITNESS) return fail(GA_EINVAL, "the genome model has no string");
+  if (r->batch) return fail(GA_ESTATE, "run is a batch member");
+  GA_HIP(hipStreamSynchronize(r->stream), "stream sync");
+  const size_t A = r->view.agents;
+  std::vector<uint32_t> planes(A * 2);
+  for (size_t a = 0; a < A; ++a) {
+    planes[a] = words[a * 2];
+    planes[A + a] = words[a * 2 + 1];
+  }
+  for (size_t w = 0; w < 2; ++w)
+    GA_HIP(hipMemcpy(r->view.pop_P + w * r->view.agent_stride, planes.data() + w * A, A * 4,
+                     hipMemcpyHostToDevice), "write strings");
   return GA_OK;
 }
 
@@ -667,6 +739,8 @@ int ga_batch_add(ga_batch* b, ga_run* r, uint64_t budget) {
   if (!b || !r) return fail(GA_EINVAL, "batch or run is NULL");
   if (r->cfg.schedule == GA_SCHEDULE_ASYNC)
     return fail(GA_EINVAL, "a batch advances synchronous runs only");
+  if (r->view.model != GA_MODEL_FITNESS)
+    return fail(GA_EINVAL, "a batch advances fitness-valued genomes only");
   if (r->batch) return fail(GA_ESTATE, "run is already in a batch");
   GA_HIP(hipStreamSynchronize(r->stream), "stream sync");
   unsigned long long left = budget;

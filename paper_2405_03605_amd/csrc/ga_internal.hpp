@@ -47,6 +47,10 @@ struct RunView {
   uint32_t* seen;
   uint32_t* prog;
   unsigned long long* waits;
+  // genome model (0 fitness-valued; 1 OneMax, 2 Trap-4 on a 64-bit string)
+  // and, with a string, its two word planes pop_P[w * agent_stride + a]
+  uint32_t model;
+  uint32_t* pop_P;
 };
 
 // Asynchronous pacing: no bound on how far an island may run ahead, and the
@@ -74,6 +78,10 @@ hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint3
 // Wavefronts of the async kernel the current device holds at once.
 hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, uint32_t* waves);
 hipError_t launch_advance(unsigned long long* gen, uint64_t n, hipStream_t stream);
+// Founders' strings and fitness for a genome model with a string.
+hipError_t launch_init_strings(const RunView& v, hipStream_t stream);
+// Dynamic LDS bytes of a launch.
+size_t lds_bytes(uint32_t ipw, uint32_t waves, uint32_t model);
 hipError_t launch_fill(uint32_t* p, uint32_t value, size_t words, hipStream_t stream);
 hipError_t launch_sample(const RunView& v, uint32_t* ids, hipStream_t stream);
 hipError_t launch_gather(const RunView& v, const uint32_t* ids, uint32_t n, uint32_t* T_out,

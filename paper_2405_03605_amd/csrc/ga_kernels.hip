@@ -192,33 +192,65 @@ __device__ __forceinline__ void drain_memory() {
 struct Genome {
   float f = 0.f;
   uint32_t T = 0, D0 = 0, D1 = 0;
+  uint32_t P0 = 0, P1 = 0;  // string of a genome model (models 1 and 2)
 };
 
 __device__ __forceinline__ Genome load_genome(const float* pf, const uint32_t* pT,
                                               const uint32_t* pD0, const uint32_t* pD1,
-                                              uint32_t off, uint32_t words) {
+                                              const uint32_t* pP0, const uint32_t* pP1,
+                                              uint32_t off, uint32_t words, bool strings) {
   Genome g;
   g.f = *at_byte(pf, off);
   g.T = *at_byte(pT, off);
   g.D0 = *at_byte(pD0, off);
   if (words > 1) g.D1 = *at_byte(pD1, off);
+  if (strings) {
+    g.P0 = *at_byte(pP0, off);
+    g.P1 = *at_byte(pP1, off);
+  }
   return g;
 }
 
-// One generation for islands [base, base + v.ipw) of a run, by one wavefront.
-// LC / SWC: log2 N and surface words fixed at compile time, or -1 to read them
-// from the view. `lds` is this wavefront's table of 5 * ipw + 1 16-byte
-// entries: arrivals [4 * local + q], emissions [4 * ipw + local], and one
-// scratch entry read when a lane has no arrival.
+// Genome models (the paper's kernel serves any fixed-length genome through
+// initialize, mutate and evaluate, Sec. 2 Methods). Model 0: the genome is its
+// fitness value, mutated directly. Models 1 and 2: a 64-bit string (words P0,
+// P1; bit b is bit b % 32 of word b / 32); founders draw it from the sampling
+// stream at generation 2^64 - 1; mutation flips bit (w3 mod 64); the fitness
+// is re-evaluated after each flip:
+//   1 OneMax: the number of one bits;
+//   2 Trap-4 (Deb and Goldberg's deceptive trap of order 4): 16 four-bit
+//     blocks, a block with u one bits scoring 4 if u = 4, else 3 - u. The sum
+//     is 48 - ones + 5 * (blocks with all four bits set).
+constexpr int kModelFitness = 0;
+constexpr int kModelOneMax = 1;
+constexpr int kModelTrap4 = 2;
+
+template <int MODEL>
+__device__ __forceinline__ float evaluate_string(uint32_t p0, uint32_t p1) {
+  const uint32_t ones = __popc(p0) + __popc(p1);
+  if (MODEL == kModelOneMax) return (float)ones;
+  const uint32_t full0 = p0 & (p0 >> 1) & (p0 >> 2) & (p0 >> 3) & 0x11111111u;
+  const uint32_t full1 = p1 & (p1 >> 1) & (p1 >> 2) & (p1 >> 3) & 0x11111111u;
+  return (float)(48u - ones + 5u * (__popc(full0) + __popc(full1)));
+}
+
 // Per-wavefront state of the asynchronous schedule.
 struct AsyncCtx {
   uint32_t lead;     // how many generations an island may run ahead of a neighbour
   uint32_t gave_up;  // waits for a neighbour that hit the spin limit
 };
 
-template <int LC, int SWC, bool ASYNC = false>
+// One generation for islands [base, base + v.ipw) of a run, by one wavefront.
+// LC / SWC: log2 N and surface words fixed at compile time, or -1 to read them
+// from the view. MODEL: the genome model. `lds` is this wavefront's table of
+// 5 * ipw + 1 entries (16 bytes for model 0, 32 with a string): arrivals
+// [4 * local + q], emissions [4 * ipw + local], and one scratch entry read when
+// a lane has no arrival.
+template <int LC, int SWC, bool ASYNC = false, int MODEL = kModelFitness>
 __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base, uint64_t t,
                                                  uint4* lds, AsyncCtx* ax = nullptr) {
+  constexpr bool kStr = MODEL != kModelFitness;  // genomes carry a string
+  constexpr uint32_t ES = kStr ? 2u : 1u;        // 16-byte units per LDS entry
   const uint32_t L = LC >= 0 ? (uint32_t)LC : v.log2n;
   const uint32_t SW = SWC >= 0 ? (uint32_t)SWC : v.words;
   const uint32_t s_log = 4u + SW;  // log2 S: 5 for 32 sites, 6 for 64
@@ -232,8 +264,10 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   const uint32_t W = v.width, H = v.height;
   const uint32_t* __restrict__ in_ob = odd_gen ? v.ob[0] : v.ob[1];
   uint32_t* __restrict__ out_ob = odd_gen ? v.ob[1] : v.ob[0];
-  const uint32_t ob_stride = SW == 1 ? 4u : 8u;  // words per outbox entry
-  const uint32_t ob_hdr = 2u + SW;               // header word
+  // words per outbox entry and header word: f, T, surface, header (model 0);
+  // f, T, D0, D1, P0, P1, header (strings)
+  const uint32_t ob_stride = (SW == 1 && !kStr) ? 4u : 8u;
+  const uint32_t ob_hdr = kStr ? 6u : 2u + SW;
 
   // chunk base pointers (uniform) and this lane's byte offset in the chunk
   const uint32_t first_agent = base << L;
@@ -241,12 +275,14 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   uint32_t* __restrict__ pT = v.pop_T + first_agent;
   uint32_t* __restrict__ pD0 = v.pop_D + first_agent;
   uint32_t* __restrict__ pD1 = v.pop_D + v.agent_stride + first_agent;
+  uint32_t* __restrict__ pP0 = v.pop_P + first_agent;
+  uint32_t* __restrict__ pP1 = v.pop_P + v.agent_stride + first_agent;
   const uint32_t n_iter = v.ipw >> (6u - L);
   uint32_t off = lane << 2;
 
   // the first iteration's genomes go in flight before the island pass, whose
   // own loads and draws then hide their latency
-  Genome g = load_genome(pf, pT, pD0, pD1, off, SW);
+  Genome g = load_genome(pf, pT, pD0, pD1, pP0, pP1, off, SW, kStr);
 
   // ---- island pass: lane l handles island base + l ---------------------------
   const bool own_ok = lane < v.ipw && base + lane < v.islands;
@@ -264,11 +300,16 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     for (uint32_t q = 0; q < 4; ++q) {
       const uint32_t* e = in_ob + torus_step(ox, oy, q, W, H) * ob_stride;
       const uint4 entry = *reinterpret_cast<const uint4*>(e);  // f, T, D0, header or D1
-      const uint32_t header = SW == 1 ? entry.w : e[ob_hdr];
+      uint4 more = make_uint4(0u, 0u, 0u, 0u);                  // P0, P1, header
+      if (kStr) more = *reinterpret_cast<const uint4*>(e + 4);
+      const uint32_t header = kStr ? more.z : (SW == 1 ? entry.w : e[ob_hdr]);
       const bool hit = own_ok && header == (kMetaValid | (q ^ 2u));
       const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
       desc = hit ? (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q)) : desc;
-      if (lane < v.ipw) lds[lane * 4u + q] = entry;  // the table holds ipw islands
+      if (lane < v.ipw) {  // the table holds ipw islands
+        lds[(lane * 4u + q) * ES] = entry;
+        if (kStr) lds[(lane * 4u + q) * ES + 1u] = more;
+      }
     }
   } else {
     // Asynchronous schedule. The neighbour in direction q keeps two buffers
@@ -332,13 +373,18 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
         box[q] += take1 ? ob_stride : 0u;
       }
     }
-    uint4 pay[4];
+    uint4 pay[4], pstr[4];
 #pragma unroll
     for (uint32_t q = 0; q < 4; ++q) {
       pay[q].x = load_agent(box[q]);
       pay[q].y = load_agent(box[q] + 1);
       pay[q].z = load_agent(box[q] + 2);
       pay[q].w = SW > 1 ? load_agent(box[q] + 3) : 0u;
+      pstr[q] = make_uint4(0u, 0u, 0u, 0u);
+      if (kStr) {
+        pstr[q].x = load_agent(box[q] + 4);
+        pstr[q].y = load_agent(box[q] + 5);
+      }
     }
     drain_memory();
 #pragma unroll
@@ -348,7 +394,10 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
       seen_q[q] = hit ? stamp[q] : seen_q[q];
       const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
       desc = hit ? (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q)) : desc;
-      if (lane < v.ipw) lds[lane * 4u + q] = pay[q];
+      if (lane < v.ipw) {
+        lds[(lane * 4u + q) * ES] = pay[q];
+        if (kStr) lds[(lane * 4u + q) * ES + 1u] = pstr[q];
+      }
     }
     if (own_ok)
       *reinterpret_cast<uint4*>(seen_at) = make_uint4(seen_q[0], seen_q[1], seen_q[2], seen_q[3]);
@@ -381,9 +430,9 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   for (uint32_t it = 0; it < n_iter; ++it) {
     // next iteration's genomes (past the chunk's end this reads padding or the
     // next chunk's first genomes, and the values go unused)
-    const Genome next = load_genome(pf, pT, pD0, pD1, off + 256u, SW);
+    const Genome next = load_genome(pf, pT, pD0, pD1, pP0, pP1, off + 256u, SW, kStr);
     float f = g.f;
-    uint32_t T = g.T, D0 = g.D0, D1 = g.D1;
+    uint32_t T = g.T, D0 = g.D0, D1 = g.D1, P0 = g.P0, P1 = g.P1;
     const uint32_t local = it * per_iter + (lane >> L);
     const uint32_t island = base + local;
 
@@ -397,16 +446,24 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
       // no branch: lanes without an arrival read the scratch entry and keep
       // their genome, so the loop carries no memory access under divergence
       const uint32_t q = (31u - __clz(z | 1u)) >> 3;
-      const uint4 a = lds[z ? local * 4u + q : scratch];
+      const uint32_t at = (z ? local * 4u + q : scratch) * ES;
+      const uint4 a = lds[at];
       f = z ? __uint_as_float(a.x) : f;
       T = z ? a.y : T;
       D0 = z ? a.z : D0;
       D1 = z ? a.w : D1;
+      if (kStr) {
+        const uint4 b = lds[at + 1u];
+        P0 = z ? b.x : P0;
+        P1 = z ? b.y : P1;
+      }
     }
 
     // 2. the lane holding the island's drawn emigrant parks it in LDS
-    if ((permute(emit, local << 2) & 0xFFu) == slot)
-      lds[emit_base + local] = make_uint4(__float_as_uint(f), T, D0, D1);
+    if ((permute(emit, local << 2) & 0xFFu) == slot) {
+      lds[(emit_base + local) * ES] = make_uint4(__float_as_uint(f), T, D0, D1);
+      if (kStr) lds[(emit_base + local) * ES + 1u] = make_uint4(P0, P1, 0u, 0u);
+    }
 
     // 3-5. evaluate (read fitness) and run the tournament over permuted entrants
     const Block r = sel.block(island);
@@ -429,11 +486,21 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     uint32_t cT = permute(T, best);
     uint32_t cD0 = permute(D0, best);
     uint32_t cD1 = SW > 1 ? permute(D1, best) : 0u;
+    uint32_t cP0 = kStr ? permute(P0, best) : 0u;
+    uint32_t cP1 = kStr ? permute(P1, best) : 0u;
     float cfit = fbest;
 
     // 6. mutation: delta index (w & 0x7FFFFFFF) * 5 >> 31 = hi32((w & 0x7FFFFFFF) * 10)
     //    maps 0..4 to {-1, -1/2, 0, 1/2, 1}
-    if (v.law == 0) {
+    if constexpr (kStr) {
+      if (r.z < v.p32) {
+        const uint32_t bit = r.w & 63u;
+        const uint32_t mask = 1u << (bit & 31u);
+        cP0 ^= bit < 32u ? mask : 0u;
+        cP1 ^= bit < 32u ? 0u : mask;
+        cfit = evaluate_string<MODEL>(cP0, cP1);
+      }
+    } else if (v.law == 0) {
       if (r.z < v.p32) {
         // di * 0.5 is exact, so a fused multiply-add rounds like the plain add
         const int di = (int)__umulhi(r.w & 0x7FFFFFFFu, 10u) - 2;  // -2..2
@@ -476,6 +543,10 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     *at_byte(pT, off) = cT;
     *at_byte(pD0, off) = cD0;
     if (SW > 1) *at_byte(pD1, off) = cD1;
+    if (kStr) {
+      *at_byte(pP0, off) = cP0;
+      *at_byte(pP1, off) = cP1;
+    }
 
     off += 256u;
     g = next;
@@ -496,11 +567,16 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     if (sending) store_agent(box + ob_hdr, stamp - 1u);
     drain_memory();
     if (sending) {
-      const uint4 g = lds[emit_base + lane];
+      const uint4 g = lds[(emit_base + lane) * ES];
       store_agent(box, g.x);
       store_agent(box + 1, g.y);
       store_agent(box + 2, g.z);
       if (SW > 1) store_agent(box + 3, g.w);
+      if (kStr) {
+        const uint4 p = lds[(emit_base + lane) * ES + 1u];
+        store_agent(box + 4, p.x);
+        store_agent(box + 5, p.y);
+      }
     }
     drain_memory();
     if (sending) store_agent(box + ob_hdr, stamp);
@@ -512,8 +588,12 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     uint32_t* e = out_ob + own * ob_stride;
     const uint32_t hdr = emit >> 8;
     if (hdr) {
-      const uint4 g = lds[emit_base + lane];
-      if (SW == 1) {
+      const uint4 g = lds[(emit_base + lane) * ES];
+      if (kStr) {
+        const uint4 p = lds[(emit_base + lane) * ES + 1u];
+        *reinterpret_cast<uint4*>(e) = g;
+        *reinterpret_cast<uint4*>(e + 4) = make_uint4(p.x, p.y, hdr, 0u);
+      } else if (SW == 1) {
         *reinterpret_cast<uint4*>(e) = make_uint4(g.x, g.y, g.z, hdr);
       } else {
         *reinterpret_cast<uint4*>(e) = g;
@@ -525,36 +605,53 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   }
 }
 
-// Dynamic LDS: a table of 5 * ipw + 1 16-byte entries per wavefront.
+// Dynamic LDS: a table of 5 * ipw + 1 entries per wavefront, each of `units`
+// 16-byte units (1 for model 0, 2 for genomes with a string).
 extern __shared__ uint4 ga_lds[];
 
 __device__ __forceinline__ uint32_t lds_entries(uint32_t ipw) { return 5u * ipw + 1u; }
 
-__device__ __forceinline__ uint4* wave_lds(uint32_t wave_in_group, uint32_t ipw) {
-  return ga_lds + wave_in_group * lds_entries(ipw);
+__device__ __forceinline__ uint4* wave_lds(uint32_t wave_in_group, uint32_t ipw, uint32_t units) {
+  return ga_lds + wave_in_group * lds_entries(ipw) * units;
 }
 
-template <int LC, int SWC>
+template <int LC, int SWC, int MODEL>
 __global__ __launch_bounds__(1024) void generation_kernel(RunView v, uint32_t gen_offset) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wig;
   const uint32_t base = wave * v.ipw;
   if (base >= v.islands) return;
-  chunk_generation<LC, SWC>(v, base, *v.gen + gen_offset, wave_lds(wig, v.ipw));
+  chunk_generation<LC, SWC, false, MODEL>(v, base, *v.gen + gen_offset,
+                                          wave_lds(wig, v.ipw, MODEL ? 2u : 1u));
 }
 
 // Whole run in one workgroup: the generation loop stays on the GPU, with a
 // workgroup barrier between generations (the outbox hand-over).
-template <int LC, int SWC>
+template <int LC, int SWC, int MODEL>
 __global__ __launch_bounds__(1024) void resident_kernel(RunView v, uint64_t n_gens) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t base = wig * v.ipw;
   const uint64_t t0 = *v.gen;
+  uint4* lds = wave_lds(wig, v.ipw, MODEL ? 2u : 1u);
   for (uint64_t g = 0; g < n_gens; ++g) {
-    if (base < v.islands) chunk_generation<LC, SWC>(v, base, t0 + g, wave_lds(wig, v.ipw));
+    if (base < v.islands) chunk_generation<LC, SWC, false, MODEL>(v, base, t0 + g, lds);
     __syncthreads();
   }
   if (threadIdx.x == 0) *v.gen = t0 + n_gens;
+}
+
+// Founders of a genome model with a string: words 0 and 1 of the sampling
+// stream's block at generation 2^64 - 1 for (slot, island), and their fitness.
+template <int MODEL>
+__global__ void strings_init_kernel(RunView v) {
+  const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= v.agents) return;
+  const uint32_t island = a >> v.log2n, slot = a & ((1u << v.log2n) - 1u);
+  const Block b = philox10(slot, island, 0xFFFFFFFFu, 0xFFFFFFFCu | kStreamSample, v.seed,
+                           v.run_id);
+  v.pop_P[a] = b.x;
+  v.pop_P[v.agent_stride + a] = b.y;
+  v.pop_f[a] = evaluate_string<MODEL>(b.x, b.y);
 }
 
 // Asynchronous schedule: each wavefront owns `chunks` consecutive chunks and
@@ -569,7 +666,7 @@ __global__ __launch_bounds__(1024) void resident_kernel(RunView v, uint64_t n_ge
 // skew generations apart.
 // eight wavefronts per SIMD: registers (scalar ones included) must fit, or the
 // occupancy query would promise more resident wavefronts than the GPU holds
-template <int LC, int SWC>
+template <int LC, int SWC, int MODEL>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, uint32_t skew) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -578,13 +675,13 @@ void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, ui
   if (first >= v.islands) return;
   const uint32_t end = min(first + chunks * v.ipw, v.islands);
   const uint64_t t0 = *v.gen;
-  uint4* lds = wave_lds(wig, v.ipw);
+  uint4* lds = wave_lds(wig, v.ipw, MODEL ? 2u : 1u);
   AsyncCtx ax{lead, 0u};
   for (uint64_t step = 0; step < n_gens + skew; ++step) {
     for (uint32_t base = first; base < end; base += v.ipw) {
       const uint64_t lag = skew ? (base / v.ipw) % (skew + 1u) : 0u;
       if (step < lag || step - lag >= n_gens) continue;
-      chunk_generation<LC, SWC, true>(v, base, t0 + step - lag, lds, &ax);
+      chunk_generation<LC, SWC, true, MODEL>(v, base, t0 + step - lag, lds, &ax);
     }
   }
   if (__lane_id() == 0u && ax.gave_up)
@@ -592,9 +689,10 @@ void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, ui
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int LC, int SWC>
+template <int LC, int SWC, int MODEL>
 hipError_t async_occupancy(int* groups, int block, size_t lds) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, async_kernel<LC, SWC>, block, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, async_kernel<LC, SWC, MODEL>, block,
+                                                      lds);
 }
 
 __global__ void advance_kernel(unsigned long long* gen, uint64_t n) {
@@ -643,7 +741,7 @@ void batch_generation_kernel(const RunView* __restrict__ views,
   const RunView v = views[tile.run];
   if (*v.left <= gen_offset) return;
   const uint64_t t = *v.gen + gen_offset;
-  uint4* arr = wave_lds(wig, max_ipw);
+  uint4* arr = wave_lds(wig, max_ipw, 1u);
 #ifndef GA_BATCH_GENERIC
   // wavefront-uniform dispatch to the specialised bodies
   switch (v.log2n * 2u + v.words - 1u) {
@@ -677,27 +775,42 @@ __global__ void batch_advance_kernel(const RunView* views, uint32_t n_runs, uint
   *v.left = left - done;
 }
 
-size_t lds_bytes(uint32_t ipw, uint32_t waves) { return (5u * ipw + 1u) * sizeof(uint4) * waves; }
+}  // namespace
+
+size_t lds_bytes(uint32_t ipw, uint32_t waves, uint32_t model) {
+  return (5u * ipw + 1u) * sizeof(uint4) * (model ? 2u : 1u) * waves;
+}
+
+namespace {
 
 }  // namespace
 
-#define GA_DISPATCH(KERNEL, L, SW, ...)                                        \
+#define GA_SHAPES(KERNEL, M, L, SW, ...)                                       \
+  switch ((L) * 2 + ((SW) - 1)) {                                              \
+    case 0: KERNEL<0, 1, M> __VA_ARGS__; break;                                \
+    case 1: KERNEL<0, 2, M> __VA_ARGS__; break;                                \
+    case 2: KERNEL<1, 1, M> __VA_ARGS__; break;                                \
+    case 3: KERNEL<1, 2, M> __VA_ARGS__; break;                                \
+    case 4: KERNEL<2, 1, M> __VA_ARGS__; break;                                \
+    case 5: KERNEL<2, 2, M> __VA_ARGS__; break;                                \
+    case 6: KERNEL<3, 1, M> __VA_ARGS__; break;                                \
+    case 7: KERNEL<3, 2, M> __VA_ARGS__; break;                                \
+    case 8: KERNEL<4, 1, M> __VA_ARGS__; break;                                \
+    case 9: KERNEL<4, 2, M> __VA_ARGS__; break;                                \
+    case 10: KERNEL<5, 1, M> __VA_ARGS__; break;                               \
+    case 11: KERNEL<5, 2, M> __VA_ARGS__; break;                               \
+    case 12: KERNEL<6, 1, M> __VA_ARGS__; break;                               \
+    case 13: KERNEL<6, 2, M> __VA_ARGS__; break;                               \
+    default: return hipErrorInvalidValue;                                      \
+  }
+
+// Dispatch to KERNEL<log2 N, surface words, genome model>.
+#define GA_DISPATCH(KERNEL, L, SW, M, ...)                                     \
   do {                                                                         \
-    switch ((L) * 2 + ((SW) - 1)) {                                            \
-      case 0: KERNEL<0, 1> __VA_ARGS__; break;                                 \
-      case 1: KERNEL<0, 2> __VA_ARGS__; break;                                 \
-      case 2: KERNEL<1, 1> __VA_ARGS__; break;                                 \
-      case 3: KERNEL<1, 2> __VA_ARGS__; break;                                 \
-      case 4: KERNEL<2, 1> __VA_ARGS__; break;                                 \
-      case 5: KERNEL<2, 2> __VA_ARGS__; break;                                 \
-      case 6: KERNEL<3, 1> __VA_ARGS__; break;                                 \
-      case 7: KERNEL<3, 2> __VA_ARGS__; break;                                 \
-      case 8: KERNEL<4, 1> __VA_ARGS__; break;                                 \
-      case 9: KERNEL<4, 2> __VA_ARGS__; break;                                 \
-      case 10: KERNEL<5, 1> __VA_ARGS__; break;                                \
-      case 11: KERNEL<5, 2> __VA_ARGS__; break;                                \
-      case 12: KERNEL<6, 1> __VA_ARGS__; break;                                \
-      case 13: KERNEL<6, 2> __VA_ARGS__; break;                                \
+    switch (M) {                                                               \
+      case 0: GA_SHAPES(KERNEL, 0, L, SW, __VA_ARGS__) break;                  \
+      case 1: GA_SHAPES(KERNEL, 1, L, SW, __VA_ARGS__) break;                  \
+      case 2: GA_SHAPES(KERNEL, 2, L, SW, __VA_ARGS__) break;                  \
       default: return hipErrorInvalidValue;                                    \
     }                                                                          \
   } while (0)
@@ -707,8 +820,8 @@ hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t wav
   if (waves == 0) return hipSuccess;
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
   const dim3 grid(groups), block(64 * waves_per_group);
-  const size_t lds = lds_bytes(v.ipw, waves_per_group);
-  GA_DISPATCH(generation_kernel, v.log2n, v.words,
+  const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
+  GA_DISPATCH(generation_kernel, v.log2n, v.words, v.model,
               <<<grid, block, lds, stream>>>(v, gen_offset));
   return hipGetLastError();
 }
@@ -716,8 +829,9 @@ hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t wav
 hipError_t launch_resident(const RunView& v, uint64_t n_gens, uint32_t waves, hipStream_t stream) {
   if (waves == 0 || waves > (uint32_t)kMaxWavesPerGroup) return hipErrorInvalidValue;
   const dim3 grid(1), block(64 * waves);
-  const size_t lds = lds_bytes(v.ipw, waves);
-  GA_DISPATCH(resident_kernel, v.log2n, v.words, <<<grid, block, lds, stream>>>(v, n_gens));
+  const size_t lds = lds_bytes(v.ipw, waves, v.model);
+  GA_DISPATCH(resident_kernel, v.log2n, v.words, v.model,
+              <<<grid, block, lds, stream>>>(v, n_gens));
   return hipGetLastError();
 }
 
@@ -727,8 +841,8 @@ hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint3
   if (waves == 0 || n_gens == 0) return hipSuccess;
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
   const dim3 grid(groups), block(64 * waves_per_group);
-  const size_t lds = lds_bytes(v.ipw, waves_per_group);
-  GA_DISPATCH(async_kernel, v.log2n, v.words,
+  const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
+  GA_DISPATCH(async_kernel, v.log2n, v.words, v.model,
               <<<grid, block, lds, stream>>>(v, chunks, n_gens, lead, skew));
   return hipGetLastError();
 }
@@ -739,11 +853,22 @@ hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, uint32_t* 
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
   const int block = 64 * (int)waves_per_group;
-  const size_t lds = lds_bytes(v.ipw, waves_per_group);
-  GA_DISPATCH(e = async_occupancy, v.log2n, v.words, (&groups, block, lds));
+  const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
+  GA_DISPATCH(e = async_occupancy, v.log2n, v.words, v.model, (&groups, block, lds));
   if (e != hipSuccess) return e;
   *waves = (uint32_t)groups * (uint32_t)cus * waves_per_group;
   return hipSuccess;
+}
+
+hipError_t launch_init_strings(const RunView& v, hipStream_t stream) {
+  if (v.agents == 0) return hipSuccess;
+  const dim3 grid((v.agents + 255) / 256), block(256);
+  switch (v.model) {
+    case 1: strings_init_kernel<1><<<grid, block, 0, stream>>>(v); break;
+    case 2: strings_init_kernel<2><<<grid, block, 0, stream>>>(v); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_advance(unsigned long long* gen, uint64_t n, hipStream_t stream) {
@@ -777,7 +902,7 @@ hipError_t launch_batch_generation(const RunView* views, const Tile* tiles, uint
                                    uint32_t max_ipw, hipStream_t stream) {
   if (n_tiles == 0) return hipSuccess;
   const uint32_t groups = (n_tiles + waves_per_group - 1) / waves_per_group;
-  const size_t lds = lds_bytes(max_ipw, waves_per_group);
+  const size_t lds = lds_bytes(max_ipw, waves_per_group, 0u);
   batch_generation_kernel<<<dim3(groups), dim3(64 * waves_per_group), lds, stream>>>(
       views, tiles, n_tiles, gen_offset, max_ipw);
   return hipGetLastError();

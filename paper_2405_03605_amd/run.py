@@ -10,8 +10,8 @@ import numpy as np
 from ._lib import (FORM_AUTO, GA_EINVAL, Config, GAError, OutboxEntry, check, load)
 
 CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32", "migration",
-                 "seed", "run_id", "law", "p_ben32", "schedule")
-OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "schedule": 0}
+                 "seed", "run_id", "law", "p_ben32", "schedule", "model")
+OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "schedule": 0, "model": 0}
 
 
 def _fields(cfg: dict) -> dict:
@@ -30,7 +30,7 @@ def make_config(cfg: dict) -> Config:
                   mutation_threshold=cfg["p32"], migration=cfg["migration"],
                   seed=cfg["seed"], run_id=cfg["run_id"],
                   mutation_law=cfg.get("law", 0), beneficial_threshold=cfg.get("p_ben32", 0),
-                  schedule=cfg.get("schedule", 0))
+                  schedule=cfg.get("schedule", 0), genome_model=cfg.get("model", 0))
 
 
 def state_bytes(cfg: dict) -> int:
@@ -114,9 +114,24 @@ class GARun:
     def asynchronous(self) -> bool:
         return self.cfg["schedule"] == 1
 
+    @property
+    def has_strings(self) -> bool:
+        return self.cfg["model"] != 0
+
+    def read_strings(self) -> np.ndarray:
+        """Genome strings (models 1 and 2), shape (agents, 2) uint32."""
+        out = np.empty((self.agents, 2), dtype=np.uint32)
+        check(load().ga_read_strings(self._h, _ptr(out)))
+        return out
+
+    def write_strings(self, words):
+        a = np.ascontiguousarray(words, dtype=np.uint32).reshape(self.agents, 2)
+        check(load().ga_write_strings(self._h, _ptr(a)))
+
     def read(self, outbox: bool = True) -> dict:
-        """Population, generation and (synchronous runs) the pending outbox."""
-        outbox = outbox and not self.asynchronous
+        """Population, generation, the strings of a genome model that has them,
+        and (synchronous fitness-valued runs) the pending outbox."""
+        outbox = outbox and not self.asynchronous and not self.has_strings
         A, I, W = self.agents, self.islands, self.words
         f = np.empty(A, dtype=np.float32)
         T = np.empty(A, dtype=np.uint32)
@@ -126,6 +141,8 @@ class GARun:
         obp = ctypes.cast(ob, ctypes.c_void_p) if ob is not None else None
         check(load().ga_read_population(self._h, _ptr(f), _ptr(T), _ptr(D), obp, ctypes.byref(gen)))
         out = {"f": f, "T": T, "D": D, "generation": int(gen.value)}
+        if self.has_strings:
+            out["P"] = self.read_strings()
         if ob is not None:
             raw = np.frombuffer(ob, dtype=np.uint32).reshape(I, 6)
             out["outbox"] = {

@@ -30,6 +30,11 @@ def assert_same_state(got: dict, ref: "oracle.OracleRun", what: str = ""):
     if not np.array_equal(got["D"], D):
         bad = np.flatnonzero((got["D"] != D).any(axis=1))
         raise AssertionError(f"{what}: surfaces differ at {bad.size} agents, first {bad[:5]}")
+    if "P" in got:
+        P = ref.payload()
+        if not np.array_equal(got["P"], P):
+            bad = np.flatnonzero((got["P"] != P).any(axis=1))
+            raise AssertionError(f"{what}: genome strings differ at {bad.size} agents, first {bad[:5]}")
     if "outbox" in got:
         ob = ref.outbox()
         g = got["outbox"]

@@ -47,14 +47,24 @@ def test_state_bytes_layout(lib):
         W = c["sites"] // 32
         al = lambda b: (b + 255) // 256 * 256
         ob = 4 if W == 1 else 8   # AoS outbox entry words
+        # a genome model with a string adds two string planes and uses 32-byte
+        # entries
+        strings = c.get("model", 0) != 0
+        if strings:
+            ob = 8
         exchange = ((al(4 * 8 * I * ob) + al(4 * 4 * I) + al(4 * I)) if c.get("schedule")
                     else 2 * al(4 * I * ob))
-        return (al(4 * A) * 2 + al(4 * A * W) + exchange + 256
-                + 2 * al(4 * I) + al(4 * I * W))
+        return (al(4 * A) * 2 + al(4 * A * W) + (al(4 * A * 2) if strings else 0) + exchange
+                + 256 + 2 * al(4 * I) + al(4 * I * W))
     for c in (TINY, MID, PAPER, run_config(width=3, height=5, pop=1, sites=32)):
         assert ga.state_bytes(c) == expect(c)
         a = dict(c, schedule=1)
         assert ga.state_bytes(a) == expect(a) > ga.state_bytes(c)
+        for model in (1, 2):
+            m = dict(c, model=model)
+            assert ga.state_bytes(m) == expect(m) > ga.state_bytes(c)
+            ma = dict(m, schedule=1)
+            assert ga.state_bytes(ma) == expect(ma)
     # paper-scale run: 16.8M agents, 12 B each
     assert 200e6 < ga.state_bytes(PAPER) < 230e6
 
@@ -63,7 +73,8 @@ def test_state_bytes_layout(lib):
     dict(pop=24), dict(pop=128), dict(pop=0), dict(sites=48), dict(sites=16), dict(k=0),
     dict(k=9), dict(width=0), dict(height=0), dict(width=70000), dict(selection=2),
     dict(migration=3), dict(width=65535, height=65535, pop=64), dict(width=65535, height=8193, pop=2),
-    dict(law=2), dict(law=1, p32=2 ** 32 - 10, p_ben32=100), dict(schedule=2)])
+    dict(law=2), dict(law=1, p32=2 ** 32 - 10, p_ben32=100), dict(schedule=2), dict(model=3),
+    dict(model=1, law=1, p_ben32=5)])
 def test_invalid_configs_rejected(lib, bad):
     c = make_config(run_config(**bad))
     assert lib.ga_state_bytes(ctypes.byref(c)) == 0
@@ -112,3 +123,8 @@ def test_first_release_config_size_accepted(lib):
     assert lib.ga_state_bytes(ct.byref(c)) == full
     c.schedule = 7                                      # not read at that size
     assert lib.ga_state_bytes(ct.byref(c)) == full
+    # size before the genome model: fitness-valued, whatever the field says
+    c = make_config(run_config(schedule=1, model=2))
+    async_bytes = lib.ga_state_bytes(ct.byref(make_config(run_config(schedule=1))))
+    c.struct_size = _lib.Config.genome_model.offset
+    assert lib.ga_state_bytes(ct.byref(c)) == async_bytes
