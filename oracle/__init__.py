@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
 class _Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "width", "height", "pop", "sites", "k", "selection", "p32", "migration",
-        "seed", "run_id", "law", "p_ben32", "model")]
+        "seed", "run_id", "law", "p_ben32", "model", "dbits")]
 
 
 _lib = None
@@ -91,6 +91,8 @@ def _load():
     lib.orc_true_mrca_matrix.argtypes = [P, P, sz, P]
     lib.orc_true_mrca_matrix.restype = ctypes.c_int
     lib.orc_mrca_interval_matrix.argtypes = [P, P, sz, u32, u32, P, P]
+    lib.orc_mrca_interval_bits.argtypes = [u32, P, u32, P, u32, u32, u32, P, P]
+    lib.orc_mrca_interval_matrix_bits.argtypes = [P, P, sz, u32, u32, u32, P, P]
     lib.orc_get_payload.argtypes = [P, P]
     lib.orc_set_payload.argtypes = [P, P]
     lib.orc_evaluate.argtypes = [u32, u32, u32]
@@ -132,31 +134,33 @@ def site_of_range(first: int, count: int, sites: int) -> np.ndarray:
     return out
 
 
-def mrca_interval(Ta: int, Da, Tb: int, Db, sites: int, kc: int = 5):
-    """(L, U) bounds on the MRCA's deposit counter from two surfaces."""
+def mrca_interval(Ta: int, Da, Tb: int, Db, sites: int, kc: int = 5, bits: int = 1):
+    """(L, U) bounds on the MRCA's deposit counter from two surfaces of
+    ``sites`` differentia of ``bits`` bits each."""
     a = np.ascontiguousarray(Da, dtype=np.uint32)
     b = np.ascontiguousarray(Db, dtype=np.uint32)
     L = ctypes.c_uint32()
     U = ctypes.c_uint32()
-    _load().orc_mrca_interval(Ta, _ptr(a), Tb, _ptr(b), sites, kc,
-                              ctypes.byref(L), ctypes.byref(U))
+    _load().orc_mrca_interval_bits(Ta, _ptr(a), Tb, _ptr(b), sites, bits, kc,
+                                   ctypes.byref(L), ctypes.byref(U))
     return int(L.value), int(U.value)
 
 
-def mrca_interval_matrix(T, D, sites: int, kc: int = 5):
-    """(L, U) matrices for every pair of the n surfaces (T[n], D[n, S/32])."""
+def mrca_interval_matrix(T, D, sites: int, kc: int = 5, bits: int = 1):
+    """(L, U) matrices for every pair of the n surfaces (T[n], D[n, S*bits/32])."""
     Ta = np.ascontiguousarray(T, dtype=np.uint32)
     Da = np.ascontiguousarray(D, dtype=np.uint32)
     n = Ta.size
     L = np.empty((n, n), dtype=np.uint32)
     U = np.empty((n, n), dtype=np.uint32)
-    _load().orc_mrca_interval_matrix(_ptr(Ta), _ptr(Da), n, sites, kc, _ptr(L), _ptr(U))
+    _load().orc_mrca_interval_matrix_bits(_ptr(Ta), _ptr(Da), n, sites, bits, kc, _ptr(L),
+                                          _ptr(U))
     return L, U
 
 
 CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32",
-                 "migration", "seed", "run_id", "law", "p_ben32", "model")
-OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "model": 0}
+                 "migration", "seed", "run_id", "law", "p_ben32", "model", "dbits")
+OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "model": 0, "dbits": 1}
 
 
 def _fields(cfg: dict) -> dict:
@@ -180,7 +184,7 @@ class OracleRun:
         if not h:
             raise ValueError(f"oracle rejected configuration {self.cfg}")
         self._h = ctypes.c_void_p(h)
-        self.words = self.cfg["sites"] // 32
+        self.words = self.cfg["sites"] * self.cfg["dbits"] // 32
         self.islands = self.cfg["width"] * self.cfg["height"]
         self.agents = self.islands * self.cfg["pop"]
 

@@ -184,7 +184,10 @@ int orc_validate(const orc_config* cfg) {
   if (!cfg) return -1;
   if (cfg->width == 0 || cfg->height == 0) return -1;
   if (!is_pow2(cfg->pop) || cfg->pop > 256) return -1;
-  if (cfg->sites != 32 && cfg->sites != 64) return -1;
+  /* S sites of dbits-bit differentia in one or two 32-bit words */
+  if (cfg->dbits != 1 && cfg->dbits != 2 && cfg->dbits != 4 && cfg->dbits != 8) return -1;
+  if (!is_pow2(cfg->sites) || cfg->sites < 4 || cfg->sites > 64) return -1;
+  if (cfg->sites * cfg->dbits != 32 && cfg->sites * cfg->dbits != 64) return -1;
   if (cfg->k < 1 || cfg->k > 8) return -1;
   if (cfg->selection > 1 || cfg->migration > 1) return -1;
   if (cfg->law > 1) return -1;
@@ -261,7 +264,7 @@ orc_run* orc_create(const orc_config* cfg, int record_lineage) {
   if (!r) return NULL;
   r->cfg = *cfg;
   r->log2pop = log2_exact(cfg->pop);
-  r->words = cfg->sites / 32;
+  r->words = cfg->sites * cfg->dbits / 32;
   r->islands = (uint64_t)cfg->width * cfg->height;
   r->agents = r->islands * cfg->pop;
   r->t = 0;
@@ -397,11 +400,21 @@ static void reproduce_island(orc_run* r, uint64_t i, uint64_t t, uint8_t* win_ro
       }
     }
 
+    /* the differentia: one bit, the top bit of the selection block's word
+     * 3; wider ones, the top dbits bits of word 0 of a block of their own
+     * (mutation stream, counter word 0 = slot + 256) */
     uint32_t site = orc_site_of(r->nT[child], cfg->sites);
     if (site != ORC_DISCARD) {
-      uint32_t bit = w[3] >> 31;
-      uint32_t* word = &r->nD[child * r->words + (site >> 5)];
-      *word = (*word & ~(1u << (site & 31))) | (bit << (site & 31));
+      uint32_t value = w[3] >> 31;
+      if (cfg->dbits > 1) {
+        uint32_t d[4];
+        draw(cfg, (uint32_t)s + 256u, (uint32_t)i, t, TAG_MUTATE, d);
+        value = d[0] >> (32 - cfg->dbits);
+      }
+      const uint32_t pos = site * cfg->dbits;
+      const uint32_t field = cfg->dbits == 32 ? ~0u : (1u << cfg->dbits) - 1u;
+      uint32_t* word = &r->nD[child * r->words + (pos >> 5)];
+      *word = (*word & ~(field << (pos & 31))) | (value << (pos & 31));
     }
     r->nT[child] = r->nT[child] + 1;
   }
@@ -753,21 +766,30 @@ int64_t orc_true_mrca(const orc_run* r, uint64_t agent_a, uint64_t agent_b) {
 /* 1/2, so kc matches in a row below that bound leave the MRCA earlier than */
 /* them with probability at most 2^-kc.                                     */
 /* ----------------------------------------------------------------------- */
-static uint32_t bit_at(const uint32_t* D, uint32_t site) { return (D[site >> 5] >> (site & 31)) & 1u; }
+/* The dbits-bit differentia held at a site. */
+static uint32_t field_at(const uint32_t* D, uint32_t site, uint32_t dbits) {
+  const uint32_t pos = site * dbits;
+  return (D[pos >> 5] >> (pos & 31)) & ((1u << dbits) - 1u);
+}
 
-void orc_mrca_interval(uint32_t Ta, const uint32_t* Da, uint32_t Tb, const uint32_t* Db,
-                       uint32_t sites, uint32_t kc, uint32_t* L, uint32_t* U) {
+void orc_mrca_interval_bits(uint32_t Ta, const uint32_t* Da, uint32_t Tb, const uint32_t* Db,
+                            uint32_t sites, uint32_t dbits, uint32_t kc, uint32_t* L, uint32_t* U) {
   uint32_t ea = orc_epoch(Ta, sites), eb = orc_epoch(Tb, sites);
   uint64_t step = (uint64_t)1 << (ea > eb ? ea : eb);
   uint64_t n = Ta < Tb ? Ta : Tb;
   uint64_t first_mismatch = n;
   for (uint64_t r = 0; r < n; r += step) {
     uint32_t site = orc_site_of(r, sites);
-    if (bit_at(Da, site) != bit_at(Db, site)) { first_mismatch = r; break; }
+    if (field_at(Da, site, dbits) != field_at(Db, site, dbits)) { first_mismatch = r; break; }
   }
   *U = (uint32_t)first_mismatch;
   uint64_t below = (first_mismatch + step - 1) / step; /* common ranks below the bound */
   *L = below < kc ? 0u : (uint32_t)((below - kc) * step + 1);
+}
+
+void orc_mrca_interval(uint32_t Ta, const uint32_t* Da, uint32_t Tb, const uint32_t* Db,
+                       uint32_t sites, uint32_t kc, uint32_t* L, uint32_t* U) {
+  orc_mrca_interval_bits(Ta, Da, Tb, Db, sites, 1, kc, L, U);
 }
 
 int orc_true_mrca_matrix(const orc_run* r, const uint64_t* ids, size_t n, int32_t* out) {
@@ -815,11 +837,17 @@ int orc_true_mrca_matrix(const orc_run* r, const uint64_t* ids, size_t n, int32_
   return 0;
 }
 
-void orc_mrca_interval_matrix(const uint32_t* T, const uint32_t* D, size_t n, uint32_t sites,
-                              uint32_t kc, uint32_t* L, uint32_t* U) {
-  const uint32_t words = sites / 32;
+void orc_mrca_interval_matrix_bits(const uint32_t* T, const uint32_t* D, size_t n,
+                                   uint32_t sites, uint32_t dbits, uint32_t kc, uint32_t* L,
+                                   uint32_t* U) {
+  const uint32_t words = sites * dbits / 32;
   for (size_t x = 0; x < n; ++x)
     for (size_t y = 0; y < n; ++y)
-      orc_mrca_interval(T[x], D + x * words, T[y], D + y * words, sites, kc, &L[x * n + y],
-                        &U[x * n + y]);
+      orc_mrca_interval_bits(T[x], D + x * words, T[y], D + y * words, sites, dbits, kc,
+                             &L[x * n + y], &U[x * n + y]);
+}
+
+void orc_mrca_interval_matrix(const uint32_t* T, const uint32_t* D, size_t n, uint32_t sites,
+                              uint32_t kc, uint32_t* L, uint32_t* U) {
+  orc_mrca_interval_matrix_bits(T, D, n, sites, 1, kc, L, U);
 }

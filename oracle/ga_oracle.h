@@ -37,7 +37,7 @@ typedef struct orc_config {
   uint32_t width;       /* islands per row (x extent) */
   uint32_t height;      /* rows (y extent); island id = y*width + x */
   uint32_t pop;         /* agents per island, power of two, 1..256 */
-  uint32_t sites;       /* surface sites S, 32 or 64 */
+  uint32_t sites;       /* surface sites S, a power of two in 4..64 */
   uint32_t k;           /* tournament size, 1..8 */
   uint32_t selection;   /* 1 tournament, 0 neutral (uniform parent) */
   uint32_t p32;         /* mutate iff a 32-bit draw is below this */
@@ -51,6 +51,8 @@ typedef struct orc_config {
   uint32_t model;       /* genome model: 0 the genome is its fitness (law 0 or 1);
                            1 OneMax, 2 Trap-4, both on a 64-bit string (law 0's
                            probability p flips one bit) */
+  uint32_t dbits;       /* bits per differentia: 1, 2, 4 or 8; sites * dbits is 32
+                           or 64 (the surface fills one or two words) */
 } orc_config;
 
 typedef struct orc_run orc_run;
@@ -144,6 +146,14 @@ void orc_mrca_interval_matrix(const uint32_t* T, const uint32_t* D, size_t n, ui
 void orc_mrca_interval(uint32_t Ta, const uint32_t* Da, uint32_t Tb,
                        const uint32_t* Db, uint32_t sites, uint32_t kc,
                        uint32_t* L, uint32_t* U);
+/* The same for dbits-bit differentia (sites * dbits = 32 or 64 bits of
+ * surface); g < *L then has probability at most 2^-(dbits * kc). */
+void orc_mrca_interval_bits(uint32_t Ta, const uint32_t* Da, uint32_t Tb, const uint32_t* Db,
+                            uint32_t sites, uint32_t dbits, uint32_t kc, uint32_t* L,
+                            uint32_t* U);
+void orc_mrca_interval_matrix_bits(const uint32_t* T, const uint32_t* D, size_t n,
+                                   uint32_t sites, uint32_t dbits, uint32_t kc, uint32_t* L,
+                                   uint32_t* U);
 
 #ifdef __cplusplus
 }
