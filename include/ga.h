@@ -66,7 +66,9 @@ typedef struct ga_config {
   uint32_t width;              /* islands per row, 1..65535 */
   uint32_t height;             /* rows, 1..65535; width * height * N < 2^31 */
   uint32_t pop_per_island;     /* N: power of two, 1..64 (Sec. 2 uses 32) */
-  uint32_t surface_sites;      /* S: 32 or 64 one-bit differentia */
+  uint32_t surface_sites;      /* S sites: 32 or 64 one-bit differentia (or, with
+                                * differentia_bits b > 1, a power of two with
+                                * S * b = 32 or 64) */
   uint32_t tournament_size;    /* k: 1..8 (Sec. 2 uses 5) */
   uint32_t selection;          /* 1 tournament, 0 neutral (uniform parent) */
   uint32_t mutation_threshold; /* p * 2^32: mutate iff a 32-bit draw < this */
@@ -85,8 +87,18 @@ typedef struct ga_config {
   /* Added later still; struct_size = offsetof(ga_config, schedule) gets the
    * synchronous schedule. */
   uint32_t schedule;           /* GA_SCHEDULE_SYNC or GA_SCHEDULE_ASYNC */
-  /* Added last; struct_size = offsetof(ga_config, genome_model) gets model 0. */
+  /* Added later; struct_size = offsetof(ga_config, genome_model) gets model 0. */
   uint32_t genome_model;       /* GA_MODEL_* below */
+  /* Added last; struct_size = offsetof(ga_config, differentia_bits) gets 1. */
+  uint32_t differentia_bits;   /* b: bits per differentia, 1, 2, 4 or 8, with
+                                * S * b = 32 or 64 (the surface keeps its 32- or
+                                * 64-bit footprint; wider differentia make a
+                                * spurious match at a common rank a 2^-b event
+                                * but leave fewer sites). A deposit writes the top
+                                * b bits of word 0 of the Philox block with
+                                * counter (slot + 256, island, t low word,
+                                * t high word * 4 + 3); b = 1 writes the top bit
+                                * of the selection block's word 3 as always. */
 } ga_config;
 
 /* Genome models (ga_config.genome_model). The paper's kernel serves any
@@ -167,7 +179,7 @@ int ga_step(ga_run* run, uint64_t n_gens);
 
 /* Copy the population at the start of the current generation to the host,
  * after waiting for the run's stream. fitness[agents], T[agents] and
- * surface_words[agents * S/32] (agent-major) may each be NULL; outbox, if not
+ * surface_words[agents * S*b/32] (agent-major) may each be NULL; outbox, if not
  * NULL, receives one ga_outbox_entry per island (the emissions the next
  * generation will absorb); generation, if not NULL, receives t. */
 int ga_read_population(ga_run* run, float* fitness, uint32_t* T,
@@ -191,7 +203,7 @@ int ga_write_strings(ga_run* run, const uint32_t* words);
  * sampled per island). agent_ids == NULL picks one agent per island from the
  * sampling stream at the current generation (n must equal the island count);
  * otherwise the n listed agents are gathered. Writes ids_out[n] (may be NULL),
- * T_out[n] and surface_words_out[n * S/32]. Synchronous. */
+ * T_out[n] and surface_words_out[n * S*b/32]. Synchronous. */
 int ga_extract_surfaces(ga_run* run, const uint64_t* agent_ids, size_t n,
                         uint64_t* ids_out, uint32_t* T_out,
                         uint32_t* surface_words_out);
@@ -264,7 +276,8 @@ typedef struct ga_batch ga_batch;
 int ga_batch_create(void* hip_stream, ga_batch** out);
 /* Add a run (created by ga_init, bound to any stream; from now on it is
  * advanced only through the batch) with a generation budget: the batch stops
- * advancing it after budget more generations. Returns GA_OK. */
+ * advancing it after budget more generations. Returns GA_OK; GA_EINVAL for an
+ * asynchronous run, a genome model with a string, or differentia_bits > 1. */
 int ga_batch_add(ga_batch* batch, ga_run* run, uint64_t budget);
 /* Remove a member (after waiting for the batch's stream). */
 int ga_batch_remove(ga_batch* batch, ga_run* run);
@@ -305,6 +318,13 @@ size_t ga_mrca_workspace_bytes(size_t n);
 int ga_mrca_matrix(const uint32_t* T, const uint32_t* surface_words, size_t n,
                    uint32_t surface_sites, uint32_t kc, void* workspace,
                    size_t workspace_bytes, uint32_t* L, uint32_t* U, void* hip_stream);
+/* The same for surfaces of b = differentia_bits bits per site (S * b = 32 or
+ * 64; surface_words holds S * b / 32 words per surface). Differentia are
+ * compared as b-bit fields, so g < L has probability at most 2^-(b kc). */
+int ga_mrca_matrix_bits(const uint32_t* T, const uint32_t* surface_words, size_t n,
+                        uint32_t surface_sites, uint32_t differentia_bits, uint32_t kc,
+                        void* workspace, size_t workspace_bytes, uint32_t* L, uint32_t* U,
+                        void* hip_stream);
 
 /* Message for a return code, and the calling thread's last error message. */
 const char* ga_strerror(int code);

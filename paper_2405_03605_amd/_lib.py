@@ -41,7 +41,8 @@ class Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "struct_size", "width", "height", "pop_per_island", "surface_sites",
         "tournament_size", "selection", "mutation_threshold", "migration", "seed", "run_id",
-        "mutation_law", "beneficial_threshold", "schedule", "genome_model")]
+        "mutation_law", "beneficial_threshold", "schedule", "genome_model",
+        "differentia_bits")]
 
 
 class OutboxEntry(ctypes.Structure):
@@ -79,6 +80,7 @@ SIGNATURES = {
     "ga_batch_destroy": (None, [P]),
     "ga_mrca_workspace_bytes": (sz, [sz]),
     "ga_mrca_matrix": (i32, [P, P, sz, u32, u32, P, sz, P, P, P]),
+    "ga_mrca_matrix_bits": (i32, [P, P, sz, u32, u32, u32, P, sz, P, P, P]),
     "ga_strerror": (ctypes.c_char_p, [i32]),
     "ga_last_error": (ctypes.c_char_p, []),
 }

@@ -41,6 +41,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 constexpr uint32_t kConfigV1Size = (uint32_t)offsetof(ga_config, mutation_law);
 constexpr uint32_t kConfigV2Size = (uint32_t)offsetof(ga_config, schedule);
 constexpr uint32_t kConfigV3Size = (uint32_t)offsetof(ga_config, genome_model);
+constexpr uint32_t kConfigV4Size = (uint32_t)offsetof(ga_config, differentia_bits);
 
 bool is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
 uint32_t log2u(uint32_t v) {
@@ -49,6 +50,19 @@ uint32_t log2u(uint32_t v) {
   return l;
 }
 
+uint32_t dbits_of(const ga_config* c) {
+  return c->struct_size > kConfigV4Size ? c->differentia_bits : 1u;
+}
+
+// S sites of b-bit differentia filling one or two 32-bit words
+bool surface_ok(uint32_t sites, uint32_t b) {
+  if (b != 1 && b != 2 && b != 4 && b != 8) return false;
+  if (!is_pow2(sites) || sites < 4 || sites > 64) return false;
+  return sites * b == 32 || sites * b == 64;
+}
+
+size_t surface_words(const ga_config* c) { return c->surface_sites * dbits_of(c) / 32; }
+
 bool config_ok(const ga_config* c, std::string* why) {
   auto no = [&](const char* m) {
     if (why) *why = m;
@@ -56,19 +70,22 @@ bool config_ok(const ga_config* c, std::string* why) {
   };
   if (!c) return no("config is NULL");
   if (c->struct_size != sizeof(ga_config) && c->struct_size != kConfigV1Size &&
-      c->struct_size != kConfigV2Size && c->struct_size != kConfigV3Size)
+      c->struct_size != kConfigV2Size && c->struct_size != kConfigV3Size &&
+      c->struct_size != kConfigV4Size)
     return no("struct_size must be sizeof(ga_config)");
   if (c->width < 1 || c->width > 65535) return no("width must be in [1, 65535]");
   if (c->height < 1 || c->height > 65535) return no("height must be in [1, 65535]");
   if (!is_pow2(c->pop_per_island) || c->pop_per_island > 64)
     return no("pop_per_island must be a power of two in [1, 64]");
-  if (c->surface_sites != 32 && c->surface_sites != 64) return no("surface_sites must be 32 or 64");
+  if (!surface_ok(c->surface_sites, dbits_of(c)))
+    return no("surface_sites x differentia_bits must be 32 or 64 bits, differentia_bits 1, 2, "
+              "4 or 8, surface_sites a power of two >= 4");
   if (c->tournament_size < 1 || c->tournament_size > 8) return no("tournament_size must be in [1, 8]");
   if (c->selection > 1) return no("selection must be 0 or 1");
   if (c->migration > 1) return no("migration must be 0 or 1");
   if (c->struct_size > kConfigV2Size && c->schedule > GA_SCHEDULE_ASYNC)
     return no("schedule must be 0 (synchronous) or 1 (asynchronous)");
-  if (c->struct_size == sizeof(ga_config)) {
+  if (c->struct_size > kConfigV3Size) {
     if (c->genome_model > GA_MODEL_TRAP4)
       return no("genome_model must be 0 (fitness), 1 (OneMax) or 2 (Trap-4)");
     if (c->genome_model != GA_MODEL_FITNESS && c->mutation_law != 0)
@@ -100,13 +117,13 @@ bool is_async(const ga_config* c) {
 }
 
 uint32_t model_of(const ga_config* c) {
-  return c->struct_size == sizeof(ga_config) ? c->genome_model : GA_MODEL_FITNESS;
+  return c->struct_size > kConfigV3Size ? c->genome_model : GA_MODEL_FITNESS;
 }
 
 // words per AoS outbox entry: fitness, T, surface words, header, padding to 16 B;
 // with a string: fitness, T, two surface words, two string words, header, pad
 size_t outbox_stride(const ga_config* c) {
-  return c->surface_sites == 32 && model_of(c) == GA_MODEL_FITNESS ? 4 : 8;
+  return surface_words(c) == 1 && model_of(c) == GA_MODEL_FITNESS ? 4 : 8;
 }
 
 // Planes run 128 islands past the last 64-island boundary: a wavefront's last
@@ -120,7 +137,7 @@ size_t padded_islands(const ga_config* c) {
 Layout layout_of(const ga_config* c) {
   const size_t islands = padded_islands(c);
   const size_t agents = islands * c->pop_per_island;
-  const size_t words = c->surface_sites / 32;
+  const size_t words = surface_words(c);
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -385,7 +402,9 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   v.island_stride = (uint32_t)padded_islands(cfg);
   v.agent_stride = v.island_stride * cfg->pop_per_island;
   v.log2n = log2u(cfg->pop_per_island);
-  v.words = cfg->surface_sites / 32;
+  v.words = (uint32_t)surface_words(cfg);
+  v.s_log = log2u(cfg->surface_sites);
+  v.dlog = log2u(dbits_of(cfg));
   v.k = cfg->tournament_size;
   v.selection = cfg->selection;
   v.p32 = cfg->mutation_threshold;
@@ -741,6 +760,8 @@ int ga_batch_add(ga_batch* b, ga_run* r, uint64_t budget) {
     return fail(GA_EINVAL, "a batch advances synchronous runs only");
   if (r->view.model != GA_MODEL_FITNESS)
     return fail(GA_EINVAL, "a batch advances fitness-valued genomes only");
+  if (r->view.dlog != 0u)
+    return fail(GA_EINVAL, "a batch advances one-bit differentia only");
   if (r->batch) return fail(GA_ESTATE, "run is already in a batch");
   GA_HIP(hipStreamSynchronize(r->stream), "stream sync");
   unsigned long long left = budget;
@@ -918,19 +939,31 @@ void ga_batch_destroy(ga_batch* b) {
 
 size_t ga_mrca_workspace_bytes(size_t n) { return ga::mrca_workspace_bytes(n); }
 
-int ga_mrca_matrix(const uint32_t* T, const uint32_t* surface_words, size_t n,
-                   uint32_t surface_sites, uint32_t kc, void* workspace, size_t workspace_bytes,
-                   uint32_t* L, uint32_t* U, void* hip_stream) {
+int ga_mrca_matrix_bits(const uint32_t* T, const uint32_t* surface_words, size_t n,
+                        uint32_t surface_sites, uint32_t differentia_bits, uint32_t kc,
+                        void* workspace, size_t workspace_bytes, uint32_t* L, uint32_t* U,
+                        void* hip_stream) {
   if (n == 0) return GA_OK;
   if (n > 65535) return fail(GA_EINVAL, "n must be <= 65535");
-  if (surface_sites != 32 && surface_sites != 64) return fail(GA_EINVAL, "surface_sites must be 32 or 64");
+  if (!surface_ok(surface_sites, differentia_bits))
+    return fail(GA_EINVAL, "surface_sites x differentia_bits must be 32 or 64 bits");
   if (kc < 1) return fail(GA_EINVAL, "kc must be >= 1");
   if (!T || !surface_words || !workspace || !L || !U) return fail(GA_EINVAL, "NULL pointer");
   if (workspace_bytes < ga::mrca_workspace_bytes(n)) return fail(GA_ENOMEM, "workspace too small");
-  GA_HIP(ga::launch_mrca_matrix(T, surface_words, (uint32_t)n, surface_sites / 32, kc, workspace,
-                                L, U, static_cast<hipStream_t>(hip_stream)),
+  GA_HIP(ga::launch_mrca_matrix(T, surface_words, (uint32_t)n, log2u(surface_sites),
+                                log2u(differentia_bits), kc, workspace, L, U,
+                                static_cast<hipStream_t>(hip_stream)),
          "mrca launch");
   return GA_OK;
+}
+
+int ga_mrca_matrix(const uint32_t* T, const uint32_t* surface_words, size_t n,
+                   uint32_t surface_sites, uint32_t kc, void* workspace, size_t workspace_bytes,
+                   uint32_t* L, uint32_t* U, void* hip_stream) {
+  if (n != 0 && surface_sites != 32 && surface_sites != 64)
+    return fail(GA_EINVAL, "surface_sites must be 32 or 64");
+  return ga_mrca_matrix_bits(T, surface_words, n, surface_sites, 1, kc, workspace,
+                             workspace_bytes, L, U, hip_stream);
 }
 
 }  // extern "C"

@@ -51,6 +51,8 @@ struct RunView {
   // and, with a string, its two word planes pop_P[w * agent_stride + a]
   uint32_t model;
   uint32_t* pop_P;
+  // surface: S = 2^s_log sites of 2^dlog-bit differentia in `words` words
+  uint32_t s_log, dlog;
 };
 
 // Asynchronous pacing: no bound on how far an island may run ahead, and the
@@ -93,8 +95,8 @@ hipError_t launch_batch_advance(const RunView* views, uint32_t n_runs, uint64_t 
                                 hipStream_t stream);
 
 size_t mrca_workspace_bytes(size_t n);
-hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, uint32_t words,
-                              uint32_t kc, void* workspace, uint32_t* L, uint32_t* U,
-                              hipStream_t stream);
+hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, uint32_t s_log,
+                              uint32_t dlog, uint32_t kc, void* workspace, uint32_t* L,
+                              uint32_t* U, hipStream_t stream);
 
 }  // namespace ga

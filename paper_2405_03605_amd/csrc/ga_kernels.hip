@@ -246,14 +246,17 @@ struct AsyncCtx {
 // 5 * ipw + 1 entries (16 bytes for model 0, 32 with a string): arrivals
 // [4 * local + q], emissions [4 * ipw + local], and one scratch entry read when
 // a lane has no arrival.
-template <int LC, int SWC, bool ASYNC = false, int MODEL = kModelFitness>
+template <int LC, int SWC, bool ASYNC = false, int MODEL = kModelFitness, bool WIDE = false>
 __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base, uint64_t t,
                                                  uint4* lds, AsyncCtx* ax = nullptr) {
   constexpr bool kStr = MODEL != kModelFitness;  // genomes carry a string
   constexpr uint32_t ES = kStr ? 2u : 1u;        // 16-byte units per LDS entry
   const uint32_t L = LC >= 0 ? (uint32_t)LC : v.log2n;
   const uint32_t SW = SWC >= 0 ? (uint32_t)SWC : v.words;
-  const uint32_t s_log = 4u + SW;  // log2 S: 5 for 32 sites, 6 for 64
+  // surface: S = 2^s_log sites of 2^dlog-bit differentia; one bit (32 or 64
+  // sites) is fixed at compile time, WIDE reads both from the view
+  const uint32_t dlog = WIDE ? v.dlog : 0u;
+  const uint32_t s_log = WIDE ? v.s_log : 4u + SW;
   const uint32_t S = 1u << s_log;
   const uint32_t lane = __lane_id();
   const uint32_t N = 1u << L;
@@ -529,12 +532,21 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
       if (write) site = surface_site_walk(cT, e, s_log);
     }
     if (write) {
-      const uint32_t mask = 1u << (site & 31u);
-      const uint32_t bit = (r.w >> 31) ? mask : 0u;
-      if (SW == 1 || site < 32u) {
-        cD0 = (cD0 & ~mask) | bit;
+      // the differentia: one bit, the top bit of the selection block's w3;
+      // b = 2^dlog > 1 bits, the top b bits of word 0 of a block of their own
+      // (mutation stream, counter word 0 = slot + 256), drawn only by the
+      // lanes that write
+      const uint32_t pos = site << dlog;
+      uint32_t value = r.w >> 31;
+      if (WIDE)
+        value = philox10(slot + 256u, island, t_lo, t_hi4 | kStreamMutate, v.seed, v.run_id).x >>
+                (32u - (1u << dlog));
+      const uint32_t field = ((2u << ((1u << dlog) - 1u)) - 1u) << (pos & 31u);
+      const uint32_t bits = value << (pos & 31u);
+      if (SW == 1 || pos < 32u) {
+        cD0 = (cD0 & ~field) | bits;
       } else {
-        cD1 = (cD1 & ~mask) | bit;
+        cD1 = (cD1 & ~field) | bits;
       }
     }
     cT += 1u;
@@ -615,26 +627,26 @@ __device__ __forceinline__ uint4* wave_lds(uint32_t wave_in_group, uint32_t ipw,
   return ga_lds + wave_in_group * lds_entries(ipw) * units;
 }
 
-template <int LC, int SWC, int MODEL>
+template <int LC, int SWC, int MODEL, bool WIDE>
 __global__ __launch_bounds__(1024) void generation_kernel(RunView v, uint32_t gen_offset) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wig;
   const uint32_t base = wave * v.ipw;
   if (base >= v.islands) return;
-  chunk_generation<LC, SWC, false, MODEL>(v, base, *v.gen + gen_offset,
-                                          wave_lds(wig, v.ipw, MODEL ? 2u : 1u));
+  chunk_generation<LC, SWC, false, MODEL, WIDE>(v, base, *v.gen + gen_offset,
+                                                wave_lds(wig, v.ipw, MODEL ? 2u : 1u));
 }
 
 // Whole run in one workgroup: the generation loop stays on the GPU, with a
 // workgroup barrier between generations (the outbox hand-over).
-template <int LC, int SWC, int MODEL>
+template <int LC, int SWC, int MODEL, bool WIDE>
 __global__ __launch_bounds__(1024) void resident_kernel(RunView v, uint64_t n_gens) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t base = wig * v.ipw;
   const uint64_t t0 = *v.gen;
   uint4* lds = wave_lds(wig, v.ipw, MODEL ? 2u : 1u);
   for (uint64_t g = 0; g < n_gens; ++g) {
-    if (base < v.islands) chunk_generation<LC, SWC, false, MODEL>(v, base, t0 + g, lds);
+    if (base < v.islands) chunk_generation<LC, SWC, false, MODEL, WIDE>(v, base, t0 + g, lds);
     __syncthreads();
   }
   if (threadIdx.x == 0) *v.gen = t0 + n_gens;
@@ -666,7 +678,7 @@ __global__ void strings_init_kernel(RunView v) {
 // skew generations apart.
 // eight wavefronts per SIMD: registers (scalar ones included) must fit, or the
 // occupancy query would promise more resident wavefronts than the GPU holds
-template <int LC, int SWC, int MODEL>
+template <int LC, int SWC, int MODEL, bool WIDE>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, uint32_t skew) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -681,7 +693,7 @@ void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, ui
     for (uint32_t base = first; base < end; base += v.ipw) {
       const uint64_t lag = skew ? (base / v.ipw) % (skew + 1u) : 0u;
       if (step < lag || step - lag >= n_gens) continue;
-      chunk_generation<LC, SWC, true, MODEL>(v, base, t0 + step - lag, lds, &ax);
+      chunk_generation<LC, SWC, true, MODEL, WIDE>(v, base, t0 + step - lag, lds, &ax);
     }
   }
   if (__lane_id() == 0u && ax.gave_up)
@@ -689,10 +701,10 @@ void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, ui
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int LC, int SWC, int MODEL>
+template <int LC, int SWC, int MODEL, bool WIDE>
 hipError_t async_occupancy(int* groups, int block, size_t lds) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, async_kernel<LC, SWC, MODEL>, block,
-                                                      lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, async_kernel<LC, SWC, MODEL, WIDE>,
+                                                      block, lds);
 }
 
 __global__ void advance_kernel(unsigned long long* gen, uint64_t n) {
@@ -726,7 +738,8 @@ __global__ void gather_kernel(RunView v, const uint32_t* ids, uint32_t n, uint32
 }
 
 // Batched form: wavefront i works on tiles[i]; members whose budget for this
-// block is spent sit the generation out.
+// block is spent sit the generation out. Members are fitness-valued genomes
+// with one-bit differentia.
 // eight wavefronts per SIMD: the specialised bodies must fit 64 registers
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 void batch_generation_kernel(const RunView* __restrict__ views,
@@ -785,32 +798,35 @@ namespace {
 
 }  // namespace
 
-#define GA_SHAPES(KERNEL, M, L, SW, ...)                                       \
+#define GA_SHAPES(KERNEL, M, WD, L, SW, ...)                                   \
   switch ((L) * 2 + ((SW) - 1)) {                                              \
-    case 0: KERNEL<0, 1, M> __VA_ARGS__; break;                                \
-    case 1: KERNEL<0, 2, M> __VA_ARGS__; break;                                \
-    case 2: KERNEL<1, 1, M> __VA_ARGS__; break;                                \
-    case 3: KERNEL<1, 2, M> __VA_ARGS__; break;                                \
-    case 4: KERNEL<2, 1, M> __VA_ARGS__; break;                                \
-    case 5: KERNEL<2, 2, M> __VA_ARGS__; break;                                \
-    case 6: KERNEL<3, 1, M> __VA_ARGS__; break;                                \
-    case 7: KERNEL<3, 2, M> __VA_ARGS__; break;                                \
-    case 8: KERNEL<4, 1, M> __VA_ARGS__; break;                                \
-    case 9: KERNEL<4, 2, M> __VA_ARGS__; break;                                \
-    case 10: KERNEL<5, 1, M> __VA_ARGS__; break;                               \
-    case 11: KERNEL<5, 2, M> __VA_ARGS__; break;                               \
-    case 12: KERNEL<6, 1, M> __VA_ARGS__; break;                               \
-    case 13: KERNEL<6, 2, M> __VA_ARGS__; break;                               \
+    case 0: KERNEL<0, 1, M, WD> __VA_ARGS__; break;                            \
+    case 1: KERNEL<0, 2, M, WD> __VA_ARGS__; break;                            \
+    case 2: KERNEL<1, 1, M, WD> __VA_ARGS__; break;                            \
+    case 3: KERNEL<1, 2, M, WD> __VA_ARGS__; break;                            \
+    case 4: KERNEL<2, 1, M, WD> __VA_ARGS__; break;                            \
+    case 5: KERNEL<2, 2, M, WD> __VA_ARGS__; break;                            \
+    case 6: KERNEL<3, 1, M, WD> __VA_ARGS__; break;                            \
+    case 7: KERNEL<3, 2, M, WD> __VA_ARGS__; break;                            \
+    case 8: KERNEL<4, 1, M, WD> __VA_ARGS__; break;                            \
+    case 9: KERNEL<4, 2, M, WD> __VA_ARGS__; break;                            \
+    case 10: KERNEL<5, 1, M, WD> __VA_ARGS__; break;                           \
+    case 11: KERNEL<5, 2, M, WD> __VA_ARGS__; break;                           \
+    case 12: KERNEL<6, 1, M, WD> __VA_ARGS__; break;                           \
+    case 13: KERNEL<6, 2, M, WD> __VA_ARGS__; break;                           \
     default: return hipErrorInvalidValue;                                      \
   }
 
-// Dispatch to KERNEL<log2 N, surface words, genome model>.
-#define GA_DISPATCH(KERNEL, L, SW, M, ...)                                     \
+// Dispatch to KERNEL<log2 N, surface words, genome model, wide differentia>.
+#define GA_DISPATCH(KERNEL, L, SW, M, WIDE, ...)                               \
   do {                                                                         \
-    switch (M) {                                                               \
-      case 0: GA_SHAPES(KERNEL, 0, L, SW, __VA_ARGS__) break;                  \
-      case 1: GA_SHAPES(KERNEL, 1, L, SW, __VA_ARGS__) break;                  \
-      case 2: GA_SHAPES(KERNEL, 2, L, SW, __VA_ARGS__) break;                  \
+    switch ((M) * 2 + ((WIDE) ? 1 : 0)) {                                      \
+      case 0: GA_SHAPES(KERNEL, 0, false, L, SW, __VA_ARGS__) break;           \
+      case 1: GA_SHAPES(KERNEL, 0, true, L, SW, __VA_ARGS__) break;            \
+      case 2: GA_SHAPES(KERNEL, 1, false, L, SW, __VA_ARGS__) break;           \
+      case 3: GA_SHAPES(KERNEL, 1, true, L, SW, __VA_ARGS__) break;            \
+      case 4: GA_SHAPES(KERNEL, 2, false, L, SW, __VA_ARGS__) break;           \
+      case 5: GA_SHAPES(KERNEL, 2, true, L, SW, __VA_ARGS__) break;            \
       default: return hipErrorInvalidValue;                                    \
     }                                                                          \
   } while (0)
@@ -821,7 +837,7 @@ hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t wav
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
   const dim3 grid(groups), block(64 * waves_per_group);
   const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
-  GA_DISPATCH(generation_kernel, v.log2n, v.words, v.model,
+  GA_DISPATCH(generation_kernel, v.log2n, v.words, v.model, v.dlog != 0u,
               <<<grid, block, lds, stream>>>(v, gen_offset));
   return hipGetLastError();
 }
@@ -830,7 +846,7 @@ hipError_t launch_resident(const RunView& v, uint64_t n_gens, uint32_t waves, hi
   if (waves == 0 || waves > (uint32_t)kMaxWavesPerGroup) return hipErrorInvalidValue;
   const dim3 grid(1), block(64 * waves);
   const size_t lds = lds_bytes(v.ipw, waves, v.model);
-  GA_DISPATCH(resident_kernel, v.log2n, v.words, v.model,
+  GA_DISPATCH(resident_kernel, v.log2n, v.words, v.model, v.dlog != 0u,
               <<<grid, block, lds, stream>>>(v, n_gens));
   return hipGetLastError();
 }
@@ -842,7 +858,7 @@ hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint3
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
   const dim3 grid(groups), block(64 * waves_per_group);
   const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
-  GA_DISPATCH(async_kernel, v.log2n, v.words, v.model,
+  GA_DISPATCH(async_kernel, v.log2n, v.words, v.model, v.dlog != 0u,
               <<<grid, block, lds, stream>>>(v, chunks, n_gens, lead, skew));
   return hipGetLastError();
 }
@@ -854,7 +870,8 @@ hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, uint32_t* 
   if (e != hipSuccess) return e;
   const int block = 64 * (int)waves_per_group;
   const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
-  GA_DISPATCH(e = async_occupancy, v.log2n, v.words, v.model, (&groups, block, lds));
+  GA_DISPATCH(e = async_occupancy, v.log2n, v.words, v.model, v.dlog != 0u,
+              (&groups, block, lds));
   if (e != hipSuccess) return e;
   *waves = (uint32_t)groups * (uint32_t)cus * waves_per_group;
   return hipSuccess;

@@ -6,14 +6,17 @@
 // For two surfaces with deposit counters Ta, Tb on S sites, the ranks both
 // retain are the multiples of 2^e, e = max(e(Ta), e(Tb)), below min(Ta, Tb)
 // (e(n) = max(0, ceil(log2 n) - log2 S), "doubling steady" surface). Ranks
-// older than the MRCA hold identical bits, so the first common rank whose bits
-// differ bounds the MRCA's counter from above (U); kc matching common ranks in
-// a row below U make an MRCA earlier than them a 2^-kc event (L).
+// older than the MRCA hold identical differentia, so the first common rank
+// whose differentia differ bounds the MRCA's counter from above (U); kc
+// matching common ranks in a row below U make an MRCA earlier than them a
+// 2^-(b kc) event for b-bit differentia (L).
 //
 // Layout of the work: `normalize_kernel` turns each surface into its retained
-// bits in rank order (bit j = rank j * 2^e(T)), a 64-bit string; the pair
-// kernel keeps every 2^(e - e(T))-th bit of each string (stride compaction),
-// XORs them and takes the lowest set bit: O(1) per pair, integer only.
+// differentia in rank order (field j, b bits wide, = rank j * 2^e(T)), a
+// 64-bit string (S * b <= 64); for one-bit differentia the pair kernel keeps
+// every 2^(e - e(T))-th bit of each string (stride compaction), XORs them and
+// takes the lowest set bit, O(1) per pair; wider fields are compared field by
+// field up to the first mismatch (at most S <= 32 of them). Integer only.
 #include "ga_internal.hpp"
 
 namespace ga {
@@ -50,19 +53,22 @@ __device__ uint32_t site_of_retained(uint32_t r, uint32_t s) {
 }
 
 __global__ void normalize_kernel(const uint32_t* __restrict__ T, const uint32_t* __restrict__ D,
-                                 uint32_t n, uint32_t words, uint32_t s, Normalized* out) {
+                                 uint32_t n, uint32_t s, uint32_t dlog, Normalized* out) {
   const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n) return;
+  const uint32_t words = (1u << (s + dlog)) >> 5;  // S * b / 32
+  const uint32_t b = 1u << dlog;
+  const unsigned long long fmask = (1ull << b) - 1ull;
   const uint32_t t = T[a];
   const uint32_t e = epoch_of(t, s);
   const uint32_t count = t == 0u ? 0u : ((t - 1u) >> e) + 1u;  // ceil(t / 2^e) <= S
-  const uint32_t w0 = D[(size_t)a * words];
-  const uint32_t w1 = words > 1 ? D[(size_t)a * words + 1] : 0u;
+  const unsigned long long w = (unsigned long long)D[(size_t)a * words] |
+                               (words > 1 ? (unsigned long long)D[(size_t)a * words + 1] << 32
+                                          : 0ull);
   unsigned long long bits = 0ull;
   for (uint32_t j = 0; j < count; ++j) {
     const uint32_t site = site_of_retained(j << e, s);
-    const uint32_t word = site < 32u ? w0 : w1;
-    bits |= (unsigned long long)((word >> (site & 31u)) & 1u) << j;
+    bits |= ((w >> (site << dlog)) & fmask) << (j << dlog);
   }
   out[a] = Normalized{bits, t, e};
 }
@@ -83,7 +89,8 @@ __device__ __forceinline__ unsigned long long compact_stride(unsigned long long 
 // One thread per pair (x, y); rows of the grid are x, 64 consecutive y per
 // wavefront so the two output rows are written coalesced.
 __global__ __launch_bounds__(256) void pairs_kernel(const Normalized* __restrict__ nz, uint32_t n,
-                                                    uint32_t kc, uint32_t* __restrict__ L,
+                                                    uint32_t dlog, uint32_t kc,
+                                                    uint32_t* __restrict__ L,
                                                     uint32_t* __restrict__ U) {
   const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t x = blockIdx.y;
@@ -93,19 +100,28 @@ __global__ __launch_bounds__(256) void pairs_kernel(const Normalized* __restrict
   const uint32_t e = a.epoch > b.epoch ? a.epoch : b.epoch;
   const uint32_t tmin = a.T < b.T ? a.T : b.T;
   const uint32_t common = tmin == 0u ? 0u : ((tmin - 1u) >> e) + 1u;  // ranks j*2^e < tmin
-  const unsigned long long diff =
-      compact_stride(a.bits, e - a.epoch) ^ compact_stride(b.bits, e - b.epoch);
-  const unsigned long long mask = common >= 64u ? ~0ull : ((1ull << common) - 1ull);
-  const unsigned long long hit = diff & mask;
-  uint32_t upper, below;
-  if (hit) {
-    const uint32_t j = (uint32_t)__ffsll((long long)hit) - 1u;  // first mismatching common rank
-    upper = j << e;
-    below = j;
+  uint32_t j = common;  // first mismatching common rank index, or common
+  if (dlog == 0u) {
+    const unsigned long long diff =
+        compact_stride(a.bits, e - a.epoch) ^ compact_stride(b.bits, e - b.epoch);
+    const unsigned long long mask = common >= 64u ? ~0ull : ((1ull << common) - 1ull);
+    const unsigned long long hit = diff & mask;
+    if (hit) j = (uint32_t)__ffsll((long long)hit) - 1u;
   } else {
-    upper = tmin;
-    below = common;
+    // common rank i is field i << (e - epoch) of each string
+    const unsigned long long fmask = (1ull << (1u << dlog)) - 1ull;
+    const uint32_t da = e - a.epoch, db = e - b.epoch;
+    for (uint32_t i = 0; i < common; ++i) {
+      const unsigned long long fa = (a.bits >> ((i << da) << dlog)) & fmask;
+      const unsigned long long fb = (b.bits >> ((i << db) << dlog)) & fmask;
+      if (fa != fb) {
+        j = i;
+        break;
+      }
+    }
   }
+  const uint32_t upper = j < common ? j << e : tmin;
+  const uint32_t below = j;
   const size_t at = (size_t)x * n + y;
   U[at] = upper;
   L[at] = below < kc ? 0u : ((below - kc) << e) + 1u;
@@ -115,16 +131,15 @@ __global__ __launch_bounds__(256) void pairs_kernel(const Normalized* __restrict
 
 size_t mrca_workspace_bytes(size_t n) { return n * sizeof(Normalized); }
 
-hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, uint32_t words,
-                              uint32_t kc, void* workspace, uint32_t* L, uint32_t* U,
-                              hipStream_t stream) {
+hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, uint32_t s_log,
+                              uint32_t dlog, uint32_t kc, void* workspace, uint32_t* L,
+                              uint32_t* U, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   Normalized* nz = static_cast<Normalized*>(workspace);
-  const uint32_t s = 4u + words;  // log2 S
-  normalize_kernel<<<dim3((n + 255) / 256), dim3(256), 0, stream>>>(T, D, n, words, s, nz);
+  normalize_kernel<<<dim3((n + 255) / 256), dim3(256), 0, stream>>>(T, D, n, s_log, dlog, nz);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  pairs_kernel<<<dim3((n + 255) / 256, n), dim3(256), 0, stream>>>(nz, n, kc, L, U);
+  pairs_kernel<<<dim3((n + 255) / 256, n), dim3(256), 0, stream>>>(nz, n, dlog, kc, L, U);
   return hipGetLastError();
 }
 

@@ -19,14 +19,14 @@ import numpy as np
 from ._lib import check, load
 
 
-def mrca_matrix(T, D, sites: int, kc: int = 5, device=None):
+def mrca_matrix(T, D, sites: int, kc: int = 5, device=None, bits: int = 1):
     """(L, U) interval matrices for every pair of the n sampled surfaces, on the GPU.
-    T: (n,) deposit counters; D: (n, sites/32) surface words."""
+    T: (n,) deposit counters; D: (n, sites * bits / 32) surface words."""
     import torch
     lib = load()
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     Tn = np.ascontiguousarray(T, dtype=np.uint32)
-    Dn = np.ascontiguousarray(np.asarray(D, dtype=np.uint32).reshape(Tn.size, sites // 32))
+    Dn = np.ascontiguousarray(np.asarray(D, dtype=np.uint32).reshape(Tn.size, sites * bits // 32))
     n = Tn.size
     if n == 0:
         return np.zeros((0, 0), np.uint32), np.zeros((0, 0), np.uint32)
@@ -38,9 +38,9 @@ def mrca_matrix(T, D, sites: int, kc: int = 5, device=None):
     U = torch.empty((n, n), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
     P = ctypes.c_void_p
-    check(lib.ga_mrca_matrix(P(t_dev.data_ptr()), P(d_dev.data_ptr()), n, sites, kc,
-                             P(ws.data_ptr()), ws_bytes, P(L.data_ptr()), P(U.data_ptr()),
-                             P(stream.cuda_stream)))
+    check(lib.ga_mrca_matrix_bits(P(t_dev.data_ptr()), P(d_dev.data_ptr()), n, sites, bits, kc,
+                                  P(ws.data_ptr()), ws_bytes, P(L.data_ptr()), P(U.data_ptr()),
+                                  P(stream.cuda_stream)))
     return L.cpu().numpy().view(np.uint32), U.cpu().numpy().view(np.uint32)
 
 
@@ -92,8 +92,8 @@ def phylometrics(Z: np.ndarray) -> dict:
             "root_height": float(height[2 * n - 2]) if n > 1 else 0.0}
 
 
-def reconstruct(T, D, sites: int, kc: int = 5, device=None):
+def reconstruct(T, D, sites: int, kc: int = 5, device=None, bits: int = 1):
     """Tree (linkage matrix) and phylometrics for sampled surfaces."""
-    L, U = mrca_matrix(T, D, sites, kc, device)
+    L, U = mrca_matrix(T, D, sites, kc, device, bits)
     Z = upgma(estimated_distance(T, L, U))
     return Z, phylometrics(Z)

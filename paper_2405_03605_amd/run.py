@@ -10,8 +10,8 @@ import numpy as np
 from ._lib import (FORM_AUTO, GA_EINVAL, Config, GAError, OutboxEntry, check, load)
 
 CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32", "migration",
-                 "seed", "run_id", "law", "p_ben32", "schedule", "model")
-OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "schedule": 0, "model": 0}
+                 "seed", "run_id", "law", "p_ben32", "schedule", "model", "dbits")
+OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "schedule": 0, "model": 0, "dbits": 1}
 
 
 def _fields(cfg: dict) -> dict:
@@ -30,7 +30,8 @@ def make_config(cfg: dict) -> Config:
                   mutation_threshold=cfg["p32"], migration=cfg["migration"],
                   seed=cfg["seed"], run_id=cfg["run_id"],
                   mutation_law=cfg.get("law", 0), beneficial_threshold=cfg.get("p_ben32", 0),
-                  schedule=cfg.get("schedule", 0), genome_model=cfg.get("model", 0))
+                  schedule=cfg.get("schedule", 0), genome_model=cfg.get("model", 0),
+                  differentia_bits=cfg.get("dbits", 1))
 
 
 def state_bytes(cfg: dict) -> int:
@@ -61,7 +62,7 @@ class GARun:
         self.state_bytes = nbytes
         self.islands = self.cfg["width"] * self.cfg["height"]
         self.agents = self.islands * self.cfg["pop"]
-        self.words = self.cfg["sites"] // 32
+        self.words = self.cfg["sites"] * self.cfg["dbits"] // 32
 
     @property
     def handle(self):

@@ -44,7 +44,7 @@ def test_state_bytes_layout(lib):
     def expect(c):
         I = (c["width"] * c["height"] + 63) // 64 * 64 + 128
         A = I * c["pop"]
-        W = c["sites"] // 32
+        W = c["sites"] * c.get("dbits", 1) // 32
         al = lambda b: (b + 255) // 256 * 256
         ob = 4 if W == 1 else 8   # AoS outbox entry words
         # a genome model with a string adds two string planes and uses 32-byte
@@ -60,6 +60,9 @@ def test_state_bytes_layout(lib):
         assert ga.state_bytes(c) == expect(c)
         a = dict(c, schedule=1)
         assert ga.state_bytes(a) == expect(a) > ga.state_bytes(c)
+        for sites, bits in ((16, 4), (8, 8), (16, 2), (4, 8)):
+            w = dict(c, sites=sites, dbits=bits)
+            assert ga.state_bytes(w) == expect(w)
         for model in (1, 2):
             m = dict(c, model=model)
             assert ga.state_bytes(m) == expect(m) > ga.state_bytes(c)
@@ -74,7 +77,8 @@ def test_state_bytes_layout(lib):
     dict(k=9), dict(width=0), dict(height=0), dict(width=70000), dict(selection=2),
     dict(migration=3), dict(width=65535, height=65535, pop=64), dict(width=65535, height=8193, pop=2),
     dict(law=2), dict(law=1, p32=2 ** 32 - 10, p_ben32=100), dict(schedule=2), dict(model=3),
-    dict(model=1, law=1, p_ben32=5)])
+    dict(model=1, law=1, p_ben32=5), dict(sites=32, dbits=4), dict(sites=64, dbits=2),
+    dict(sites=16, dbits=3), dict(sites=2, dbits=16), dict(sites=12, dbits=4)])
 def test_invalid_configs_rejected(lib, bad):
     c = make_config(run_config(**bad))
     assert lib.ga_state_bytes(ctypes.byref(c)) == 0
@@ -128,3 +132,8 @@ def test_first_release_config_size_accepted(lib):
     async_bytes = lib.ga_state_bytes(ct.byref(make_config(run_config(schedule=1))))
     c.struct_size = _lib.Config.genome_model.offset
     assert lib.ga_state_bytes(ct.byref(c)) == async_bytes
+    # size before the differentia width: one bit per site, so 16 sites is invalid
+    c = make_config(run_config(sites=16, dbits=4))
+    assert lib.ga_state_bytes(ct.byref(c)) > 0
+    c.struct_size = _lib.Config.differentia_bits.offset
+    assert lib.ga_state_bytes(ct.byref(c)) == 0

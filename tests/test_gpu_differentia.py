@@ -1,0 +1,91 @@
+"""GPU parity for wider differentia (b = 2, 4, 8 bits per site at the surface's
+32- or 64-bit footprint): surfaces, T, fitness and generation equal the CPU
+oracle bit for bit across (S, b) shapes, launch forms, edge shapes and the
+asynchronous schedule (batches refuse them); the all-pairs MRCA intervals of b-bit surfaces
+equal the oracle's."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import assert_same_state, oracle_after, say
+from paper_2405_03605_amd import (ASYNC_UNPACED, FORM_RESIDENT, FORM_STREAMING, GABatch, GAError,
+                                  GARun, phylo)
+from paper_2405_03605_amd.workloads import run_config
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(32, 2), (16, 4), (8, 8), (16, 2), (8, 4), (4, 8)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("sites,bits", SHAPES)
+@pytest.mark.parametrize("form", [FORM_STREAMING, FORM_RESIDENT])
+def test_wide_parity(sites, bits, form):
+    cfg = run_config(width=9, height=7, pop=16, sites=sites, dbits=bits, k=3)
+    say(f"S={sites} b={bits} form {form}")
+    run = GARun(cfg)
+    run.set_launch(0, 0, form)
+    for n in (1, 60, 239):
+        run.step(n)
+    got = run.read()
+    run.close()
+    assert_same_state(got, oracle_after(cfg, 300), f"S={sites} b={bits} form {form}")
+
+
+@pytest.mark.parametrize("kw", [dict(pop=1, width=20, height=5), dict(pop=64, width=5, height=4),
+                                dict(pop=8, width=1, height=11, selection=0),
+                                dict(pop=32, width=40, height=30, law=1, p_ben32=12884902,
+                                     p32=1417339207, k=5),
+                                dict(pop=32, width=12, height=12, model=2)])
+def test_wide_edges(kw):
+    cfg = run_config(sites=8, dbits=8, **kw)
+    run = GARun(cfg)
+    run.step(400)
+    got = run.read()
+    run.close()
+    assert_same_state(got, oracle_after(cfg, 400), f"S=8 b=8 {kw}")
+
+
+def test_wide_async_and_batch_refusal():
+    run = GARun(run_config(width=7, height=5, pop=8, sites=16, dbits=4))
+    batch = GABatch()
+    with pytest.raises(GAError):
+        batch.add(run, 10)
+    batch.close()
+    run.close()
+    cfg = run_config(width=17, height=9, pop=16, sites=16, dbits=4, schedule=1)
+    run = GARun(cfg)
+    run.set_launch(4)
+    run.set_async(1, ASYNC_UNPACED, 2)
+    run.step(120)
+    ref = oracle.OracleRun({k: v for k, v in cfg.items() if k != "schedule"})
+    ref.step_async(120, 4, 2)
+    assert_same_state(run.read(), ref, "async skewed S=16 b=4")
+    run.close()
+
+
+@pytest.mark.parametrize("sites,bits", SHAPES)
+def test_wide_mrca_matrix(sites, bits):
+    cfg = run_config(width=24, height=16, pop=16, sites=sites, dbits=bits, seed=77)
+    run = GARun(cfg)
+    run.step(700)
+    ids, T, D = run.extract()
+    run.close()
+    rng = np.random.default_rng(sites * bits)
+    T2 = np.concatenate([T, rng.integers(0, 2 ** 31, 40).astype(np.uint32), [0, 1, sites - 1, sites]
+                         ]).astype(np.uint32)
+    D2 = np.concatenate([D, rng.integers(0, 2 ** 32, (44, D.shape[1]), dtype=np.uint64)
+                         .astype(np.uint32)])
+    for kc in (1, 3):
+        L, U = phylo.mrca_matrix(T2, D2, sites, kc, bits=bits)
+        L0, U0 = oracle.mrca_interval_matrix(T2, D2, sites, kc, bits)
+        assert np.array_equal(U, U0) and np.array_equal(L, L0), (sites, bits, kc)
