@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
 class _Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "width", "height", "pop", "sites", "k", "selection", "p32", "migration",
-        "seed", "run_id", "law", "p_ben32", "model", "dbits")]
+        "seed", "run_id", "law", "p_ben32", "model", "dbits", "policy")]
 
 
 _lib = None
@@ -92,6 +92,14 @@ def _load():
     lib.orc_true_mrca_matrix.restype = ctypes.c_int
     lib.orc_mrca_interval_matrix.argtypes = [P, P, sz, u32, u32, P, P]
     lib.orc_mrca_interval_bits.argtypes = [u32, P, u32, P, u32, u32, u32, P, P]
+    lib.orc_site_of_tilted.argtypes = [u64, u32]
+    lib.orc_site_of_tilted.restype = u32
+    lib.orc_site_of_policy.argtypes = [u64, u32, u32]
+    lib.orc_site_of_policy.restype = u32
+    lib.orc_retained.argtypes = [u64, u32, u32, P]
+    lib.orc_retained.restype = sz
+    lib.orc_mrca_interval_policy.argtypes = [u32, P, u32, P, u32, u32, u32, u32, P, P]
+    lib.orc_mrca_interval_matrix_policy.argtypes = [P, P, sz, u32, u32, u32, u32, P, P]
     lib.orc_mrca_interval_matrix_bits.argtypes = [P, P, sz, u32, u32, u32, P, P]
     lib.orc_get_payload.argtypes = [P, P]
     lib.orc_set_payload.argtypes = [P, P]
@@ -134,33 +142,55 @@ def site_of_range(first: int, count: int, sites: int) -> np.ndarray:
     return out
 
 
-def mrca_interval(Ta: int, Da, Tb: int, Db, sites: int, kc: int = 5, bits: int = 1):
+def mrca_interval(Ta: int, Da, Tb: int, Db, sites: int, kc: int = 5, bits: int = 1,
+                  policy: int = 0, general: bool = False):
     """(L, U) bounds on the MRCA's deposit counter from two surfaces of
-    ``sites`` differentia of ``bits`` bits each."""
+    ``sites`` differentia of ``bits`` bits each under a surface policy (0
+    steady, 1 tilted). The steady policy uses its closed form unless
+    ``general`` asks for the retained-rank estimator every policy uses."""
     a = np.ascontiguousarray(Da, dtype=np.uint32)
     b = np.ascontiguousarray(Db, dtype=np.uint32)
     L = ctypes.c_uint32()
     U = ctypes.c_uint32()
-    _load().orc_mrca_interval_bits(Ta, _ptr(a), Tb, _ptr(b), sites, bits, kc,
-                                   ctypes.byref(L), ctypes.byref(U))
+    if policy == 0 and not general:
+        _load().orc_mrca_interval_bits(Ta, _ptr(a), Tb, _ptr(b), sites, bits, kc,
+                                       ctypes.byref(L), ctypes.byref(U))
+    else:
+        _load().orc_mrca_interval_policy(Ta, _ptr(a), Tb, _ptr(b), sites, bits, policy, kc,
+                                         ctypes.byref(L), ctypes.byref(U))
     return int(L.value), int(U.value)
 
 
-def mrca_interval_matrix(T, D, sites: int, kc: int = 5, bits: int = 1):
+def site_of_tilted(rank: int, sites: int) -> int:
+    return int(_load().orc_site_of_tilted(rank, sites))
+
+
+def retained(n: int, sites: int, policy: int) -> np.ndarray:
+    """Ranks a surface holds after n deposits, ascending."""
+    out = np.empty(64, dtype=np.uint64)
+    c = _load().orc_retained(n, sites, policy, _ptr(out))
+    return out[:c].copy()
+
+
+def mrca_interval_matrix(T, D, sites: int, kc: int = 5, bits: int = 1, policy: int = 0):
     """(L, U) matrices for every pair of the n surfaces (T[n], D[n, S*bits/32])."""
     Ta = np.ascontiguousarray(T, dtype=np.uint32)
     Da = np.ascontiguousarray(D, dtype=np.uint32)
     n = Ta.size
     L = np.empty((n, n), dtype=np.uint32)
     U = np.empty((n, n), dtype=np.uint32)
-    _load().orc_mrca_interval_matrix_bits(_ptr(Ta), _ptr(Da), n, sites, bits, kc, _ptr(L),
-                                          _ptr(U))
+    if policy == 0:
+        _load().orc_mrca_interval_matrix_bits(_ptr(Ta), _ptr(Da), n, sites, bits, kc, _ptr(L),
+                                              _ptr(U))
+    else:
+        _load().orc_mrca_interval_matrix_policy(_ptr(Ta), _ptr(Da), n, sites, bits, policy, kc,
+                                                _ptr(L), _ptr(U))
     return L, U
 
 
 CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32",
-                 "migration", "seed", "run_id", "law", "p_ben32", "model", "dbits")
-OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "model": 0, "dbits": 1}
+                 "migration", "seed", "run_id", "law", "p_ben32", "model", "dbits", "policy")
+OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "model": 0, "dbits": 1, "policy": 0}
 
 
 def _fields(cfg: dict) -> dict:

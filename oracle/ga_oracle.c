@@ -125,6 +125,58 @@ uint32_t orc_site_of(uint64_t rank, uint32_t sites) {
   }
 }
 
+/* ----------------------------------------------------------------------- */
+/* Surface policy "tilted" (recency-proportional resolution), S = 32 m      */
+/* sites as 32 levels of m slots. A rank with k trailing zero bits (k       */
+/* capped at 31; rank 0 counts as 31) belongs to level k and overwrites     */
+/* slot (r >> (k + 1)) mod m of it (slot (r >> 31) mod m on level 31), so   */
+/* each level holds its m most recent ranks. Ranks with k trailing zeros    */
+/* come once every 2^(k+1) deposits, so level k's ranks are under about     */
+/* m 2^(k+1) deposits old: the retained ranks thin out in proportion to    */
+/* their age, and every deposit is written (no discards).                   */
+/* ----------------------------------------------------------------------- */
+uint32_t orc_site_of_tilted(uint64_t rank, uint32_t sites) {
+  const uint32_t m = sites / 32;
+  uint32_t k = 0;
+  while (k < 31 && ((rank >> k) & 1u) == 0) ++k;
+  const uint64_t slot = k < 31 ? (rank >> (k + 1)) % m : (rank >> 31) % m;
+  return k * m + (uint32_t)slot;
+}
+
+uint32_t orc_site_of_policy(uint64_t rank, uint32_t sites, uint32_t policy) {
+  return policy == 1 ? orc_site_of_tilted(rank, sites) : orc_site_of(rank, sites);
+}
+
+static int cmp_u64(const void* a, const void* b) {
+  const uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* Ranks whose differentia a surface holds after n deposits, ascending;
+ * returns their count (at most S). Steady: the multiples of 2^e(n) below n.
+ * Tilted: per level, its m most recent ranks below n. */
+size_t orc_retained(uint64_t n, uint32_t sites, uint32_t policy, uint64_t* out) {
+  size_t c = 0;
+  if (n == 0) return 0;
+  if (policy == 0) {
+    const uint64_t step = (uint64_t)1 << orc_epoch(n, sites);
+    for (uint64_t r = 0; r < n; r += step) out[c++] = r;
+    return c;
+  }
+  const uint32_t m = sites / 32;
+  for (uint32_t k = 0; k < 31; ++k) {
+    /* odd multiples 2^k (2j + 1) <= n - 1 */
+    const uint64_t q = (n - 1) >> k;
+    if (q == 0) continue;
+    const uint64_t jmax = (q - 1) / 2;
+    for (uint64_t i = 0; i < m && i <= jmax; ++i) out[c++] = ((2 * (jmax - i) + 1) << k);
+  }
+  const uint64_t imax = (n - 1) >> 31; /* multiples of 2^31 below n */
+  for (uint64_t i = 0; i < m && i <= imax; ++i) out[c++] = (imax - i) << 31;
+  qsort(out, c, sizeof(uint64_t), cmp_u64);
+  return c;
+}
+
 void orc_site_of_range(uint64_t first, size_t count, uint32_t sites, uint32_t* out) {
   for (size_t i = 0; i < count; ++i) out[i] = orc_site_of(first + i, sites);
 }
@@ -179,6 +231,7 @@ struct orc_run {
 };
 
 static int is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
+uint32_t orc_site_of_policy(uint64_t rank, uint32_t sites, uint32_t policy);
 
 int orc_validate(const orc_config* cfg) {
   if (!cfg) return -1;
@@ -188,6 +241,8 @@ int orc_validate(const orc_config* cfg) {
   if (cfg->dbits != 1 && cfg->dbits != 2 && cfg->dbits != 4 && cfg->dbits != 8) return -1;
   if (!is_pow2(cfg->sites) || cfg->sites < 4 || cfg->sites > 64) return -1;
   if (cfg->sites * cfg->dbits != 32 && cfg->sites * cfg->dbits != 64) return -1;
+  if (cfg->policy > 1) return -1;
+  if (cfg->policy == 1 && cfg->sites != 32 && cfg->sites != 64) return -1;
   if (cfg->k < 1 || cfg->k > 8) return -1;
   if (cfg->selection > 1 || cfg->migration > 1) return -1;
   if (cfg->law > 1) return -1;
@@ -403,7 +458,7 @@ static void reproduce_island(orc_run* r, uint64_t i, uint64_t t, uint8_t* win_ro
     /* the differentia: one bit, the top bit of the selection block's word
      * 3; wider ones, the top dbits bits of word 0 of a block of their own
      * (mutation stream, counter word 0 = slot + 256) */
-    uint32_t site = orc_site_of(r->nT[child], cfg->sites);
+    uint32_t site = orc_site_of_policy(r->nT[child], cfg->sites, cfg->policy);
     if (site != ORC_DISCARD) {
       uint32_t value = w[3] >> 31;
       if (cfg->dbits > 1) {
@@ -790,6 +845,41 @@ void orc_mrca_interval_bits(uint32_t Ta, const uint32_t* Da, uint32_t Tb, const 
 void orc_mrca_interval(uint32_t Ta, const uint32_t* Da, uint32_t Tb, const uint32_t* Db,
                        uint32_t sites, uint32_t kc, uint32_t* L, uint32_t* U) {
   orc_mrca_interval_bits(Ta, Da, Tb, Db, sites, 1, kc, L, U);
+}
+
+/* MRCA interval for any policy, from the retained ranks: the common ranks
+ * c_0 < c_1 < ... are compared oldest first; U is the first whose
+ * differentia differ (or min(Ta, Tb)); L = c_{j - kc} + 1 for the first
+ * mismatch index j, or 0 if fewer than kc common ranks lie below it. */
+void orc_mrca_interval_policy(uint32_t Ta, const uint32_t* Da, uint32_t Tb, const uint32_t* Db,
+                              uint32_t sites, uint32_t dbits, uint32_t policy, uint32_t kc,
+                              uint32_t* L, uint32_t* U) {
+  uint64_t ra[64], rb[64], common[64];
+  const size_t na = orc_retained(Ta, sites, policy, ra);
+  const size_t nb = orc_retained(Tb, sites, policy, rb);
+  size_t n = 0, x = 0, y = 0;
+  while (x < na && y < nb) {
+    if (ra[x] == rb[y]) { common[n++] = ra[x]; ++x; ++y; }
+    else if (ra[x] < rb[y]) ++x;
+    else ++y;
+  }
+  size_t j = n;
+  for (size_t i = 0; i < n; ++i) {
+    const uint32_t site = orc_site_of_policy(common[i], sites, policy);
+    if (field_at(Da, site, dbits) != field_at(Db, site, dbits)) { j = i; break; }
+  }
+  *U = j < n ? (uint32_t)common[j] : (Ta < Tb ? Ta : Tb);
+  *L = j >= kc ? (uint32_t)(common[j - kc] + 1) : 0u;
+}
+
+void orc_mrca_interval_matrix_policy(const uint32_t* T, const uint32_t* D, size_t n,
+                                     uint32_t sites, uint32_t dbits, uint32_t policy, uint32_t kc,
+                                     uint32_t* L, uint32_t* U) {
+  const uint32_t words = sites * dbits / 32;
+  for (size_t x = 0; x < n; ++x)
+    for (size_t y = 0; y < n; ++y)
+      orc_mrca_interval_policy(T[x], D + x * words, T[y], D + y * words, sites, dbits, policy,
+                               kc, &L[x * n + y], &U[x * n + y]);
 }
 
 int orc_true_mrca_matrix(const orc_run* r, const uint64_t* ids, size_t n, int32_t* out) {

@@ -53,6 +53,8 @@ typedef struct orc_config {
                            probability p flips one bit) */
   uint32_t dbits;       /* bits per differentia: 1, 2, 4 or 8; sites * dbits is 32
                            or 64 (the surface fills one or two words) */
+  uint32_t policy;      /* surface policy: 0 "doubling steady", 1 "tilted"
+                           (recency-proportional; sites 32 or 64) */
 } orc_config;
 
 typedef struct orc_run orc_run;
@@ -64,6 +66,25 @@ void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 uint32_t orc_site_of(uint64_t rank, uint32_t sites);
 /* Epoch after n deposits: max(0, ceil(log2 n) - log2 S). */
 uint32_t orc_epoch(uint64_t n, uint32_t sites);
+/* Tilted policy (S = 32 m sites, 32 levels of m slots): rank r with k
+ * trailing zeros (capped at 31; rank 0 counts as 31) takes slot
+ * (r >> (k+1)) mod m of level k ((r >> 31) mod m on level 31), site k m + slot.
+ * Every deposit is written. */
+uint32_t orc_site_of_tilted(uint64_t rank, uint32_t sites);
+/* Site of a deposit under policy 0 (steady) or 1 (tilted). */
+uint32_t orc_site_of_policy(uint64_t rank, uint32_t sites, uint32_t policy);
+/* Ranks a surface holds after n deposits, ascending (at most S); returns the
+ * count. */
+size_t orc_retained(uint64_t n, uint32_t sites, uint32_t policy, uint64_t* out);
+/* MRCA interval for any policy from the common retained ranks c_0 < c_1 < ...:
+ * U = the first with differing differentia (or min T), L = c_{j-kc} + 1 (0 if
+ * j < kc); P(g < L) <= 2^-(dbits kc). */
+void orc_mrca_interval_policy(uint32_t Ta, const uint32_t* Da, uint32_t Tb, const uint32_t* Db,
+                              uint32_t sites, uint32_t dbits, uint32_t policy, uint32_t kc,
+                              uint32_t* L, uint32_t* U);
+void orc_mrca_interval_matrix_policy(const uint32_t* T, const uint32_t* D, size_t n,
+                                     uint32_t sites, uint32_t dbits, uint32_t policy, uint32_t kc,
+                                     uint32_t* L, uint32_t* U);
 /* Bulk form for tests: out[i] = orc_site_of(first + i, sites). */
 void orc_site_of_range(uint64_t first, size_t count, uint32_t sites, uint32_t* out);
 
