@@ -89,7 +89,7 @@ typedef struct ga_config {
   uint32_t schedule;           /* GA_SCHEDULE_SYNC or GA_SCHEDULE_ASYNC */
   /* Added later; struct_size = offsetof(ga_config, genome_model) gets model 0. */
   uint32_t genome_model;       /* GA_MODEL_* below */
-  /* Added last; struct_size = offsetof(ga_config, differentia_bits) gets 1. */
+  /* Added later; struct_size = offsetof(ga_config, differentia_bits) gets 1. */
   uint32_t differentia_bits;   /* b: bits per differentia, 1, 2, 4 or 8, with
                                 * S * b = 32 or 64 (the surface keeps its 32- or
                                 * 64-bit footprint; wider differentia make a
@@ -99,7 +99,23 @@ typedef struct ga_config {
                                 * counter (slot + 256, island, t low word,
                                 * t high word * 4 + 3); b = 1 writes the top bit
                                 * of the selection block's word 3 as always. */
+  /* Added last; struct_size = offsetof(ga_config, surface_policy) gets steady. */
+  uint32_t surface_policy;     /* GA_POLICY_STEADY or GA_POLICY_TILTED */
 } ga_config;
+
+/* Surface policies (ga_config.surface_policy): which site a deposit of rank r
+ * overwrites.
+ * GA_POLICY_STEADY ("doubling steady"): after n deposits the multiples of
+ * 2^e(n) below n are kept, e(n) = max(0, ceil(log2 n) - log2 S); evenly spaced
+ * over the whole history.
+ * GA_POLICY_TILTED (recency-proportional; S = 32 or 64, m = S / 32): rank r
+ * with k trailing zero bits (k capped at 31; rank 0 counts as 31) overwrites
+ * slot (r >> (k+1)) mod m ((r >> 31) mod m for k = 31) of level k, site
+ * k * m + slot. Each level keeps its m most recent ranks, so about m ranks per
+ * doubling of age survive: recent ancestry is resolved finely, old ancestry
+ * coarsely. Every deposit is written. */
+#define GA_POLICY_STEADY 0
+#define GA_POLICY_TILTED 1
 
 /* Genome models (ga_config.genome_model). The paper's kernel serves any
  * fixed-length genome through three functions, initialize, mutate and
@@ -319,12 +335,15 @@ int ga_mrca_matrix(const uint32_t* T, const uint32_t* surface_words, size_t n,
                    uint32_t surface_sites, uint32_t kc, void* workspace,
                    size_t workspace_bytes, uint32_t* L, uint32_t* U, void* hip_stream);
 /* The same for surfaces of b = differentia_bits bits per site (S * b = 32 or
- * 64; surface_words holds S * b / 32 words per surface). Differentia are
- * compared as b-bit fields, so g < L has probability at most 2^-(b kc). */
-int ga_mrca_matrix_bits(const uint32_t* T, const uint32_t* surface_words, size_t n,
-                        uint32_t surface_sites, uint32_t differentia_bits, uint32_t kc,
-                        void* workspace, size_t workspace_bytes, uint32_t* L, uint32_t* U,
-                        void* hip_stream);
+ * 64; surface_words holds S * b / 32 words per surface) under either surface
+ * policy. The ranks both surfaces still hold, c_0 < c_1 < ..., are compared
+ * oldest first as b-bit fields: U is the first that differs (or min(Tx, Ty)),
+ * L = c_{j-kc} + 1 for its index j (0 if j < kc), so g < L has probability at
+ * most 2^-(b kc). The tilted policy needs no workspace (NULL is accepted). */
+int ga_mrca_matrix_ex(const uint32_t* T, const uint32_t* surface_words, size_t n,
+                      uint32_t surface_sites, uint32_t differentia_bits, uint32_t surface_policy,
+                      uint32_t kc, void* workspace, size_t workspace_bytes, uint32_t* L,
+                      uint32_t* U, void* hip_stream);
 
 /* Message for a return code, and the calling thread's last error message. */
 const char* ga_strerror(int code);

@@ -20,6 +20,7 @@ FORM_AUTO, FORM_STREAMING, FORM_RESIDENT = 0, 1, 2
 SCHEDULE_SYNC, SCHEDULE_ASYNC = 0, 1
 ASYNC_UNPACED = 0xFFFFFFFF
 MODEL_FITNESS, MODEL_ONEMAX, MODEL_TRAP4 = 0, 1, 2
+POLICY_STEADY, POLICY_TILTED = 0, 1
 
 
 class GAError(RuntimeError):
@@ -42,7 +43,7 @@ class Config(ctypes.Structure):
         "struct_size", "width", "height", "pop_per_island", "surface_sites",
         "tournament_size", "selection", "mutation_threshold", "migration", "seed", "run_id",
         "mutation_law", "beneficial_threshold", "schedule", "genome_model",
-        "differentia_bits")]
+        "differentia_bits", "surface_policy")]
 
 
 class OutboxEntry(ctypes.Structure):
@@ -80,7 +81,7 @@ SIGNATURES = {
     "ga_batch_destroy": (None, [P]),
     "ga_mrca_workspace_bytes": (sz, [sz]),
     "ga_mrca_matrix": (i32, [P, P, sz, u32, u32, P, sz, P, P, P]),
-    "ga_mrca_matrix_bits": (i32, [P, P, sz, u32, u32, u32, P, sz, P, P, P]),
+    "ga_mrca_matrix_ex": (i32, [P, P, sz, u32, u32, u32, u32, P, sz, P, P, P]),
     "ga_strerror": (ctypes.c_char_p, [i32]),
     "ga_last_error": (ctypes.c_char_p, []),
 }

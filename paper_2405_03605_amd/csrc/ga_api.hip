@@ -42,6 +42,7 @@ constexpr uint32_t kConfigV1Size = (uint32_t)offsetof(ga_config, mutation_law);
 constexpr uint32_t kConfigV2Size = (uint32_t)offsetof(ga_config, schedule);
 constexpr uint32_t kConfigV3Size = (uint32_t)offsetof(ga_config, genome_model);
 constexpr uint32_t kConfigV4Size = (uint32_t)offsetof(ga_config, differentia_bits);
+constexpr uint32_t kConfigV5Size = (uint32_t)offsetof(ga_config, surface_policy);
 
 bool is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
 uint32_t log2u(uint32_t v) {
@@ -52,6 +53,10 @@ uint32_t log2u(uint32_t v) {
 
 uint32_t dbits_of(const ga_config* c) {
   return c->struct_size > kConfigV4Size ? c->differentia_bits : 1u;
+}
+
+uint32_t policy_of(const ga_config* c) {
+  return c->struct_size > kConfigV5Size ? c->surface_policy : GA_POLICY_STEADY;
 }
 
 // S sites of b-bit differentia filling one or two 32-bit words
@@ -71,7 +76,7 @@ bool config_ok(const ga_config* c, std::string* why) {
   if (!c) return no("config is NULL");
   if (c->struct_size != sizeof(ga_config) && c->struct_size != kConfigV1Size &&
       c->struct_size != kConfigV2Size && c->struct_size != kConfigV3Size &&
-      c->struct_size != kConfigV4Size)
+      c->struct_size != kConfigV4Size && c->struct_size != kConfigV5Size)
     return no("struct_size must be sizeof(ga_config)");
   if (c->width < 1 || c->width > 65535) return no("width must be in [1, 65535]");
   if (c->height < 1 || c->height > 65535) return no("height must be in [1, 65535]");
@@ -83,6 +88,9 @@ bool config_ok(const ga_config* c, std::string* why) {
   if (c->tournament_size < 1 || c->tournament_size > 8) return no("tournament_size must be in [1, 8]");
   if (c->selection > 1) return no("selection must be 0 or 1");
   if (c->migration > 1) return no("migration must be 0 or 1");
+  if (policy_of(c) > GA_POLICY_TILTED) return no("surface_policy must be 0 (steady) or 1 (tilted)");
+  if (policy_of(c) == GA_POLICY_TILTED && c->surface_sites != 32 && c->surface_sites != 64)
+    return no("the tilted policy needs 32 or 64 sites");
   if (c->struct_size > kConfigV2Size && c->schedule > GA_SCHEDULE_ASYNC)
     return no("schedule must be 0 (synchronous) or 1 (asynchronous)");
   if (c->struct_size > kConfigV3Size) {
@@ -405,6 +413,7 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   v.words = (uint32_t)surface_words(cfg);
   v.s_log = log2u(cfg->surface_sites);
   v.dlog = log2u(dbits_of(cfg));
+  v.policy = policy_of(cfg);
   v.k = cfg->tournament_size;
   v.selection = cfg->selection;
   v.p32 = cfg->mutation_threshold;
@@ -760,8 +769,8 @@ int ga_batch_add(ga_batch* b, ga_run* r, uint64_t budget) {
     return fail(GA_EINVAL, "a batch advances synchronous runs only");
   if (r->view.model != GA_MODEL_FITNESS)
     return fail(GA_EINVAL, "a batch advances fitness-valued genomes only");
-  if (r->view.dlog != 0u)
-    return fail(GA_EINVAL, "a batch advances one-bit differentia only");
+  if (r->view.dlog != 0u || r->view.policy != GA_POLICY_STEADY)
+    return fail(GA_EINVAL, "a batch advances one-bit differentia on the steady policy only");
   if (r->batch) return fail(GA_ESTATE, "run is already in a batch");
   GA_HIP(hipStreamSynchronize(r->stream), "stream sync");
   unsigned long long left = budget;
@@ -939,19 +948,25 @@ void ga_batch_destroy(ga_batch* b) {
 
 size_t ga_mrca_workspace_bytes(size_t n) { return ga::mrca_workspace_bytes(n); }
 
-int ga_mrca_matrix_bits(const uint32_t* T, const uint32_t* surface_words, size_t n,
-                        uint32_t surface_sites, uint32_t differentia_bits, uint32_t kc,
-                        void* workspace, size_t workspace_bytes, uint32_t* L, uint32_t* U,
-                        void* hip_stream) {
+int ga_mrca_matrix_ex(const uint32_t* T, const uint32_t* surface_words, size_t n,
+                      uint32_t surface_sites, uint32_t differentia_bits, uint32_t surface_policy,
+                      uint32_t kc, void* workspace, size_t workspace_bytes, uint32_t* L,
+                      uint32_t* U, void* hip_stream) {
   if (n == 0) return GA_OK;
   if (n > 65535) return fail(GA_EINVAL, "n must be <= 65535");
   if (!surface_ok(surface_sites, differentia_bits))
     return fail(GA_EINVAL, "surface_sites x differentia_bits must be 32 or 64 bits");
+  if (surface_policy > GA_POLICY_TILTED) return fail(GA_EINVAL, "unknown surface_policy");
+  if (surface_policy == GA_POLICY_TILTED && surface_sites != 32 && surface_sites != 64)
+    return fail(GA_EINVAL, "the tilted policy needs 32 or 64 sites");
   if (kc < 1) return fail(GA_EINVAL, "kc must be >= 1");
-  if (!T || !surface_words || !workspace || !L || !U) return fail(GA_EINVAL, "NULL pointer");
-  if (workspace_bytes < ga::mrca_workspace_bytes(n)) return fail(GA_ENOMEM, "workspace too small");
+  if (!T || !surface_words || !L || !U) return fail(GA_EINVAL, "NULL pointer");
+  if (surface_policy == GA_POLICY_STEADY) {
+    if (!workspace) return fail(GA_EINVAL, "NULL workspace");
+    if (workspace_bytes < ga::mrca_workspace_bytes(n)) return fail(GA_ENOMEM, "workspace too small");
+  }
   GA_HIP(ga::launch_mrca_matrix(T, surface_words, (uint32_t)n, log2u(surface_sites),
-                                log2u(differentia_bits), kc, workspace, L, U,
+                                log2u(differentia_bits), surface_policy, kc, workspace, L, U,
                                 static_cast<hipStream_t>(hip_stream)),
          "mrca launch");
   return GA_OK;
@@ -962,8 +977,8 @@ int ga_mrca_matrix(const uint32_t* T, const uint32_t* surface_words, size_t n,
                    uint32_t* L, uint32_t* U, void* hip_stream) {
   if (n != 0 && surface_sites != 32 && surface_sites != 64)
     return fail(GA_EINVAL, "surface_sites must be 32 or 64");
-  return ga_mrca_matrix_bits(T, surface_words, n, surface_sites, 1, kc, workspace,
-                             workspace_bytes, L, U, hip_stream);
+  return ga_mrca_matrix_ex(T, surface_words, n, surface_sites, 1, GA_POLICY_STEADY, kc,
+                           workspace, workspace_bytes, L, U, hip_stream);
 }
 
 }  // extern "C"

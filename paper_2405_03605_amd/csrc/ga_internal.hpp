@@ -51,8 +51,9 @@ struct RunView {
   // and, with a string, its two word planes pop_P[w * agent_stride + a]
   uint32_t model;
   uint32_t* pop_P;
-  // surface: S = 2^s_log sites of 2^dlog-bit differentia in `words` words
-  uint32_t s_log, dlog;
+  // surface: S = 2^s_log sites of 2^dlog-bit differentia in `words` words,
+  // policy 0 "doubling steady", 1 "tilted"
+  uint32_t s_log, dlog, policy;
 };
 
 // Asynchronous pacing: no bound on how far an island may run ahead, and the
@@ -96,7 +97,7 @@ hipError_t launch_batch_advance(const RunView* views, uint32_t n_runs, uint64_t 
 
 size_t mrca_workspace_bytes(size_t n);
 hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, uint32_t s_log,
-                              uint32_t dlog, uint32_t kc, void* workspace, uint32_t* L,
-                              uint32_t* U, hipStream_t stream);
+                              uint32_t dlog, uint32_t policy, uint32_t kc, void* workspace,
+                              uint32_t* L, uint32_t* U, hipStream_t stream);
 
 }  // namespace ga

@@ -253,9 +253,11 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   constexpr uint32_t ES = kStr ? 2u : 1u;        // 16-byte units per LDS entry
   const uint32_t L = LC >= 0 ? (uint32_t)LC : v.log2n;
   const uint32_t SW = SWC >= 0 ? (uint32_t)SWC : v.words;
-  // surface: S = 2^s_log sites of 2^dlog-bit differentia; one bit (32 or 64
-  // sites) is fixed at compile time, WIDE reads both from the view
+  // surface: S = 2^s_log sites of 2^dlog-bit differentia under the steady
+  // policy; one bit on 32 or 64 sites is fixed at compile time, WIDE reads
+  // the width, the site count and the policy from the view
   const uint32_t dlog = WIDE ? v.dlog : 0u;
+  const bool tilted = WIDE && v.policy != 0u;
   const uint32_t s_log = WIDE ? v.s_log : 4u + SW;
   const uint32_t S = 1u << s_log;
   const uint32_t lane = __lane_id();
@@ -526,7 +528,13 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     // 7. stratum deposit at rank T, then T + 1
     uint32_t site = cT;
     bool write = true;
-    if (cT >= S) {
+    if (tilted) {
+      // level k = trailing zeros of T (capped at 31; T = 0 counts as 31), slot
+      // (T >> (k+1)) mod m ((T >> 31) mod m on level 31), m = S / 32
+      const uint32_t k = cT ? min((uint32_t)__ffs(cT) - 1u, 31u) : 31u;
+      const uint32_t slot = (k < 31u ? cT >> (k + 1u) : cT >> 31) & ((S >> 5) - 1u);
+      site = (k << (s_log - 5u)) + slot;
+    } else if (cT >= S) {
       const uint32_t e = (32u - __clz(cT)) - s_log;
       write = (cT & ((1u << e) - 1u)) == 0u;
       if (write) site = surface_site_walk(cT, e, s_log);
@@ -538,7 +546,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
       // lanes that write
       const uint32_t pos = site << dlog;
       uint32_t value = r.w >> 31;
-      if (WIDE)
+      if (WIDE && dlog != 0u)
         value = philox10(slot + 256u, island, t_lo, t_hi4 | kStreamMutate, v.seed, v.run_id).x >>
                 (32u - (1u << dlog));
       const uint32_t field = ((2u << ((1u << dlog) - 1u)) - 1u) << (pos & 31u);
@@ -837,7 +845,7 @@ hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t wav
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
   const dim3 grid(groups), block(64 * waves_per_group);
   const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
-  GA_DISPATCH(generation_kernel, v.log2n, v.words, v.model, v.dlog != 0u,
+  GA_DISPATCH(generation_kernel, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
               <<<grid, block, lds, stream>>>(v, gen_offset));
   return hipGetLastError();
 }
@@ -846,7 +854,7 @@ hipError_t launch_resident(const RunView& v, uint64_t n_gens, uint32_t waves, hi
   if (waves == 0 || waves > (uint32_t)kMaxWavesPerGroup) return hipErrorInvalidValue;
   const dim3 grid(1), block(64 * waves);
   const size_t lds = lds_bytes(v.ipw, waves, v.model);
-  GA_DISPATCH(resident_kernel, v.log2n, v.words, v.model, v.dlog != 0u,
+  GA_DISPATCH(resident_kernel, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
               <<<grid, block, lds, stream>>>(v, n_gens));
   return hipGetLastError();
 }
@@ -858,7 +866,7 @@ hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint3
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
   const dim3 grid(groups), block(64 * waves_per_group);
   const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
-  GA_DISPATCH(async_kernel, v.log2n, v.words, v.model, v.dlog != 0u,
+  GA_DISPATCH(async_kernel, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
               <<<grid, block, lds, stream>>>(v, chunks, n_gens, lead, skew));
   return hipGetLastError();
 }
@@ -870,7 +878,7 @@ hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, uint32_t* 
   if (e != hipSuccess) return e;
   const int block = 64 * (int)waves_per_group;
   const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
-  GA_DISPATCH(e = async_occupancy, v.log2n, v.words, v.model, v.dlog != 0u,
+  GA_DISPATCH(e = async_occupancy, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
               (&groups, block, lds));
   if (e != hipSuccess) return e;
   *waves = (uint32_t)groups * (uint32_t)cus * waves_per_group;

@@ -127,14 +127,88 @@ __global__ __launch_bounds__(256) void pairs_kernel(const Normalized* __restrict
   L[at] = below < kc ? 0u : ((below - kc) << e) + 1u;
 }
 
+// Tilted surfaces (S = 32 m sites, level k = site / m, slot j = site % m):
+// the rank a slot holds after T deposits is the most recent rank below T of
+// its level whose index along the level is j mod m. A rank sits at one site
+// whatever T is, so the ranks two surfaces share are the slots where both
+// hold the same rank.
+__device__ __forceinline__ bool tilted_rank(uint32_t T, uint32_t k, uint32_t j, uint32_t m,
+                                            uint32_t* rank) {
+  if (T == 0u) return false;
+  // level k < 31: ranks 2^k (2i + 1); level 31: ranks i 2^31; slot = i mod m
+  const uint32_t q = (T - 1u) >> k;
+  if (k < 31u && q == 0u) return false;
+  const uint32_t imax = k < 31u ? (q - 1u) >> 1 : q;
+  if (imax < j) return false;
+  const uint32_t i = imax - ((imax - j) & (m - 1u));
+  *rank = k < 31u ? ((2u * i + 1u) << k) : (i << 31);
+  return true;
+}
+
+// One thread per pair: U = the oldest common rank whose differentia differ
+// (or min(Ta, Tb)); L = the kc-th common rank below U, plus one (0 if fewer).
+__global__ __launch_bounds__(256) void pairs_tilted_kernel(const uint32_t* __restrict__ T,
+                                                           const uint32_t* __restrict__ D,
+                                                           uint32_t n, uint32_t s_log,
+                                                           uint32_t dlog, uint32_t kc,
+                                                           uint32_t* __restrict__ L,
+                                                           uint32_t* __restrict__ U) {
+  const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t x = blockIdx.y;
+  if (y >= n) return;
+  const uint32_t S = 1u << s_log, m = S >> 5, words = (S << dlog) >> 5;
+  const uint32_t ta = T[x], tb = T[y];
+  const unsigned long long wa = (unsigned long long)D[(size_t)x * words] |
+                                (words > 1 ? (unsigned long long)D[(size_t)x * words + 1] << 32
+                                           : 0ull);
+  const unsigned long long wb = (unsigned long long)D[(size_t)y * words] |
+                                (words > 1 ? (unsigned long long)D[(size_t)y * words + 1] << 32
+                                           : 0ull);
+  const unsigned long long fmask = (1ull << (1u << dlog)) - 1ull;
+  const uint32_t tmin = ta < tb ? ta : tb;
+  uint32_t upper = tmin;
+  for (uint32_t site = 0; site < S; ++site) {
+    uint32_t ra, rb;
+    if (!tilted_rank(ta, site / m, site % m, m, &ra) || !tilted_rank(tb, site / m, site % m, m, &rb) ||
+        ra != rb)
+      continue;
+    const uint32_t shift = site << dlog;
+    if (((wa >> shift) & fmask) != ((wb >> shift) & fmask) && ra < upper) upper = ra;
+  }
+  // kc-th largest common rank below upper
+  uint32_t bound = upper;
+  bool found = true;
+  for (uint32_t c = 0; c < kc && found; ++c) {
+    found = false;
+    uint32_t best = 0u;
+    for (uint32_t site = 0; site < S; ++site) {
+      uint32_t ra, rb;
+      if (!tilted_rank(ta, site / m, site % m, m, &ra) ||
+          !tilted_rank(tb, site / m, site % m, m, &rb) || ra != rb || ra >= bound)
+        continue;
+      if (!found || ra > best) best = ra;
+      found = true;
+    }
+    bound = best;
+  }
+  const size_t at = (size_t)x * n + y;
+  U[at] = upper;
+  L[at] = found ? bound + 1u : 0u;
+}
+
 }  // namespace
 
 size_t mrca_workspace_bytes(size_t n) { return n * sizeof(Normalized); }
 
 hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, uint32_t s_log,
-                              uint32_t dlog, uint32_t kc, void* workspace, uint32_t* L,
-                              uint32_t* U, hipStream_t stream) {
+                              uint32_t dlog, uint32_t policy, uint32_t kc, void* workspace,
+                              uint32_t* L, uint32_t* U, hipStream_t stream) {
   if (n == 0) return hipSuccess;
+  if (policy != 0u) {
+    pairs_tilted_kernel<<<dim3((n + 255) / 256, n), dim3(256), 0, stream>>>(T, D, n, s_log, dlog,
+                                                                           kc, L, U);
+    return hipGetLastError();
+  }
   Normalized* nz = static_cast<Normalized*>(workspace);
   normalize_kernel<<<dim3((n + 255) / 256), dim3(256), 0, stream>>>(T, D, n, s_log, dlog, nz);
   hipError_t e = hipGetLastError();

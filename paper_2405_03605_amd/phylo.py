@@ -19,9 +19,10 @@ import numpy as np
 from ._lib import check, load
 
 
-def mrca_matrix(T, D, sites: int, kc: int = 5, device=None, bits: int = 1):
+def mrca_matrix(T, D, sites: int, kc: int = 5, device=None, bits: int = 1, policy: int = 0):
     """(L, U) interval matrices for every pair of the n sampled surfaces, on the GPU.
-    T: (n,) deposit counters; D: (n, sites * bits / 32) surface words."""
+    T: (n,) deposit counters; D: (n, sites * bits / 32) surface words; policy 0
+    steady, 1 tilted."""
     import torch
     lib = load()
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -38,9 +39,9 @@ def mrca_matrix(T, D, sites: int, kc: int = 5, device=None, bits: int = 1):
     U = torch.empty((n, n), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
     P = ctypes.c_void_p
-    check(lib.ga_mrca_matrix_bits(P(t_dev.data_ptr()), P(d_dev.data_ptr()), n, sites, bits, kc,
-                                  P(ws.data_ptr()), ws_bytes, P(L.data_ptr()), P(U.data_ptr()),
-                                  P(stream.cuda_stream)))
+    check(lib.ga_mrca_matrix_ex(P(t_dev.data_ptr()), P(d_dev.data_ptr()), n, sites, bits, policy,
+                                kc, P(ws.data_ptr()), ws_bytes, P(L.data_ptr()),
+                                P(U.data_ptr()), P(stream.cuda_stream)))
     return L.cpu().numpy().view(np.uint32), U.cpu().numpy().view(np.uint32)
 
 
@@ -92,8 +93,8 @@ def phylometrics(Z: np.ndarray) -> dict:
             "root_height": float(height[2 * n - 2]) if n > 1 else 0.0}
 
 
-def reconstruct(T, D, sites: int, kc: int = 5, device=None, bits: int = 1):
+def reconstruct(T, D, sites: int, kc: int = 5, device=None, bits: int = 1, policy: int = 0):
     """Tree (linkage matrix) and phylometrics for sampled surfaces."""
-    L, U = mrca_matrix(T, D, sites, kc, device, bits)
+    L, U = mrca_matrix(T, D, sites, kc, device, bits, policy)
     Z = upgma(estimated_distance(T, L, U))
     return Z, phylometrics(Z)

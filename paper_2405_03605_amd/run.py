@@ -10,8 +10,8 @@ import numpy as np
 from ._lib import (FORM_AUTO, GA_EINVAL, Config, GAError, OutboxEntry, check, load)
 
 CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32", "migration",
-                 "seed", "run_id", "law", "p_ben32", "schedule", "model", "dbits")
-OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "schedule": 0, "model": 0, "dbits": 1}
+                 "seed", "run_id", "law", "p_ben32", "schedule", "model", "dbits", "policy")
+OPTIONAL_FIELDS = {"law": 0, "p_ben32": 0, "schedule": 0, "model": 0, "dbits": 1, "policy": 0}
 
 
 def _fields(cfg: dict) -> dict:
@@ -31,7 +31,7 @@ def make_config(cfg: dict) -> Config:
                   seed=cfg["seed"], run_id=cfg["run_id"],
                   mutation_law=cfg.get("law", 0), beneficial_threshold=cfg.get("p_ben32", 0),
                   schedule=cfg.get("schedule", 0), genome_model=cfg.get("model", 0),
-                  differentia_bits=cfg.get("dbits", 1))
+                  differentia_bits=cfg.get("dbits", 1), surface_policy=cfg.get("policy", 0))
 
 
 def state_bytes(cfg: dict) -> int:

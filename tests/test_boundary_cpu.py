@@ -63,6 +63,8 @@ def test_state_bytes_layout(lib):
         for sites, bits in ((16, 4), (8, 8), (16, 2), (4, 8)):
             w = dict(c, sites=sites, dbits=bits)
             assert ga.state_bytes(w) == expect(w)
+        # the surface policy does not change the layout
+        assert ga.state_bytes(dict(c, policy=1)) == expect(c)
         for model in (1, 2):
             m = dict(c, model=model)
             assert ga.state_bytes(m) == expect(m) > ga.state_bytes(c)
@@ -78,7 +80,8 @@ def test_state_bytes_layout(lib):
     dict(migration=3), dict(width=65535, height=65535, pop=64), dict(width=65535, height=8193, pop=2),
     dict(law=2), dict(law=1, p32=2 ** 32 - 10, p_ben32=100), dict(schedule=2), dict(model=3),
     dict(model=1, law=1, p_ben32=5), dict(sites=32, dbits=4), dict(sites=64, dbits=2),
-    dict(sites=16, dbits=3), dict(sites=2, dbits=16), dict(sites=12, dbits=4)])
+    dict(sites=16, dbits=3), dict(sites=2, dbits=16), dict(sites=12, dbits=4), dict(policy=2),
+    dict(policy=1, sites=16, dbits=4)])
 def test_invalid_configs_rejected(lib, bad):
     c = make_config(run_config(**bad))
     assert lib.ga_state_bytes(ctypes.byref(c)) == 0
@@ -137,3 +140,8 @@ def test_first_release_config_size_accepted(lib):
     assert lib.ga_state_bytes(ct.byref(c)) > 0
     c.struct_size = _lib.Config.differentia_bits.offset
     assert lib.ga_state_bytes(ct.byref(c)) == 0
+    # size before the surface policy: steady, whatever the field says
+    c = make_config(run_config(policy=9))
+    assert lib.ga_state_bytes(ct.byref(c)) == 0
+    c.struct_size = _lib.Config.surface_policy.offset
+    assert lib.ga_state_bytes(ct.byref(c)) > 0

@@ -1,7 +1,8 @@
-"""GPU parity for wider differentia (b = 2, 4, 8 bits per site at the surface's
-32- or 64-bit footprint): surfaces, T, fitness and generation equal the CPU
-oracle bit for bit across (S, b) shapes, launch forms, edge shapes and the
-asynchronous schedule (batches refuse them); the all-pairs MRCA intervals of b-bit surfaces
+"""GPU parity for the surface variants: wider differentia (b = 2, 4, 8 bits per
+site at the surface's 32- or 64-bit footprint) and the tilted
+(recency-proportional) policy. Surfaces, T, fitness and generation equal the
+CPU oracle bit for bit across shapes, launch forms, edge shapes and the
+asynchronous schedule (batches refuse them); the all-pairs MRCA intervals
 equal the oracle's."""
 import numpy as np
 import pytest
@@ -88,4 +89,63 @@ def test_wide_mrca_matrix(sites, bits):
     for kc in (1, 3):
         L, U = phylo.mrca_matrix(T2, D2, sites, kc, bits=bits)
         L0, U0 = oracle.mrca_interval_matrix(T2, D2, sites, kc, bits)
+        assert np.array_equal(U, U0) and np.array_equal(L, L0), (sites, bits, kc)
+
+
+TILTED = [(32, 1), (64, 1), (32, 2)]
+
+
+@pytest.mark.parametrize("sites,bits", TILTED)
+@pytest.mark.parametrize("form", [FORM_STREAMING, FORM_RESIDENT])
+def test_tilted_parity(sites, bits, form):
+    cfg = run_config(width=9, height=7, pop=16, sites=sites, dbits=bits, policy=1, k=3)
+    say(f"tilted S={sites} b={bits} form {form}")
+    run = GARun(cfg)
+    run.set_launch(0, 0, form)
+    for n in (1, 200, 599):
+        run.step(n)
+    got = run.read()
+    run.close()
+    assert_same_state(got, oracle_after(cfg, 800), f"tilted S={sites} b={bits} form {form}")
+
+
+def test_tilted_mid_run_async_and_strings():
+    cfg = run_config(width=96, height=64, pop=32, sites=64, policy=1, model=1)
+    run = GARun(cfg)
+    run.step(500)
+    got = run.read()
+    run.close()
+    assert_same_state(got, oracle_after(cfg, 500), "tilted 96x64x32 OneMax")
+    cfg = run_config(width=17, height=9, pop=16, sites=32, policy=1, schedule=1)
+    run = GARun(cfg)
+    run.set_launch(4)
+    run.set_async(1, ASYNC_UNPACED, 3)
+    run.step(150)
+    ref = oracle.OracleRun({k: v for k, v in cfg.items() if k != "schedule"})
+    ref.step_async(150, 4, 3)
+    assert_same_state(run.read(), ref, "async skewed tilted")
+    run.close()
+    with pytest.raises(GAError):
+        GABatch().add(GARun(run_config(policy=1)), 5)
+
+
+@pytest.mark.parametrize("sites,bits", TILTED)
+def test_tilted_mrca_matrix(sites, bits):
+    cfg = run_config(width=24, height=16, pop=16, sites=sites, dbits=bits, policy=1, seed=79)
+    run = GARun(cfg)
+    run.step(1500)
+    ids, T, D = run.extract()
+    run.close()
+    rng = np.random.default_rng(sites + bits)
+    extra = np.array([0, 1, 2, 3, 2 ** 31 - 1, 2 ** 31, 2 ** 31 + 1, 2 ** 32 - 1], np.uint32)
+    T2 = np.concatenate([T, rng.integers(0, 2 ** 32, 40, dtype=np.uint64).astype(np.uint32),
+                         extra]).astype(np.uint32)
+    D2 = np.concatenate([D, rng.integers(0, 2 ** 32, (48, D.shape[1]), dtype=np.uint64)
+                         .astype(np.uint32)])
+    # a copy of each run surface at an older count shares ranks with it
+    T2 = np.concatenate([T2, (T // 3).astype(np.uint32)])
+    D2 = np.concatenate([D2, D])
+    for kc in (1, 4):
+        L, U = phylo.mrca_matrix(T2, D2, sites, kc, bits=bits, policy=1)
+        L0, U0 = oracle.mrca_interval_matrix(T2, D2, sites, kc, bits, policy=1)
         assert np.array_equal(U, U0) and np.array_equal(L, L0), (sites, bits, kc)
