@@ -94,6 +94,8 @@ def _load():
     lib.orc_mrca_interval_bits.argtypes = [u32, P, u32, P, u32, u32, u32, P, P]
     lib.orc_site_of_tilted.argtypes = [u64, u32]
     lib.orc_site_of_tilted.restype = u32
+    lib.orc_site_of_hybrid.argtypes = [u64]
+    lib.orc_site_of_hybrid.restype = u32
     lib.orc_site_of_policy.argtypes = [u64, u32, u32]
     lib.orc_site_of_policy.restype = u32
     lib.orc_retained.argtypes = [u64, u32, u32, P]
@@ -163,6 +165,12 @@ def mrca_interval(Ta: int, Da, Tb: int, Db, sites: int, kc: int = 5, bits: int =
 
 def site_of_tilted(rank: int, sites: int) -> int:
     return int(_load().orc_site_of_tilted(rank, sites))
+
+
+def site_of_policy(rank: int, sites: int, policy: int) -> int:
+    """Site a deposit of ``rank`` writes under policy 0 (steady), 1 (tilted)
+    or 2 (hybrid), or DISCARD."""
+    return int(_load().orc_site_of_policy(rank, sites, policy))
 
 
 def retained(n: int, sites: int, policy: int) -> np.ndarray:

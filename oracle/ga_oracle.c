@@ -143,7 +143,19 @@ uint32_t orc_site_of_tilted(uint64_t rank, uint32_t sites) {
   return k * m + (uint32_t)slot;
 }
 
+/* ----------------------------------------------------------------------- */
+/* Surface policy "hybrid" (64 sites): the ranks alternate between two      */
+/* 32-site halves, even ranks 2q into a steady surface (sites 0..31, as its */
+/* rank q) and odd ranks 2q + 1 into a tilted one (sites 32..63, as its     */
+/* rank q): even coverage of the whole history beside fine recent ranks.    */
+/* ----------------------------------------------------------------------- */
+uint32_t orc_site_of_hybrid(uint64_t rank) {
+  if ((rank & 1u) == 0) return orc_site_of(rank >> 1, 32);
+  return 32u + orc_site_of_tilted(rank >> 1, 32);
+}
+
 uint32_t orc_site_of_policy(uint64_t rank, uint32_t sites, uint32_t policy) {
+  if (policy == 2) return orc_site_of_hybrid(rank);
   return policy == 1 ? orc_site_of_tilted(rank, sites) : orc_site_of(rank, sites);
 }
 
@@ -158,6 +170,16 @@ static int cmp_u64(const void* a, const void* b) {
 size_t orc_retained(uint64_t n, uint32_t sites, uint32_t policy, uint64_t* out) {
   size_t c = 0;
   if (n == 0) return 0;
+  if (policy == 2) {
+    /* n deposits: ceil(n/2) even ranks (steady half), floor(n/2) odd ones */
+    uint64_t half[64];
+    const size_t ne = orc_retained((n + 1) / 2, 32, 0, half);
+    for (size_t i = 0; i < ne; ++i) out[c++] = 2 * half[i];
+    const size_t no = orc_retained(n / 2, 32, 1, half);
+    for (size_t i = 0; i < no; ++i) out[c++] = 2 * half[i] + 1;
+    qsort(out, c, sizeof(uint64_t), cmp_u64);
+    return c;
+  }
   if (policy == 0) {
     const uint64_t step = (uint64_t)1 << orc_epoch(n, sites);
     for (uint64_t r = 0; r < n; r += step) out[c++] = r;
@@ -241,8 +263,9 @@ int orc_validate(const orc_config* cfg) {
   if (cfg->dbits != 1 && cfg->dbits != 2 && cfg->dbits != 4 && cfg->dbits != 8) return -1;
   if (!is_pow2(cfg->sites) || cfg->sites < 4 || cfg->sites > 64) return -1;
   if (cfg->sites * cfg->dbits != 32 && cfg->sites * cfg->dbits != 64) return -1;
-  if (cfg->policy > 1) return -1;
+  if (cfg->policy > 2) return -1;
   if (cfg->policy == 1 && cfg->sites != 32 && cfg->sites != 64) return -1;
+  if (cfg->policy == 2 && (cfg->sites != 64 || cfg->dbits != 1)) return -1;
   if (cfg->k < 1 || cfg->k > 8) return -1;
   if (cfg->selection > 1 || cfg->migration > 1) return -1;
   if (cfg->law > 1) return -1;

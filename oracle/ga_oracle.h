@@ -54,7 +54,8 @@ typedef struct orc_config {
   uint32_t dbits;       /* bits per differentia: 1, 2, 4 or 8; sites * dbits is 32
                            or 64 (the surface fills one or two words) */
   uint32_t policy;      /* surface policy: 0 "doubling steady", 1 "tilted"
-                           (recency-proportional; sites 32 or 64) */
+                           (recency-proportional; sites 32 or 64), 2 "hybrid"
+                           (64 one-bit sites: steady and tilted halves) */
 } orc_config;
 
 typedef struct orc_run orc_run;
@@ -71,7 +72,10 @@ uint32_t orc_epoch(uint64_t n, uint32_t sites);
  * (r >> (k+1)) mod m of level k ((r >> 31) mod m on level 31), site k m + slot.
  * Every deposit is written. */
 uint32_t orc_site_of_tilted(uint64_t rank, uint32_t sites);
-/* Site of a deposit under policy 0 (steady) or 1 (tilted). */
+/* Hybrid policy (64 sites): even rank 2q at steady site orc_site_of(q, 32)
+ * (or nowhere), odd rank 2q + 1 at 32 + orc_site_of_tilted(q, 32). */
+uint32_t orc_site_of_hybrid(uint64_t rank);
+/* Site of a deposit under policy 0 (steady), 1 (tilted) or 2 (hybrid). */
 uint32_t orc_site_of_policy(uint64_t rank, uint32_t sites, uint32_t policy);
 /* Ranks a surface holds after n deposits, ascending (at most S); returns the
  * count. */

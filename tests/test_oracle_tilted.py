@@ -6,8 +6,9 @@ equal to a brute-force replay of every deposit's write (last writer per site);
 the recency-proportional guarantee (at least k + 1 retained ranks among the
 last 2^(k+1) deposits); the general estimator equal to the steady policy's
 closed form on steady surfaces; intervals bracketing the true MRCA with the
-lower-bound miss rate within 2^-kc; and recent MRCAs resolved more tightly
-than under the steady policy."""
+lower-bound miss rate within 2^-kc; recent MRCAs resolved more tightly than
+under the steady policy; and the hybrid policy's two halves replaying as a
+steady and a tilted surface on the even and odd ranks."""
 import numpy as np
 import pytest
 
@@ -133,4 +134,64 @@ def test_validation():
     assert oracle.validate(cfg(sites=32)) and oracle.validate(cfg(sites=64))
     assert oracle.validate(cfg(sites=32, dbits=2))
     assert not oracle.validate(cfg(sites=16, dbits=4))
-    assert not oracle.validate(cfg(policy=2))
+    assert not oracle.validate(cfg(policy=3))
+
+
+# --------------------------------------------------------------------------
+# hybrid policy (64 sites): even ranks to a steady half, odd ranks to a tilted
+# half
+# --------------------------------------------------------------------------
+def test_hybrid_sites_hand_worked():
+    want = {0: 0, 2: 1, 4: 2, 62: 31, 1: 32 + 31, 3: 32 + 0, 5: 32 + 1, 7: 32 + 0, 9: 32 + 2}
+    for r, site in want.items():
+        assert oracle.site_of_policy(r, 64, 2) == site, r
+    # even ranks 2q follow the steady half's policy on rank q (64 = 2 * 32)
+    assert oracle.site_of_policy(64, 64, 2) == oracle.site_of(32, 32)
+    assert oracle.site_of_policy(66, 64, 2) == oracle.site_of(33, 32) == oracle.DISCARD
+
+
+def test_hybrid_retained_set_matches_replay():
+    # Every retained rank is still the last writer of its site. The tilted half
+    # keeps exactly its odd ranks; the steady half keeps the multiples of its
+    # epoch's step, while ranks between them may linger until their sites are
+    # taken over (the estimator does not rely on those).
+    last = {}
+    for n in range(1, 3001):
+        site = oracle.site_of_policy(n - 1, 64, 2)
+        if site != oracle.DISCARD:
+            last[site] = n - 1
+        R = oracle.retained(n, 64, 2)
+        for r in R:
+            assert last[oracle.site_of_policy(int(r), 64, 2)] == r, (n, r)
+        odd = sorted(r for r in last.values() if r % 2)
+        assert np.array_equal(R[R % 2 == 1], np.array(odd, dtype=np.uint64)), n
+        even = R[R % 2 == 0] // 2
+        assert np.array_equal(even, oracle.retained((n + 1) // 2, 32, 0)), n
+
+
+def test_hybrid_interval_brackets_true_mrca():
+    c = cfg(sites=64, policy=2, seed=53)
+    run = oracle.OracleRun(c, lineage=True)
+    run.step(1200)
+    _, T, D = run.population()
+    rng = np.random.default_rng(11)
+    sample = rng.choice(run.agents, size=140, replace=False)
+    hi = lo = pairs = 0
+    kc = 4
+    for x in range(len(sample)):
+        for y in range(x + 1, len(sample)):
+            a, b = int(sample[x]), int(sample[y])
+            g = max(run.true_mrca(a, b), 0)
+            L, U = oracle.mrca_interval(int(T[a]), D[a], int(T[b]), D[b], 64, kc, 1, policy=2)
+            pairs += 1
+            hi += g > U
+            lo += g < L
+    assert hi == 0
+    bound = 2.0 ** -kc
+    assert lo <= 1.25 * bound * pairs + 4 * np.sqrt(bound * pairs) + 1
+
+
+def test_hybrid_validation():
+    assert oracle.validate(cfg(sites=64, policy=2))
+    assert not oracle.validate(cfg(sites=32, policy=2))
+    assert not oracle.validate(cfg(sites=32, dbits=2, policy=2))
