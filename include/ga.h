@@ -100,7 +100,7 @@ typedef struct ga_config {
                                 * t high word * 4 + 3); b = 1 writes the top bit
                                 * of the selection block's word 3 as always. */
   /* Added last; struct_size = offsetof(ga_config, surface_policy) gets steady. */
-  uint32_t surface_policy;     /* GA_POLICY_STEADY or GA_POLICY_TILTED */
+  uint32_t surface_policy;     /* GA_POLICY_STEADY, GA_POLICY_TILTED or GA_POLICY_HYBRID */
 } ga_config;
 
 /* Surface policies (ga_config.surface_policy): which site a deposit of rank r
@@ -113,9 +113,14 @@ typedef struct ga_config {
  * slot (r >> (k+1)) mod m ((r >> 31) mod m for k = 31) of level k, site
  * k * m + slot. Each level keeps its m most recent ranks, so about m ranks per
  * doubling of age survive: recent ancestry is resolved finely, old ancestry
- * coarsely. Every deposit is written. */
+ * coarsely. Every deposit is written.
+ * GA_POLICY_HYBRID (64 one-bit sites): even ranks 2q go to a 32-site steady
+ * half (sites 0..31) as its rank q, odd ranks 2q + 1 to a 32-site tilted half
+ * (sites 32..63) as its rank q: even coverage of the whole history beside fine
+ * recent resolution. */
 #define GA_POLICY_STEADY 0
 #define GA_POLICY_TILTED 1
+#define GA_POLICY_HYBRID 2
 
 /* Genome models (ga_config.genome_model). The paper's kernel serves any
  * fixed-length genome through three functions, initialize, mutate and
@@ -339,7 +344,8 @@ int ga_mrca_matrix(const uint32_t* T, const uint32_t* surface_words, size_t n,
  * policy. The ranks both surfaces still hold, c_0 < c_1 < ..., are compared
  * oldest first as b-bit fields: U is the first that differs (or min(Tx, Ty)),
  * L = c_{j-kc} + 1 for its index j (0 if j < kc), so g < L has probability at
- * most 2^-(b kc). The tilted policy needs no workspace (NULL is accepted). */
+ * most 2^-(b kc). The tilted and hybrid policies need no workspace (NULL is
+ * accepted). */
 int ga_mrca_matrix_ex(const uint32_t* T, const uint32_t* surface_words, size_t n,
                       uint32_t surface_sites, uint32_t differentia_bits, uint32_t surface_policy,
                       uint32_t kc, void* workspace, size_t workspace_bytes, uint32_t* L,

@@ -20,7 +20,7 @@ FORM_AUTO, FORM_STREAMING, FORM_RESIDENT = 0, 1, 2
 SCHEDULE_SYNC, SCHEDULE_ASYNC = 0, 1
 ASYNC_UNPACED = 0xFFFFFFFF
 MODEL_FITNESS, MODEL_ONEMAX, MODEL_TRAP4 = 0, 1, 2
-POLICY_STEADY, POLICY_TILTED = 0, 1
+POLICY_STEADY, POLICY_TILTED, POLICY_HYBRID = 0, 1, 2
 
 
 class GAError(RuntimeError):

@@ -66,6 +66,17 @@ bool surface_ok(uint32_t sites, uint32_t b) {
   return sites * b == 32 || sites * b == 64;
 }
 
+bool policy_ok(uint32_t policy, uint32_t sites, uint32_t b, std::string* why) {
+  const char* m = nullptr;
+  if (policy > GA_POLICY_HYBRID) m = "surface_policy must be 0 (steady), 1 (tilted) or 2 (hybrid)";
+  else if (policy == GA_POLICY_TILTED && sites != 32 && sites != 64)
+    m = "the tilted policy needs 32 or 64 sites";
+  else if (policy == GA_POLICY_HYBRID && (sites != 64 || b != 1))
+    m = "the hybrid policy needs 64 one-bit sites";
+  if (m && why) *why = m;
+  return m == nullptr;
+}
+
 size_t surface_words(const ga_config* c) { return c->surface_sites * dbits_of(c) / 32; }
 
 bool config_ok(const ga_config* c, std::string* why) {
@@ -88,9 +99,7 @@ bool config_ok(const ga_config* c, std::string* why) {
   if (c->tournament_size < 1 || c->tournament_size > 8) return no("tournament_size must be in [1, 8]");
   if (c->selection > 1) return no("selection must be 0 or 1");
   if (c->migration > 1) return no("migration must be 0 or 1");
-  if (policy_of(c) > GA_POLICY_TILTED) return no("surface_policy must be 0 (steady) or 1 (tilted)");
-  if (policy_of(c) == GA_POLICY_TILTED && c->surface_sites != 32 && c->surface_sites != 64)
-    return no("the tilted policy needs 32 or 64 sites");
+  if (!policy_ok(policy_of(c), c->surface_sites, dbits_of(c), why)) return false;
   if (c->struct_size > kConfigV2Size && c->schedule > GA_SCHEDULE_ASYNC)
     return no("schedule must be 0 (synchronous) or 1 (asynchronous)");
   if (c->struct_size > kConfigV3Size) {
@@ -956,9 +965,9 @@ int ga_mrca_matrix_ex(const uint32_t* T, const uint32_t* surface_words, size_t n
   if (n > 65535) return fail(GA_EINVAL, "n must be <= 65535");
   if (!surface_ok(surface_sites, differentia_bits))
     return fail(GA_EINVAL, "surface_sites x differentia_bits must be 32 or 64 bits");
-  if (surface_policy > GA_POLICY_TILTED) return fail(GA_EINVAL, "unknown surface_policy");
-  if (surface_policy == GA_POLICY_TILTED && surface_sites != 32 && surface_sites != 64)
-    return fail(GA_EINVAL, "the tilted policy needs 32 or 64 sites");
+  std::string why;
+  if (!policy_ok(surface_policy, surface_sites, differentia_bits, &why))
+    return fail(GA_EINVAL, why);
   if (kc < 1) return fail(GA_EINVAL, "kc must be >= 1");
   if (!T || !surface_words || !L || !U) return fail(GA_EINVAL, "NULL pointer");
   if (surface_policy == GA_POLICY_STEADY) {

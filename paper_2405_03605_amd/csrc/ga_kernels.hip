@@ -257,7 +257,8 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   // policy; one bit on 32 or 64 sites is fixed at compile time, WIDE reads
   // the width, the site count and the policy from the view
   const uint32_t dlog = WIDE ? v.dlog : 0u;
-  const bool tilted = WIDE && v.policy != 0u;
+  const bool tilted = WIDE && v.policy == 1u;
+  const bool hybrid = WIDE && v.policy == 2u;
   const uint32_t s_log = WIDE ? v.s_log : 4u + SW;
   const uint32_t S = 1u << s_log;
   const uint32_t lane = __lane_id();
@@ -525,20 +526,32 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
       }
     }
 
-    // 7. stratum deposit at rank T, then T + 1
-    uint32_t site = cT;
-    bool write = true;
-    if (tilted) {
-      // level k = trailing zeros of T (capped at 31; T = 0 counts as 31), slot
-      // (T >> (k+1)) mod m ((T >> 31) mod m on level 31), m = S / 32
-      const uint32_t k = cT ? min((uint32_t)__ffs(cT) - 1u, 31u) : 31u;
-      const uint32_t slot = (k < 31u ? cT >> (k + 1u) : cT >> 31) & ((S >> 5) - 1u);
-      site = (k << (s_log - 5u)) + slot;
-    } else if (cT >= S) {
-      const uint32_t e = (32u - __clz(cT)) - s_log;
-      write = (cT & ((1u << e) - 1u)) == 0u;
-      if (write) site = surface_site_walk(cT, e, s_log);
+    // 7. stratum deposit at rank T, then T + 1. The hybrid policy sends even
+    //    ranks 2q to a 32-site steady half (sites 0..31) and odd ranks 2q + 1
+    //    to a 32-site tilted half (sites 32..63), each as its rank q.
+    uint32_t q = cT, q_log = s_log, site_base = 0u;
+    bool on_tilted = tilted;
+    if (hybrid) {
+      q = cT >> 1;
+      q_log = 5u;
+      on_tilted = (cT & 1u) != 0u;
+      site_base = on_tilted ? 32u : 0u;
     }
+    uint32_t site = q;
+    bool write = true;
+    if (on_tilted) {
+      // level k = trailing zeros of q (capped at 31; q = 0 counts as 31), slot
+      // (q >> (k+1)) mod m ((q >> 31) mod m on level 31), m = sites / 32
+      const uint32_t m_log = q_log - 5u;
+      const uint32_t k = q ? min((uint32_t)__ffs(q) - 1u, 31u) : 31u;
+      const uint32_t ring = (k < 31u ? q >> (k + 1u) : q >> 31) & ((1u << m_log) - 1u);
+      site = (k << m_log) + ring;
+    } else if (q >= (1u << q_log)) {
+      const uint32_t e = (32u - __clz(q)) - q_log;
+      write = (q & ((1u << e) - 1u)) == 0u;
+      if (write) site = surface_site_walk(q, e, q_log);
+    }
+    site += site_base;
     if (write) {
       // the differentia: one bit, the top bit of the selection block's w3;
       // b = 2^dlog > 1 bits, the top b bits of word 0 of a block of their own

@@ -196,6 +196,74 @@ __global__ __launch_bounds__(256) void pairs_tilted_kernel(const uint32_t* __res
   L[at] = found ? bound + 1u : 0u;
 }
 
+// Hybrid surfaces (64 one-bit sites): even ranks 2q sit on a 32-site steady
+// half (sites 0..31), odd ranks 2q + 1 on a 32-site tilted half (sites
+// 32..63). The common ranks of the steady halves are 2 j 2^E for
+// j < common, E the larger epoch; those of the tilted halves are the slots
+// holding the same rank in both. U and L as for the other policies, over the
+// union of the two sets.
+__global__ __launch_bounds__(256) void pairs_hybrid_kernel(const uint32_t* __restrict__ T,
+                                                           const uint32_t* __restrict__ D,
+                                                           uint32_t n, uint32_t kc,
+                                                           uint32_t* __restrict__ L,
+                                                           uint32_t* __restrict__ U) {
+  const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t x = blockIdx.y;
+  if (y >= n) return;
+  const uint32_t ta = T[x], tb = T[y];
+  const unsigned long long diff =
+      ((unsigned long long)D[(size_t)x * 2] | (unsigned long long)D[(size_t)x * 2 + 1] << 32) ^
+      ((unsigned long long)D[(size_t)y * 2] | (unsigned long long)D[(size_t)y * 2 + 1] << 32);
+  // steady halves: (t + 1) / 2 even deposits each
+  const uint32_t na = (ta >> 1) + (ta & 1u), nb = (tb >> 1) + (tb & 1u);
+  const uint32_t ea = epoch_of(na, 5u), eb = epoch_of(nb, 5u);
+  const uint32_t E = ea > eb ? ea : eb;
+  const uint32_t nmin = na < nb ? na : nb;
+  const uint32_t cs = nmin == 0u ? 0u : ((nmin - 1u) >> E) + 1u;  // common steady ranks
+  uint32_t upper = ta < tb ? ta : tb;
+  for (uint32_t j = 0; j < cs; ++j) {
+    const uint32_t q = j << E;
+    if ((diff >> site_of_retained(q, 5u)) & 1ull) {
+      upper = min(upper, 2u * q);
+      break;
+    }
+  }
+  // tilted halves: t / 2 odd deposits each, one slot per level
+  const uint32_t ma = ta >> 1, mb = tb >> 1;
+  for (uint32_t k = 0; k < 32; ++k) {
+    uint32_t ra, rb;
+    if (!tilted_rank(ma, k, 0u, 1u, &ra) || !tilted_rank(mb, k, 0u, 1u, &rb) || ra != rb) continue;
+    if (((diff >> (32u + k)) & 1ull) && 2u * ra + 1u < upper) upper = 2u * ra + 1u;
+  }
+  // kc-th largest common rank below upper
+  uint32_t bound = upper;
+  bool found = true;
+  for (uint32_t c = 0; c < kc && found; ++c) {
+    found = false;
+    uint32_t best = 0u;
+    if (cs > 0u && bound > 0u) {
+      uint32_t jm = (bound - 1u) >> (E + 1u);  // largest j with 2 j 2^E < bound
+      if (jm > cs - 1u) jm = cs - 1u;
+      best = 2u * (jm << E);
+      found = true;
+    }
+    for (uint32_t k = 0; k < 32; ++k) {
+      uint32_t ra, rb;
+      if (!tilted_rank(ma, k, 0u, 1u, &ra) || !tilted_rank(mb, k, 0u, 1u, &rb) || ra != rb)
+        continue;
+      const uint32_t r = 2u * ra + 1u;
+      if (r < bound && (!found || r > best)) {
+        best = r;
+        found = true;
+      }
+    }
+    bound = best;
+  }
+  const size_t at = (size_t)x * n + y;
+  U[at] = upper;
+  L[at] = found ? bound + 1u : 0u;
+}
+
 }  // namespace
 
 size_t mrca_workspace_bytes(size_t n) { return n * sizeof(Normalized); }
@@ -204,9 +272,13 @@ hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, 
                               uint32_t dlog, uint32_t policy, uint32_t kc, void* workspace,
                               uint32_t* L, uint32_t* U, hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  if (policy != 0u) {
+  if (policy == 1u) {
     pairs_tilted_kernel<<<dim3((n + 255) / 256, n), dim3(256), 0, stream>>>(T, D, n, s_log, dlog,
                                                                            kc, L, U);
+    return hipGetLastError();
+  }
+  if (policy == 2u) {
+    pairs_hybrid_kernel<<<dim3((n + 255) / 256, n), dim3(256), 0, stream>>>(T, D, n, kc, L, U);
     return hipGetLastError();
   }
   Normalized* nz = static_cast<Normalized*>(workspace);

@@ -80,8 +80,9 @@ def test_state_bytes_layout(lib):
     dict(migration=3), dict(width=65535, height=65535, pop=64), dict(width=65535, height=8193, pop=2),
     dict(law=2), dict(law=1, p32=2 ** 32 - 10, p_ben32=100), dict(schedule=2), dict(model=3),
     dict(model=1, law=1, p_ben32=5), dict(sites=32, dbits=4), dict(sites=64, dbits=2),
-    dict(sites=16, dbits=3), dict(sites=2, dbits=16), dict(sites=12, dbits=4), dict(policy=2),
-    dict(policy=1, sites=16, dbits=4)])
+    dict(sites=16, dbits=3), dict(sites=2, dbits=16), dict(sites=12, dbits=4),
+    dict(policy=1, sites=16, dbits=4), dict(policy=2, sites=32), dict(policy=2, sites=32, dbits=2),
+    dict(policy=3)])
 def test_invalid_configs_rejected(lib, bad):
     c = make_config(run_config(**bad))
     assert lib.ga_state_bytes(ctypes.byref(c)) == 0

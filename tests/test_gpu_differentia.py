@@ -1,6 +1,6 @@
 """GPU parity for the surface variants: wider differentia (b = 2, 4, 8 bits per
-site at the surface's 32- or 64-bit footprint) and the tilted
-(recency-proportional) policy. Surfaces, T, fitness and generation equal the
+site at the surface's 32- or 64-bit footprint), the tilted
+(recency-proportional) policy and the hybrid (steady + tilted halves) policy. Surfaces, T, fitness and generation equal the
 CPU oracle bit for bit across shapes, launch forms, edge shapes and the
 asynchronous schedule (batches refuse them); the all-pairs MRCA intervals
 equal the oracle's."""
@@ -149,3 +149,44 @@ def test_tilted_mrca_matrix(sites, bits):
         L, U = phylo.mrca_matrix(T2, D2, sites, kc, bits=bits, policy=1)
         L0, U0 = oracle.mrca_interval_matrix(T2, D2, sites, kc, bits, policy=1)
         assert np.array_equal(U, U0) and np.array_equal(L, L0), (sites, bits, kc)
+
+
+@pytest.mark.parametrize("form", [FORM_STREAMING, FORM_RESIDENT])
+@pytest.mark.parametrize("kw", [dict(width=9, height=7, pop=16, k=3),
+                                dict(width=5, height=3, pop=1), dict(width=4, height=4, pop=64)])
+def test_hybrid_parity(form, kw):
+    cfg = run_config(sites=64, policy=2, **kw)
+    run = GARun(cfg)
+    run.set_launch(0, 0, form)
+    for n in (1, 200, 799):
+        run.step(n)
+    got = run.read()
+    run.close()
+    assert_same_state(got, oracle_after(cfg, 1000), f"hybrid {kw} form {form}")
+
+
+def test_hybrid_async_and_mrca_matrix():
+    cfg = run_config(width=17, height=9, pop=16, sites=64, policy=2, schedule=1)
+    run = GARun(cfg)
+    run.set_launch(4)
+    run.set_async(1, ASYNC_UNPACED, 2)
+    run.step(300)
+    ref = oracle.OracleRun({k: v for k, v in cfg.items() if k != "schedule"})
+    ref.step_async(300, 4, 2)
+    assert_same_state(run.read(), ref, "async skewed hybrid")
+    run.close()
+    cfg = run_config(width=24, height=16, pop=16, sites=64, policy=2, seed=81)
+    run = GARun(cfg)
+    run.step(1500)
+    ids, T, D = run.extract()
+    run.close()
+    rng = np.random.default_rng(64)
+    extra = np.array([0, 1, 2, 3, 64, 65, 2 ** 31 - 1, 2 ** 31, 2 ** 32 - 1], np.uint32)
+    T2 = np.concatenate([T, rng.integers(0, 2 ** 32, 40, dtype=np.uint64).astype(np.uint32),
+                         extra, (T // 3).astype(np.uint32)]).astype(np.uint32)
+    D2 = np.concatenate([D, rng.integers(0, 2 ** 32, (49, 2), dtype=np.uint64).astype(np.uint32),
+                         D])
+    for kc in (1, 4):
+        L, U = phylo.mrca_matrix(T2, D2, 64, kc, policy=2)
+        L0, U0 = oracle.mrca_interval_matrix(T2, D2, 64, kc, 1, policy=2)
+        assert np.array_equal(U, U0) and np.array_equal(L, L0), kc
