@@ -144,8 +144,7 @@ size_t outbox_stride(const ga_config* c) {
 }
 
 // Planes run 128 islands past the last 64-island boundary: a wavefront's last
-// chunk may end up to 63 islands past the last island, and its one-iteration
-// prefetch reads up to 64 more.
+// chunk may end up to 63 islands past the last island (the rest is slack).
 size_t padded_islands(const ga_config* c) {
   const size_t islands = (size_t)c->width * c->height;
   return (islands + 63) / 64 * 64 + 128;

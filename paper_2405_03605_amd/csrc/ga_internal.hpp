@@ -15,9 +15,9 @@ namespace ga {
 //   2 + words header (bit 2 valid, bits 0-1 direction); ob_stride = 4 or 8
 //   words; p = generation parity.
 // Planes are padded to island_stride = roundup(islands, 64) + 128 islands
-// (agent_stride = island_stride * N agents): a wavefront's last chunk, and its
-// one-iteration prefetch, may run past the last island and then only touch
-// padding.
+// (agent_stride = island_stride * N agents): a wavefront's last chunk may run
+// up to 63 islands past the last island and then only touches padding (the
+// rest is slack).
 struct RunView {
   float* pop_f;
   uint32_t* pop_T;

@@ -434,9 +434,12 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   // wait is for the prefetched genomes, at the end of the iteration.
   __builtin_amdgcn_s_waitcnt(0);
   for (uint32_t it = 0; it < n_iter; ++it) {
-    // next iteration's genomes (past the chunk's end this reads padding or the
-    // next chunk's first genomes, and the values go unused)
-    const Genome next = load_genome(pf, pT, pD0, pD1, pP0, pP1, off + 256u, SW, kStr);
+    // next iteration's genomes; the last iteration reloads its own (cache
+    // hits, values unused) rather than reaching into the next chunk, whose
+    // lines often belong to another XCD's wavefront and would be fetched from
+    // HBM a second time
+    const uint32_t next_off = it + 1u < n_iter ? off + 256u : off;
+    const Genome next = load_genome(pf, pT, pD0, pD1, pP0, pP1, next_off, SW, kStr);
     float f = g.f;
     uint32_t T = g.T, D0 = g.D0, D1 = g.D1, P0 = g.P0, P1 = g.P1;
     const uint32_t local = it * per_iter + (lane >> L);
