@@ -311,7 +311,8 @@ size_t ga_batch_size(const ga_batch* batch);
 /* Generations per graph replay for the batch (default 100; 0 disables). */
 int ga_batch_set_graph_block(ga_batch* batch, uint32_t gens_per_block);
 /* Launch shape for the whole batch: islands per wavefront for every member
- * (0 = the default 16; rounded down to a multiple of 64/N, at most 64) and
+ * (0 = the default, 512/N for each member: about 512 agents per wavefront;
+ * rounded down to a multiple of 64/N, at most 64) and
  * wavefronts per workgroup (1..16; 0 keeps the current value, default 4).
  * Results do not depend on either. */
 int ga_batch_set_launch(ga_batch* batch, uint32_t islands_per_wave, uint32_t waves_per_group);

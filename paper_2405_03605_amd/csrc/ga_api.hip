@@ -815,11 +815,13 @@ uint64_t ga_batch_remaining(const ga_batch* b, const ga_run* r) {
 
 namespace {
 
-// Islands per wavefront for a member: the batch setting, 16 by default (a
-// batch has wavefronts enough, so small members need no finer chunks).
+// Islands per wavefront for a member: the batch setting, else about 512
+// agents per wavefront whatever the island size (a batch has wavefronts
+// enough, so small members need no finer chunks, and short wavefronts would
+// spend their time in the per-wavefront set-up).
 uint32_t batch_ipw(const ga_batch* b, const ga_run* r) {
   const uint32_t g = per_iter(r);
-  uint32_t ipw = b->ipw_override ? b->ipw_override : 16u;
+  uint32_t ipw = b->ipw_override ? b->ipw_override : std::max(1u, 512u >> r->view.log2n);
   ipw = std::max(g, ipw / g * g);
   return std::min(64u, ipw);
 }
@@ -835,6 +837,11 @@ int rebuild_tables(ga_batch* b) {
     views.push_back(v);
     for (uint32_t first = 0; first < v.islands; first += v.ipw) tiles.push_back({m, first});
   }
+  // Wavefronts of one specialised body (island size, surface words) side by
+  // side: neighbouring wavefronts on a CU then share instruction-cache lines.
+  std::stable_sort(tiles.begin(), tiles.end(), [&](const ga::Tile& a, const ga::Tile& c) {
+    return views[a.run].log2n * 2u + views[a.run].words < views[c.run].log2n * 2u + views[c.run].words;
+  });
   if (views.size() > b->cap_views) {
     if (b->d_views) GA_HIP(hipFree(b->d_views), "free views");
     b->d_views = nullptr;

@@ -651,10 +651,20 @@ __device__ __forceinline__ uint4* wave_lds(uint32_t wave_in_group, uint32_t ipw,
   return ga_lds + wave_in_group * lds_entries(ipw) * units;
 }
 
+// The dispatcher hands workgroups to the eight XCDs in turn (group g to XCD
+// g mod 8), each XCD with its own L2. Renumbering the groups so that every XCD
+// takes one contiguous band of the grid keeps an island's four neighbours, and
+// the outbox entries it reads from them, mostly on its own XCD.
+__device__ __forceinline__ uint32_t xcd_band_group() {
+  const uint32_t g = blockIdx.x, n = gridDim.x;
+  const uint32_t x = g & 7u, q = n >> 3, r = n & 7u;
+  return (x < r ? x * (q + 1u) : r * (q + 1u) + (x - r) * q) + (g >> 3);
+}
+
 template <int LC, int SWC, int MODEL, bool WIDE>
 __global__ __launch_bounds__(1024) void generation_kernel(RunView v, uint32_t gen_offset) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wig;
+  const uint32_t wave = xcd_band_group() * (blockDim.x >> 6) + wig;
   const uint32_t base = wave * v.ipw;
   if (base >= v.islands) return;
   chunk_generation<LC, SWC, false, MODEL, WIDE>(v, base, *v.gen + gen_offset,
@@ -772,7 +782,7 @@ void batch_generation_kernel(const RunView* __restrict__ views,
                                                                 uint32_t gen_offset,
                                                                 uint32_t max_ipw) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wig;
+  const uint32_t wave = xcd_band_group() * (blockDim.x >> 6) + wig;
   if (wave >= n_tiles) return;
   const Tile tile = tiles[wave];
   const RunView v = views[tile.run];
