@@ -123,7 +123,7 @@ bool config_ok(const ga_config* c, std::string* why) {
 struct Layout {
   size_t pop_f, pop_T, pop_D, pop_P;
   size_t ob[2];     // synchronous schedule
-  size_t mail, seen, prog;  // asynchronous schedule
+  size_t mail, seen, prog, lock;  // asynchronous schedule
   size_t counters;  // generation counter, batch budget
   size_t st_ids, st_T, st_D;
   size_t total;
@@ -166,11 +166,13 @@ Layout layout_of(const ga_config* c) {
   L.pop_D = take(agents * 4 * words);
   if (model_of(c) != GA_MODEL_FITNESS) L.pop_P = take(agents * 4 * 2);
   if (is_async(c)) {
-    // eight buffers per island (direction x parity), four stamps, and one
-    // progress word per possible chunk
+    // eight buffers per island (direction x parity), four stamps, one
+    // progress word per possible chunk, and the lockstep headers (eight per
+    // island)
     L.mail = take(islands * 8 * 4 * outbox_stride(c));
     L.seen = take(islands * 4 * 4);
     L.prog = take(islands * 4);
+    L.lock = take(islands * 8 * 4);
   } else {
     for (int p = 0; p < 2; ++p) L.ob[p] = take(islands * 4 * outbox_stride(c));
   }
@@ -329,8 +331,10 @@ int step_async(ga_run* r, uint64_t n) {
   ga::RunView v = r->view;
   v.ipw = r->ipw;
   const uint32_t chunks = waves_for(r, r->ipw);
+  // no lead and no skew: the lockstep exchange
+  const bool lockstep = r->async_lead == 0u && r->async_skew == 0u;
   uint32_t cap = 0;
-  GA_HIP(ga::async_capacity(v, r->wpg, &cap), "occupancy query");
+  GA_HIP(ga::async_capacity(v, r->wpg, lockstep, &cap), "occupancy query");
   uint32_t waves = std::max(1u, std::min(chunks, cap));
   if (r->async_max_waves) waves = std::min(waves, r->async_max_waves);
   const uint32_t per_wave = (chunks + waves - 1) / waves;
@@ -344,10 +348,16 @@ int step_async(ga_run* r, uint64_t n) {
   uint64_t left = n;
   while (left > 0) {
     const uint64_t slice = std::min(left, slice_max);
-    // every chunk starts the launch having completed the current generation
-    GA_HIP(ga::launch_fill(v.prog, (uint32_t)r->gen_host, v.island_stride, r->stream), "progress reset");
-    GA_HIP(ga::launch_async(v, slice, waves, per_wave, r->wpg, r->async_lead, r->async_skew,
-                            r->stream), "async launch");
+    if (lockstep) {
+      GA_HIP(ga::launch_lockstep(v, r->gen_host, slice, waves, per_wave, r->wpg, r->stream),
+             "lockstep launch");
+    } else {
+      // every chunk starts the launch having completed the current generation
+      GA_HIP(ga::launch_fill(v.prog, (uint32_t)r->gen_host, v.island_stride, r->stream),
+             "progress reset");
+      GA_HIP(ga::launch_async(v, slice, waves, per_wave, r->wpg, r->async_lead, r->async_skew,
+                              r->stream), "async launch");
+    }
     GA_HIP(ga::launch_advance(v.gen, slice, r->stream), "advance launch");
     left -= slice;
     r->gen_host += slice;
@@ -407,6 +417,7 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   v.mail = async ? reinterpret_cast<uint32_t*>(b + lay.mail) : nullptr;
   v.seen = async ? reinterpret_cast<uint32_t*>(b + lay.seen) : nullptr;
   v.prog = async ? reinterpret_cast<uint32_t*>(b + lay.prog) : nullptr;
+  v.lock = async ? reinterpret_cast<uint32_t*>(b + lay.lock) : nullptr;
   v.ob_stride = (uint32_t)outbox_stride(cfg);
   v.gen = reinterpret_cast<unsigned long long*>(b + lay.counters);
   v.left = v.gen + 1;

@@ -42,10 +42,15 @@ struct RunView {
   //     odd while being rewritten;
   //   seen[i * 4 + q]: stamp of the last genome island i took from direction q;
   //   prog[c]: generations chunk c (islands c * ipw ...) has completed, low word;
+  //   lock[(p * 4 + d) * island_stride + i]: lockstep header of island i's
+  //     buffer toward direction d for sending generations of parity p:
+  //     2 * (g + 1) if it sent a genome that way in generation g, else
+  //     2 * (g + 1) + 1;
   //   waits: how often a wavefront stopped waiting for a neighbour and went on.
   uint32_t* mail;
   uint32_t* seen;
   uint32_t* prog;
+  uint32_t* lock;
   unsigned long long* waits;
   // genome model (0 fitness-valued; 1 OneMax, 2 Trap-4 on a 64-bit string)
   // and, with a string, its two word planes pop_P[w * agent_stride + a]
@@ -78,8 +83,13 @@ hipError_t launch_resident(const RunView& v, uint64_t n_gens, uint32_t waves, hi
 hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint32_t chunks,
                         uint32_t waves_per_group, uint32_t lead, uint32_t skew,
                         hipStream_t stream);
-// Wavefronts of the async kernel the current device holds at once.
-hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, uint32_t* waves);
+// The lockstep asynchronous launch (no lead, no skew) at generation `gen`:
+// its header prologue, then the persistent kernel.
+hipError_t launch_lockstep(const RunView& v, uint64_t gen, uint64_t n_gens, uint32_t waves,
+                           uint32_t chunks, uint32_t waves_per_group, hipStream_t stream);
+// Wavefronts of the async (or lockstep) kernel the current device holds at once.
+hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, bool lockstep,
+                          uint32_t* waves);
 hipError_t launch_advance(unsigned long long* gen, uint64_t n, hipStream_t stream);
 // Founders' strings and fitness for a genome model with a string.
 hipError_t launch_init_strings(const RunView& v, hipStream_t stream);

@@ -184,6 +184,17 @@ __device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
 __device__ __forceinline__ void store_agent(uint32_t* p, uint32_t value) {
   __hip_atomic_store(p, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Two words at once (8-byte aligned), for entries whose stability the
+// exchange protocol already guarantees while they are read.
+__device__ __forceinline__ uint2 load_agent2(const uint32_t* p) {
+  const uint64_t x = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return make_uint2((uint32_t)x, (uint32_t)(x >> 32));
+}
+__device__ __forceinline__ void store_agent2(uint32_t* p, uint32_t lo, uint32_t hi) {
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), ((uint64_t)hi << 32) | lo, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void drain_memory() {
   // also a compiler barrier: no memory access moves across it
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -246,7 +257,8 @@ struct AsyncCtx {
 // 5 * ipw + 1 entries (16 bytes for model 0, 32 with a string): arrivals
 // [4 * local + q], emissions [4 * ipw + local], and one scratch entry read when
 // a lane has no arrival.
-template <int LC, int SWC, bool ASYNC = false, int MODEL = kModelFitness, bool WIDE = false>
+template <int LC, int SWC, bool ASYNC = false, int MODEL = kModelFitness, bool WIDE = false,
+          bool LOCK = false>
 __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base, uint64_t t,
                                                  uint4* lds, AsyncCtx* ax = nullptr) {
   constexpr bool kStr = MODEL != kModelFitness;  // genomes carry a string
@@ -301,6 +313,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   // genome; for 64 sites it is the next word), so the pass pays one memory
   // round trip; only the packed slots say which entries are arrivals.
   uint32_t desc = 0xFFFFFFFFu;  // byte q: slot taken by the arrival from direction q, or 0xFF
+  uint32_t ready = 0u;          // lockstep: bit q set once the neighbour in direction q is done
   if constexpr (!ASYNC) {
 #pragma unroll
     for (uint32_t q = 0; q < 4; ++q) {
@@ -315,6 +328,81 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
       if (lane < v.ipw) {  // the table holds ipw islands
         lds[(lane * 4u + q) * ES] = entry;
         if (kStr) lds[(lane * 4u + q) * ES + 1u] = more;
+      }
+    }
+  } else if constexpr (LOCK) {
+    // Asynchronous schedule in lockstep (no lead). Every island writes, at the
+    // end of generation g, the lockstep header of each of its four buffers of
+    // parity g & 1: 2 (g + 1) toward the direction it sent a genome to,
+    // 2 (g + 1) + 1 ("nothing") toward the others. So in generation t the
+    // header of the neighbour's buffer of parity (t - 1) & 1 toward this
+    // island says both that the neighbour has finished generation t - 1
+    // (header >= 2t) and whether it sent a genome this way then (header ==
+    // 2t). One wait on the four headers is the pacing, one read of the
+    // payloads the exchange. The headers sit in a plane of their own, island
+    // index fastest, so the headers a wavefront waits on share a few cache
+    // lines. No re-read is needed: an island rewrites a buffer's payload only
+    // after seeing that the neighbour it faces has finished the generation
+    // that read the buffer's previous contents; after a wait that gave up it
+    // sends nothing that way.
+    const uint32_t due = 2u * t_lo;
+    const uint32_t prev = (t_lo & 1u) ^ 1u;
+    const uint32_t* mail = v.mail;
+    const uint32_t* lock = v.lock + prev * 4u * v.island_stride;
+    uint32_t hits = 0u;  // bit q: a genome was sent this way in generation t - 1
+    for (uint32_t spin = 0;; ++spin) {
+      uint32_t h[4];
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q)
+        h[q] = load_agent(lock + (q ^ 2u) * v.island_stride + torus_step(ox, oy, q, W, H));
+      drain_memory();
+      hits = 0u;
+      ready = 0u;
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        hits |= (h[q] == due ? 1u : 0u) << q;
+        ready |= ((int32_t)(h[q] - due) >= 0 ? 1u : 0u) << q;
+      }
+      if (__ballot(own_ok && ready != 15u) == 0ull) break;
+      if (spin == kPaceSpins) {
+        ++ax->gave_up;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(8);
+    }
+    hits = own_ok ? hits : 0u;
+    // the entries, each with its stamp (the last one taken, as recorded)
+    uint4 pay[4], pstr[4];
+    uint32_t stamp[4];
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      // byte offset of the neighbour's buffer toward this island
+      const uint32_t b =
+          (((torus_step(ox, oy, q, W, H) * 4u + (q ^ 2u)) * 2u + prev) * ob_stride) << 2;
+      const uint2 lo = load_agent2(at_byte(mail, b));
+      const uint2 hi = load_agent2(at_byte(mail, b + 8u));  // D0, then D1 or the stamp
+      pay[q] = make_uint4(lo.x, lo.y, hi.x, hi.y);
+      pstr[q] = make_uint4(0u, 0u, 0u, 0u);
+      stamp[q] = 0u;
+      if (kStr) {
+        const uint2 p = load_agent2(at_byte(mail, b + 16u));
+        const uint2 h2 = load_agent2(at_byte(mail, b + 24u));  // stamp, padding
+        pstr[q] = make_uint4(p.x, p.y, 0u, 0u);
+        stamp[q] = h2.x;
+      } else if (SW > 1) {
+        stamp[q] = load_agent(at_byte(mail, b + 16u));
+      }
+    }
+    drain_memory();
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      const bool hit = ((hits >> q) & 1u) != 0u;
+      if (hit) v.seen[own * 4u + q] = (SW == 1 && !kStr) ? pay[q].w : stamp[q];
+      const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
+      desc = hit ? (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q)) : desc;
+      if (lane < v.ipw) {
+        lds[(lane * 4u + q) * ES] = pay[q];
+        if (kStr) lds[(lane * 4u + q) * ES + 1u] = pstr[q];
       }
     }
   } else {
@@ -382,14 +470,13 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     uint4 pay[4], pstr[4];
 #pragma unroll
     for (uint32_t q = 0; q < 4; ++q) {
-      pay[q].x = load_agent(box[q]);
-      pay[q].y = load_agent(box[q] + 1);
-      pay[q].z = load_agent(box[q] + 2);
-      pay[q].w = SW > 1 ? load_agent(box[q] + 3) : 0u;
+      const uint2 lo = load_agent2(box[q]);
+      const uint2 hi = load_agent2(box[q] + 2);  // D0, then D1 or the stamp
+      pay[q] = make_uint4(lo.x, lo.y, hi.x, SW > 1 || kStr ? hi.y : 0u);
       pstr[q] = make_uint4(0u, 0u, 0u, 0u);
       if (kStr) {
-        pstr[q].x = load_agent(box[q] + 4);
-        pstr[q].y = load_agent(box[q] + 5);
+        const uint2 p = load_agent2(box[q] + 4);
+        pstr[q] = make_uint4(p.x, p.y, 0u, 0u);
       }
     }
     drain_memory();
@@ -592,7 +679,38 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  if constexpr (ASYNC) {
+  if constexpr (ASYNC && LOCK) {
+    // the payload toward the drawn direction (if that neighbour is done with
+    // the buffer) with its stamp in the entry's header word, as the general
+    // exchange reads it; complete before the four lockstep headers
+    const uint32_t hdr = emit >> 8;
+    const uint32_t d = hdr & 3u;
+    const bool sending = own_ok && hdr != 0u && ((ready >> d) & 1u) != 0u;
+    const uint32_t stamp = 2u * (t_lo + 1u);
+    if (sending) {
+      uint32_t* box = v.mail + ((own * 4u + d) * 2u + (t_lo & 1u)) * ob_stride;
+      const uint4 g = lds[(emit_base + lane) * ES];
+      store_agent2(box, g.x, g.y);
+      if (kStr) {
+        const uint4 p = lds[(emit_base + lane) * ES + 1u];
+        store_agent2(box + 2, g.z, g.w);
+        store_agent2(box + 4, p.x, p.y);
+        store_agent(box + 6, stamp);
+      } else if (SW > 1) {
+        store_agent2(box + 2, g.z, g.w);
+        store_agent(box + 4, stamp);
+      } else {
+        store_agent2(box + 2, g.z, stamp);
+      }
+    }
+    drain_memory();
+    if (own_ok) {
+      uint32_t* lock = v.lock + (t_lo & 1u) * 4u * v.island_stride + own;
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q)
+        store_agent(lock + q * v.island_stride, (sending && q == d) ? stamp : stamp + 1u);
+    }
+  } else if constexpr (ASYNC) {
     // publish into this island's buffer toward the drawn direction for this
     // generation's parity: odd stamp, genome, even stamp, each step complete
     // before the next issues; then the chunk's progress
@@ -604,14 +722,15 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     drain_memory();
     if (sending) {
       const uint4 g = lds[(emit_base + lane) * ES];
-      store_agent(box, g.x);
-      store_agent(box + 1, g.y);
-      store_agent(box + 2, g.z);
-      if (SW > 1) store_agent(box + 3, g.w);
+      store_agent2(box, g.x, g.y);
+      if (SW > 1 || kStr) {
+        store_agent2(box + 2, g.z, g.w);
+      } else {
+        store_agent(box + 2, g.z);
+      }
       if (kStr) {
         const uint4 p = lds[(emit_base + lane) * ES + 1u];
-        store_agent(box + 4, p.x);
-        store_agent(box + 5, p.y);
+        store_agent2(box + 4, p.x, p.y);
       }
     }
     drain_memory();
@@ -735,9 +854,64 @@ void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, ui
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The asynchronous schedule with no lead and no skew: the lockstep exchange
+// (same results as the synchronous schedule while no wait gives up), each
+// wavefront over its `chunks` consecutive chunks as in async_kernel.
+template <int LC, int SWC, int MODEL, bool WIDE>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+void lockstep_kernel(RunView v, uint32_t chunks, uint64_t n_gens) {
+  const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wig;
+  const uint32_t first = wave * chunks * v.ipw;
+  if (first >= v.islands) return;
+  const uint32_t end = min(first + chunks * v.ipw, v.islands);
+  const uint64_t t0 = *v.gen;
+  uint4* lds = wave_lds(wig, v.ipw, MODEL ? 2u : 1u);
+  AsyncCtx ax{0u, 0u};
+  for (uint64_t step = 0; step < n_gens; ++step)
+    for (uint32_t base = first; base < end; base += v.ipw)
+      chunk_generation<LC, SWC, true, MODEL, WIDE, true>(v, base, t0 + step, lds, &ax);
+  if (__lane_id() == 0u && ax.gave_up)
+    __hip_atomic_fetch_add(v.waits, (unsigned long long)ax.gave_up, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Before a lockstep launch at generation t0. After one generation under the
+// lockstep headers, the genome sent in the previous generation is the only
+// one the general rule could take (any older one was taken or passed over);
+// in generation t0 itself, a launch with a lead or a skew before this one may
+// have left an older genome pending. Thread (i, q) applies the general rule to
+// the two buffers island i reads from direction q, once: the newest buffer
+// whose stamp is even, at most 2 t0 and newer than the last one taken. If that
+// is the buffer of parity t0 & 1, its entry (stamp included) is copied into
+// the one of parity (t0 - 1) & 1, which the lockstep exchange reads in
+// generation t0. The lockstep header of parity (t0 - 1) & 1 then reads 2 t0 if
+// there is a genome to take, 2 t0 + 1 if not.
+__global__ void lockstep_prologue_kernel(RunView v, uint32_t t0) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= v.islands * 4u) return;
+  const uint32_t i = k >> 2, q = k & 3u, d = q ^ 2u, p = (t0 & 1u) ^ 1u;
+  const uint32_t ob_hdr = v.model ? 6u : 2u + v.words;
+  const uint32_t j = torus_step(i % v.width, i / v.width, q, v.width, v.height);
+  uint32_t* read = v.mail + ((j * 4u + d) * 2u + p) * v.ob_stride;
+  const uint32_t* other = v.mail + ((j * 4u + d) * 2u + (p ^ 1u)) * v.ob_stride;
+  const uint32_t due = 2u * t0, seen = v.seen[k];
+  const uint32_t s0 = read[ob_hdr], s1 = other[ob_hdr];
+  const bool e0 = (s0 & 1u) == 0u && (int32_t)(due - s0) >= 0 && (int32_t)(s0 - seen) > 0;
+  const bool e1 = (s1 & 1u) == 0u && (int32_t)(due - s1) >= 0 && (int32_t)(s1 - seen) > 0;
+  if (e1 && (!e0 || (int32_t)(s1 - s0) > 0))
+    for (uint32_t w = 0; w < v.ob_stride; ++w) read[w] = other[w];
+  v.lock[(p * 4u + d) * v.island_stride + j] = (e0 || e1) ? due : due + 1u;
+}
+
 template <int LC, int SWC, int MODEL, bool WIDE>
 hipError_t async_occupancy(int* groups, int block, size_t lds) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, async_kernel<LC, SWC, MODEL, WIDE>,
+                                                      block, lds);
+}
+template <int LC, int SWC, int MODEL, bool WIDE>
+hipError_t lockstep_occupancy(int* groups, int block, size_t lds) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, lockstep_kernel<LC, SWC, MODEL, WIDE>,
                                                       block, lds);
 }
 
@@ -897,15 +1071,35 @@ hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint3
   return hipGetLastError();
 }
 
-hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, uint32_t* waves) {
+hipError_t launch_lockstep(const RunView& v, uint64_t gen, uint64_t n_gens, uint32_t waves,
+                           uint32_t chunks, uint32_t waves_per_group, hipStream_t stream) {
+  if (waves == 0 || n_gens == 0) return hipSuccess;
+  const uint32_t fix = v.islands * 4u;
+  lockstep_prologue_kernel<<<dim3((fix + 255u) / 256u), dim3(256), 0, stream>>>(v, (uint32_t)gen);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
+  const dim3 grid(groups), block(64 * waves_per_group);
+  const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
+  GA_DISPATCH(lockstep_kernel, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
+              <<<grid, block, lds, stream>>>(v, chunks, n_gens));
+  return hipGetLastError();
+}
+
+hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, bool lockstep,
+                          uint32_t* waves) {
   int device = 0, cus = 0, groups = 0;
   hipError_t e = hipGetDevice(&device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
   const int block = 64 * (int)waves_per_group;
   const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
-  GA_DISPATCH(e = async_occupancy, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
-              (&groups, block, lds));
+  if (lockstep)
+    GA_DISPATCH(e = lockstep_occupancy, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
+                (&groups, block, lds));
+  else
+    GA_DISPATCH(e = async_occupancy, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
+                (&groups, block, lds));
   if (e != hipSuccess) return e;
   *waves = (uint32_t)groups * (uint32_t)cus * waves_per_group;
   return hipSuccess;

@@ -40,7 +40,8 @@ def test_state_bytes_layout(lib):
     # (fitness, T, surface words, header) per island; counters; extraction staging.
     # Planes are padded to roundup(islands, 64) + 128 islands.
     # The asynchronous schedule has eight buffers (direction x parity), four
-    # stamps and a progress word per island instead of the two outboxes.
+    # stamps, a progress word and eight lockstep headers per island instead of
+    # the two outboxes.
     def expect(c):
         I = (c["width"] * c["height"] + 63) // 64 * 64 + 128
         A = I * c["pop"]
@@ -52,7 +53,8 @@ def test_state_bytes_layout(lib):
         strings = c.get("model", 0) != 0
         if strings:
             ob = 8
-        exchange = ((al(4 * 8 * I * ob) + al(4 * 4 * I) + al(4 * I)) if c.get("schedule")
+        exchange = ((al(4 * 8 * I * ob) + al(4 * 4 * I) + al(4 * I) + al(4 * 8 * I))
+                    if c.get("schedule")
                     else 2 * al(4 * I * ob))
         return (al(4 * A) * 2 + al(4 * A * W) + (al(4 * A * 2) if strings else 0) + exchange
                 + 256 + 2 * al(4 * I) + al(4 * I * W))

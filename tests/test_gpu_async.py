@@ -120,6 +120,74 @@ def test_paced_free_running_is_synchronous(kw, gens):
     assert_same_state(got, oracle_after(_oracle_cfg(cfg), gens), f"async paced {kw}")
 
 
+@pytest.mark.parametrize("max_waves", [5, 24, 0])
+def test_lockstep_with_several_chunks_per_wavefront(max_waves):
+    # No lead and no skew is the lockstep exchange: an island waits for its
+    # four neighbours' headers of the previous generation. With 192 chunks of
+    # 4 islands over 5 or 24 wavefronts, each wavefront runs many chunks in
+    # turn, and neighbouring chunks often belong to one wavefront.
+    cfg = _async(width=48, height=16, pop=16, sites=32, k=3)
+    say(f"async lockstep 48x16x16, ipw 4, max_waves {max_waves}")
+    run = GARun(cfg)
+    run.set_launch(4)
+    run.set_async(max_waves, 0)
+    for n in (1, 150, 149):
+        run.step(n)
+    got = run.read()
+    waits = run.async_waits()
+    run.close()
+    assert waits == 0, f"{waits} waits gave up"
+    assert_same_state(got, oracle_after(_oracle_cfg(cfg), 300), f"lockstep max_waves {max_waves}")
+
+
+def test_lockstep_and_general_exchange_alternate():
+    # Skewed one-wavefront launches (the general exchange; genomes late,
+    # overwritten or still pending at the end of a launch) alternate with
+    # lockstep launches, on one and on several wavefronts. A lockstep launch
+    # starts by applying the general rule once (a pending older genome is
+    # taken in its first generation), so every segment matches the oracle's
+    # interleaving, down to the last genome taken from each side.
+    cfg = _async(width=24, height=16, pop=16, sites=64, k=4, seed=31)
+    ipw = 8
+    run = GARun(cfg)
+    run.set_launch(ipw)
+    ref = oracle.OracleRun(_oracle_cfg(cfg))
+    plan = [((1, ASYNC_UNPACED, 3), 37, 3), ((0, 0, 0), 25, 0), ((1, ASYNC_UNPACED, 2), 31, 2),
+            ((5, 0, 0), 40, 0), ((1, ASYNC_UNPACED, 5), 23, 5), ((1, 0, 0), 30, 0)]
+    for (mw, lead, skew), n, ref_skew in plan:
+        say(f"async segment max_waves {mw} lead {lead} skew {skew}, {n} generations")
+        run.set_async(mw, lead, skew)
+        run.step(n)
+        ref.step_async(n, ipw, ref_skew)
+        assert_same_state(run.read(), ref, f"after segment {mw, lead, skew}")
+        seen = ref.mailboxes()["seen"].astype(np.int64) - 1
+        assert np.array_equal(run.async_last_taken(), seen), f"last taken after {mw, lead, skew}"
+    assert run.async_waits() == 0
+    run.close()
+
+
+def test_lockstep_resume_from_a_written_population():
+    cfg = _async(width=40, height=12, pop=32, sites=32, k=2)
+    run = GARun(cfg)
+    run.step(120)
+    mid = run.read()
+    run.close()
+    ref = oracle_after(_oracle_cfg(cfg), 120)
+    assert_same_state(mid, ref, "lockstep at 120")
+    run2 = GARun(cfg)
+    run2.set_launch(4)
+    run2.set_async(7, 0)
+    run2.write(mid["f"], mid["T"], mid["D"], generation=120)
+    run2.step(90)
+    ref.set_outbox(np.zeros(ref.islands, np.uint8), np.zeros(ref.islands, np.uint8),
+                   np.zeros(ref.islands, np.float32), np.zeros(ref.islands, np.uint32),
+                   np.zeros((ref.islands, ref.words), np.uint32))
+    ref.step(90)
+    assert_same_state(run2.read(), ref, "lockstep resumed at 210")
+    assert run2.async_waits() == 0
+    run2.close()
+
+
 def test_paced_last_taken_follows_the_migration_draws():
     # Equal to the synchronous schedule, the last genome island i took from
     # side q was sent in the last generation g <= t-2 in which the neighbour
