@@ -263,6 +263,13 @@ int ga_set_launch(ga_run* run, uint32_t islands_per_wave, uint32_t waves_per_gro
  * island waits for its neighbours to finish the previous generation, which
  * makes the results equal to the synchronous schedule's whenever no wait gave
  * up, with no barrier across the grid. GA_ASYNC_UNPACED: no waiting at all.
+ * With max_lead 0 and no skew the launch uses the lockstep exchange: each
+ * island publishes, every generation, one header per side saying whether it
+ * sent a genome that way, and a neighbour's header doubles as its progress, so
+ * one wait and one read replace the stamped reads; its first generation
+ * applies the general rule above, so it takes what any other launch would. A
+ * wait that gives up in lockstep drops the genome toward the late neighbour
+ * (its buffer may still be in use) rather than overwrite it.
  *
  * skew > 0 (needs max_wavefronts 1 and GA_ASYNC_UNPACED): the reproducible
  * interleaving in which chunk c (islands c*ipw ...) runs its generation g of a
