@@ -86,17 +86,9 @@ __device__ __forceinline__ unsigned long long compact_stride(unsigned long long 
   return x;
 }
 
-// One thread per pair (x, y); rows of the grid are x, 64 consecutive y per
-// wavefront so the two output rows are written coalesced.
-__global__ __launch_bounds__(256) void pairs_kernel(const Normalized* __restrict__ nz, uint32_t n,
-                                                    uint32_t dlog, uint32_t kc,
-                                                    uint32_t* __restrict__ L,
-                                                    uint32_t* __restrict__ U) {
-  const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t x = blockIdx.y;
-  if (y >= n) return;
-  const Normalized a = nz[x];
-  const Normalized b = nz[y];
+// Interval for the pair (a, b) of normalised surfaces.
+__device__ __forceinline__ uint2 pair_interval(const Normalized& a, const Normalized& b,
+                                               uint32_t dlog, uint32_t kc) {
   const uint32_t e = a.epoch > b.epoch ? a.epoch : b.epoch;
   const uint32_t tmin = a.T < b.T ? a.T : b.T;
   const uint32_t common = tmin == 0u ? 0u : ((tmin - 1u) >> e) + 1u;  // ranks j*2^e < tmin
@@ -107,6 +99,13 @@ __global__ __launch_bounds__(256) void pairs_kernel(const Normalized* __restrict
     const unsigned long long mask = common >= 64u ? ~0ull : ((1ull << common) - 1ull);
     const unsigned long long hit = diff & mask;
     if (hit) j = (uint32_t)__ffsll((long long)hit) - 1u;
+  } else if (a.epoch == b.epoch) {
+    // common rank i is field i of both strings: the first differing field
+    // holds the lowest set bit of the XOR
+    const uint32_t used = common << dlog;  // bits of the common fields
+    const unsigned long long mask = used >= 64u ? ~0ull : ((1ull << used) - 1ull);
+    const unsigned long long hit = (a.bits ^ b.bits) & mask;
+    if (hit) j = ((uint32_t)__ffsll((long long)hit) - 1u) >> dlog;
   } else {
     // common rank i is field i << (e - epoch) of each string
     const unsigned long long fmask = (1ull << (1u << dlog)) - 1ull;
@@ -121,10 +120,29 @@ __global__ __launch_bounds__(256) void pairs_kernel(const Normalized* __restrict
     }
   }
   const uint32_t upper = j < common ? j << e : tmin;
-  const uint32_t below = j;
-  const size_t at = (size_t)x * n + y;
-  U[at] = upper;
-  L[at] = below < kc ? 0u : ((below - kc) << e) + 1u;
+  const uint32_t lower = j < kc ? 0u : ((j - kc) << e) + 1u;
+  return make_uint2(lower, upper);
+}
+
+// One thread per pair (x, y) in each of eight passes over 2,048 consecutive y
+// (256 per pass, lane-consecutive, so loads and the two output rows are
+// coalesced); rows of the grid are x.
+__global__ __launch_bounds__(256) void pairs_kernel(const Normalized* __restrict__ nz, uint32_t n,
+                                                    uint32_t dlog, uint32_t kc,
+                                                    uint32_t* __restrict__ L,
+                                                    uint32_t* __restrict__ U) {
+  const uint32_t x = blockIdx.y;
+  const Normalized a = nz[x];
+  const size_t row = (size_t)x * n;
+#pragma unroll
+  for (uint32_t pass = 0; pass < 8; ++pass) {
+    const uint32_t y = blockIdx.x * 2048u + pass * 256u + threadIdx.x;
+    if (y < n) {
+      const uint2 r = pair_interval(a, nz[y], dlog, kc);
+      U[row + y] = r.y;
+      L[row + y] = r.x;
+    }
+  }
 }
 
 // Tilted surfaces (S = 32 m sites, level k = site / m, slot j = site % m):
@@ -132,31 +150,38 @@ __global__ __launch_bounds__(256) void pairs_kernel(const Normalized* __restrict
 // its level whose index along the level is j mod m. A rank sits at one site
 // whatever T is, so the ranks two surfaces share are the slots where both
 // hold the same rank.
-__device__ __forceinline__ bool tilted_rank(uint32_t T, uint32_t k, uint32_t j, uint32_t m,
-                                            uint32_t* rank) {
-  if (T == 0u) return false;
-  // level k < 31: ranks 2^k (2i + 1); level 31: ranks i 2^31; slot = i mod m
+// The rank slot j of level k holds after T deposits, or kNone. Level k < 31
+// holds the odd multiples 2^k (2i + 1), level 31 the multiples i 2^31 (rank 0
+// among them); slot j keeps the newest one below T with i = j mod 2^m_log.
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+__device__ __forceinline__ uint32_t tilted_slot_rank(uint32_t T, uint32_t k, uint32_t j,
+                                                     uint32_t m_log) {
+  if (T == 0u) return kNone;
   const uint32_t q = (T - 1u) >> k;
-  if (k < 31u && q == 0u) return false;
+  if (k < 31u && q == 0u) return kNone;
   const uint32_t imax = k < 31u ? (q - 1u) >> 1 : q;
-  if (imax < j) return false;
-  const uint32_t i = imax - ((imax - j) & (m - 1u));
-  *rank = k < 31u ? ((2u * i + 1u) << k) : (i << 31);
-  return true;
+  if (imax < j) return kNone;
+  const uint32_t i = imax - ((imax - j) & ((1u << m_log) - 1u));
+  return k < 31u ? ((2u * i + 1u) << k) : (i << 31);
 }
 
 // One thread per pair: U = the oldest common rank whose differentia differ
 // (or min(Ta, Tb)); L = the kc-th common rank below U, plus one (0 if fewer).
+// The common ranks (a rank sits at one site whatever T is, so they are the
+// sites where both surfaces hold the same rank) are found once and kept in
+// registers, S known at compile time.
+template <uint32_t S>
 __global__ __launch_bounds__(256) void pairs_tilted_kernel(const uint32_t* __restrict__ T,
                                                            const uint32_t* __restrict__ D,
-                                                           uint32_t n, uint32_t s_log,
-                                                           uint32_t dlog, uint32_t kc,
+                                                           uint32_t n, uint32_t dlog,
+                                                           uint32_t kc,
                                                            uint32_t* __restrict__ L,
                                                            uint32_t* __restrict__ U) {
+  constexpr uint32_t m_log = S == 64u ? 1u : 0u;
   const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t x = blockIdx.y;
   if (y >= n) return;
-  const uint32_t S = 1u << s_log, m = S >> 5, words = (S << dlog) >> 5;
+  const uint32_t words = (S << dlog) >> 5;
   const uint32_t ta = T[x], tb = T[y];
   const unsigned long long wa = (unsigned long long)D[(size_t)x * words] |
                                 (words > 1 ? (unsigned long long)D[(size_t)x * words + 1] << 32
@@ -165,29 +190,30 @@ __global__ __launch_bounds__(256) void pairs_tilted_kernel(const uint32_t* __res
                                 (words > 1 ? (unsigned long long)D[(size_t)y * words + 1] << 32
                                            : 0ull);
   const unsigned long long fmask = (1ull << (1u << dlog)) - 1ull;
-  const uint32_t tmin = ta < tb ? ta : tb;
-  uint32_t upper = tmin;
+  const unsigned long long diff = wa ^ wb;
+  uint32_t upper = ta < tb ? ta : tb;
+  uint32_t common[S];  // the rank both hold at each site, or kNone
+#pragma unroll
   for (uint32_t site = 0; site < S; ++site) {
-    uint32_t ra, rb;
-    if (!tilted_rank(ta, site / m, site % m, m, &ra) || !tilted_rank(tb, site / m, site % m, m, &rb) ||
-        ra != rb)
-      continue;
-    const uint32_t shift = site << dlog;
-    if (((wa >> shift) & fmask) != ((wb >> shift) & fmask) && ra < upper) upper = ra;
+    const uint32_t k = site >> m_log, j = site & ((1u << m_log) - 1u);
+    const uint32_t ra = tilted_slot_rank(ta, k, j, m_log);
+    const uint32_t rb = tilted_slot_rank(tb, k, j, m_log);
+    common[site] = ra == rb ? ra : kNone;
+    if (ra == rb && ra != kNone && ((diff >> (site << dlog)) & fmask) != 0ull && ra < upper)
+      upper = ra;
   }
-  // kc-th largest common rank below upper
+  // kc-th largest common rank below upper (the common ranks are distinct)
   uint32_t bound = upper;
   bool found = true;
   for (uint32_t c = 0; c < kc && found; ++c) {
     found = false;
     uint32_t best = 0u;
+#pragma unroll
     for (uint32_t site = 0; site < S; ++site) {
-      uint32_t ra, rb;
-      if (!tilted_rank(ta, site / m, site % m, m, &ra) ||
-          !tilted_rank(tb, site / m, site % m, m, &rb) || ra != rb || ra >= bound)
-        continue;
-      if (!found || ra > best) best = ra;
-      found = true;
+      const uint32_t r = common[site];
+      const bool ok = r != kNone && r < bound && (!found || r > best);
+      best = ok ? r : best;
+      found = found || ok;
     }
     bound = best;
   }
@@ -228,12 +254,16 @@ __global__ __launch_bounds__(256) void pairs_hybrid_kernel(const uint32_t* __res
       break;
     }
   }
-  // tilted halves: t / 2 odd deposits each, one slot per level
+  // tilted halves: t / 2 odd deposits each, one slot per level; the common
+  // ones (as odd ranks 2r + 1) found once and kept in registers
   const uint32_t ma = ta >> 1, mb = tb >> 1;
+  uint32_t common[32];
+#pragma unroll
   for (uint32_t k = 0; k < 32; ++k) {
-    uint32_t ra, rb;
-    if (!tilted_rank(ma, k, 0u, 1u, &ra) || !tilted_rank(mb, k, 0u, 1u, &rb) || ra != rb) continue;
-    if (((diff >> (32u + k)) & 1ull) && 2u * ra + 1u < upper) upper = 2u * ra + 1u;
+    const uint32_t ra = tilted_slot_rank(ma, k, 0u, 0u);
+    const uint32_t rb = tilted_slot_rank(mb, k, 0u, 0u);
+    common[k] = ra == rb && ra != kNone ? 2u * ra + 1u : kNone;
+    if (common[k] != kNone && ((diff >> (32u + k)) & 1ull) && common[k] < upper) upper = common[k];
   }
   // kc-th largest common rank below upper
   uint32_t bound = upper;
@@ -247,15 +277,12 @@ __global__ __launch_bounds__(256) void pairs_hybrid_kernel(const uint32_t* __res
       best = 2u * (jm << E);
       found = true;
     }
+#pragma unroll
     for (uint32_t k = 0; k < 32; ++k) {
-      uint32_t ra, rb;
-      if (!tilted_rank(ma, k, 0u, 1u, &ra) || !tilted_rank(mb, k, 0u, 1u, &rb) || ra != rb)
-        continue;
-      const uint32_t r = 2u * ra + 1u;
-      if (r < bound && (!found || r > best)) {
-        best = r;
-        found = true;
-      }
+      const uint32_t r = common[k];
+      const bool ok = r != kNone && r < bound && (!found || r > best);
+      best = ok ? r : best;
+      found = found || ok;
     }
     bound = best;
   }
@@ -273,8 +300,13 @@ hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, 
                               uint32_t* L, uint32_t* U, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   if (policy == 1u) {
-    pairs_tilted_kernel<<<dim3((n + 255) / 256, n), dim3(256), 0, stream>>>(T, D, n, s_log, dlog,
-                                                                           kc, L, U);
+    const dim3 grid((n + 255) / 256, n);
+    if (s_log == 6u)
+      pairs_tilted_kernel<64><<<grid, dim3(256), 0, stream>>>(T, D, n, dlog, kc, L, U);
+    else if (s_log == 5u)
+      pairs_tilted_kernel<32><<<grid, dim3(256), 0, stream>>>(T, D, n, dlog, kc, L, U);
+    else
+      return hipErrorInvalidValue;
     return hipGetLastError();
   }
   if (policy == 2u) {
@@ -285,7 +317,7 @@ hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, 
   normalize_kernel<<<dim3((n + 255) / 256), dim3(256), 0, stream>>>(T, D, n, s_log, dlog, nz);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  pairs_kernel<<<dim3((n + 255) / 256, n), dim3(256), 0, stream>>>(nz, n, dlog, kc, L, U);
+  pairs_kernel<<<dim3((n + 2047) / 2048, n), dim3(256), 0, stream>>>(nz, n, dlog, kc, L, U);
   return hipGetLastError();
 }
 

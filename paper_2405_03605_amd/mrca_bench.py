@@ -81,6 +81,23 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("mrca_bench needs an MI355X GPU")
     torch.cuda.set_device(0)
+    # practical write ceiling: a plain fill of the same two n x n u32 outputs
+    n = args.n
+    out = torch.empty((2, n, n), dtype=torch.int32, device="cuda")
+    out.zero_()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.reps):
+        out.zero_()
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / args.reps
+    print(json.dumps({"variant": "fill of both outputs (write ceiling)", "n": n,
+                      "us_per_matrix": round(sec * 1e6, 1),
+                      "GB_per_s": round(8 * n * n / sec / 1e9, 1)}), flush=True)
+    del out
     for name, sites, bits, policy in VARIANTS:
         T, D = sample(sites, bits, policy, args.n, args.gens)
         sec = time_matrix(T, D, sites, bits, policy, args.kc, args.reps, torch)
