@@ -135,10 +135,18 @@ def bench_batched(gens: int, torch):
     batch.close()
     for r in runs:
         r.close()
+    # every member's algorithmic bytes per generation over the batched wall time
+    # (graph replays and the per-block advance included)
+    bytes_gen = sum(algorithmic_bytes_per_generation(c) for c in cfgs)
+    achieved = bytes_gen * gens / batched / 1e9
     return {"runs": len(cfgs), "agents": agents, "generations": gens,
             "batched_agent_gens_per_s": agents * gens / batched,
             "plain_agent_gens_per_s": agents * gens / plain,
-            "speedup": plain / batched}
+            "speedup": plain / batched,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+                         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                         "bytes_per_generation": bytes_gen,
+                         "kernel": "batch_generation_kernel"}}
 
 
 def bench_served(n_requests: int, capacity: float, torch):

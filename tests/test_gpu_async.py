@@ -120,14 +120,21 @@ def test_paced_free_running_is_synchronous(kw, gens):
     assert_same_state(got, oracle_after(_oracle_cfg(cfg), gens), f"async paced {kw}")
 
 
-@pytest.mark.parametrize("max_waves", [5, 24, 0])
-def test_lockstep_with_several_chunks_per_wavefront(max_waves):
+@pytest.mark.parametrize("kw,max_waves", [(dict(width=48, height=16), 5),
+                                          (dict(width=48, height=16), 24),
+                                          (dict(width=48, height=16), 0),
+                                          (dict(width=1, height=300), 9),
+                                          (dict(width=300, height=1), 0),
+                                          (dict(width=2, height=2), 0)])
+def test_lockstep_with_several_chunks_per_wavefront(kw, max_waves):
     # No lead and no skew is the lockstep exchange: an island waits for its
-    # four neighbours' headers of the previous generation. With 192 chunks of
-    # 4 islands over 5 or 24 wavefronts, each wavefront runs many chunks in
-    # turn, and neighbouring chunks often belong to one wavefront.
-    cfg = _async(width=48, height=16, pop=16, sites=32, k=3)
-    say(f"async lockstep 48x16x16, ipw 4, max_waves {max_waves}")
+    # four neighbours' headers of the previous generation. With chunks of 4
+    # islands over a few wavefronts, each wavefront runs many chunks in turn,
+    # and neighbouring chunks often belong to one wavefront; on a torus one
+    # island wide or high an island is its own east-west (north-south)
+    # neighbour.
+    cfg = _async(pop=16, sites=32, k=3, **kw)
+    say(f"async lockstep {kw}, ipw 4, max_waves {max_waves}")
     run = GARun(cfg)
     run.set_launch(4)
     run.set_async(max_waves, 0)
@@ -137,7 +144,7 @@ def test_lockstep_with_several_chunks_per_wavefront(max_waves):
     waits = run.async_waits()
     run.close()
     assert waits == 0, f"{waits} waits gave up"
-    assert_same_state(got, oracle_after(_oracle_cfg(cfg), 300), f"lockstep max_waves {max_waves}")
+    assert_same_state(got, oracle_after(_oracle_cfg(cfg), 300), f"lockstep {kw} {max_waves}")
 
 
 def test_lockstep_and_general_exchange_alternate():
@@ -214,13 +221,14 @@ def test_paced_last_taken_follows_the_migration_draws():
             assert got[i, q] == (sent[-1] if sent.size else -1), (i, q)
 
 
+@pytest.mark.parametrize("lead", [ASYNC_UNPACED, 0])
 @pytest.mark.parametrize("kw", [dict(width=64, height=64, pop=32, sites=32),
                                 dict(width=100, height=37, pop=8, sites=64, k=5)])
-def test_unpaced_without_migration_is_synchronous(kw):
+def test_unpaced_without_migration_is_synchronous(kw, lead):
     cfg = _async(migration=0, **kw)
-    say(f"async unpaced, no migration {kw}")
+    say(f"async lead {lead}, no migration {kw}")
     run = GARun(cfg)
-    run.set_async(0, ASYNC_UNPACED)
+    run.set_async(0, lead)
     run.step(300)
     got = run.read()
     run.close()
