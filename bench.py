@@ -188,9 +188,24 @@ def cpu_baseline(cfg: dict, budget_s: float = 12.0):
     agents = cfg["width"] * cfg["height"] * cfg["pop"]
     return {"value": agents * gens / dt, "unit": "agent-generations/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"single-threaded CPU oracle, generations 1..{gens + 1} of the "
-                      f"{cfg['width']}x{cfg['height']}x{cfg['pop']} run ({agents} agents), "
-                      f"generation loop only, {dt:.1f} s"}
+            "sample": f"single-threaded CPU oracle, generations 1 to {gens} (generation 0 "
+                      f"untimed) of the {cfg['width']}x{cfg['height']}x{cfg['pop']} run "
+                      f"({agents} agents), generation loop only, {dt:.1f} s",
+            "host": host_cpu()}
+
+
+def host_cpu() -> dict:
+    """CPU model and logical CPU count of the machine the oracle ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu": model, "logical_cpus": os.cpu_count()}
 
 
 def main():
