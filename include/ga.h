@@ -31,8 +31,9 @@
  * Every random draw is one Philox4x32-10 block (Salmon et al., SC'11) keyed
  * by (seed, run_id) with counter (slot or 0, island, generation low word,
  * generation high word * 4 + stream), stream 0 selection, 1 migration,
- * 2 sampling, 3 mutation sizes (law 1). Results are therefore bit-identical for any launch shape,
- * batching or schedule.
+ * 2 sampling, 3 mutation sizes (law 1). Results are therefore bit-identical for any launch
+ * shape and with or without batching; the asynchronous schedule (below) changes only the
+ * moment a migrant is read, and with its default pacing not even that.
  *
  * Conventions for every entry point:
  *   - Return value: GA_OK (0) or a negative GA_E* code; ga_last_error()
@@ -182,8 +183,9 @@ typedef struct ga_outbox_entry {
 typedef struct ga_run ga_run;
 
 /* Device bytes a run needs (population planes, double-buffered outboxes or,
- * for the asynchronous schedule, four buffers and four stamps per island,
- * generation counter, extraction staging). 0 for an invalid configuration. */
+ * for the asynchronous schedule, per island eight buffers (direction x parity),
+ * four last-taken stamps, a progress word and eight lockstep headers; the
+ * generation counter and extraction staging). 0 for an invalid configuration. */
 size_t ga_state_bytes(const ga_config* cfg);
 
 /* Create a run in caller-owned device memory dev_mem (>= ga_state_bytes(cfg),
@@ -305,7 +307,8 @@ int ga_batch_create(void* hip_stream, ga_batch** out);
 /* Add a run (created by ga_init, bound to any stream; from now on it is
  * advanced only through the batch) with a generation budget: the batch stops
  * advancing it after budget more generations. Returns GA_OK; GA_EINVAL for an
- * asynchronous run, a genome model with a string, or differentia_bits > 1. */
+ * asynchronous run, a genome model with a string, differentia_bits > 1 or a
+ * surface policy other than steady; GA_ESTATE if the run is already in a batch. */
 int ga_batch_add(ga_batch* batch, ga_run* run, uint64_t budget);
 /* Remove a member (after waiting for the batch's stream). */
 int ga_batch_remove(ga_batch* batch, ga_run* run);
