@@ -65,6 +65,11 @@ struct RunView {
 // number of progress checks before an island goes on regardless.
 constexpr uint32_t kUnpaced = 0xFFFFFFFFu;
 constexpr uint32_t kPaceSpins = 2048;
+// The lockstep exchange waits only on its neighbours' real progress, so its
+// bound (about 70 ms of checks) only has to end waits on a wavefront that
+// never runs; shorter bounds gave up on wavefronts held back a few
+// milliseconds (first touches of a multi-GB mail plane).
+constexpr uint32_t kLockSpins = 32768;
 
 // One wavefront's share of a batched launch: islands [first, first + ipw) of run `run`.
 struct Tile {

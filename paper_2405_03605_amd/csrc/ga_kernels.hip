@@ -200,6 +200,21 @@ __device__ __forceinline__ void drain_memory() {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// Buffer of island i toward direction d for sending generations of parity p
+// in the asynchronous mail plane, and island i's lockstep header there. Offsets
+// are 64-bit: the mail plane (up to 256 bytes per island) outgrows 32-bit
+// indexing long before the largest valid torus.
+template <typename P>
+__device__ __forceinline__ P* mail_entry(P* mail, uint32_t i, uint32_t d, uint32_t p,
+                                         uint32_t stride) {
+  return mail + ((size_t)i * 8u + d * 2u + p) * stride;
+}
+template <typename P>
+__device__ __forceinline__ P* lock_header(P* lock, uint32_t i, uint32_t d, uint32_t p,
+                                          uint32_t island_stride) {
+  return lock + (size_t)(p * 4u + d) * island_stride + i;
+}
+
 struct Genome {
   float f = 0.f;
   uint32_t T = 0, D0 = 0, D1 = 0;
@@ -317,7 +332,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   if constexpr (!ASYNC) {
 #pragma unroll
     for (uint32_t q = 0; q < 4; ++q) {
-      const uint32_t* e = in_ob + torus_step(ox, oy, q, W, H) * ob_stride;
+      const uint32_t* e = in_ob + (size_t)torus_step(ox, oy, q, W, H) * ob_stride;
       const uint4 entry = *reinterpret_cast<const uint4*>(e);  // f, T, D0, header or D1
       uint4 more = make_uint4(0u, 0u, 0u, 0u);                  // P0, P1, header
       if (kStr) more = *reinterpret_cast<const uint4*>(e + 4);
@@ -348,13 +363,14 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     const uint32_t due = 2u * t_lo;
     const uint32_t prev = (t_lo & 1u) ^ 1u;
     const uint32_t* mail = v.mail;
-    const uint32_t* lock = v.lock + prev * 4u * v.island_stride;
+    const uint32_t* lock = v.lock;
     uint32_t hits = 0u;  // bit q: a genome was sent this way in generation t - 1
     for (uint32_t spin = 0;; ++spin) {
       uint32_t h[4];
 #pragma unroll
       for (uint32_t q = 0; q < 4; ++q)
-        h[q] = load_agent(lock + (q ^ 2u) * v.island_stride + torus_step(ox, oy, q, W, H));
+        h[q] = load_agent(
+            lock_header(lock, torus_step(ox, oy, q, W, H), q ^ 2u, prev, v.island_stride));
       drain_memory();
       hits = 0u;
       ready = 0u;
@@ -364,7 +380,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
         ready |= ((int32_t)(h[q] - due) >= 0 ? 1u : 0u) << q;
       }
       if (__ballot(own_ok && ready != 15u) == 0ull) break;
-      if (spin == kPaceSpins) {
+      if (spin == kLockSpins) {
         ++ax->gave_up;
         break;
       }
@@ -376,28 +392,27 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     uint32_t stamp[4];
 #pragma unroll
     for (uint32_t q = 0; q < 4; ++q) {
-      // byte offset of the neighbour's buffer toward this island
-      const uint32_t b =
-          (((torus_step(ox, oy, q, W, H) * 4u + (q ^ 2u)) * 2u + prev) * ob_stride) << 2;
-      const uint2 lo = load_agent2(at_byte(mail, b));
-      const uint2 hi = load_agent2(at_byte(mail, b + 8u));  // D0, then D1 or the stamp
+      // the neighbour's buffer toward this island
+      const uint32_t* e = mail_entry(mail, torus_step(ox, oy, q, W, H), q ^ 2u, prev, ob_stride);
+      const uint2 lo = load_agent2(e);
+      const uint2 hi = load_agent2(e + 2);  // D0, then D1 or the stamp
       pay[q] = make_uint4(lo.x, lo.y, hi.x, hi.y);
       pstr[q] = make_uint4(0u, 0u, 0u, 0u);
       stamp[q] = 0u;
       if (kStr) {
-        const uint2 p = load_agent2(at_byte(mail, b + 16u));
-        const uint2 h2 = load_agent2(at_byte(mail, b + 24u));  // stamp, padding
+        const uint2 p = load_agent2(e + 4);
+        const uint2 h2 = load_agent2(e + 6);  // stamp, padding
         pstr[q] = make_uint4(p.x, p.y, 0u, 0u);
         stamp[q] = h2.x;
       } else if (SW > 1) {
-        stamp[q] = load_agent(at_byte(mail, b + 16u));
+        stamp[q] = load_agent(e + 4);
       }
     }
     drain_memory();
 #pragma unroll
     for (uint32_t q = 0; q < 4; ++q) {
       const bool hit = ((hits >> q) & 1u) != 0u;
-      if (hit) v.seen[own * 4u + q] = (SW == 1 && !kStr) ? pay[q].w : stamp[q];
+      if (hit) v.seen[(size_t)own * 4u + q] = (SW == 1 && !kStr) ? pay[q].w : stamp[q];
       const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
       desc = hit ? (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q)) : desc;
       if (lane < v.ipw) {
@@ -439,7 +454,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
       }
     }
 
-    uint32_t* seen_at = v.seen + own * 4u;
+    uint32_t* seen_at = v.seen + (size_t)own * 4u;
     const uint4 seen4 = *reinterpret_cast<const uint4*>(seen_at);
     uint32_t seen_q[4] = {seen4.x, seen4.y, seen4.z, seen4.w};
     const uint32_t newest_ok = 2u * t_lo;  // stamp of a genome sent in t-1
@@ -450,7 +465,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
       uint32_t s0[4], s1[4];
 #pragma unroll
       for (uint32_t q = 0; q < 4; ++q) {
-        box[q] = v.mail + (nb[q] * 4u + (q ^ 2u)) * 2u * ob_stride;
+        box[q] = mail_entry(v.mail, nb[q], q ^ 2u, 0u, ob_stride);
         s0[q] = load_agent(box[q] + ob_hdr);
         s1[q] = load_agent(box[q] + ob_stride + ob_hdr);
       }
@@ -688,7 +703,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     const bool sending = own_ok && hdr != 0u && ((ready >> d) & 1u) != 0u;
     const uint32_t stamp = 2u * (t_lo + 1u);
     if (sending) {
-      uint32_t* box = v.mail + ((own * 4u + d) * 2u + (t_lo & 1u)) * ob_stride;
+      uint32_t* box = mail_entry(v.mail, own, d, t_lo & 1u, ob_stride);
       const uint4 g = lds[(emit_base + lane) * ES];
       store_agent2(box, g.x, g.y);
       if (kStr) {
@@ -705,10 +720,10 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     }
     drain_memory();
     if (own_ok) {
-      uint32_t* lock = v.lock + (t_lo & 1u) * 4u * v.island_stride + own;
 #pragma unroll
       for (uint32_t q = 0; q < 4; ++q)
-        store_agent(lock + q * v.island_stride, (sending && q == d) ? stamp : stamp + 1u);
+        store_agent(lock_header(v.lock, own, q, t_lo & 1u, v.island_stride),
+                    (sending && q == d) ? stamp : stamp + 1u);
     }
   } else if constexpr (ASYNC) {
     // publish into this island's buffer toward the drawn direction for this
@@ -716,7 +731,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     // before the next issues; then the chunk's progress
     const uint32_t hdr = emit >> 8;
     const bool sending = own_ok && hdr != 0u;
-    uint32_t* box = v.mail + ((own * 4u + (hdr & 3u)) * 2u + (t_lo & 1u)) * ob_stride;
+    uint32_t* box = mail_entry(v.mail, own, hdr & 3u, t_lo & 1u, ob_stride);
     const uint32_t stamp = 2u * (t_lo + 1u);
     if (sending) store_agent(box + ob_hdr, stamp - 1u);
     drain_memory();
@@ -740,7 +755,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     drain_memory();
     if (lane == 0u) store_agent(v.prog + base / v.ipw, t_lo + 1u);
   } else if (own_ok) {
-    uint32_t* e = out_ob + own * ob_stride;
+    uint32_t* e = out_ob + (size_t)own * ob_stride;
     const uint32_t hdr = emit >> 8;
     if (hdr) {
       const uint4 g = lds[(emit_base + lane) * ES];
@@ -888,20 +903,20 @@ void lockstep_kernel(RunView v, uint32_t chunks, uint64_t n_gens) {
 // generation t0. The lockstep header of parity (t0 - 1) & 1 then reads 2 t0 if
 // there is a genome to take, 2 t0 + 1 if not.
 __global__ void lockstep_prologue_kernel(RunView v, uint32_t t0) {
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= v.islands * 4u) return;
-  const uint32_t i = k >> 2, q = k & 3u, d = q ^ 2u, p = (t0 & 1u) ^ 1u;
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (size_t)v.islands * 4u) return;
+  const uint32_t i = (uint32_t)(k >> 2), q = (uint32_t)k & 3u, d = q ^ 2u, p = (t0 & 1u) ^ 1u;
   const uint32_t ob_hdr = v.model ? 6u : 2u + v.words;
   const uint32_t j = torus_step(i % v.width, i / v.width, q, v.width, v.height);
-  uint32_t* read = v.mail + ((j * 4u + d) * 2u + p) * v.ob_stride;
-  const uint32_t* other = v.mail + ((j * 4u + d) * 2u + (p ^ 1u)) * v.ob_stride;
+  uint32_t* read = mail_entry(v.mail, j, d, p, v.ob_stride);
+  const uint32_t* other = mail_entry(v.mail, j, d, p ^ 1u, v.ob_stride);
   const uint32_t due = 2u * t0, seen = v.seen[k];
   const uint32_t s0 = read[ob_hdr], s1 = other[ob_hdr];
   const bool e0 = (s0 & 1u) == 0u && (int32_t)(due - s0) >= 0 && (int32_t)(s0 - seen) > 0;
   const bool e1 = (s1 & 1u) == 0u && (int32_t)(due - s1) >= 0 && (int32_t)(s1 - seen) > 0;
   if (e1 && (!e0 || (int32_t)(s1 - s0) > 0))
     for (uint32_t w = 0; w < v.ob_stride; ++w) read[w] = other[w];
-  v.lock[(p * 4u + d) * v.island_stride + j] = (e0 || e1) ? due : due + 1u;
+  *lock_header(v.lock, j, d, p, v.island_stride) = (e0 || e1) ? due : due + 1u;
 }
 
 template <int LC, int SWC, int MODEL, bool WIDE>
@@ -1074,8 +1089,9 @@ hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint3
 hipError_t launch_lockstep(const RunView& v, uint64_t gen, uint64_t n_gens, uint32_t waves,
                            uint32_t chunks, uint32_t waves_per_group, hipStream_t stream) {
   if (waves == 0 || n_gens == 0) return hipSuccess;
-  const uint32_t fix = v.islands * 4u;
-  lockstep_prologue_kernel<<<dim3((fix + 255u) / 256u), dim3(256), 0, stream>>>(v, (uint32_t)gen);
+  const size_t fix = (size_t)v.islands * 4u;
+  lockstep_prologue_kernel<<<dim3((uint32_t)((fix + 255u) / 256u)), dim3(256), 0, stream>>>(
+      v, (uint32_t)gen);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;

@@ -147,6 +147,23 @@ def test_lockstep_with_several_chunks_per_wavefront(kw, max_waves):
     assert_same_state(got, oracle_after(_oracle_cfg(cfg), 300), f"lockstep {kw} {max_waves}")
 
 
+@pytest.mark.parametrize("lead,migration", [(0, 1), (ASYNC_UNPACED, 0)])
+def test_mail_offsets_beyond_32_bits(lead, migration):
+    # 4100 x 4100 one-agent islands with 64-site surfaces: past 2^24 islands
+    # the mail plane (eight 32-byte entries per island, 4.3 GB here) needs
+    # 64-bit offsets in both exchanges
+    cfg = _async(width=4100, height=4100, pop=1, sites=64, k=2, migration=migration)
+    say(f"async 4100x4100x1 S=64, lead {lead}, migration {migration}, 3 generations")
+    run = GARun(cfg)
+    run.set_async(0, lead)
+    run.step(3)
+    got = run.read()
+    waits = run.async_waits()
+    run.close()
+    assert waits == 0
+    assert_same_state(got, oracle_after(_oracle_cfg(cfg), 3), f"4100x4100x1 lead {lead}")
+
+
 def test_lockstep_and_general_exchange_alternate():
     # Skewed one-wavefront launches (the general exchange; genomes late,
     # overwritten or still pending at the end of a launch) alternate with
