@@ -212,6 +212,33 @@ def test_lockstep_resume_from_a_written_population():
     run2.close()
 
 
+@pytest.mark.parametrize("kw,gens", [(dict(width=1024, height=512), (500, 500)),
+                                     (dict(width=256, height=256), (1000, 2000))])
+def test_lockstep_equals_the_synchronous_kernel_at_full_size(kw, gens):
+    # the synchronous kernel is pinned to the oracle at these sizes; the
+    # lockstep launch (several of them, crossing launch boundaries) must give
+    # the same bits with no barrier across the grid
+    cfg = run_config(pop=32, sites=32, k=2, **kw)
+    say(f"lockstep vs synchronous {kw}, {sum(gens)} generations")
+    sync = GARun(cfg)
+    sync.step(sum(gens))
+    want = sync.read(outbox=False)
+    sync.close()
+    run = GARun(dict(cfg, schedule=1))
+    for n in gens:
+        run.step(n)
+    got = run.read()
+    waits = run.async_waits()
+    run.close()
+    assert waits == 0
+    assert got["generation"] == want["generation"]
+    for key in ("f", "T", "D"):
+        a, b = got[key], want[key]
+        if key == "f":
+            a, b = a.view(np.uint32), b.view(np.uint32)
+        assert np.array_equal(a, b), f"{key} differs at {np.flatnonzero(a != b)[:5]}"
+
+
 def test_paced_last_taken_follows_the_migration_draws():
     # Equal to the synchronous schedule, the last genome island i took from
     # side q was sent in the last generation g <= t-2 in which the neighbour
