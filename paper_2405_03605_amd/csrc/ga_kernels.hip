@@ -978,7 +978,6 @@ void batch_generation_kernel(const RunView* __restrict__ views,
   if (*v.left <= gen_offset) return;
   const uint64_t t = *v.gen + gen_offset;
   uint4* arr = wave_lds(wig, max_ipw, 1u);
-#ifndef GA_BATCH_GENERIC
   // wavefront-uniform dispatch to the specialised bodies
   switch (v.log2n * 2u + v.words - 1u) {
     case 0: chunk_generation<0, 1>(v, tile.first, t, arr); break;
@@ -996,9 +995,6 @@ void batch_generation_kernel(const RunView* __restrict__ views,
     case 12: chunk_generation<6, 1>(v, tile.first, t, arr); break;
     default: chunk_generation<6, 2>(v, tile.first, t, arr); break;
   }
-#else
-  chunk_generation<-1, -1>(v, tile.first, t, arr);
-#endif
 }
 
 __global__ void batch_advance_kernel(const RunView* views, uint32_t n_runs, uint64_t block) {
@@ -1016,10 +1012,6 @@ __global__ void batch_advance_kernel(const RunView* views, uint32_t n_runs, uint
 size_t lds_bytes(uint32_t ipw, uint32_t waves, uint32_t model) {
   return (5u * ipw + 1u) * sizeof(uint4) * (model ? 2u : 1u) * waves;
 }
-
-namespace {
-
-}  // namespace
 
 #define GA_SHAPES(KERNEL, M, WD, L, SW, ...)                                   \
   switch ((L) * 2 + ((SW) - 1)) {                                              \
