@@ -329,6 +329,49 @@ int ga_batch_set_launch(ga_batch* batch, uint32_t islands_per_wave, uint32_t wav
 void ga_batch_destroy(ga_batch* batch);
 
 /* ---------------------------------------------------------------------- */
+/* Run pool: the served form's runtime. Runs are created inside one       */
+/* caller-owned device buffer (first fit, 256-byte aligned; a released     */
+/* run's block merges with free neighbours) and advanced together as one   */
+/* batch; each run gives the bits it would give alone. Arrival order and   */
+/* admission policy stay with the caller.                                  */
+/* ---------------------------------------------------------------------- */
+typedef struct ga_pool ga_pool;
+
+/* Create a pool over dev_mem[0, bytes) (device memory owned by the caller,
+ * 256-byte aligned, never freed by the library) holding at most max_slots
+ * runs, bound to hip_stream. */
+int ga_pool_create(void* dev_mem, size_t bytes, uint32_t max_slots, void* hip_stream,
+                   ga_pool** out);
+/* Create a run from cfg in the pool with a budget of n_gens generations and
+ * give it a ticket (> 0). GA_ENOMEM if every slot is taken or no free block
+ * holds ga_state_bytes(cfg) now (retiring runs makes room); GA_EINVAL for an
+ * invalid configuration, one larger than the whole pool, or one a batch does
+ * not take (see ga_batch_add). Founders as ga_init; enqueued on the stream. */
+int ga_pool_admit(ga_pool* pool, const ga_config* cfg, uint64_t n_gens, uint64_t* ticket);
+/* Enqueue up to n_gens generations for every run with budget left. */
+int ga_pool_step(ga_pool* pool, uint64_t n_gens);
+/* Generations per graph replay (as ga_batch_set_graph_block). */
+int ga_pool_set_graph_block(ga_pool* pool, uint32_t gens_per_block);
+/* Generations still owed to a run (host mirror). GA_EINVAL for an unknown ticket. */
+int ga_pool_remaining(const ga_pool* pool, uint64_t ticket, uint64_t* left);
+/* Tickets of the runs whose budget is spent: up to cap of them in tickets
+ * (may be NULL), in ticket order; *n_done receives how many there are. */
+int ga_pool_poll(const ga_pool* pool, uint64_t* tickets, size_t cap, size_t* n_done);
+/* Remove a run (finished or not) and release its memory. Unless all three
+ * outputs are NULL, first sample its end population as ga_extract_surfaces
+ * does with agent_ids NULL: one agent per island from the sampling stream,
+ * ids_out[islands], T_out[islands], surface_words_out[islands * S*b/32]
+ * (Sec. 3: one genome sampled per island). A failure leaves the run in the
+ * pool. Synchronous. */
+int ga_pool_retire(ga_pool* pool, uint64_t ticket, uint64_t* ids_out, uint32_t* T_out,
+                   uint32_t* surface_words_out);
+/* Bytes held by runs, the largest free block, and the number of runs; any
+ * pointer may be NULL. */
+int ga_pool_usage(const ga_pool* pool, size_t* used, size_t* largest_free, uint32_t* live);
+/* Release every run and the pool (waits for the stream). NULL is allowed. */
+void ga_pool_destroy(ga_pool* pool);
+
+/* ---------------------------------------------------------------------- */
 /* Post hoc relatedness (Fig. 1: markers on genomes support estimating how */
 /* related two lineages are after the run; Sec. 3 reconstructs phylogenies */
 /* from 10k sampled end-state genomes).                                    */

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -223,7 +224,56 @@ struct ga_batch {
   hipGraphExec_t graph = nullptr;
 };
 
+// A run pool: runs sub-allocated from one caller-owned device buffer and
+// advanced together as one batch. Free space is a map offset -> size of
+// disjoint, non-adjacent blocks (adjacent ones are merged on release); runs
+// take the first block that fits.
+struct ga_pool {
+  uint8_t* base = nullptr;
+  size_t bytes = 0;
+  uint32_t max_slots = 0;
+  ga_batch* batch = nullptr;
+  std::map<size_t, size_t> free_blocks;
+  struct Member {
+    ga_run* run;
+    size_t off, size;
+  };
+  std::map<uint64_t, Member> members;
+  uint64_t next_ticket = 1;
+  size_t used = 0;
+};
+
 namespace {
+
+// First block of the pool's free space that holds `size` bytes; SIZE_MAX if none.
+size_t pool_take(ga_pool* p, size_t size) {
+  for (auto it = p->free_blocks.begin(); it != p->free_blocks.end(); ++it) {
+    if (it->second < size) continue;
+    const size_t off = it->first, left = it->second - size;
+    p->free_blocks.erase(it);
+    if (left) p->free_blocks.emplace(off + size, left);
+    return off;
+  }
+  return SIZE_MAX;
+}
+
+// Return [off, off + size) to the pool's free space, merging with neighbours.
+void pool_give(ga_pool* p, size_t off, size_t size) {
+  auto next = p->free_blocks.lower_bound(off);
+  if (next != p->free_blocks.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      off = prev->first;
+      size += prev->second;
+      p->free_blocks.erase(prev);
+    }
+  }
+  if (next != p->free_blocks.end() && off + size == next->first) {
+    size += next->second;
+    p->free_blocks.erase(next);
+  }
+  p->free_blocks.emplace(off, size);
+}
 
 uint32_t per_iter(const ga_run* r) { return 64u >> r->view.log2n; }
 
@@ -966,6 +1016,129 @@ void ga_batch_destroy(ga_batch* b) {
   if (b->d_views) (void)hipFree(b->d_views);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   delete b;
+}
+
+// ---------------------------------------------------------------------------
+// Run pool (served form)
+// ---------------------------------------------------------------------------
+
+int ga_pool_create(void* dev_mem, size_t bytes, uint32_t max_slots, void* hip_stream,
+                   ga_pool** out) {
+  if (!out) return fail(GA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!dev_mem) return fail(GA_EINVAL, "dev_mem is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_mem) % kAlign) return fail(GA_EINVAL, "dev_mem must be 256-byte aligned");
+  if (max_slots == 0) return fail(GA_EINVAL, "max_slots must be >= 1");
+  ga_pool* p = new (std::nothrow) ga_pool();
+  if (!p) return fail(GA_EINVAL, "host allocation failed");
+  p->base = static_cast<uint8_t*>(dev_mem);
+  p->bytes = bytes / kAlign * kAlign;
+  p->max_slots = max_slots;
+  if (p->bytes) p->free_blocks.emplace(0, p->bytes);
+  const int rc = ga_batch_create(hip_stream, &p->batch);
+  if (rc != GA_OK) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return GA_OK;
+}
+
+int ga_pool_admit(ga_pool* p, const ga_config* cfg, uint64_t n_gens, uint64_t* ticket) {
+  if (!p || !ticket) return fail(GA_EINVAL, "pool or ticket is NULL");
+  const size_t need = align_up(ga_state_bytes(cfg));
+  if (need == 0) return fail(GA_EINVAL, "invalid configuration");
+  if (need > p->bytes) return fail(GA_EINVAL, "run larger than the whole pool");
+  if (p->members.size() >= p->max_slots) return fail(GA_ENOMEM, "every slot is taken");
+  const size_t off = pool_take(p, need);
+  if (off == SIZE_MAX) return fail(GA_ENOMEM, "no free block holds the run");
+  ga_run* r = nullptr;
+  int rc = ga_init(cfg, p->base + off, need, p->batch->stream, &r);
+  if (rc == GA_OK) {
+    rc = ga_batch_add(p->batch, r, n_gens);
+    if (rc != GA_OK) ga_destroy(r);
+  }
+  if (rc != GA_OK) {
+    pool_give(p, off, need);
+    return rc;
+  }
+  *ticket = p->next_ticket++;
+  p->members.emplace(*ticket, ga_pool::Member{r, off, need});
+  p->used += need;
+  return GA_OK;
+}
+
+int ga_pool_step(ga_pool* p, uint64_t n_gens) {
+  if (!p) return fail(GA_EINVAL, "pool is NULL");
+  return ga_batch_step(p->batch, n_gens);
+}
+
+int ga_pool_set_graph_block(ga_pool* p, uint32_t gens_per_block) {
+  if (!p) return fail(GA_EINVAL, "pool is NULL");
+  return ga_batch_set_graph_block(p->batch, gens_per_block);
+}
+
+int ga_pool_remaining(const ga_pool* p, uint64_t ticket, uint64_t* left) {
+  if (!p || !left) return fail(GA_EINVAL, "pool or left is NULL");
+  auto it = p->members.find(ticket);
+  if (it == p->members.end()) return fail(GA_EINVAL, "unknown ticket");
+  *left = ga_batch_remaining(p->batch, it->second.run);
+  return GA_OK;
+}
+
+int ga_pool_poll(const ga_pool* p, uint64_t* tickets, size_t cap, size_t* n_done) {
+  if (!p || !n_done) return fail(GA_EINVAL, "pool or n_done is NULL");
+  size_t n = 0;
+  for (const auto& m : p->members) {
+    if (ga_batch_remaining(p->batch, m.second.run) != 0) continue;
+    if (tickets && n < cap) tickets[n] = m.first;
+    ++n;
+  }
+  *n_done = n;
+  return GA_OK;
+}
+
+int ga_pool_retire(ga_pool* p, uint64_t ticket, uint64_t* ids_out, uint32_t* T_out,
+                   uint32_t* surface_words_out) {
+  if (!p) return fail(GA_EINVAL, "pool is NULL");
+  auto it = p->members.find(ticket);
+  if (it == p->members.end()) return fail(GA_EINVAL, "unknown ticket");
+  ga_run* r = it->second.run;
+  // sample while the run is still a member (a failure leaves the pool as it was)
+  if (ids_out || T_out || surface_words_out) {
+    const int rc = ga_extract_surfaces(r, nullptr, r->view.islands, ids_out, T_out,
+                                       surface_words_out);
+    if (rc != GA_OK) return rc;
+  }
+  const int rc = ga_batch_remove(p->batch, r);
+  if (rc != GA_OK) return rc;
+  ga_destroy(r);
+  pool_give(p, it->second.off, it->second.size);
+  p->used -= it->second.size;
+  p->members.erase(it);
+  return GA_OK;
+}
+
+int ga_pool_usage(const ga_pool* p, size_t* used, size_t* largest_free, uint32_t* live) {
+  if (!p) return fail(GA_EINVAL, "pool is NULL");
+  if (used) *used = p->used;
+  if (largest_free) {
+    size_t big = 0;
+    for (const auto& b : p->free_blocks) big = std::max(big, b.second);
+    *largest_free = big;
+  }
+  if (live) *live = (uint32_t)p->members.size();
+  return GA_OK;
+}
+
+void ga_pool_destroy(ga_pool* p) {
+  if (!p) return;
+  for (auto& m : p->members) {
+    (void)ga_batch_remove(p->batch, m.second.run);
+    ga_destroy(m.second.run);
+  }
+  ga_batch_destroy(p->batch);
+  delete p;
 }
 
 // ---------------------------------------------------------------------------

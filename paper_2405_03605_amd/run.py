@@ -7,7 +7,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import (FORM_AUTO, GA_EINVAL, Config, GAError, OutboxEntry, check, load)
+from ._lib import (FORM_AUTO, GA_EINVAL, GA_ENOMEM, Config, GAError, OutboxEntry, check, load)
 
 CONFIG_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "p32", "migration",
                  "seed", "run_id", "law", "p_ben32", "schedule", "model", "dbits", "policy")
@@ -228,6 +228,90 @@ class GABatch:
             load().ga_batch_destroy(self._h)
             self._h = None
             self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GAPool:
+    """Runs created inside one device buffer and advanced together (ga_pool_*):
+    admission fails softly (None) while no slot or free block fits the run."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64, device=None, stream=None):
+        import torch
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.mem = torch.empty(int(budget_bytes), dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        check(load().ga_pool_create(ctypes.c_void_p(self.mem.data_ptr()), int(budget_bytes),
+                                    int(max_slots), ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(h)))
+        self._h = h
+        self.budget = int(budget_bytes)
+        self._shape = {}
+
+    def admit(self, cfg: dict, gens: int):
+        """Ticket of the new run, or None if it does not fit now."""
+        c = _fields(cfg)
+        ticket = ctypes.c_uint64()
+        code = load().ga_pool_admit(self._h, ctypes.byref(make_config(c)), int(gens),
+                                    ctypes.byref(ticket))
+        if code == GA_ENOMEM:
+            return None
+        check(code)
+        self._shape[ticket.value] = (c["width"] * c["height"], c["sites"] * c["dbits"] // 32)
+        return ticket.value
+
+    def step(self, n: int):
+        check(load().ga_pool_step(self._h, int(n)))
+
+    def set_graph_block(self, gens: int):
+        check(load().ga_pool_set_graph_block(self._h, int(gens)))
+
+    def remaining(self, ticket: int) -> int:
+        left = ctypes.c_uint64()
+        check(load().ga_pool_remaining(self._h, int(ticket), ctypes.byref(left)))
+        return int(left.value)
+
+    def done(self) -> list:
+        """Tickets of the runs whose budget is spent."""
+        n = ctypes.c_size_t()
+        check(load().ga_pool_poll(self._h, None, 0, ctypes.byref(n)))
+        out = np.empty(n.value, dtype=np.uint64)
+        check(load().ga_pool_poll(self._h, _ptr(out), out.size, ctypes.byref(n)))
+        return [int(t) for t in out[:n.value]]
+
+    def retire(self, ticket: int, sample: bool = True):
+        """Remove a run; with sample, return (ids, T, surfaces) of one agent per island."""
+        islands, words = self._shape.pop(int(ticket))
+        if not sample:
+            check(load().ga_pool_retire(self._h, int(ticket), None, None, None))
+            return None
+        ids = np.empty(islands, dtype=np.uint64)
+        T = np.empty(islands, dtype=np.uint32)
+        D = np.empty((islands, words), dtype=np.uint32)
+        check(load().ga_pool_retire(self._h, int(ticket), _ptr(ids), _ptr(T), _ptr(D)))
+        return ids, T, D
+
+    def usage(self) -> dict:
+        if getattr(self, "_h", None) is None:
+            return {"used": 0, "largest_free": 0, "live": 0}   # closed
+        used, big, live = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_uint32()
+        check(load().ga_pool_usage(self._h, ctypes.byref(used), ctypes.byref(big),
+                                   ctypes.byref(live)))
+        return {"used": int(used.value), "largest_free": int(big.value), "live": int(live.value)}
+
+    @property
+    def used(self) -> int:
+        return self.usage()["used"]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ga_pool_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

@@ -5,14 +5,16 @@ server keeps every admitted run's state on the device and advances all of them
 together in the batched form (one launch per generation over every member's
 islands, blocks of generations replayed from a HIP graph). Between blocks it
 retires runs whose budget is spent (their end-population surfaces are sampled,
-one agent per island, as in the paper's Sec. 3 end-state sampling), frees their
-memory, and admits waiting requests while the HBM budget and the slot count
-allow, in arrival order. Each run's result is bit-identical to running it alone,
+one agent per island, as in the paper's Sec. 3 end-state sampling), which frees
+their memory, and admits waiting requests in arrival order for as long as the
+pool takes them. Each run's result is bit-identical to running it alone,
 because its random stream depends only on (seed, run_id, island, generation,
 slot).
 
-The device side is injected (`make_run`, `make_batch`) so the admission and
-retirement logic can be exercised on the CPU with stand-ins.
+Memory, slots and the batch belong to the pool: by default the native run pool
+(`GAPool`, ga_pool_* in the C ABI: runs sub-allocated first fit from one device
+buffer of the budget's size). The pool is injected (`make_pool`), so the
+arrival-order policy here can be exercised on the CPU with a stand-in.
 """
 from __future__ import annotations
 
@@ -37,26 +39,28 @@ class Request:
 
 class Server:
     def __init__(self, budget_bytes: int, max_slots: int = 64, block: int = 100,
-                 make_run=None, make_batch=None, state_bytes=None, clock=time.perf_counter):
-        if make_run is None or make_batch is None or state_bytes is None:
-            from .run import GABatch, GARun, state_bytes as sb
-            make_run = make_run or GARun
-            make_batch = make_batch or GABatch
+                 make_pool=None, state_bytes=None, clock=time.perf_counter):
+        if make_pool is None or state_bytes is None:
+            from .run import GAPool, state_bytes as sb
+            make_pool = make_pool or GAPool
             state_bytes = state_bytes or sb
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.block = int(block)
-        self._make_run = make_run
         self._state_bytes = state_bytes
-        self.batch = make_batch()
-        self.batch.set_graph_block(self.block)
+        self.pool = make_pool(self.budget, self.max_slots)
+        self.pool.set_graph_block(self.block)
         self.clock = clock
         self.waiting: deque[Request] = deque()
-        self.live: dict[int, tuple[Request, object]] = {}
+        self.live: dict[int, tuple[Request, int]] = {}   # ticket -> (request, ticket)
         self.done: list[Request] = []
-        self.used = 0
         self.agent_gens = 0
         self._next_id = 0
+
+    @property
+    def used(self) -> int:
+        """Device bytes held by live runs."""
+        return self.pool.used
 
     # -- requests ---------------------------------------------------------
     def submit(self, cfg: dict, gens: int, arrival: float | None = None) -> Request:
@@ -73,34 +77,26 @@ class Server:
 
     # -- one scheduling round ---------------------------------------------
     def admit(self) -> int:
-        """Admit waiting requests in arrival order while memory and slots allow."""
+        """Admit waiting requests in arrival order while the pool takes them."""
         n = 0
-        while self.waiting and len(self.live) < self.max_slots:
+        while self.waiting:
             req = self.waiting[0]
-            if self.used + req.footprint > self.budget:
+            ticket = self.pool.admit(req.cfg, req.gens)
+            if ticket is None:
                 break
             self.waiting.popleft()
-            run = self._make_run(req.cfg)
-            self.batch.add(run, req.gens)
-            self.used += req.footprint
             req.admitted = self.clock()
-            self.live[req.rid] = (req, run)
+            self.live[ticket] = (req, ticket)
             n += 1
         return n
 
     def retire(self) -> int:
         """Retire runs whose generation budget is spent; sample their surfaces."""
         n = 0
-        for rid in list(self.live):
-            req, run = self.live[rid]
-            if self.batch.remaining(run) > 0:
-                continue
-            self.batch.remove(run)
-            req.result = run.extract()
+        for ticket in self.pool.done():
+            req, _ = self.live.pop(ticket)
+            req.result = self.pool.retire(ticket)
             req.finished = self.clock()
-            run.close()
-            del self.live[rid]
-            self.used -= req.footprint
             self.done.append(req)
             n += 1
         return n
@@ -109,10 +105,10 @@ class Server:
         """One block of generations for every live run."""
         if not self.live:
             return
-        for req, run in self.live.values():
-            self.agent_gens += min(self.block, self.batch.remaining(run)) * (
+        for ticket, (req, _) in self.live.items():
+            self.agent_gens += min(self.block, self.pool.remaining(ticket)) * (
                 req.cfg["width"] * req.cfg["height"] * req.cfg["pop"])
-        self.batch.step(self.block)
+        self.pool.step(self.block)
 
     def drain(self, arrivals=None, time_limit: float | None = None, progress=None,
               progress_every: float = 10.0):
@@ -142,11 +138,10 @@ class Server:
         return self.done
 
     def close(self):
-        for rid in list(self.live):
-            req, run = self.live.pop(rid)
-            self.batch.remove(run)
-            run.close()
-        self.batch.close()
+        for ticket in list(self.live):
+            self.live.pop(ticket)
+            self.pool.retire(ticket, sample=False)
+        self.pool.close()
 
     # -- reporting ----------------------------------------------------------
     def report(self, wall: float) -> dict:

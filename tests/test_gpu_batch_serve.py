@@ -140,3 +140,54 @@ def test_served_results_equal_alone_and_oracle():
         assert np.array_equal(ids, ref.sample_one_per_island())
         assert np.array_equal(T, T0[ids.astype(np.int64)])
         assert np.array_equal(D, D0[ids.astype(np.int64)])
+
+
+def test_pool_first_fit_release_merging_and_results():
+    # three runs fill the pool exactly; a larger run fits only once the run
+    # between the two freed blocks is gone and all three blocks have merged
+    import paper_2405_03605_amd as ga
+    from paper_2405_03605_amd import GAError, GAPool
+    a = run_config(width=8, height=6, pop=16, sites=32, seed=1, run_id=900)
+    b = run_config(width=20, height=12, pop=32, sites=64, k=4, seed=1, run_id=901)
+    c = run_config(width=9, height=7, pop=8, sites=32, seed=1, run_id=902)
+    big = run_config(width=16, height=12, pop=32, sites=64, seed=1, run_id=903)
+    al = lambda x: (x + 255) // 256 * 256
+    sa, sb, sc, sbig = (al(ga.state_bytes(x)) for x in (a, b, c, big))
+    assert max(sa, sc) < sbig <= sa + sb + sc
+    pool = GAPool(sa + sb + sc, max_slots=3)
+    ta, tb, tc = pool.admit(a, 50), pool.admit(b, 80), pool.admit(c, 50)
+    assert None not in (ta, tb, tc)
+    assert pool.usage() == {"used": sa + sb + sc, "largest_free": 0, "live": 3}
+    assert pool.admit(c, 10) is None             # no slot and no memory
+    pool.step(50)
+    assert pool.done() == [ta, tc] and pool.remaining(tb) == 30
+    ra = pool.retire(ta)
+    assert pool.usage()["largest_free"] == sa
+    assert pool.admit(big, 40) is None           # a's block alone is too small
+    rc = pool.retire(tc)                         # not adjacent to a's block
+    assert pool.usage() == {"used": sb, "largest_free": max(sa, sc), "live": 1}
+    assert pool.admit(big, 40) is None
+    pool.step(30)
+    rb = pool.retire(tb)
+    assert pool.usage() == {"used": 0, "largest_free": sa + sb + sc, "live": 0}
+    tbig = pool.admit(big, 40)
+    assert tbig is not None
+    pool.step(40)
+    rbig = pool.retire(tbig)
+    for cfg, gens, (ids, T, D) in ((a, 50, ra), (c, 50, rc), (b, 80, rb), (big, 40, rbig)):
+        ref = oracle_after(cfg, gens)
+        f0, T0, D0 = ref.population()
+        assert np.array_equal(ids, ref.sample_one_per_island()), cfg["run_id"]
+        assert np.array_equal(T, T0[ids.astype(np.int64)]), cfg["run_id"]
+        assert np.array_equal(D, D0[ids.astype(np.int64)]), cfg["run_id"]
+    # a run retired before its budget is spent, without sampling
+    t = pool.admit(a, 1000)
+    pool.step(5)
+    assert pool.remaining(t) == 995 and pool.done() == []
+    pool.retire(t, sample=False)
+    with pytest.raises(GAError):
+        pool.remaining(t)
+    with pytest.raises(GAError):
+        pool.admit(run_config(width=100, height=100, pop=32), 10)   # larger than the pool
+    assert pool.usage()["used"] == 0
+    pool.close()

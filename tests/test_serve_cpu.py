@@ -1,49 +1,58 @@
-"""Host logic of the continuous-batching server on the CPU, with stand-ins for
-the device runs: admission by footprint and slot count in arrival order,
-retirement when a budget is spent, memory returned, latency report."""
+"""Host logic of the continuous-batching server on the CPU, with a stand-in for
+the device run pool: admission in arrival order while the pool takes runs
+(memory and slots), retirement when a budget is spent, memory returned,
+latency report. The native pool's allocator is checked on the GPU."""
 import pytest
 
 from paper_2405_03605_amd.serve import Server
 
 
-class FakeRun:
-    def __init__(self, cfg):
-        self.cfg = cfg
-        self.closed = False
+class FakePool:
+    """Budget and slot accounting by sums (no fragmentation), budgets counted
+    down per step, results tagged with the run id."""
 
-    def extract(self):
-        return ("ids", self.cfg["run_id"])
-
-    def close(self):
-        self.closed = True
-
-
-class FakeBatch:
-    def __init__(self):
-        self.left = {}
-        self.block = None
+    def __init__(self, budget, slots):
+        self.budget, self.slots = budget, slots
+        self.left, self.size, self.cfgs = {}, {}, {}
+        self.next = 1
         self.steps = 0
+        self.block = None
+        self.closed = False
 
     def set_graph_block(self, n):
         self.block = n
 
-    def add(self, run, budget):
-        assert run not in self.left
-        self.left[run] = budget
+    @property
+    def used(self):
+        return sum(self.size.values())
 
-    def remove(self, run):
-        del self.left[run]
+    def admit(self, cfg, gens):
+        need = sb(cfg)
+        if len(self.left) >= self.slots or self.used + need > self.budget:
+            return None
+        t = self.next
+        self.next += 1
+        self.left[t], self.size[t], self.cfgs[t] = gens, need, cfg
+        return t
 
-    def remaining(self, run):
-        return self.left[run]
+    def remaining(self, t):
+        return self.left[t]
 
     def step(self, n):
         self.steps += 1
-        for r in self.left:
-            self.left[r] -= min(n, self.left[r])
+        for t in self.left:
+            self.left[t] -= min(n, self.left[t])
+
+    def done(self):
+        return sorted(t for t, v in self.left.items() if v == 0)
+
+    def retire(self, t, sample=True):
+        cfg = self.cfgs.pop(t)
+        del self.left[t], self.size[t]
+        return ("ids", cfg["run_id"]) if sample else None
 
     def close(self):
-        pass
+        self.closed = True
 
 
 class Clock:
@@ -65,8 +74,8 @@ def sb(c):
 
 
 def make_server(budget, slots=8, block=10):
-    return Server(budget, max_slots=slots, block=block, make_run=FakeRun,
-                  make_batch=FakeBatch, state_bytes=sb, clock=Clock())
+    return Server(budget, max_slots=slots, block=block, make_pool=FakePool, state_bytes=sb,
+                  clock=Clock())
 
 
 def test_admission_respects_memory_and_order():
@@ -91,7 +100,13 @@ def test_slots_limit_and_head_of_line_order():
     for i in range(1, 6):
         srv.submit(cfg(i), gens=5)
     assert srv.admit() == 3
-    assert len(srv.live) == 3 and big.rid in srv.live
+    assert len(srv.live) == 3 and any(req is big for req, _ in srv.live.values())
+    # a head-of-line request that does not fit holds back those behind it
+    srv2 = make_server(budget=64 * 100 * 2, slots=8)
+    srv2.submit(cfg(0), gens=5)
+    srv2.submit(cfg(1, agents=128), gens=5)     # needs the whole budget
+    srv2.submit(cfg(2), gens=5)
+    assert srv2.admit() == 1 and [r.rid for r in srv2.waiting] == [1, 2]
 
 
 def test_oversized_and_invalid_requests_rejected():
@@ -108,7 +123,10 @@ def test_drain_completes_everything_and_reports():
     assert all(r.result == ("ids", r.cfg["run_id"]) for r in done)
     assert all(r.finished >= r.admitted >= r.arrival for r in done)
     assert srv.used == 0 and not srv.live and not srv.waiting
+    assert srv.pool.block == 7
     rep = srv.report(wall=1.0)
     assert rep["completed"] == 6
     assert rep["agent_gens"] == sum(64 * (10 + 5 * i) for i in range(6))
     assert rep["latency_p99_s"] >= rep["latency_p50_s"] > 0
+    srv.close()
+    assert srv.pool.closed
