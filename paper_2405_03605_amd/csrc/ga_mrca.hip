@@ -165,130 +165,243 @@ __device__ __forceinline__ uint32_t tilted_slot_rank(uint32_t T, uint32_t k, uin
   return k < 31u ? ((2u * i + 1u) << k) : (i << 31);
 }
 
-// One thread per pair: U = the oldest common rank whose differentia differ
-// (or min(Ta, Tb)); L = the kc-th common rank below U, plus one (0 if fewer).
-// The common ranks (a rank sits at one site whatever T is, so they are the
-// sites where both surfaces hold the same rank) are found once and kept in
-// registers, S known at compile time.
-template <uint32_t S>
-__global__ __launch_bounds__(256) void pairs_tilted_kernel(const uint32_t* __restrict__ T,
-                                                           const uint32_t* __restrict__ D,
-                                                           uint32_t n, uint32_t dlog,
-                                                           uint32_t kc,
-                                                           uint32_t* __restrict__ L,
-                                                           uint32_t* __restrict__ U) {
-  constexpr uint32_t m_log = S == 64u ? 1u : 0u;
-  const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t x = blockIdx.y;
-  if (y >= n) return;
-  const uint32_t words = (S << dlog) >> 5;
-  const uint32_t ta = T[x], tb = T[y];
-  const unsigned long long wa = (unsigned long long)D[(size_t)x * words] |
-                                (words > 1 ? (unsigned long long)D[(size_t)x * words + 1] << 32
-                                           : 0ull);
-  const unsigned long long wb = (unsigned long long)D[(size_t)y * words] |
-                                (words > 1 ? (unsigned long long)D[(size_t)y * words + 1] << 32
-                                           : 0ull);
-  const unsigned long long fmask = (1ull << (1u << dlog)) - 1ull;
-  const unsigned long long diff = wa ^ wb;
-  uint32_t upper = ta < tb ? ta : tb;
-  uint32_t common[S];  // the rank both hold at each site, or kNone
-#pragma unroll
-  for (uint32_t site = 0; site < S; ++site) {
-    const uint32_t k = site >> m_log, j = site & ((1u << m_log) - 1u);
-    const uint32_t ra = tilted_slot_rank(ta, k, j, m_log);
-    const uint32_t rb = tilted_slot_rank(tb, k, j, m_log);
-    common[site] = ra == rb ? ra : kNone;
-    if (ra == rb && ra != kNone && ((diff >> (site << dlog)) & fmask) != 0ull && ra < upper)
-      upper = ra;
+// Tiled pairs for the tilted and hybrid policies. U and L are symmetric in
+// the two surfaces, so a workgroup takes a 64 x 64 block of pairs (rows
+// x0.., columns y0..) only when y0 >= x0 and writes the block and its mirror
+// image. Each lane keeps its column surface's per-site ranks in registers for
+// the 16 rows its wavefront visits (the rank computation is paid once per
+// lane, not once per pair); the rows' ranks are built once per workgroup in
+// LDS and read back as wavefront-uniform broadcasts. The mirror image goes
+// out through an LDS transpose so both writes are whole-row and coalesced.
+constexpr uint32_t kPairTile = 64;
+constexpr uint32_t kRowsPerWave = kPairTile / 4;
+
+struct PairStage {
+  uint32_t u[kPairTile][kPairTile + 1];  // [row in block][column in block]
+  uint32_t l[kPairTile][kPairTile + 1];
+};
+
+// Row r (x = x0 + r) of the block: write (x, y) directly and keep it for the
+// mirror image.
+__device__ __forceinline__ void put_pair(PairStage& st, uint32_t r, uint32_t lane, uint32_t x,
+                                         uint32_t y, uint32_t n, uint32_t u, uint32_t l,
+                                         uint32_t* __restrict__ L, uint32_t* __restrict__ U) {
+  if (x < n && y < n) {
+    const size_t at = (size_t)x * n + y;
+    U[at] = u;
+    L[at] = l;
   }
-  // kc-th largest common rank below upper (the common ranks are distinct)
-  uint32_t bound = upper;
-  bool found = true;
-  for (uint32_t c = 0; c < kc && found; ++c) {
-    found = false;
-    uint32_t best = 0u;
-#pragma unroll
-    for (uint32_t site = 0; site < S; ++site) {
-      const uint32_t r = common[site];
-      const bool ok = r != kNone && r < bound && (!found || r > best);
-      best = ok ? r : best;
-      found = found || ok;
-    }
-    bound = best;
-  }
-  const size_t at = (size_t)x * n + y;
-  U[at] = upper;
-  L[at] = found ? bound + 1u : 0u;
+  st.u[r][lane] = u;
+  st.l[r][lane] = l;
 }
 
-// Hybrid surfaces (64 one-bit sites): even ranks 2q sit on a 32-site steady
-// half (sites 0..31), odd ranks 2q + 1 on a 32-site tilted half (sites
-// 32..63). The common ranks of the steady halves are 2 j 2^E for
-// j < common, E the larger epoch; those of the tilted halves are the slots
-// holding the same rank in both. U and L as for the other policies, over the
-// union of the two sets.
-__global__ __launch_bounds__(256) void pairs_hybrid_kernel(const uint32_t* __restrict__ T,
-                                                           const uint32_t* __restrict__ D,
-                                                           uint32_t n, uint32_t kc,
-                                                           uint32_t* __restrict__ L,
-                                                           uint32_t* __restrict__ U) {
-  const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t x = blockIdx.y;
-  if (y >= n) return;
-  const uint32_t ta = T[x], tb = T[y];
-  const unsigned long long diff =
-      ((unsigned long long)D[(size_t)x * 2] | (unsigned long long)D[(size_t)x * 2 + 1] << 32) ^
-      ((unsigned long long)D[(size_t)y * 2] | (unsigned long long)D[(size_t)y * 2 + 1] << 32);
-  // steady halves: (t + 1) / 2 even deposits each
-  const uint32_t na = (ta >> 1) + (ta & 1u), nb = (tb >> 1) + (tb & 1u);
-  const uint32_t ea = epoch_of(na, 5u), eb = epoch_of(nb, 5u);
-  const uint32_t E = ea > eb ? ea : eb;
-  const uint32_t nmin = na < nb ? na : nb;
-  const uint32_t cs = nmin == 0u ? 0u : ((nmin - 1u) >> E) + 1u;  // common steady ranks
-  uint32_t upper = ta < tb ? ta : tb;
-  for (uint32_t j = 0; j < cs; ++j) {
-    const uint32_t q = j << E;
-    if ((diff >> site_of_retained(q, 5u)) & 1ull) {
-      upper = min(upper, 2u * q);
-      break;
+// The mirror image of an off-diagonal block: (y, x) for every staged (x, y).
+__device__ __forceinline__ void put_mirror(const PairStage& st, uint32_t x0, uint32_t y0,
+                                           uint32_t n, uint32_t* __restrict__ L,
+                                           uint32_t* __restrict__ U) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wid = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t x = x0 + lane;
+  for (uint32_t c = wid * kRowsPerWave; c < (wid + 1u) * kRowsPerWave; ++c) {
+    const uint32_t y = y0 + c;
+    if (x < n && y < n) {
+      const size_t at = (size_t)y * n + x;
+      U[at] = st.u[lane][c];
+      L[at] = st.l[lane][c];
     }
   }
-  // tilted halves: t / 2 odd deposits each, one slot per level; the common
-  // ones (as odd ranks 2r + 1) found once and kept in registers
-  const uint32_t ma = ta >> 1, mb = tb >> 1;
-  uint32_t common[32];
-#pragma unroll
-  for (uint32_t k = 0; k < 32; ++k) {
-    const uint32_t ra = tilted_slot_rank(ma, k, 0u, 0u);
-    const uint32_t rb = tilted_slot_rank(mb, k, 0u, 0u);
-    common[k] = ra == rb && ra != kNone ? 2u * ra + 1u : kNone;
-    if (common[k] != kNone && ((diff >> (32u + k)) & 1ull) && common[k] < upper) upper = common[k];
-  }
-  // kc-th largest common rank below upper
-  uint32_t bound = upper;
-  bool found = true;
-  for (uint32_t c = 0; c < kc && found; ++c) {
-    found = false;
-    uint32_t best = 0u;
-    if (cs > 0u && bound > 0u) {
+}
+
+// The kc passes for L over common ranks held as c1 = rank + 1 (0: the site
+// is not common). Pass p keeps the largest c1 <= bound, i.e. the largest
+// common rank below the previous one (below U on the first pass); a pass
+// that finds none leaves 0, and 0 stays. The last pass's value is L: the
+// kc-th common rank below U, plus one, or 0 when there are fewer.
+// `steady` adds the hybrid's steady half, whose common ranks 2 j 2^E
+// (j < cs) give the largest one below a bound in closed form.
+template <uint32_t S, bool STEADY>
+__device__ __forceinline__ uint32_t kth_common_below(const uint32_t (&c1)[S], uint32_t upper,
+                                                     uint32_t kc, uint32_t cs, uint32_t E) {
+  uint32_t bound = upper, best = 0u;
+  for (uint32_t p = 0; p < kc; ++p) {
+    best = 0u;
+    if (STEADY && cs > 0u && bound > 0u) {
       uint32_t jm = (bound - 1u) >> (E + 1u);  // largest j with 2 j 2^E < bound
       if (jm > cs - 1u) jm = cs - 1u;
-      best = 2u * (jm << E);
-      found = true;
+      best = 2u * (jm << E) + 1u;
     }
 #pragma unroll
-    for (uint32_t k = 0; k < 32; ++k) {
-      const uint32_t r = common[k];
-      const bool ok = r != kNone && r < bound && (!found || r > best);
-      best = ok ? r : best;
-      found = found || ok;
+    for (uint32_t site = 0; site < S; ++site) {
+      const uint32_t v = c1[site] <= bound ? c1[site] : 0u;
+      best = v > best ? v : best;
     }
-    bound = best;
+    bound = best - (best != 0u);
   }
-  const size_t at = (size_t)x * n + y;
-  U[at] = upper;
-  L[at] = found ? bound + 1u : 0u;
+  return best;
+}
+
+template <uint32_t S, uint32_t DLOG>
+__global__ __launch_bounds__(256) void pairs_tilted_tile_kernel(const uint32_t* __restrict__ T,
+                                                                const uint32_t* __restrict__ D,
+                                                                uint32_t n, uint32_t kc,
+                                                                uint32_t* __restrict__ L,
+                                                                uint32_t* __restrict__ U) {
+  const uint32_t x0 = blockIdx.y * kPairTile, y0 = blockIdx.x * kPairTile;
+  if (y0 < x0) return;
+  constexpr uint32_t m_log = S == 64u ? 1u : 0u;
+  constexpr uint32_t s_log = S == 64u ? 6u : 5u;
+  constexpr uint32_t words = (S << DLOG) >> 5;
+  constexpr unsigned long long fmask = (1ull << (1u << DLOG)) - 1ull;
+  __shared__ uint32_t xr[kPairTile][S];
+  __shared__ PairStage st;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wid = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (uint32_t e = threadIdx.x; e < kPairTile * S; e += blockDim.x) {
+    const uint32_t r = e >> s_log, site = e & (S - 1u);
+    const uint32_t x = x0 + r;
+    xr[r][site] = tilted_slot_rank(x < n ? T[x] : 0u, site >> m_log, site & ((1u << m_log) - 1u),
+                                   m_log);
+  }
+  const uint32_t y = y0 + lane;
+  const uint32_t yc = y < n ? y : n - 1u;  // a valid surface for lanes past the end
+  const uint32_t tb = T[yc];
+  const unsigned long long wb = (unsigned long long)D[(size_t)yc * words] |
+                                (words > 1 ? (unsigned long long)D[(size_t)yc * words + 1] << 32
+                                           : 0ull);
+  uint32_t rb[S];
+#pragma unroll
+  for (uint32_t site = 0; site < S; ++site)
+    rb[site] = tilted_slot_rank(tb, site >> m_log, site & ((1u << m_log) - 1u), m_log);
+  __syncthreads();
+#pragma unroll 1
+  for (uint32_t i = 0; i < kRowsPerWave; ++i) {
+    const uint32_t r = wid * kRowsPerWave + i, x = x0 + r;
+    const uint32_t xc = x < n ? x : n - 1u;
+    const uint32_t ta = T[xc];
+    const unsigned long long wa = (unsigned long long)D[(size_t)xc * words] |
+                                  (words > 1 ? (unsigned long long)D[(size_t)xc * words + 1] << 32
+                                             : 0ull);
+    const unsigned long long diff = wa ^ wb;
+    uint32_t upper = ta < tb ? ta : tb;
+    uint32_t c1[S];  // common rank + 1, or 0 (kNone + 1 wraps to 0)
+#pragma unroll
+    for (uint32_t site = 0; site < S; ++site) {
+      const uint32_t ra = xr[r][site];
+      const bool common = ra == rb[site];
+      c1[site] = common ? ra + 1u : 0u;
+      const bool differs = ((diff >> (site << DLOG)) & fmask) != 0ull;
+      const uint32_t cand = common && differs ? ra : kNone;
+      upper = cand < upper ? cand : upper;
+    }
+    put_pair(st, r, lane, x, y, n, upper, kth_common_below<S, false>(c1, upper, kc, 0u, 0u), L,
+             U);
+  }
+  if (x0 == y0) return;
+  __syncthreads();
+  put_mirror(st, x0, y0, n, L, U);
+}
+
+// Steady half of a hybrid surface (sites 0..31 of the low word, (t + 1) / 2
+// deposits on the even ranks) in rank order: bit j is the differentia of its
+// j-th retained deposit, rank j 2^e of the half, e its epoch.
+__device__ __forceinline__ uint32_t steady_half_bits(uint32_t t, uint32_t w_lo, uint32_t* epoch) {
+  const uint32_t nh = (t >> 1) + (t & 1u);
+  const uint32_t e = epoch_of(nh, 5u);
+  const uint32_t count = nh == 0u ? 0u : ((nh - 1u) >> e) + 1u;  // <= 32
+  uint32_t bits = 0u;
+  for (uint32_t j = 0; j < count; ++j) bits |= ((w_lo >> site_of_retained(j << e, 5u)) & 1u) << j;
+  *epoch = e;
+  return bits;
+}
+
+// Keep bits 0, 2^d, 2 * 2^d, ... of a 32-bit string, packed to the bottom.
+__device__ __forceinline__ uint32_t compact_stride32(uint32_t x, uint32_t d) {
+  for (uint32_t i = 0; i < d && i < 5u; ++i) {
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    x = (x | (x >> 8)) & 0x0000FFFFu;
+  }
+  return x;
+}
+
+// Hybrid surfaces, tiled as above: the tilted half's ranks (odd ranks) per
+// lane in registers and per row in LDS; the steady halves in rank order (per
+// lane and per row), so their first differing common rank 2 j 2^E is the
+// lowest set bit of the XOR of the two strings thinned to the common ranks,
+// and the largest of their common ranks below a bound is closed-form.
+__global__ __launch_bounds__(256) void pairs_hybrid_tile_kernel(const uint32_t* __restrict__ T,
+                                                                const uint32_t* __restrict__ D,
+                                                                uint32_t n, uint32_t kc,
+                                                                uint32_t* __restrict__ L,
+                                                                uint32_t* __restrict__ U) {
+  const uint32_t x0 = blockIdx.y * kPairTile, y0 = blockIdx.x * kPairTile;
+  if (y0 < x0) return;
+  __shared__ uint32_t xr[kPairTile][32];
+  __shared__ uint32_t xs[kPairTile][2];  // steady half in rank order, its epoch
+  __shared__ PairStage st;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wid = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (uint32_t e = threadIdx.x; e < kPairTile * 32u; e += blockDim.x) {
+    const uint32_t r = e >> 5, k = e & 31u;
+    const uint32_t x = x0 + r;
+    const uint32_t ra = tilted_slot_rank((x < n ? T[x] : 0u) >> 1, k, 0u, 0u);
+    xr[r][k] = ra == kNone ? kNone : 2u * ra + 1u;
+  }
+  if (threadIdx.x < kPairTile) {
+    const uint32_t x = x0 + threadIdx.x;
+    uint32_t e = 0u;
+    xs[threadIdx.x][0] = x < n ? steady_half_bits(T[x], D[(size_t)x * 2], &e) : 0u;
+    xs[threadIdx.x][1] = e;
+  }
+  const uint32_t y = y0 + lane;
+  const uint32_t yc = y < n ? y : n - 1u;
+  const uint32_t tb = T[yc];
+  const unsigned long long wb =
+      (unsigned long long)D[(size_t)yc * 2] | (unsigned long long)D[(size_t)yc * 2 + 1] << 32;
+  uint32_t rb[32];
+#pragma unroll
+  for (uint32_t k = 0; k < 32; ++k) {
+    const uint32_t r = tilted_slot_rank(tb >> 1, k, 0u, 0u);
+    rb[k] = r == kNone ? kNone : 2u * r + 1u;
+  }
+  const uint32_t nb = (tb >> 1) + (tb & 1u);
+  uint32_t eb = 0u;
+  const uint32_t sb = steady_half_bits(tb, (uint32_t)wb, &eb);
+  __syncthreads();
+#pragma unroll 1
+  for (uint32_t i = 0; i < kRowsPerWave; ++i) {
+    const uint32_t r = wid * kRowsPerWave + i, x = x0 + r;
+    const uint32_t xc = x < n ? x : n - 1u;
+    const uint32_t ta = T[xc];
+    const unsigned long long diff =
+        ((unsigned long long)D[(size_t)xc * 2] | (unsigned long long)D[(size_t)xc * 2 + 1] << 32) ^
+        wb;
+    // steady halves: common ranks 2 j 2^E for j < cs
+    const uint32_t na = (ta >> 1) + (ta & 1u);
+    const uint32_t ea = xs[r][1];
+    const uint32_t E = ea > eb ? ea : eb;
+    const uint32_t nmin = na < nb ? na : nb;
+    const uint32_t cs = nmin == 0u ? 0u : ((nmin - 1u) >> E) + 1u;  // <= 32
+    uint32_t upper = ta < tb ? ta : tb;
+    const uint32_t hit = (compact_stride32(xs[r][0], E - ea) ^ compact_stride32(sb, E - eb)) &
+                         (cs >= 32u ? 0xFFFFFFFFu : (1u << cs) - 1u);
+    if (hit) upper = min(upper, 2u * ((uint32_t)(__ffs(hit) - 1) << E));
+    uint32_t c1[32];  // common odd rank + 1, or 0
+#pragma unroll
+    for (uint32_t k = 0; k < 32; ++k) {
+      const uint32_t ra = xr[r][k];
+      const bool common = ra == rb[k];
+      c1[k] = common ? ra + 1u : 0u;
+      const uint32_t cand = common && ((diff >> (32u + k)) & 1ull) ? ra : kNone;
+      upper = cand < upper ? cand : upper;
+    }
+    put_pair(st, r, lane, x, y, n, upper, kth_common_below<32, true>(c1, upper, kc, cs, E), L, U);
+  }
+  if (x0 == y0) return;
+  __syncthreads();
+  put_mirror(st, x0, y0, n, L, U);
 }
 
 }  // namespace
@@ -299,18 +412,19 @@ hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, 
                               uint32_t dlog, uint32_t policy, uint32_t kc, void* workspace,
                               uint32_t* L, uint32_t* U, hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  if (policy == 1u) {
-    const dim3 grid((n + 255) / 256, n);
-    if (s_log == 6u)
-      pairs_tilted_kernel<64><<<grid, dim3(256), 0, stream>>>(T, D, n, dlog, kc, L, U);
-    else if (s_log == 5u)
-      pairs_tilted_kernel<32><<<grid, dim3(256), 0, stream>>>(T, D, n, dlog, kc, L, U);
+  if (policy == 1u || policy == 2u) {
+    const uint32_t tiles = (n + kPairTile - 1u) / kPairTile;
+    const dim3 grid(tiles, tiles);
+    if (policy == 2u)
+      pairs_hybrid_tile_kernel<<<grid, dim3(256), 0, stream>>>(T, D, n, kc, L, U);
+    else if (s_log == 6u && dlog == 0u)
+      pairs_tilted_tile_kernel<64, 0><<<grid, dim3(256), 0, stream>>>(T, D, n, kc, L, U);
+    else if (s_log == 5u && dlog == 0u)
+      pairs_tilted_tile_kernel<32, 0><<<grid, dim3(256), 0, stream>>>(T, D, n, kc, L, U);
+    else if (s_log == 5u && dlog == 1u)
+      pairs_tilted_tile_kernel<32, 1><<<grid, dim3(256), 0, stream>>>(T, D, n, kc, L, U);
     else
       return hipErrorInvalidValue;
-    return hipGetLastError();
-  }
-  if (policy == 2u) {
-    pairs_hybrid_kernel<<<dim3((n + 255) / 256, n), dim3(256), 0, stream>>>(T, D, n, kc, L, U);
     return hipGetLastError();
   }
   Normalized* nz = static_cast<Normalized*>(workspace);

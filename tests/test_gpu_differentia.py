@@ -190,3 +190,24 @@ def test_hybrid_async_and_mrca_matrix():
         L, U = phylo.mrca_matrix(T2, D2, 64, kc, policy=2)
         L0, U0 = oracle.mrca_interval_matrix(T2, D2, 64, kc, 1, policy=2)
         assert np.array_equal(U, U0) and np.array_equal(L, L0), kc
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 130])
+@pytest.mark.parametrize("sites,bits,policy", [(32, 1, 1), (64, 1, 1), (32, 2, 1), (64, 1, 2)])
+def test_tilted_and_hybrid_mrca_block_edges(n, sites, bits, policy):
+    # the tiled kernels take 64 x 64 blocks on and above the diagonal and
+    # mirror them: one partial block, exactly one block, one block and a
+    # ragged row/column, two blocks and a ragged one; counters near each other
+    # (many common ranks) and far apart
+    say(f"MRCA blocks n={n} S={sites} b={bits} policy={policy}")
+    rng = np.random.default_rng(1000 * n + 10 * sites + bits + policy)
+    base = rng.integers(1, 2 ** 20, n, dtype=np.int64)
+    base[::3] = rng.integers(0, 2 ** 32, len(base[::3]), dtype=np.uint64).astype(np.int64)
+    T = base.astype(np.uint32)
+    words = sites * bits // 32
+    D = rng.integers(0, 2 ** 32, (n, words), dtype=np.uint64).astype(np.uint32)
+    D[1::2] = D[0:n - 1:2]      # identical pairs of surfaces
+    for kc in (1, 5):
+        L, U = phylo.mrca_matrix(T, D, sites, kc, bits=bits, policy=policy)
+        L0, U0 = oracle.mrca_interval_matrix(T, D, sites, kc, bits, policy=policy)
+        assert np.array_equal(U, U0) and np.array_equal(L, L0), (n, sites, bits, policy, kc)
