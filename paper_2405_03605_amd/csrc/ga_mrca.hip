@@ -213,28 +213,32 @@ __device__ __forceinline__ void put_mirror(const PairStage& st, uint32_t x0, uin
 }
 
 // The kc passes for L over common ranks held as c1 = rank + 1 (0: the site
-// is not common). Pass p keeps the largest c1 <= bound, i.e. the largest
+// is not common). Pass p takes the largest c1 <= bound, i.e. the largest
 // common rank below the previous one (below U on the first pass); a pass
-// that finds none leaves 0, and 0 stays. The last pass's value is L: the
-// kc-th common rank below U, plus one, or 0 when there are fewer.
-// `steady` adds the hybrid's steady half, whose common ranks 2 j 2^E
-// (j < cs) give the largest one below a bound in closed form.
+// that finds none gives 0, and 0 stays. The last pass's value is L: the kc-th
+// common rank below U, plus one, or 0 when there are fewer. The largest
+// c1 <= bound is bound minus the smallest bound - c1 in unsigned arithmetic:
+// a c1 above the bound wraps to a difference above the bound, never the
+// smallest once bound itself (a c1 of 0) is a candidate.
+// `STEADY` adds the hybrid's steady half, whose common ranks 2 j 2^E (j < cs)
+// give the largest one below a bound in closed form.
 template <uint32_t S, bool STEADY>
 __device__ __forceinline__ uint32_t kth_common_below(const uint32_t (&c1)[S], uint32_t upper,
                                                      uint32_t kc, uint32_t cs, uint32_t E) {
   uint32_t bound = upper, best = 0u;
   for (uint32_t p = 0; p < kc; ++p) {
-    best = 0u;
+    uint32_t gap = bound;
     if (STEADY && cs > 0u && bound > 0u) {
       uint32_t jm = (bound - 1u) >> (E + 1u);  // largest j with 2 j 2^E < bound
       if (jm > cs - 1u) jm = cs - 1u;
-      best = 2u * (jm << E) + 1u;
+      gap = bound - (2u * (jm << E) + 1u);
     }
 #pragma unroll
     for (uint32_t site = 0; site < S; ++site) {
-      const uint32_t v = c1[site] <= bound ? c1[site] : 0u;
-      best = v > best ? v : best;
+      const uint32_t d = bound - c1[site];
+      gap = d < gap ? d : gap;
     }
+    best = bound - gap;
     bound = best - (best != 0u);
   }
   return best;
