@@ -212,18 +212,18 @@ __device__ __forceinline__ void put_mirror(const PairStage& st, uint32_t x0, uin
   }
 }
 
-// The kc passes for L over common ranks held as c1 = rank + 1 (0: the site
-// is not common). Pass p takes the largest c1 <= bound, i.e. the largest
-// common rank below the previous one (below U on the first pass); a pass
-// that finds none gives 0, and 0 stays. The last pass's value is L: the kc-th
-// common rank below U, plus one, or 0 when there are fewer. The largest
-// c1 <= bound is bound minus the smallest bound - c1 in unsigned arithmetic:
-// a c1 above the bound wraps to a difference above the bound, never the
-// smallest once bound itself (a c1 of 0) is a candidate.
+// The kc passes for L over the common ranks cr[site] (kNone: the site is not
+// common). Pass p takes the largest common rank below bound (U on the first
+// pass, then the previous pass's rank) and keeps it plus one; a pass that
+// finds none gives 0, and 0 stays. The last pass's value is L: the kc-th
+// common rank below U, plus one, or 0 when there are fewer. In unsigned
+// arithmetic that value is bound minus the smallest (bound - 1) - cr: a rank
+// at or above the bound wraps to a difference above the bound, and kNone
+// gives exactly bound (nothing found), which is also where the search starts.
 // `STEADY` adds the hybrid's steady half, whose common ranks 2 j 2^E (j < cs)
 // give the largest one below a bound in closed form.
 template <uint32_t S, bool STEADY>
-__device__ __forceinline__ uint32_t kth_common_below(const uint32_t (&c1)[S], uint32_t upper,
+__device__ __forceinline__ uint32_t kth_common_below(const uint32_t (&cr)[S], uint32_t upper,
                                                      uint32_t kc, uint32_t cs, uint32_t E) {
   uint32_t bound = upper, best = 0u;
   for (uint32_t p = 0; p < kc; ++p) {
@@ -233,15 +233,22 @@ __device__ __forceinline__ uint32_t kth_common_below(const uint32_t (&c1)[S], ui
       if (jm > cs - 1u) jm = cs - 1u;
       gap = bound - (2u * (jm << E) + 1u);
     }
+    const uint32_t below = bound - 1u;
 #pragma unroll
     for (uint32_t site = 0; site < S; ++site) {
-      const uint32_t d = bound - c1[site];
+      const uint32_t d = below - cr[site];
       gap = d < gap ? d : gap;
     }
     best = bound - gap;
     bound = best - (best != 0u);
   }
   return best;
+}
+
+// All ones where bit `pos` of the word is set, else zero (one bit-field
+// extract, sign-extended; pos is a constant once the site loops unroll).
+__device__ __forceinline__ uint32_t bit_mask_dyn(uint32_t word, uint32_t pos) {
+  return (uint32_t)__builtin_amdgcn_sbfe((int)word, pos, 1);
 }
 
 template <uint32_t S, uint32_t DLOG>
@@ -255,7 +262,6 @@ __global__ __launch_bounds__(256) void pairs_tilted_tile_kernel(const uint32_t* 
   constexpr uint32_t m_log = S == 64u ? 1u : 0u;
   constexpr uint32_t s_log = S == 64u ? 6u : 5u;
   constexpr uint32_t words = (S << DLOG) >> 5;
-  constexpr unsigned long long fmask = (1ull << (1u << DLOG)) - 1ull;
   __shared__ uint32_t xr[kPairTile][S];
   __shared__ PairStage st;
   const uint32_t lane = threadIdx.x & 63u;
@@ -285,19 +291,22 @@ __global__ __launch_bounds__(256) void pairs_tilted_tile_kernel(const uint32_t* 
     const unsigned long long wa = (unsigned long long)D[(size_t)xc * words] |
                                   (words > 1 ? (unsigned long long)D[(size_t)xc * words + 1] << 32
                                              : 0ull);
-    const unsigned long long diff = wa ^ wb;
+    unsigned long long diff = wa ^ wb;
+    if (DLOG == 1u) diff |= diff >> 1;  // bit 2 s: field s differs
+    // all ones over the sites whose fields agree: the sign-extended bit of ~diff
+    const uint32_t agree_lo = ~(uint32_t)diff, agree_hi = ~(uint32_t)(diff >> 32);
     uint32_t upper = ta < tb ? ta : tb;
-    uint32_t c1[S];  // common rank + 1, or 0 (kNone + 1 wraps to 0)
+    uint32_t cr[S];  // the rank both surfaces hold at the site, or kNone
 #pragma unroll
     for (uint32_t site = 0; site < S; ++site) {
       const uint32_t ra = xr[r][site];
-      const bool common = ra == rb[site];
-      c1[site] = common ? ra + 1u : 0u;
-      const bool differs = ((diff >> (site << DLOG)) & fmask) != 0ull;
-      const uint32_t cand = common && differs ? ra : kNone;
+      cr[site] = ra == rb[site] ? ra : kNone;
+      const uint32_t pos = site << DLOG;
+      const uint32_t agree = pos < 32u ? bit_mask_dyn(agree_lo, pos) : bit_mask_dyn(agree_hi, pos - 32u);
+      const uint32_t cand = cr[site] | agree;  // kNone unless common and differing
       upper = cand < upper ? cand : upper;
     }
-    put_pair(st, r, lane, x, y, n, upper, kth_common_below<S, false>(c1, upper, kc, 0u, 0u), L,
+    put_pair(st, r, lane, x, y, n, upper, kth_common_below<S, false>(cr, upper, kc, 0u, 0u), L,
              U);
   }
   if (x0 == y0) return;
@@ -392,16 +401,16 @@ __global__ __launch_bounds__(256) void pairs_hybrid_tile_kernel(const uint32_t* 
     const uint32_t hit = (compact_stride32(xs[r][0], E - ea) ^ compact_stride32(sb, E - eb)) &
                          (cs >= 32u ? 0xFFFFFFFFu : (1u << cs) - 1u);
     if (hit) upper = min(upper, 2u * ((uint32_t)(__ffs(hit) - 1) << E));
-    uint32_t c1[32];  // common odd rank + 1, or 0
+    const uint32_t agree_hi = ~(uint32_t)(diff >> 32);  // tilted half: sites 32..63
+    uint32_t cr[32];  // the odd rank both surfaces hold at the level, or kNone
 #pragma unroll
     for (uint32_t k = 0; k < 32; ++k) {
       const uint32_t ra = xr[r][k];
-      const bool common = ra == rb[k];
-      c1[k] = common ? ra + 1u : 0u;
-      const uint32_t cand = common && ((diff >> (32u + k)) & 1ull) ? ra : kNone;
+      cr[k] = ra == rb[k] ? ra : kNone;
+      const uint32_t cand = cr[k] | bit_mask_dyn(agree_hi, k);  // kNone unless differing
       upper = cand < upper ? cand : upper;
     }
-    put_pair(st, r, lane, x, y, n, upper, kth_common_below<32, true>(c1, upper, kc, cs, E), L, U);
+    put_pair(st, r, lane, x, y, n, upper, kth_common_below<32, true>(cr, upper, kc, cs, E), L, U);
   }
   if (x0 == y0) return;
   __syncthreads();

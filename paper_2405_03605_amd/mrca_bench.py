@@ -28,6 +28,8 @@ VARIANTS = [  # (name, sites, bits, policy)
     ("steady S=64", 64, 1, 0),
     ("steady S=16 b=4", 16, 4, 0),
     ("tilted S=32", 32, 1, 1),
+    ("tilted S=64", 64, 1, 1),
+    ("tilted S=32 b=2", 32, 2, 1),
     ("hybrid S=64", 64, 1, 2),
 ]
 
