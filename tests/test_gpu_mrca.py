@@ -91,3 +91,45 @@ def test_gpu_mrca_matrix_on_run_surfaces():
     assert np.array_equal(U, U0) and np.array_equal(L, L0)
     Z, m = phylo.reconstruct(T, D, 64)
     assert m["tips"] == len(ids) and m["sum_branch_length"] > 0
+
+
+@pytest.mark.parametrize("sites,bits,policy", [(32, 1, 0), (16, 4, 0), (32, 1, 1), (64, 1, 1),
+                                               (32, 2, 1), (64, 1, 2)])
+def test_mrca_matrix_full_size_sampled(sites, bits, policy):
+    # the benchmark's size: 10,000 surfaces sampled from a 256 x 256-island run
+    # after 3,000 generations, the whole n x n matrix on the GPU in the
+    # launch the benchmark times; a sample of rows x columns (first and last
+    # included, both sides of the diagonal) against the oracle
+    import ctypes
+    import torch
+    from paper_2405_03605_amd._lib import check, load
+    say(f"MRCA full size S={sites} b={bits} policy={policy}")
+    cfg = run_config(width=256, height=256, pop=32, sites=sites, dbits=bits, policy=policy,
+                     seed=5)
+    run = GARun(cfg)
+    run.step(3000)
+    n = 10000
+    ids = np.random.default_rng(5).choice(run.agents, size=n, replace=False)
+    _, T, D = run.extract(ids.astype(np.uint64))
+    run.close()
+    lib = load()
+    dev = torch.device("cuda", 0)
+    t_dev = torch.from_numpy(np.ascontiguousarray(T).view(np.int32)).to(dev)
+    d_dev = torch.from_numpy(np.ascontiguousarray(D).view(np.int32)).to(dev)
+    ws_bytes = int(lib.ga_mrca_workspace_bytes(n))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    L = torch.empty((n, n), dtype=torch.int32, device=dev)
+    U = torch.empty((n, n), dtype=torch.int32, device=dev)
+    P = ctypes.c_void_p
+    stream = torch.cuda.current_stream(dev)
+    check(lib.ga_mrca_matrix_ex(P(t_dev.data_ptr()), P(d_dev.data_ptr()), n, sites, bits, policy,
+                                5, P(ws.data_ptr()), ws_bytes, P(L.data_ptr()), P(U.data_ptr()),
+                                P(stream.cuda_stream)))
+    torch.cuda.synchronize()
+    pick = np.unique(np.concatenate([[0, 1, 63, 64, n - 2, n - 1],
+                                     np.random.default_rng(6).choice(n, 90, replace=False)]))
+    idx = torch.from_numpy(pick).to(dev)
+    Lg = L[idx][:, idx].cpu().numpy().view(np.uint32)
+    Ug = U[idx][:, idx].cpu().numpy().view(np.uint32)
+    L0, U0 = oracle.mrca_interval_matrix(T[pick], D[pick], sites, 5, bits, policy=policy)
+    assert np.array_equal(Ug, U0) and np.array_equal(Lg, L0), (sites, bits, policy)
