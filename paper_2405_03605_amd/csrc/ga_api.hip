@@ -887,6 +887,27 @@ uint32_t batch_ipw(const ga_batch* b, const ga_run* r) {
   return std::min(64u, ipw);
 }
 
+extern "C++" {
+namespace {
+template <typename T>
+T* table_offset(T* p, const void* table) {
+  return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) - reinterpret_cast<uintptr_t>(table));
+}
+
+// The pointers the batch kernels follow, as byte offsets from the device table
+// (the kernels add them back to the table's address).
+void to_table(ga::RunView& v, const void* table) {
+  v.pop_f = table_offset(v.pop_f, table);
+  v.pop_T = table_offset(v.pop_T, table);
+  v.pop_D = table_offset(v.pop_D, table);
+  v.ob[0] = table_offset(v.ob[0], table);
+  v.ob[1] = table_offset(v.ob[1], table);
+  v.gen = table_offset(v.gen, table);
+  v.left = table_offset(v.left, table);
+}
+}  // namespace
+}  // extern "C++"
+
 int rebuild_tables(ga_batch* b) {
   std::vector<ga::RunView> views;
   std::vector<ga::Tile> tiles;
@@ -919,6 +940,8 @@ int rebuild_tables(ga_batch* b) {
     GA_HIP(hipMalloc(&b->d_tiles, cap * sizeof(ga::Tile)), "alloc tiles");
     b->cap_tiles = cap;
   }
+  // the device table holds each run's pointers as byte offsets from the table
+  for (ga::RunView& v : views) to_table(v, b->d_views);
   if (!views.empty())
     GA_HIP(hipMemcpyAsync(b->d_views, views.data(), views.size() * sizeof(ga::RunView),
                           hipMemcpyHostToDevice, b->stream), "upload views");

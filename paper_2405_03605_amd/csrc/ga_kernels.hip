@@ -960,6 +960,24 @@ __global__ void gather_kernel(RunView v, const uint32_t* ids, uint32_t n, uint32
     D_out[(size_t)w * n + j] = v.pop_D[(size_t)w * v.agent_stride + a];
 }
 
+// The member table holds each run's pointers as byte offsets from the table
+// itself: rebuilt from the kernel's table argument they are known to address
+// global memory, so the bodies use global (not flat) loads and stores.
+template <typename T>
+__device__ __forceinline__ T* table_ptr(const RunView* table, T* off) {
+  return reinterpret_cast<T*>(const_cast<char*>(reinterpret_cast<const char*>(table)) +
+                              reinterpret_cast<uintptr_t>(off));
+}
+__device__ __forceinline__ void from_table(RunView& v, const RunView* table) {
+  v.pop_f = table_ptr(table, v.pop_f);
+  v.pop_T = table_ptr(table, v.pop_T);
+  v.pop_D = table_ptr(table, v.pop_D);
+  v.ob[0] = table_ptr(table, v.ob[0]);
+  v.ob[1] = table_ptr(table, v.ob[1]);
+  v.gen = table_ptr(table, v.gen);
+  v.left = table_ptr(table, v.left);
+}
+
 // Batched form: wavefront i works on tiles[i]; members whose budget for this
 // block is spent sit the generation out. Members are fitness-valued genomes
 // with one-bit differentia.
@@ -974,7 +992,8 @@ void batch_generation_kernel(const RunView* __restrict__ views,
   const uint32_t wave = xcd_band_group() * (blockDim.x >> 6) + wig;
   if (wave >= n_tiles) return;
   const Tile tile = tiles[wave];
-  const RunView v = views[tile.run];
+  RunView v = views[tile.run];
+  from_table(v, views);
   if (*v.left <= gen_offset) return;
   const uint64_t t = *v.gen + gen_offset;
   uint4* arr = wave_lds(wig, max_ipw, 1u);
@@ -1000,7 +1019,8 @@ void batch_generation_kernel(const RunView* __restrict__ views,
 __global__ void batch_advance_kernel(const RunView* views, uint32_t n_runs, uint64_t block) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_runs) return;
-  const RunView v = views[i];
+  RunView v = views[i];
+  from_table(v, views);
   const unsigned long long left = *v.left;
   const unsigned long long done = left < block ? left : block;
   *v.gen = *v.gen + done;
