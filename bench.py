@@ -232,8 +232,8 @@ def main():
     args.max_lead = 0xFFFFFFFF if args.max_lead == "unpaced" else int(args.max_lead)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the island grid "
-              "would shard as 2D tiles with a per-generation halo exchange, which this "
-              "build does not run.", file=sys.stderr)
+              "would shard as 2D tiles with a per-generation halo exchange, which is not "
+              "implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
