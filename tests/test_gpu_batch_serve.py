@@ -191,3 +191,45 @@ def test_pool_first_fit_release_merging_and_results():
         pool.admit(run_config(width=100, height=100, pop=32), 10)   # larger than the pool
     assert pool.usage()["used"] == 0
     pool.close()
+
+
+def test_pool_churn_keeps_runs_apart():
+    # runs of uneven sizes admitted, stepped and retired in a random order
+    # until the pool has fragmented and merged many times; every retired
+    # run's sample must be the oracle's (overlapping blocks would corrupt one)
+    import paper_2405_03605_amd as ga
+    from paper_2405_03605_amd import GAPool
+    rng = np.random.default_rng(77)
+    al = lambda x: (x + 255) // 256 * 256
+    cfgs = [run_config(width=int(rng.integers(3, 10)), height=int(rng.integers(2, 8)),
+                       pop=int(rng.choice([4, 8, 16])), sites=int(rng.choice([32, 64])),
+                       k=int(rng.integers(1, 5)), seed=3, run_id=2000 + i) for i in range(60)]
+    budget = 6 * max(al(ga.state_bytes(c)) for c in cfgs)
+    pool = GAPool(budget, max_slots=8)
+    pool.set_graph_block(7)
+    pending = list(range(len(cfgs)))
+    live, results = {}, {}
+    gens = {i: int(rng.integers(5, 60)) for i in pending}
+    for _ in range(400):
+        while pending:
+            t = pool.admit(cfgs[pending[0]], gens[pending[0]])
+            if t is None:
+                break
+            live[t] = pending.pop(0)
+        if not live:
+            break
+        pool.step(int(rng.integers(1, 25)))
+        for t in pool.done():
+            results[live.pop(t)] = pool.retire(t)
+        u = pool.usage()
+        assert u["used"] <= budget and u["live"] == len(live)
+    assert not pending and not live and len(results) == len(cfgs)
+    assert pool.usage() == {"used": 0, "largest_free": budget, "live": 0}
+    for i in range(len(cfgs)):
+        ids, T, D = results[i]
+        ref = oracle_after(cfgs[i], gens[i])
+        f0, T0, D0 = ref.population()
+        assert np.array_equal(ids, ref.sample_one_per_island()), i
+        assert np.array_equal(T, T0[ids.astype(np.int64)]), i
+        assert np.array_equal(D, D0[ids.astype(np.int64)]), i
+    pool.close()
