@@ -233,3 +233,28 @@ def test_pool_churn_keeps_runs_apart():
         assert np.array_equal(T, T0[ids.astype(np.int64)]), i
         assert np.array_equal(D, D0[ids.astype(np.int64)]), i
     pool.close()
+
+
+def test_pool_argument_errors():
+    import ctypes
+    import torch
+    from paper_2405_03605_amd._lib import GA_EINVAL, load
+    lib = load()
+    mem = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    h = ctypes.c_void_p()
+    P = ctypes.c_void_p
+    base = mem.data_ptr()
+    assert lib.ga_pool_create(P(base + 1), 1 << 19, 4, P(stream.cuda_stream), ctypes.byref(h)) == GA_EINVAL
+    assert lib.ga_pool_create(P(base), 1 << 19, 0, P(stream.cuda_stream), ctypes.byref(h)) == GA_EINVAL
+    assert lib.ga_pool_create(None, 1 << 19, 4, P(stream.cuda_stream), ctypes.byref(h)) == GA_EINVAL
+    assert lib.ga_pool_create(P(base), 1 << 19, 4, P(stream.cuda_stream), None) == GA_EINVAL
+    # a pool smaller than one 256-byte block holds nothing
+    assert lib.ga_pool_create(P(base), 255, 4, P(stream.cuda_stream), ctypes.byref(h)) == 0
+    left = ctypes.c_uint64()
+    assert lib.ga_pool_remaining(h, 1, ctypes.byref(left)) == GA_EINVAL
+    used, big, live = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_uint32()
+    assert lib.ga_pool_usage(h, ctypes.byref(used), ctypes.byref(big), ctypes.byref(live)) == 0
+    assert (used.value, big.value, live.value) == (0, 0, 0)
+    lib.ga_pool_destroy(h)
+    lib.ga_pool_destroy(None)
