@@ -286,14 +286,17 @@ class GAPool:
 
     def retire(self, ticket: int, sample: bool = True):
         """Remove a run; with sample, return (ids, T, surfaces) of one agent per island."""
-        islands, words = self._shape.pop(int(ticket))
         if not sample:
             check(load().ga_pool_retire(self._h, int(ticket), None, None, None))
+            self._shape.pop(int(ticket), None)
             return None
+        # an unknown ticket is refused by the library (GAError), as for the other calls
+        islands, words = self._shape.get(int(ticket), (0, 0))
         ids = np.empty(islands, dtype=np.uint64)
         T = np.empty(islands, dtype=np.uint32)
         D = np.empty((islands, words), dtype=np.uint32)
         check(load().ga_pool_retire(self._h, int(ticket), _ptr(ids), _ptr(T), _ptr(D)))
+        self._shape.pop(int(ticket), None)   # a failed retire leaves the run in the pool
         return ids, T, D
 
     def usage(self) -> dict:

@@ -188,6 +188,10 @@ def test_pool_first_fit_release_merging_and_results():
     with pytest.raises(GAError):
         pool.remaining(t)
     with pytest.raises(GAError):
+        pool.retire(t)
+    with pytest.raises(GAError):
+        pool.retire(t, sample=False)
+    with pytest.raises(GAError):
         pool.admit(run_config(width=100, height=100, pop=32), 10)   # larger than the pool
     assert pool.usage()["used"] == 0
     pool.close()
