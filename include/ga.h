@@ -65,7 +65,7 @@ extern "C" {
 typedef struct ga_config {
   uint32_t struct_size;        /* sizeof(ga_config) */
   uint32_t width;              /* islands per row, 1..65535 */
-  uint32_t height;             /* rows, 1..65535; width * height * N < 2^31 */
+  uint32_t height;             /* rows, 1..65535; width * height * N < 2^30 */
   uint32_t pop_per_island;     /* N: power of two, 1..64 (Sec. 2 uses 32) */
   uint32_t surface_sites;      /* S sites: 32 or 64 one-bit differentia (or, with
                                 * differentia_bits b > 1, a power of two with
@@ -125,8 +125,10 @@ typedef struct ga_config {
 
 /* Genome models (ga_config.genome_model). The paper's kernel serves any
  * fixed-length genome through three functions, initialize, mutate and
- * evaluate (Sec. 2 Methods); here a model is compiled into the generation
- * kernels as one more template case.
+ * evaluate (Sec. 2 Methods); here a model is a type with those three device
+ * functions (one header each, listed with its id in the library's model
+ * registry) compiled into every generation kernel as a template argument.
+ * Ids not in the registry are GA_EINVAL.
  *
  * GA_MODEL_FITNESS: the genome is its fitness value (the paper's runs):
  * founders +0, mutation as mutation_law says.
@@ -204,7 +206,10 @@ int ga_step(ga_run* run, uint64_t n_gens);
  * after waiting for the run's stream. fitness[agents], T[agents] and
  * surface_words[agents * S*b/32] (agent-major) may each be NULL; outbox, if not
  * NULL, receives one ga_outbox_entry per island (the emissions the next
- * generation will absorb); generation, if not NULL, receives t. */
+ * generation will absorb); generation, if not NULL, receives t.
+ * GA_EDEVICE if a resident-form tile ever stopped waiting for a neighbouring
+ * tile (its workgroups were not all resident at once): the state is then not
+ * the synchronous schedule's (the same check guards ga_extract_surfaces). */
 int ga_read_population(ga_run* run, float* fitness, uint32_t* T,
                        uint32_t* surface_words, ga_outbox_entry* outbox,
                        uint64_t* generation);
@@ -238,21 +243,51 @@ uint64_t ga_generation(const ga_run* run);
  * the caller. NULL is allowed. */
 void ga_destroy(ga_run* run);
 
-/* Launch forms for ga_step. */
-#define GA_FORM_AUTO 0       /* resident when the run fits one workgroup, else streaming */
-#define GA_FORM_STREAMING 1  /* one kernel per generation over all islands */
-#define GA_FORM_RESIDENT 2   /* one workgroup loops over generations (<= 16 wavefronts) */
+/* Launch forms for ga_step (synchronous runs).
+ * GA_FORM_STREAMING: one kernel per generation over all islands, the
+ * population read from and written back to HBM every generation.
+ * GA_FORM_RESIDENT: the population held in LDS across generations, as each
+ * processing element of the paper's design holds its island in local memory
+ * (Sec. 2 Methods). The torus is cut into tiles of tile_w x tile_h islands
+ * (the last column and row of tiles ragged); one workgroup per tile runs every
+ * generation of a launch, all tiles' workgroups resident at once. Between
+ * generations tiles exchange only their edge islands' emissions through the
+ * HBM outbox, each tile waiting (a bounded number of times) until its four
+ * neighbouring tiles have published generation t - 1. HBM carries the
+ * population only at the start and end of a launch (at most 2^16 generations
+ * or about 2^34 agent-generations each). Needs a tiling whose tiles fit the
+ * LDS of a CU (160 KiB: per agent 4 bytes each of fitness, T, the surface
+ * words and any string words; per island two outbox entries) with every
+ * workgroup resident at once.
+ * GA_FORM_AUTO (default): the resident form when such a tiling exists, else
+ * streaming. Results do not depend on the form. */
+#define GA_FORM_AUTO 0
+#define GA_FORM_STREAMING 1
+#define GA_FORM_RESIDENT 2
 
 /* Launch tuning for one run: islands per wavefront (a multiple of 64/N, at
- * most 64; default 16, or fewer for small grids), wavefronts per workgroup
- * (1..16; default 4) and the launch form. 0 keeps the current value of the
- * first two. Results do not depend on any of these.
- * GA_EINVAL if the resident form is asked for a run that needs more than 16
- * wavefronts at the given islands per wavefront, or if a workgroup's LDS table
- * (5 * islands_per_wave + 1 entries of 16 bytes, 32 with a genome string, per
- * wavefront) would exceed the 160 KiB of a CU. */
+ * most 64; default 16, or fewer for small grids) and wavefronts per workgroup
+ * (1..16; default 4) of the streaming form, and the launch form. 0 keeps the
+ * current value of the first two. Results do not depend on any of these.
+ * GA_EINVAL if a streaming workgroup's LDS table (5 * islands_per_wave + 1
+ * entries of 16 bytes, 32 with a genome string, per wavefront) would exceed
+ * the 160 KiB of a CU, or if the resident form is asked for a run with no
+ * tiling that fits (or for an asynchronous run). */
 int ga_set_launch(ga_run* run, uint32_t islands_per_wave, uint32_t waves_per_group,
                   uint32_t form);
+
+/* Tile shape of the resident form: tile_w x tile_h islands (clamped to the
+ * torus), or 0, 0 to let the library choose (the default: the smallest tiles,
+ * but not under 2,048 agents, whose workgroups all fit the GPU at once; then
+ * the fewest and squarest). GA_EINVAL for an asynchronous run, for one side
+ * given without the other, or if the tiles do not fit (LDS of a CU, or more
+ * workgroups than the GPU holds at once); the run then keeps its tiling.
+ * Results do not depend on the tile shape. */
+int ga_set_tiles(ga_run* run, uint32_t tile_w, uint32_t tile_h);
+
+/* The tiling ga_step uses for this run: tile sides and tile count, all 0 when
+ * it runs the streaming form (or is asynchronous or a batch member). */
+int ga_get_tiles(ga_run* run, uint32_t* tile_w, uint32_t* tile_h, uint32_t* tiles);
 /* Asynchronous runs only (GA_EINVAL for a synchronous run).
  *
  * max_wavefronts caps the wavefronts of a launch (0, the default: as many as

@@ -6,13 +6,16 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libga_hip.so")
 HEADER = os.path.join(ROOT, "include", "ga.h")
-SOURCES = [os.path.join(_HERE, "csrc", n) for n in ("ga_kernels.hip", "ga_mrca.hip", "ga_api.hip")]
-HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+SOURCES = [os.path.join(_HERE, "csrc", n)
+           for n in ("ga_kernels.hip", "ga_tile.hip", "ga_mrca.hip", "ga_api.hip")]
+BUILD_DIR = os.path.join(_HERE, "_build")
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_ESTATE = 0, -1, -2, -3, -4
@@ -30,10 +33,21 @@ class GAError(RuntimeError):
 
 
 def build(hipcc: str = "hipcc") -> str:
-    """Compile libga_hip.so for gfx950 in-tree."""
+    """Compile libga_hip.so for gfx950 in-tree (one object per source, in
+    parallel, then one link)."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    quiet = subprocess.DEVNULL if os.environ.get("GA_QUIET_BUILD") else None
+    objs = [os.path.join(BUILD_DIR, os.path.basename(src) + ".o") for src in SOURCES]
+
+    def compile_one(src_obj):
+        src, obj = src_obj
+        subprocess.run([hipcc] + HIPCC_FLAGS + ["-c", src, "-o", obj], check=True, stderr=quiet)
+
+    with ThreadPoolExecutor(len(SOURCES)) as pool:
+        list(pool.map(compile_one, zip(SOURCES, objs)))
     tmp = LIB_PATH + ".tmp"
-    subprocess.run([hipcc] + HIPCC_FLAGS + ["-o", tmp] + SOURCES, check=True,
-                   stderr=subprocess.DEVNULL if os.environ.get("GA_QUIET_BUILD") else None)
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs,
+                   check=True, stderr=quiet)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -67,6 +81,8 @@ SIGNATURES = {
     "ga_destroy": (None, [P]),
     "ga_set_launch": (i32, [P, u32, u32, u32]),
     "ga_set_graph_block": (i32, [P, u32]),
+    "ga_set_tiles": (i32, [P, u32, u32]),
+    "ga_get_tiles": (i32, [P, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
     "ga_set_async": (i32, [P, u32, u32, u32]),
     "ga_async_waits": (i32, [P, ctypes.POINTER(u64)]),
     "ga_async_last_taken": (i32, [P, P]),

@@ -35,6 +35,8 @@ int hip_fail(hipError_t e, const char* what) {
   } while (0)
 
 constexpr size_t kAlign = 256;
+// Most tiles of the LDS-resident form (one workgroup each, all resident at once).
+constexpr uint32_t kMaxTiles = 8192;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Sizes of earlier configuration layouts: before mutation_law /
@@ -104,9 +106,9 @@ bool config_ok(const ga_config* c, std::string* why) {
   if (c->struct_size > kConfigV2Size && c->schedule > GA_SCHEDULE_ASYNC)
     return no("schedule must be 0 (synchronous) or 1 (asynchronous)");
   if (c->struct_size > kConfigV3Size) {
-    if (c->genome_model > GA_MODEL_TRAP4)
-      return no("genome_model must be 0 (fitness), 1 (OneMax) or 2 (Trap-4)");
-    if (c->genome_model != GA_MODEL_FITNESS && c->mutation_law != 0)
+    if (c->genome_model >= ga::model_count())
+      return no("genome_model must name a compiled-in model (0 fitness, 1 OneMax, 2 Trap-4)");
+    if (ga::model_has_string_host(c->genome_model) && c->mutation_law != 0)
       return no("a genome model with a string uses mutation_law 0");
   }
   if (c->struct_size >= kConfigV2Size) {
@@ -141,7 +143,7 @@ uint32_t model_of(const ga_config* c) {
 // words per AoS outbox entry: fitness, T, surface words, header, padding to 16 B;
 // with a string: fitness, T, two surface words, two string words, header, pad
 size_t outbox_stride(const ga_config* c) {
-  return surface_words(c) == 1 && model_of(c) == GA_MODEL_FITNESS ? 4 : 8;
+  return surface_words(c) == 1 && !ga::model_has_string_host(model_of(c)) ? 4 : 8;
 }
 
 // Planes run 128 islands past the last 64-island boundary: a wavefront's last
@@ -165,7 +167,7 @@ Layout layout_of(const ga_config* c) {
   L.pop_f = take(agents * 4);
   L.pop_T = take(agents * 4);
   L.pop_D = take(agents * 4 * words);
-  if (model_of(c) != GA_MODEL_FITNESS) L.pop_P = take(agents * 4 * 2);
+  if (ga::model_has_string_host(model_of(c))) L.pop_P = take(agents * 4 * 2);
   if (is_async(c)) {
     // eight buffers per island (direction x parity), four stamps, one
     // progress word per possible chunk, and the lockstep headers (eight per
@@ -176,6 +178,8 @@ Layout layout_of(const ga_config* c) {
     L.lock = take(islands * 8 * 4);
   } else {
     for (int p = 0; p < 2; ++p) L.ob[p] = take(islands * 4 * outbox_stride(c));
+    // LDS-resident tiles: a progress word per tile (never more tiles than islands)
+    L.prog = take(std::min<size_t>(kMaxTiles, (size_t)c->width * c->height) * 4);
   }
   L.counters = take(24);  // generation, batch budget, async give-ups
   L.st_ids = take(islands * 4);
@@ -205,6 +209,9 @@ struct ga_run {
   uint32_t async_max_waves = 0;  // 0: as many as the GPU holds at once
   uint32_t async_lead = 0;       // pacing bound (ga::kUnpaced: none)
   uint32_t async_skew = 0;       // reproducible skewed interleaving (one wavefront)
+  uint32_t want_tile_w = 0, want_tile_h = 0;  // caller's tile shape (0: chosen here)
+  int tile_state = 0;            // 0 not planned, 1 planned (view.tile_*), -1 no tiling fits
+  std::string tile_why;          // why no tiling fits
 };
 
 struct ga_batch {
@@ -291,32 +298,137 @@ uint32_t waves_for(const ga_run* r, uint32_t ipw) {
   return (r->view.islands + ipw - 1) / ipw;
 }
 
-// Islands per wavefront for the resident form: spread the islands over as many
-// wavefronts as a workgroup can hold.
-uint32_t resident_ipw(const ga_run* r) {
-  const uint32_t g = per_iter(r);
-  uint32_t want = (r->view.islands + ga::kMaxWavesPerGroup - 1) / ga::kMaxWavesPerGroup;
-  want = (want + g - 1) / g * g;
-  return std::max(g, std::min(64u, want));
-}
-
 // LDS of one CU (gfx950), the most a workgroup can take.
 constexpr size_t kMaxGroupLds = 160 * 1024;
 
-// LDS one workgroup may take for the resident form.
-constexpr size_t kResidentLds = 64 * 1024;
+// Default lower bound on a tile's agents: below it the per-generation
+// exchange between tiles costs more than the work it spreads.
+constexpr uint32_t kMinTileAgents = 2048;
 
-bool resident_fits(const ga_run* r) {
-  const uint32_t ipw = resident_ipw(r);
-  const uint32_t waves = waves_for(r, ipw);
-  return waves <= (uint32_t)ga::kMaxWavesPerGroup &&
-         ga::lds_bytes(ipw, waves, r->view.model) <= kResidentLds;
+uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+struct TileCand {
+  uint32_t tw, th, gx, gy;
+  size_t lds;
+  uint32_t threads;
+};
+
+TileCand tile_cand(const ga::RunView& v, uint32_t tw, uint32_t th) {
+  TileCand c{tw, th, ceil_div(v.width, tw), ceil_div(v.height, th), 0, 0};
+  c.lds = ga::tile_lds_bytes(tw, th, v.log2n, v.words, v.model, v.ob_stride);
+  c.threads = ga::tile_threads(tw, th, v.log2n);
+  return c;
 }
 
-bool use_resident(const ga_run* r) {
-  if (r->form == GA_FORM_RESIDENT) return true;
-  if (r->form == GA_FORM_STREAMING) return false;
-  return r->view.agents <= 4096 && resident_fits(r);
+// Whether every tile's workgroup of candidate c can be resident at once:
+// first a bound from LDS and threads per CU alone, then the occupancy query.
+int tile_fits(const ga::RunView& v, const TileCand& c, uint32_t cus, bool* fits) {
+  *fits = false;
+  if (c.lds > kMaxGroupLds || (size_t)c.gx * c.gy > kMaxTiles) return GA_OK;
+  const uint64_t bound = std::min<uint64_t>(kMaxGroupLds / c.lds, 2048u / c.threads);
+  if ((uint64_t)c.gx * c.gy > bound * cus) return GA_OK;
+  int groups = 0;
+  GA_HIP(ga::tile_occupancy(v, c.threads, c.lds, &groups), "occupancy query");
+  *fits = (uint64_t)c.gx * c.gy <= (uint64_t)groups * (uint64_t)cus;
+  return GA_OK;
+}
+
+// The tiling of the LDS-resident form: the caller's tile shape, or the one
+// that spreads the run over the most CUs (smallest tiles, but not below
+// kMinTileAgents agents), then the fewest tiles, then the squarest; every
+// tile's workgroup must be resident at once. Sets view.tile_* and tile_state.
+int plan_tiles(ga_run* r) {
+  if (r->tile_state != 0) return GA_OK;
+  ga::RunView& v = r->view;
+  const uint32_t W = v.width, H = v.height, N = 1u << v.log2n;
+  std::vector<TileCand> cands;
+  if (r->want_tile_w) {
+    cands.push_back(tile_cand(v, std::min(r->want_tile_w, W), std::min(r->want_tile_h, H)));
+  } else {
+    // distinct tile widths ceil(W / k) and heights ceil(H / k)
+    std::vector<uint32_t> ws, hs;
+    for (uint32_t k = 1; k <= W; ++k)
+      if (ws.empty() || ws.back() != ceil_div(W, k)) ws.push_back(ceil_div(W, k));
+    for (uint32_t k = 1; k <= H; ++k)
+      if (hs.empty() || hs.back() != ceil_div(H, k)) hs.push_back(ceil_div(H, k));
+    const uint64_t floor_agents = std::min<uint64_t>((uint64_t)v.agents, kMinTileAgents);
+    for (uint32_t tw : ws)
+      for (uint32_t th : hs) {
+        const TileCand c = tile_cand(v, tw, th);
+        if (c.lds > kMaxGroupLds || (uint64_t)c.gx * c.gy > kMaxTiles) continue;
+        cands.push_back(c);
+      }
+    auto key = [&](const TileCand& c) {
+      const uint64_t agents = (uint64_t)c.tw * c.th * N;
+      return std::make_tuple(std::max(agents, floor_agents), (uint64_t)c.gx * c.gy,
+                             c.tw + c.th, c.tw);
+    };
+    std::sort(cands.begin(), cands.end(),
+              [&](const TileCand& a, const TileCand& b) { return key(a) < key(b); });
+  }
+  int device = 0, cus = 0;
+  GA_HIP(hipGetDevice(&device), "get device");
+  GA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "CU count");
+  for (const TileCand& c : cands) {
+    bool fits = false;
+    const int rc = tile_fits(v, c, (uint32_t)cus, &fits);
+    if (rc != GA_OK) return rc;
+    if (!fits) continue;
+    v.tile_w = c.tw;
+    v.tile_h = c.th;
+    v.tiles_x = c.gx;
+    v.tiles_y = c.gy;
+    r->tile_state = 1;
+    return GA_OK;
+  }
+  r->tile_state = -1;
+  r->tile_why = r->want_tile_w ? "the tile shape needs more LDS than a CU has, or more "
+                                 "workgroups than the GPU holds at once"
+                               : "no tiling of the run fits the GPU's LDS";
+  return GA_OK;
+}
+
+// Whether ga_step runs the LDS-resident tile form.
+int use_tiles(ga_run* r, bool* yes) {
+  *yes = false;
+  if (r->form == GA_FORM_STREAMING) return GA_OK;
+  const int rc = plan_tiles(r);
+  if (rc != GA_OK) return rc;
+  if (r->tile_state == 1) {
+    *yes = true;
+    return GA_OK;
+  }
+  if (r->form == GA_FORM_RESIDENT) return fail(GA_EINVAL, "resident form: " + r->tile_why);
+  return GA_OK;
+}
+
+// A tile's wait that gave up leaves the state invalid (its workgroups were
+// not all resident at once); reported when the state is read.
+int check_tile_waits(ga_run* r) {
+  if (r->cfg.schedule == GA_SCHEDULE_ASYNC) return GA_OK;
+  unsigned long long n = 0;
+  GA_HIP(hipMemcpy(&n, r->view.waits, sizeof(n), hipMemcpyDeviceToHost), "read waits");
+  if (n) return fail(GA_EDEVICE, "an LDS-resident tile stopped waiting for a neighbouring tile "
+                                 "(not every tile was resident at once): the state is invalid");
+  return GA_OK;
+}
+
+int step_tiles(ga_run* r, uint64_t n) {
+  const ga::RunView& v = r->view;
+  const uint32_t n_tiles = v.tiles_x * v.tiles_y;
+  // about 2^34 agent-generations, at most 2^16 generations, per launch
+  const uint64_t slice_max =
+      std::max<uint64_t>(1, std::min<uint64_t>(1u << 16, (1ull << 34) / std::max(1u, v.agents)));
+  uint64_t left = n;
+  while (left > 0) {
+    const uint64_t slice = std::min(left, slice_max);
+    GA_HIP(ga::launch_fill(v.prog, (uint32_t)r->gen_host, n_tiles, r->stream), "progress reset");
+    GA_HIP(ga::launch_tiles(v, slice, r->stream), "tile launch");
+    GA_HIP(ga::launch_advance(v.gen, slice, r->stream), "advance launch");
+    left -= slice;
+    r->gen_host += slice;
+  }
+  return GA_OK;
 }
 
 void drop_graph(ga_run* r) {
@@ -462,11 +574,11 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   v.pop_T = reinterpret_cast<uint32_t*>(b + lay.pop_T);
   v.pop_D = reinterpret_cast<uint32_t*>(b + lay.pop_D);
   v.model = model;
-  v.pop_P = model ? reinterpret_cast<uint32_t*>(b + lay.pop_P) : nullptr;
+  v.pop_P = ga::model_has_string_host(model) ? reinterpret_cast<uint32_t*>(b + lay.pop_P) : nullptr;
   for (int p = 0; p < 2; ++p) v.ob[p] = async ? nullptr : reinterpret_cast<uint32_t*>(b + lay.ob[p]);
   v.mail = async ? reinterpret_cast<uint32_t*>(b + lay.mail) : nullptr;
   v.seen = async ? reinterpret_cast<uint32_t*>(b + lay.seen) : nullptr;
-  v.prog = async ? reinterpret_cast<uint32_t*>(b + lay.prog) : nullptr;
+  v.prog = reinterpret_cast<uint32_t*>(b + lay.prog);
   v.lock = async ? reinterpret_cast<uint32_t*>(b + lay.lock) : nullptr;
   v.ob_stride = (uint32_t)outbox_stride(cfg);
   v.gen = reinterpret_cast<unsigned long long*>(b + lay.counters);
@@ -498,7 +610,7 @@ int ga_init(const ga_config* cfg, void* dev_mem, size_t bytes, void* hip_stream,
   // Founders: all-zero bits are +0 fitness, T = 0, blank surfaces, invalid
   // outbox headers, generation 0.
   hipError_t e = ga::launch_fill(reinterpret_cast<uint32_t*>(b), 0u, lay.total / 4, r->stream);
-  if (e == hipSuccess && model) e = ga::launch_init_strings(v, r->stream);
+  if (e == hipSuccess) e = ga::launch_init(v, r->stream);
   if (e != hipSuccess) {
     delete r;
     return hip_fail(e, "init fill");
@@ -523,11 +635,50 @@ int ga_set_launch(ga_run* r, uint32_t ipw, uint32_t wpg, uint32_t form) {
   if (form > GA_FORM_RESIDENT) return fail(GA_EINVAL, "unknown form");
   if (form == GA_FORM_RESIDENT && r->cfg.schedule == GA_SCHEDULE_ASYNC)
     return fail(GA_EINVAL, "the resident form is synchronous");
-  if (form == GA_FORM_RESIDENT && !resident_fits(r))
-    return fail(GA_EINVAL, "run too large for the resident form");
+  if (form == GA_FORM_RESIDENT && r->cfg.schedule != GA_SCHEDULE_ASYNC) {
+    const int rc = plan_tiles(r);
+    if (rc != GA_OK) return rc;
+    if (r->tile_state != 1) return fail(GA_EINVAL, "resident form: " + r->tile_why);
+  }
   r->ipw = new_ipw;
   r->wpg = new_wpg;
   r->form = form;
+  return GA_OK;
+}
+
+int ga_set_tiles(ga_run* r, uint32_t tile_w, uint32_t tile_h) {
+  if (!r) return fail(GA_EINVAL, "run is NULL");
+  if (r->cfg.schedule == GA_SCHEDULE_ASYNC) return fail(GA_EINVAL, "tiles are synchronous");
+  if ((tile_w == 0) != (tile_h == 0)) return fail(GA_EINVAL, "give both tile sides or neither");
+  const uint32_t old_w = r->want_tile_w, old_h = r->want_tile_h;
+  const ga::RunView old_view = r->view;
+  const int old_state = r->tile_state;
+  const std::string old_why = r->tile_why;
+  r->want_tile_w = std::min(tile_w, r->view.width);
+  r->want_tile_h = std::min(tile_h, r->view.height);
+  r->tile_state = 0;
+  int rc = plan_tiles(r);
+  if (rc == GA_OK && r->tile_state != 1) rc = fail(GA_EINVAL, "tiles: " + r->tile_why);
+  if (rc != GA_OK) {  // a failed call leaves the run as it was
+    r->want_tile_w = old_w;
+    r->want_tile_h = old_h;
+    r->view = old_view;
+    r->tile_state = old_state;
+    r->tile_why = old_why;
+  }
+  return rc;
+}
+
+int ga_get_tiles(ga_run* r, uint32_t* tile_w, uint32_t* tile_h, uint32_t* tiles) {
+  if (!r) return fail(GA_EINVAL, "run is NULL");
+  bool yes = false;
+  if (r->cfg.schedule != GA_SCHEDULE_ASYNC && !r->batch) {
+    const int rc = use_tiles(r, &yes);
+    if (rc != GA_OK) return rc;
+  }
+  if (tile_w) *tile_w = yes ? r->view.tile_w : 0u;
+  if (tile_h) *tile_h = yes ? r->view.tile_h : 0u;
+  if (tiles) *tiles = yes ? r->view.tiles_x * r->view.tiles_y : 0u;
   return GA_OK;
 }
 
@@ -583,13 +734,10 @@ int ga_step(ga_run* r, uint64_t n) {
   if (r->batch) return fail(GA_ESTATE, "run is a batch member; advance it with ga_batch_step");
   if (n == 0) return GA_OK;
   if (r->cfg.schedule == GA_SCHEDULE_ASYNC) return step_async(r, n);
-  if (use_resident(r)) {
-    ga::RunView v = r->view;
-    v.ipw = resident_ipw(r);
-    GA_HIP(ga::launch_resident(v, n, waves_for(r, v.ipw), r->stream), "resident launch");
-    r->gen_host += n;
-    return GA_OK;
-  }
+  bool tiles = false;
+  int rc0 = use_tiles(r, &tiles);
+  if (rc0 != GA_OK) return rc0;
+  if (tiles) return step_tiles(r, n);
   uint64_t left = n;
   if (r->graph_block > 0 && left >= r->graph_block) {
     int rc = ensure_graph(r);
@@ -610,10 +758,12 @@ int ga_read_population(ga_run* r, float* fitness, uint32_t* T, uint32_t* surface
   if (!r) return fail(GA_EINVAL, "run is NULL");
   if (outbox && r->cfg.schedule == GA_SCHEDULE_ASYNC)
     return fail(GA_EINVAL, "an asynchronous run has no synchronous outbox");
-  if (outbox && r->view.model != GA_MODEL_FITNESS)
+  if (outbox && ga::model_has_string_host(r->view.model))
     return fail(GA_EINVAL, "the outbox of a genome model with a string is not exchanged");
   hipStream_t s = r->batch ? r->batch->stream : r->stream;
   GA_HIP(hipStreamSynchronize(s), "stream sync");
+  const int waited = check_tile_waits(r);
+  if (waited != GA_OK) return waited;
   const ga::RunView& v = r->view;
   const size_t A = v.agents, I = v.islands, W = v.words;
   unsigned long long t = 0;
@@ -661,7 +811,7 @@ int ga_write_population(ga_run* r, const float* fitness, const uint32_t* T,
   if (r->batch) return fail(GA_ESTATE, "run is a batch member");
   const bool async = r->cfg.schedule == GA_SCHEDULE_ASYNC;
   if (outbox && async) return fail(GA_EINVAL, "an asynchronous run has no synchronous outbox");
-  if (outbox && r->view.model != GA_MODEL_FITNESS)
+  if (outbox && ga::model_has_string_host(r->view.model))
     return fail(GA_EINVAL, "the outbox of a genome model with a string is not exchanged");
   if (outbox) {
     for (size_t i = 0; i < r->view.islands; ++i)
@@ -718,7 +868,8 @@ int ga_write_population(ga_run* r, const float* fitness, const uint32_t* T,
 
 int ga_read_strings(ga_run* r, uint32_t* words) {
   if (!r || !words) return fail(GA_EINVAL, "run or words is NULL");
-  if (r->view.model == GA_MODEL_FITNESS) return fail(GA_EINVAL, "the genome model has no string");
+  if (!ga::model_has_string_host(r->view.model))
+    return fail(GA_EINVAL, "the genome model has no string");
   hipStream_t s = r->batch ? r->batch->stream : r->stream;
   GA_HIP(hipStreamSynchronize(s), "stream sync");
   const size_t A = r->view.agents;
@@ -735,7 +886,8 @@ int ga_read_strings(ga_run* r, uint32_t* words) {
 
 int ga_write_strings(ga_run* r, const uint32_t* words) {
   if (!r || !words) return fail(GA_EINVAL, "run or words is NULL");
-  if (r->view.model == GA_MODEL_FITNESS) return fail(GA_EINVAL, "the genome model has no string");
+  if (!ga::model_has_string_host(r->view.model))
+    return fail(GA_EINVAL, "the genome model has no string");
   if (r->batch) return fail(GA_ESTATE, "run is a batch member");
   GA_HIP(hipStreamSynchronize(r->stream), "stream sync");
   const size_t A = r->view.agents;
@@ -762,6 +914,8 @@ int ga_extract_surfaces(ga_run* r, const uint64_t* agent_ids, size_t n, uint64_t
   if (n == 0) return GA_OK;
   hipStream_t s = r->batch ? r->batch->stream : r->stream;
   GA_HIP(hipStreamSynchronize(s), "stream sync");
+  const int waited = check_tile_waits(r);
+  if (waited != GA_OK) return waited;
   uint32_t* st_ids = reinterpret_cast<uint32_t*>(r->base + r->lay.st_ids);
   uint32_t* st_T = reinterpret_cast<uint32_t*>(r->base + r->lay.st_T);
   uint32_t* st_D = reinterpret_cast<uint32_t*>(r->base + r->lay.st_D);

@@ -52,13 +52,17 @@ struct RunView {
   uint32_t* prog;
   uint32_t* lock;
   unsigned long long* waits;
-  // genome model (0 fitness-valued; 1 OneMax, 2 Trap-4 on a 64-bit string)
-  // and, with a string, its two word planes pop_P[w * agent_stride + a]
+  // genome model (an id of GA_FOR_EACH_MODEL) and, for a model with a
+  // string, its two word planes pop_P[w * agent_stride + a]
   uint32_t model;
   uint32_t* pop_P;
   // surface: S = 2^s_log sites of 2^dlog-bit differentia in `words` words,
-  // policy 0 "doubling steady", 1 "tilted"
+  // policy 0 "doubling steady", 1 "tilted", 2 "hybrid"
   uint32_t s_log, dlog, policy;
+  // LDS-resident tiles (synchronous schedule): tiles of tile_w x tile_h
+  // islands, tiles_x across and tiles_y down (the last ones ragged); tile c's
+  // progress word is prog[c]
+  uint32_t tile_w, tile_h, tiles_x, tiles_y;
 };
 
 // Asynchronous pacing: no bound on how far an island may run ahead, and the
@@ -84,7 +88,16 @@ constexpr int kMaxWavesPerGroup = 16;
 // Launch wrappers (defined in ga_kernels.hip). All enqueue on `stream`.
 hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t waves,
                              uint32_t waves_per_group, hipStream_t stream);
-hipError_t launch_resident(const RunView& v, uint64_t n_gens, uint32_t waves, hipStream_t stream);
+// The LDS-resident tile form: one persistent launch of n_gens generations,
+// one workgroup per tile (v.tile_* set; v.prog holds a word per tile, equal to
+// the generation counter's low word before the launch).
+hipError_t launch_tiles(const RunView& v, uint64_t n_gens, hipStream_t stream);
+// LDS bytes and threads of a tile's workgroup, and how many such workgroups
+// one CU holds at once.
+size_t tile_lds_bytes(uint32_t tile_w, uint32_t tile_h, uint32_t log2n, uint32_t words,
+                      uint32_t model, uint32_t ob_stride);
+uint32_t tile_threads(uint32_t tile_w, uint32_t tile_h, uint32_t log2n);
+hipError_t tile_occupancy(const RunView& v, uint32_t threads, size_t lds, int* groups_per_cu);
 hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint32_t chunks,
                         uint32_t waves_per_group, uint32_t lead, uint32_t skew,
                         hipStream_t stream);
@@ -96,8 +109,11 @@ hipError_t launch_lockstep(const RunView& v, uint64_t gen, uint64_t n_gens, uint
 hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, bool lockstep,
                           uint32_t* waves);
 hipError_t launch_advance(unsigned long long* gen, uint64_t n, hipStream_t stream);
-// Founders' strings and fitness for a genome model with a string.
-hipError_t launch_init_strings(const RunView& v, hipStream_t stream);
+// Founders of the run's genome model (its initialize function).
+hipError_t launch_init(const RunView& v, hipStream_t stream);
+// Whether genome model `id` carries a 64-bit string, and how many models there are.
+bool model_has_string_host(uint32_t id);
+uint32_t model_count();
 // Dynamic LDS bytes of a launch.
 size_t lds_bytes(uint32_t ipw, uint32_t waves, uint32_t model);
 hipError_t launch_fill(uint32_t* p, uint32_t value, size_t words, hipStream_t stream);

@@ -20,185 +20,10 @@
 // wavefront reads all of an island's agents before it writes any child, and no
 // other wavefront reads them. Population and outbox planes are padded past the
 // last island, so iterations never need a tail predicate.
-#include "ga_internal.hpp"
+#include "ga_device.hpp"
 
 namespace ga {
 namespace {
-
-constexpr uint32_t kMulA = 0xD2511F53u;   // Philox4x32 round multipliers
-constexpr uint32_t kMulB = 0xCD9E8D57u;
-constexpr uint32_t kWeylA = 0x9E3779B9u;  // key schedule increments
-constexpr uint32_t kWeylB = 0xBB67AE85u;
-
-constexpr uint32_t kStreamSelect = 0u;
-constexpr uint32_t kStreamMigrate = 1u;
-constexpr uint32_t kStreamSample = 2u;
-constexpr uint32_t kStreamMutate = 3u;
-
-struct Block {
-  uint32_t x, y, z, w;
-};
-
-// a ^ b ^ c in one gfx950 three-input bitwise op (truth table 0x96)
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
-  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-}
-
-__device__ __forceinline__ uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
-
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), rounds FIRST..9 applied
-// to counter state (c0..c3) with the round-0 key (k0, k1): each round takes both
-// halves of two 32x32->64 products and mixes the high halves with the other
-// two words and the round key (k + round * Weyl increment).
-template <int FIRST>
-__device__ __forceinline__ Block philox_rounds(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int round = FIRST; round < 10; ++round) {
-    const uint64_t pa = (uint64_t)kMulA * c0;
-    const uint64_t pb = (uint64_t)kMulB * c2;
-    const uint32_t n0 = xor3(hi32(pb), c1, k0 + (uint32_t)round * kWeylA);
-    const uint32_t n2 = xor3(hi32(pa), c3, k1 + (uint32_t)round * kWeylB);
-    c1 = (uint32_t)pb;
-    c3 = (uint32_t)pa;
-    c0 = n0;
-    c2 = n2;
-  }
-  return {c0, c1, c2, c3};
-}
-
-__device__ __forceinline__ Block philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                          uint32_t k0, uint32_t k1) {
-  return philox_rounds<0>(c0, c1, c2, c3, k0, k1);
-}
-
-// Per-child stream blocks for one lane across a chunk. The counter is
-// (slot, island, t_lo, t_hi*4 + stream): only the island word changes between a lane's
-// iterations, so everything of rounds 0-2 that does not depend on it is
-// computed once. The remaining per-block cost is 2 + 7*2 products and 3 + 7*2
-// three-input ops.
-struct SelectStream {
-  uint32_t x0;      // round 0: c0' = x0 ^ island
-  uint32_t inv_a;   // round 1: c2'' = hi(M0*c0') ^ inv_a
-  uint32_t inv_b;   // round 2: c0''' = hi(M1*c2'') ^ inv_b
-  uint32_t inv_c;   // round 2: c2''' = inv_c ^ lo(M0*c0')
-  uint32_t inv_d;   // round 2: c3''' = inv_d
-  uint32_t k0, k1;
-
-  __device__ __forceinline__ void init(uint32_t slot, uint32_t t_lo, uint32_t t_hi4, uint32_t key0,
-                                       uint32_t key1, uint32_t stream) {
-    k0 = key0;
-    k1 = key1;
-    // round 0 on (slot, island, t_lo, t_hi4)
-    const uint64_t pa0 = (uint64_t)kMulA * slot;
-    const uint64_t pb0 = (uint64_t)kMulB * t_lo;
-    x0 = hi32(pb0) ^ key0;                       // c0' = hi(pb0) ^ island ^ k0
-    const uint32_t c1_1 = (uint32_t)pb0;
-    const uint32_t c2_1 = hi32(pa0) ^ (t_hi4 | stream) ^ key1;
-    const uint32_t c3_1 = (uint32_t)pa0;
-    // round 1: pb1 from c2_1 is invariant; pa1 from c0' is not
-    const uint64_t pb1 = (uint64_t)kMulB * c2_1;
-    const uint32_t c0_2 = hi32(pb1) ^ c1_1 ^ (key0 + kWeylA);
-    const uint32_t c1_2 = (uint32_t)pb1;
-    inv_a = c3_1 ^ (key1 + kWeylB);              // c2_2 = hi(pa1) ^ inv_a, c3_2 = lo(pa1)
-    // round 2: pa2 from c0_2 is invariant; pb2 from c2_2 is not
-    const uint64_t pa2 = (uint64_t)kMulA * c0_2;
-    inv_b = c1_2 ^ (key0 + 2u * kWeylA);         // c0_3 = hi(pb2) ^ inv_b
-    inv_c = hi32(pa2) ^ (key1 + 2u * kWeylB);    // c2_3 = inv_c ^ c3_2
-    inv_d = (uint32_t)pa2;                       // c3_3
-  }
-
-  __device__ __forceinline__ Block block(uint32_t island) const {
-    const uint32_t c0_1 = x0 ^ island;
-    const uint64_t pa1 = (uint64_t)kMulA * c0_1;
-    const uint32_t c2_2 = hi32(pa1) ^ inv_a;
-    const uint32_t c3_2 = (uint32_t)pa1;
-    const uint64_t pb2 = (uint64_t)kMulB * c2_2;
-    const uint32_t c0_3 = hi32(pb2) ^ inv_b;
-    const uint32_t c1_3 = (uint32_t)pb2;
-    const uint32_t c2_3 = inv_c ^ c3_2;
-    return philox_rounds<3>(c0_3, c1_3, c2_3, inv_d, k0, k1);
-  }
-};
-
-// Site written by the deposit of stratum rank r on S = 2^s sites when r >= S
-// and r is a multiple of 2^e, e = bitlen(r) - s ("doubling steady" surface):
-// the j-th rank written in epoch e takes over the site of rank (2j+1) << (e-1),
-// which left the retained set when epoch e began. Written ranks have the form
-// odd << shift, so the walk only renormalises the odd part until the rank
-// falls below S.
-__device__ __noinline__ uint32_t surface_site_walk(uint32_t r, uint32_t e, uint32_t s) {
-  const uint32_t half = 1u << (s - 1u);
-  uint32_t odd = (((r >> e) - half) << 1) | 1u;
-  uint32_t shift = e - 1u;
-  for (;;) {
-    const uint32_t len = 32u - __clz(odd);
-    if (len + shift <= s) return odd << shift;
-    const uint32_t lead = odd << (s - len);  // rank >> its epoch, in [S/2, S)
-    shift = len + shift - s - 1u;
-    odd = ((lead - half) << 1) | 1u;
-  }
-}
-
-__device__ __forceinline__ uint32_t permute(uint32_t value, uint32_t byte_addr) {
-  return (uint32_t)__builtin_amdgcn_ds_bpermute((int)byte_addr, (int)value);
-}
-__device__ __forceinline__ float permute(float value, uint32_t byte_addr) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute((int)byte_addr, __float_as_int(value)));
-}
-
-// Island next to (x, y) in direction q on the W x H torus:
-// 0 north (y-1), 1 east (x+1), 2 south (y+1), 3 west (x-1).
-__device__ __forceinline__ uint32_t torus_step(uint32_t x, uint32_t y, uint32_t q, uint32_t W,
-                                               uint32_t H) {
-  const uint32_t xe = (x + 1u == W) ? 0u : x + 1u;
-  const uint32_t xw = (x == 0u ? W : x) - 1u;
-  const uint32_t yn = (y == 0u ? H : y) - 1u;
-  const uint32_t ys = (y + 1u == H) ? 0u : y + 1u;
-  const uint32_t nx = q == 1u ? xe : (q == 3u ? xw : x);
-  const uint32_t ny = q == 0u ? yn : (q == 2u ? ys : y);
-  return ny * W + nx;
-}
-
-template <typename P>
-__device__ __forceinline__ P* at_byte(P* base, uint32_t byte_off) {
-  return reinterpret_cast<P*>(reinterpret_cast<char*>(base) + byte_off);
-}
-template <typename P>
-__device__ __forceinline__ const P* at_byte(const P* base, uint32_t byte_off) {
-  return reinterpret_cast<const P*>(reinterpret_cast<const char*>(base) + byte_off);
-}
-
-// Word accesses to the asynchronous buffers, which other wavefronts (on any
-// XCD) read and write while this one runs: relaxed atomics at device scope.
-// Each such access is coherent across the XCDs by itself (its scope bits send
-// it past the per-XCD L2's non-coherent state), so ordering two of them only
-// needs the first to have completed before the second issues: drain_memory()
-// waits for every memory access this wavefront has in flight. A device-scope
-// fence would do the same but also write back and invalidate the whole L2 of
-// the XCD, which under thousands of wavefronts streaming the population costs
-// far more than the exchange itself.
-__device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_agent(uint32_t* p, uint32_t value) {
-  __hip_atomic_store(p, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// Two words at once (8-byte aligned), for entries whose stability the
-// exchange protocol already guarantees while they are read.
-__device__ __forceinline__ uint2 load_agent2(const uint32_t* p) {
-  const uint64_t x = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-  return make_uint2((uint32_t)x, (uint32_t)(x >> 32));
-}
-__device__ __forceinline__ void store_agent2(uint32_t* p, uint32_t lo, uint32_t hi) {
-  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), ((uint64_t)hi << 32) | lo, __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void drain_memory() {
-  // also a compiler barrier: no memory access moves across it
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-}
 
 // Buffer of island i toward direction d for sending generations of parity p
 // in the asynchronous mail plane, and island i's lockstep header there. Offsets
@@ -214,12 +39,6 @@ __device__ __forceinline__ P* lock_header(P* lock, uint32_t i, uint32_t d, uint3
                                           uint32_t island_stride) {
   return lock + (size_t)(p * 4u + d) * island_stride + i;
 }
-
-struct Genome {
-  float f = 0.f;
-  uint32_t T = 0, D0 = 0, D1 = 0;
-  uint32_t P0 = 0, P1 = 0;  // string of a genome model (models 1 and 2)
-};
 
 __device__ __forceinline__ Genome load_genome(const float* pf, const uint32_t* pT,
                                               const uint32_t* pD0, const uint32_t* pD1,
@@ -237,29 +56,6 @@ __device__ __forceinline__ Genome load_genome(const float* pf, const uint32_t* p
   return g;
 }
 
-// Genome models (the paper's kernel serves any fixed-length genome through
-// initialize, mutate and evaluate, Sec. 2 Methods). Model 0: the genome is its
-// fitness value, mutated directly. Models 1 and 2: a 64-bit string (words P0,
-// P1; bit b is bit b % 32 of word b / 32); founders draw it from the sampling
-// stream at generation 2^64 - 1; mutation flips bit (w3 mod 64); the fitness
-// is re-evaluated after each flip:
-//   1 OneMax: the number of one bits;
-//   2 Trap-4 (Deb and Goldberg's deceptive trap of order 4): 16 four-bit
-//     blocks, a block with u one bits scoring 4 if u = 4, else 3 - u. The sum
-//     is 48 - ones + 5 * (blocks with all four bits set).
-constexpr int kModelFitness = 0;
-constexpr int kModelOneMax = 1;
-constexpr int kModelTrap4 = 2;
-
-template <int MODEL>
-__device__ __forceinline__ float evaluate_string(uint32_t p0, uint32_t p1) {
-  const uint32_t ones = __popc(p0) + __popc(p1);
-  if (MODEL == kModelOneMax) return (float)ones;
-  const uint32_t full0 = p0 & (p0 >> 1) & (p0 >> 2) & (p0 >> 3) & 0x11111111u;
-  const uint32_t full1 = p1 & (p1 >> 1) & (p1 >> 2) & (p1 >> 3) & 0x11111111u;
-  return (float)(48u - ones + 5u * (__popc(full0) + __popc(full1)));
-}
-
 // Per-wavefront state of the asynchronous schedule.
 struct AsyncCtx {
   uint32_t lead;     // how many generations an island may run ahead of a neighbour
@@ -268,26 +64,18 @@ struct AsyncCtx {
 
 // One generation for islands [base, base + v.ipw) of a run, by one wavefront.
 // LC / SWC: log2 N and surface words fixed at compile time, or -1 to read them
-// from the view. MODEL: the genome model. `lds` is this wavefront's table of
-// 5 * ipw + 1 entries (16 bytes for model 0, 32 with a string): arrivals
+// from the view. Model: the genome model. `lds` is this wavefront's table of
+// 5 * ipw + 1 entries (16 bytes, 32 for a model with a string): arrivals
 // [4 * local + q], emissions [4 * ipw + local], and one scratch entry read when
 // a lane has no arrival.
-template <int LC, int SWC, bool ASYNC = false, int MODEL = kModelFitness, bool WIDE = false,
+template <int LC, int SWC, bool ASYNC = false, typename Model = FitnessModel, bool WIDE = false,
           bool LOCK = false>
 __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base, uint64_t t,
                                                  uint4* lds, AsyncCtx* ax = nullptr) {
-  constexpr bool kStr = MODEL != kModelFitness;  // genomes carry a string
-  constexpr uint32_t ES = kStr ? 2u : 1u;        // 16-byte units per LDS entry
+  constexpr bool kStr = Model::kString;      // genomes carry a string
+  constexpr uint32_t ES = kStr ? 2u : 1u;    // 16-byte units per LDS entry
   const uint32_t L = LC >= 0 ? (uint32_t)LC : v.log2n;
   const uint32_t SW = SWC >= 0 ? (uint32_t)SWC : v.words;
-  // surface: S = 2^s_log sites of 2^dlog-bit differentia under the steady
-  // policy; one bit on 32 or 64 sites is fixed at compile time, WIDE reads
-  // the width, the site count and the policy from the view
-  const uint32_t dlog = WIDE ? v.dlog : 0u;
-  const bool tilted = WIDE && v.policy == 1u;
-  const bool hybrid = WIDE && v.policy == 2u;
-  const uint32_t s_log = WIDE ? v.s_log : 4u + SW;
-  const uint32_t S = 1u << s_log;
   const uint32_t lane = __lane_id();
   const uint32_t N = 1u << L;
   const uint32_t per_iter = 64u >> L;  // islands per wavefront iteration
@@ -521,14 +309,11 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 
   // ---- iterations: lanes are agent slots ------------------------------------
-  const uint32_t slot = lane & (N - 1u);
+  const BreedLane bl = breed_lane<LC>(v, t);
+  const uint32_t slot = bl.slot;
   const uint32_t slot_bytes = slot * 0x01010101u;
-  const uint32_t lane0_addr = (lane & ~(N - 1u)) << 2;  // permute address of slot 0 of my island
   const uint32_t emit_base = 4u * v.ipw;
   const uint32_t scratch = 5u * v.ipw;
-  SelectStream sel, mut;
-  sel.init(slot, t_lo, t_hi4, v.seed, v.run_id, kStreamSelect);
-  if (v.law) mut.init(slot, t_lo, t_hi4, v.seed, v.run_id, kStreamMutate);
 
   // One iteration of loads stays in flight ahead of the compute. The wait
   // below settles the prologue loads once, so the loop body has no pending
@@ -542,8 +327,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     // HBM a second time
     const uint32_t next_off = it + 1u < n_iter ? off + 256u : off;
     const Genome next = load_genome(pf, pT, pD0, pD1, pP0, pP1, next_off, SW, kStr);
-    float f = g.f;
-    uint32_t T = g.T, D0 = g.D0, D1 = g.D1, P0 = g.P0, P1 = g.P1;
+    Genome cur = g;
     const uint32_t local = it * per_iter + (lane >> L);
     const uint32_t island = base + local;
 
@@ -559,131 +343,33 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
       const uint32_t q = (31u - __clz(z | 1u)) >> 3;
       const uint32_t at = (z ? local * 4u + q : scratch) * ES;
       const uint4 a = lds[at];
-      f = z ? __uint_as_float(a.x) : f;
-      T = z ? a.y : T;
-      D0 = z ? a.z : D0;
-      D1 = z ? a.w : D1;
+      cur.f = z ? __uint_as_float(a.x) : cur.f;
+      cur.T = z ? a.y : cur.T;
+      cur.D0 = z ? a.z : cur.D0;
+      cur.D1 = z ? a.w : cur.D1;
       if (kStr) {
         const uint4 b = lds[at + 1u];
-        P0 = z ? b.x : P0;
-        P1 = z ? b.y : P1;
+        cur.P0 = z ? b.x : cur.P0;
+        cur.P1 = z ? b.y : cur.P1;
       }
     }
 
     // 2. the lane holding the island's drawn emigrant parks it in LDS
     if ((permute(emit, local << 2) & 0xFFu) == slot) {
-      lds[(emit_base + local) * ES] = make_uint4(__float_as_uint(f), T, D0, D1);
-      if (kStr) lds[(emit_base + local) * ES + 1u] = make_uint4(P0, P1, 0u, 0u);
+      lds[(emit_base + local) * ES] = make_uint4(__float_as_uint(cur.f), cur.T, cur.D0, cur.D1);
+      if (kStr) lds[(emit_base + local) * ES + 1u] = make_uint4(cur.P0, cur.P1, 0u, 0u);
     }
 
-    // 3-5. evaluate (read fitness) and run the tournament over permuted entrants
-    const Block r = sel.block(island);
-    uint32_t best = lane0_addr + (((r.x & 0xFFu) >> (8u - L)) << 2);
-    float fbest = permute(f, best);
-    if (v.selection) {
-#pragma unroll
-      for (uint32_t m = 1; m < 8; ++m) {
-        if (m < v.k) {
-          const uint32_t byte = ((m < 4 ? r.x : r.y) >> (8u * (m & 3u))) & 0xFFu;
-          const uint32_t cand = lane0_addr + ((byte >> (8u - L)) << 2);
-          const float fc = permute(f, cand);
-          if (fc > fbest) {
-            best = cand;
-            fbest = fc;
-          }
-        }
-      }
-    }
-    uint32_t cT = permute(T, best);
-    uint32_t cD0 = permute(D0, best);
-    uint32_t cD1 = SW > 1 ? permute(D1, best) : 0u;
-    uint32_t cP0 = kStr ? permute(P0, best) : 0u;
-    uint32_t cP1 = kStr ? permute(P1, best) : 0u;
-    float cfit = fbest;
+    // 3-7. tournament, copy, mutation, deposit
+    const Genome c = breed<LC, SWC, Model, WIDE>(v, bl, cur, island);
 
-    // 6. mutation: delta index (w & 0x7FFFFFFF) * 5 >> 31 = hi32((w & 0x7FFFFFFF) * 10)
-    //    maps 0..4 to {-1, -1/2, 0, 1/2, 1}
-    if constexpr (kStr) {
-      if (r.z < v.p32) {
-        const uint32_t bit = r.w & 63u;
-        const uint32_t mask = 1u << (bit & 31u);
-        cP0 ^= bit < 32u ? mask : 0u;
-        cP1 ^= bit < 32u ? 0u : mask;
-        cfit = evaluate_string<MODEL>(cP0, cP1);
-      }
-    } else if (v.law == 0) {
-      if (r.z < v.p32) {
-        // di * 0.5 is exact, so a fused multiply-add rounds like the plain add
-        const int di = (int)__umulhi(r.w & 0x7FFFFFFFu, 10u) - 2;  // -2..2
-        cfit = __fadd_rn(cfit, (float)di * 0.5f);
-      }
-    } else {
-      // treatments: beneficial iff draw < p_ben, deleterious iff below p_any;
-      // size |Z|, Z the variance-matched sum of eight uniform 16-bit halves
-      const bool ben = r.z < v.p_ben;
-      const bool del = !ben && r.z < v.p_any;
-      if (ben || del) {
-        const Block m = mut.block(island);
-        const uint32_t sum = (m.x & 0xFFFFu) + (m.x >> 16) + (m.y & 0xFFFFu) + (m.y >> 16) +
-                             (m.z & 0xFFFFu) + (m.z >> 16) + (m.w & 0xFFFFu) + (m.w >> 16);
-        const float size = fabsf(__fmul_rn((float)((int)sum - 262140), 0x1.3988e2p-16f));
-        cfit = ben ? __fadd_rn(cfit, size) : __fsub_rn(cfit, size);
-      }
-    }
-
-    // 7. stratum deposit at rank T, then T + 1. The hybrid policy sends even
-    //    ranks 2q to a 32-site steady half (sites 0..31) and odd ranks 2q + 1
-    //    to a 32-site tilted half (sites 32..63), each as its rank q.
-    uint32_t q = cT, q_log = s_log, site_base = 0u;
-    bool on_tilted = tilted;
-    if (hybrid) {
-      q = cT >> 1;
-      q_log = 5u;
-      on_tilted = (cT & 1u) != 0u;
-      site_base = on_tilted ? 32u : 0u;
-    }
-    uint32_t site = q;
-    bool write = true;
-    if (on_tilted) {
-      // level k = trailing zeros of q (capped at 31; q = 0 counts as 31), slot
-      // (q >> (k+1)) mod m ((q >> 31) mod m on level 31), m = sites / 32
-      const uint32_t m_log = q_log - 5u;
-      const uint32_t k = q ? min((uint32_t)__ffs(q) - 1u, 31u) : 31u;
-      const uint32_t ring = (k < 31u ? q >> (k + 1u) : q >> 31) & ((1u << m_log) - 1u);
-      site = (k << m_log) + ring;
-    } else if (q >= (1u << q_log)) {
-      const uint32_t e = (32u - __clz(q)) - q_log;
-      write = (q & ((1u << e) - 1u)) == 0u;
-      if (write) site = surface_site_walk(q, e, q_log);
-    }
-    site += site_base;
-    if (write) {
-      // the differentia: one bit, the top bit of the selection block's w3;
-      // b = 2^dlog > 1 bits, the top b bits of word 0 of a block of their own
-      // (mutation stream, counter word 0 = slot + 256), drawn only by the
-      // lanes that write
-      const uint32_t pos = site << dlog;
-      uint32_t value = r.w >> 31;
-      if (WIDE && dlog != 0u)
-        value = philox10(slot + 256u, island, t_lo, t_hi4 | kStreamMutate, v.seed, v.run_id).x >>
-                (32u - (1u << dlog));
-      const uint32_t field = ((2u << ((1u << dlog) - 1u)) - 1u) << (pos & 31u);
-      const uint32_t bits = value << (pos & 31u);
-      if (SW == 1 || pos < 32u) {
-        cD0 = (cD0 & ~field) | bits;
-      } else {
-        cD1 = (cD1 & ~field) | bits;
-      }
-    }
-    cT += 1u;
-
-    *at_byte(pf, off) = cfit;
-    *at_byte(pT, off) = cT;
-    *at_byte(pD0, off) = cD0;
-    if (SW > 1) *at_byte(pD1, off) = cD1;
+    *at_byte(pf, off) = c.f;
+    *at_byte(pT, off) = c.T;
+    *at_byte(pD0, off) = c.D0;
+    if (SW > 1) *at_byte(pD1, off) = c.D1;
     if (kStr) {
-      *at_byte(pP0, off) = cP0;
-      *at_byte(pP1, off) = cP1;
+      *at_byte(pP0, off) = c.P0;
+      *at_byte(pP1, off) = c.P1;
     }
 
     off += 256u;
@@ -785,53 +471,34 @@ __device__ __forceinline__ uint4* wave_lds(uint32_t wave_in_group, uint32_t ipw,
   return ga_lds + wave_in_group * lds_entries(ipw) * units;
 }
 
-// The dispatcher hands workgroups to the eight XCDs in turn (group g to XCD
-// g mod 8), each XCD with its own L2. Renumbering the groups so that every XCD
-// takes one contiguous band of the grid keeps an island's four neighbours, and
-// the outbox entries it reads from them, mostly on its own XCD.
-__device__ __forceinline__ uint32_t xcd_band_group() {
-  const uint32_t g = blockIdx.x, n = gridDim.x;
-  const uint32_t x = g & 7u, q = n >> 3, r = n & 7u;
-  return (x < r ? x * (q + 1u) : r * (q + 1u) + (x - r) * q) + (g >> 3);
-}
-
-template <int LC, int SWC, int MODEL, bool WIDE>
+template <int LC, int SWC, typename Model, bool WIDE>
 __global__ __launch_bounds__(1024) void generation_kernel(RunView v, uint32_t gen_offset) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t wave = xcd_band_group() * (blockDim.x >> 6) + wig;
   const uint32_t base = wave * v.ipw;
   if (base >= v.islands) return;
-  chunk_generation<LC, SWC, false, MODEL, WIDE>(v, base, *v.gen + gen_offset,
-                                                wave_lds(wig, v.ipw, MODEL ? 2u : 1u));
+  chunk_generation<LC, SWC, false, Model, WIDE>(v, base, *v.gen + gen_offset,
+                                                wave_lds(wig, v.ipw, Model::kString ? 2u : 1u));
 }
 
-// Whole run in one workgroup: the generation loop stays on the GPU, with a
-// workgroup barrier between generations (the outbox hand-over).
-template <int LC, int SWC, int MODEL, bool WIDE>
-__global__ __launch_bounds__(1024) void resident_kernel(RunView v, uint64_t n_gens) {
-  const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t base = wig * v.ipw;
-  const uint64_t t0 = *v.gen;
-  uint4* lds = wave_lds(wig, v.ipw, MODEL ? 2u : 1u);
-  for (uint64_t g = 0; g < n_gens; ++g) {
-    if (base < v.islands) chunk_generation<LC, SWC, false, MODEL, WIDE>(v, base, t0 + g, lds);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *v.gen = t0 + n_gens;
-}
-
-// Founders of a genome model with a string: words 0 and 1 of the sampling
-// stream's block at generation 2^64 - 1 for (slot, island), and their fitness.
-template <int MODEL>
-__global__ void strings_init_kernel(RunView v) {
+// Founders of a genome model that draws them (the initialize function): its
+// initialize from the (slot, island) block of the sampling stream at
+// generation 2^64 - 1, which no generation reaches.
+template <typename Model>
+__global__ void init_kernel(RunView v) {
   const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= v.agents) return;
   const uint32_t island = a >> v.log2n, slot = a & ((1u << v.log2n) - 1u);
   const Block b = philox10(slot, island, 0xFFFFFFFFu, 0xFFFFFFFCu | kStreamSample, v.seed,
                            v.run_id);
-  v.pop_P[a] = b.x;
-  v.pop_P[v.agent_stride + a] = b.y;
-  v.pop_f[a] = evaluate_string<MODEL>(b.x, b.y);
+  Genome g;
+  g.f = v.pop_f[a];
+  Model::initialize(g, b);
+  v.pop_f[a] = g.f;
+  if (Model::kString) {
+    v.pop_P[a] = g.P0;
+    v.pop_P[v.agent_stride + a] = g.P1;
+  }
 }
 
 // Asynchronous schedule: each wavefront owns `chunks` consecutive chunks and
@@ -846,7 +513,7 @@ __global__ void strings_init_kernel(RunView v) {
 // skew generations apart.
 // eight wavefronts per SIMD: registers (scalar ones included) must fit, or the
 // occupancy query would promise more resident wavefronts than the GPU holds
-template <int LC, int SWC, int MODEL, bool WIDE>
+template <int LC, int SWC, typename Model, bool WIDE>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, uint32_t skew) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -855,13 +522,13 @@ void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, ui
   if (first >= v.islands) return;
   const uint32_t end = min(first + chunks * v.ipw, v.islands);
   const uint64_t t0 = *v.gen;
-  uint4* lds = wave_lds(wig, v.ipw, MODEL ? 2u : 1u);
+  uint4* lds = wave_lds(wig, v.ipw, Model::kString ? 2u : 1u);
   AsyncCtx ax{lead, 0u};
   for (uint64_t step = 0; step < n_gens + skew; ++step) {
     for (uint32_t base = first; base < end; base += v.ipw) {
       const uint64_t lag = skew ? (base / v.ipw) % (skew + 1u) : 0u;
       if (step < lag || step - lag >= n_gens) continue;
-      chunk_generation<LC, SWC, true, MODEL, WIDE>(v, base, t0 + step - lag, lds, &ax);
+      chunk_generation<LC, SWC, true, Model, WIDE>(v, base, t0 + step - lag, lds, &ax);
     }
   }
   if (__lane_id() == 0u && ax.gave_up)
@@ -872,7 +539,7 @@ void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, ui
 // The asynchronous schedule with no lead and no skew: the lockstep exchange
 // (same results as the synchronous schedule while no wait gives up), each
 // wavefront over its `chunks` consecutive chunks as in async_kernel.
-template <int LC, int SWC, int MODEL, bool WIDE>
+template <int LC, int SWC, typename Model, bool WIDE>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 void lockstep_kernel(RunView v, uint32_t chunks, uint64_t n_gens) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -881,11 +548,11 @@ void lockstep_kernel(RunView v, uint32_t chunks, uint64_t n_gens) {
   if (first >= v.islands) return;
   const uint32_t end = min(first + chunks * v.ipw, v.islands);
   const uint64_t t0 = *v.gen;
-  uint4* lds = wave_lds(wig, v.ipw, MODEL ? 2u : 1u);
+  uint4* lds = wave_lds(wig, v.ipw, Model::kString ? 2u : 1u);
   AsyncCtx ax{0u, 0u};
   for (uint64_t step = 0; step < n_gens; ++step)
     for (uint32_t base = first; base < end; base += v.ipw)
-      chunk_generation<LC, SWC, true, MODEL, WIDE, true>(v, base, t0 + step, lds, &ax);
+      chunk_generation<LC, SWC, true, Model, WIDE, true>(v, base, t0 + step, lds, &ax);
   if (__lane_id() == 0u && ax.gave_up)
     __hip_atomic_fetch_add(v.waits, (unsigned long long)ax.gave_up, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -906,7 +573,7 @@ __global__ void lockstep_prologue_kernel(RunView v, uint32_t t0) {
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= (size_t)v.islands * 4u) return;
   const uint32_t i = (uint32_t)(k >> 2), q = (uint32_t)k & 3u, d = q ^ 2u, p = (t0 & 1u) ^ 1u;
-  const uint32_t ob_hdr = v.model ? 6u : 2u + v.words;
+  const uint32_t ob_hdr = model_has_string(v.model) ? 6u : 2u + v.words;
   const uint32_t j = torus_step(i % v.width, i / v.width, q, v.width, v.height);
   uint32_t* read = mail_entry(v.mail, j, d, p, v.ob_stride);
   const uint32_t* other = mail_entry(v.mail, j, d, p ^ 1u, v.ob_stride);
@@ -917,17 +584,6 @@ __global__ void lockstep_prologue_kernel(RunView v, uint32_t t0) {
   if (e1 && (!e0 || (int32_t)(s1 - s0) > 0))
     for (uint32_t w = 0; w < v.ob_stride; ++w) read[w] = other[w];
   *lock_header(v.lock, j, d, p, v.island_stride) = (e0 || e1) ? due : due + 1u;
-}
-
-template <int LC, int SWC, int MODEL, bool WIDE>
-hipError_t async_occupancy(int* groups, int block, size_t lds) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, async_kernel<LC, SWC, MODEL, WIDE>,
-                                                      block, lds);
-}
-template <int LC, int SWC, int MODEL, bool WIDE>
-hipError_t lockstep_occupancy(int* groups, int block, size_t lds) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, lockstep_kernel<LC, SWC, MODEL, WIDE>,
-                                                      block, lds);
 }
 
 __global__ void advance_kernel(unsigned long long* gen, uint64_t n) {
@@ -1030,41 +686,8 @@ __global__ void batch_advance_kernel(const RunView* views, uint32_t n_runs, uint
 }  // namespace
 
 size_t lds_bytes(uint32_t ipw, uint32_t waves, uint32_t model) {
-  return (5u * ipw + 1u) * sizeof(uint4) * (model ? 2u : 1u) * waves;
+  return (5u * ipw + 1u) * sizeof(uint4) * (model_has_string(model) ? 2u : 1u) * waves;
 }
-
-#define GA_SHAPES(KERNEL, M, WD, L, SW, ...)                                   \
-  switch ((L) * 2 + ((SW) - 1)) {                                              \
-    case 0: KERNEL<0, 1, M, WD> __VA_ARGS__; break;                            \
-    case 1: KERNEL<0, 2, M, WD> __VA_ARGS__; break;                            \
-    case 2: KERNEL<1, 1, M, WD> __VA_ARGS__; break;                            \
-    case 3: KERNEL<1, 2, M, WD> __VA_ARGS__; break;                            \
-    case 4: KERNEL<2, 1, M, WD> __VA_ARGS__; break;                            \
-    case 5: KERNEL<2, 2, M, WD> __VA_ARGS__; break;                            \
-    case 6: KERNEL<3, 1, M, WD> __VA_ARGS__; break;                            \
-    case 7: KERNEL<3, 2, M, WD> __VA_ARGS__; break;                            \
-    case 8: KERNEL<4, 1, M, WD> __VA_ARGS__; break;                            \
-    case 9: KERNEL<4, 2, M, WD> __VA_ARGS__; break;                            \
-    case 10: KERNEL<5, 1, M, WD> __VA_ARGS__; break;                           \
-    case 11: KERNEL<5, 2, M, WD> __VA_ARGS__; break;                           \
-    case 12: KERNEL<6, 1, M, WD> __VA_ARGS__; break;                           \
-    case 13: KERNEL<6, 2, M, WD> __VA_ARGS__; break;                           \
-    default: return hipErrorInvalidValue;                                      \
-  }
-
-// Dispatch to KERNEL<log2 N, surface words, genome model, wide differentia>.
-#define GA_DISPATCH(KERNEL, L, SW, M, WIDE, ...)                               \
-  do {                                                                         \
-    switch ((M) * 2 + ((WIDE) ? 1 : 0)) {                                      \
-      case 0: GA_SHAPES(KERNEL, 0, false, L, SW, __VA_ARGS__) break;           \
-      case 1: GA_SHAPES(KERNEL, 0, true, L, SW, __VA_ARGS__) break;            \
-      case 2: GA_SHAPES(KERNEL, 1, false, L, SW, __VA_ARGS__) break;           \
-      case 3: GA_SHAPES(KERNEL, 1, true, L, SW, __VA_ARGS__) break;            \
-      case 4: GA_SHAPES(KERNEL, 2, false, L, SW, __VA_ARGS__) break;           \
-      case 5: GA_SHAPES(KERNEL, 2, true, L, SW, __VA_ARGS__) break;            \
-      default: return hipErrorInvalidValue;                                    \
-    }                                                                          \
-  } while (0)
 
 hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t waves,
                              uint32_t waves_per_group, hipStream_t stream) {
@@ -1072,18 +695,10 @@ hipError_t launch_generation(const RunView& v, uint32_t gen_offset, uint32_t wav
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
   const dim3 grid(groups), block(64 * waves_per_group);
   const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
-  GA_DISPATCH(generation_kernel, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
-              <<<grid, block, lds, stream>>>(v, gen_offset));
-  return hipGetLastError();
-}
-
-hipError_t launch_resident(const RunView& v, uint64_t n_gens, uint32_t waves, hipStream_t stream) {
-  if (waves == 0 || waves > (uint32_t)kMaxWavesPerGroup) return hipErrorInvalidValue;
-  const dim3 grid(1), block(64 * waves);
-  const size_t lds = lds_bytes(v.ipw, waves, v.model);
-  GA_DISPATCH(resident_kernel, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
-              <<<grid, block, lds, stream>>>(v, n_gens));
-  return hipGetLastError();
+  return dispatch(v, [&](auto LC, auto SWC, auto M, auto WD) {
+    generation_kernel<GA_SHAPE_ARGS(LC, SWC, M, WD)><<<grid, block, lds, stream>>>(v, gen_offset);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint32_t chunks,
@@ -1093,9 +708,11 @@ hipError_t launch_async(const RunView& v, uint64_t n_gens, uint32_t waves, uint3
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
   const dim3 grid(groups), block(64 * waves_per_group);
   const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
-  GA_DISPATCH(async_kernel, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
-              <<<grid, block, lds, stream>>>(v, chunks, n_gens, lead, skew));
-  return hipGetLastError();
+  return dispatch(v, [&](auto LC, auto SWC, auto M, auto WD) {
+    async_kernel<GA_SHAPE_ARGS(LC, SWC, M, WD)><<<grid, block, lds, stream>>>(v, chunks, n_gens,
+                                                                           lead, skew);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_lockstep(const RunView& v, uint64_t gen, uint64_t n_gens, uint32_t waves,
@@ -1109,9 +726,10 @@ hipError_t launch_lockstep(const RunView& v, uint64_t gen, uint64_t n_gens, uint
   const uint32_t groups = (waves + waves_per_group - 1) / waves_per_group;
   const dim3 grid(groups), block(64 * waves_per_group);
   const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
-  GA_DISPATCH(lockstep_kernel, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
-              <<<grid, block, lds, stream>>>(v, chunks, n_gens));
-  return hipGetLastError();
+  return dispatch(v, [&](auto LC, auto SWC, auto M, auto WD) {
+    lockstep_kernel<GA_SHAPE_ARGS(LC, SWC, M, WD)><<<grid, block, lds, stream>>>(v, chunks, n_gens);
+    return hipGetLastError();
+  });
 }
 
 hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, bool lockstep,
@@ -1122,25 +740,32 @@ hipError_t async_capacity(const RunView& v, uint32_t waves_per_group, bool locks
   if (e != hipSuccess) return e;
   const int block = 64 * (int)waves_per_group;
   const size_t lds = lds_bytes(v.ipw, waves_per_group, v.model);
-  if (lockstep)
-    GA_DISPATCH(e = lockstep_occupancy, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
-                (&groups, block, lds));
-  else
-    GA_DISPATCH(e = async_occupancy, v.log2n, v.words, v.model, v.dlog != 0u || v.policy != 0u,
-                (&groups, block, lds));
+  e = dispatch(v, [&](auto LC, auto SWC, auto M, auto WD) {
+    return lockstep ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                          &groups, lockstep_kernel<GA_SHAPE_ARGS(LC, SWC, M, WD)>, block, lds)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                          &groups, async_kernel<GA_SHAPE_ARGS(LC, SWC, M, WD)>, block, lds);
+  });
   if (e != hipSuccess) return e;
   *waves = (uint32_t)groups * (uint32_t)cus * waves_per_group;
   return hipSuccess;
 }
 
-hipError_t launch_init_strings(const RunView& v, hipStream_t stream) {
+bool model_has_string_host(uint32_t id) { return model_has_string(id); }
+uint32_t model_count() { return kModelCount; }
+
+hipError_t launch_init(const RunView& v, hipStream_t stream) {
   if (v.agents == 0) return hipSuccess;
   const dim3 grid((v.agents + 255) / 256), block(256);
+#define GA_INIT_CASE(ID, M)                                \
+  case ID:                                                 \
+    init_kernel<M><<<grid, block, 0, stream>>>(v);         \
+    break;
   switch (v.model) {
-    case 1: strings_init_kernel<1><<<grid, block, 0, stream>>>(v); break;
-    case 2: strings_init_kernel<2><<<grid, block, 0, stream>>>(v); break;
+    GA_FOR_EACH_MODEL(GA_INIT_CASE)
     default: return hipErrorInvalidValue;
   }
+#undef GA_INIT_CASE
   return hipGetLastError();
 }
 

@@ -1,0 +1,336 @@
+// LDS-resident persistent form of the synchronous generation step.
+//
+// The torus is cut into tiles of tile_w x tile_h islands (ragged at the right
+// and bottom edges); one workgroup owns one tile for the whole launch and keeps
+// its population in LDS across generations, the way each processing element
+// of the paper's wafer-scale design keeps its island in local memory (Sec. 2
+// Methods). HBM then carries the population once at the start and once at the
+// end of a launch, and in between only the emissions of the islands on a
+// tile's edge (one outbox entry each per generation).
+//
+// Generation t in one workgroup, with the same results as the per-generation
+// streaming kernel (and the oracle):
+//   island pass   one thread per island: the migration draw; the four
+//                 neighbours' emissions of generation t-1 (LDS outbox for a
+//                 neighbour in the tile, the HBM outbox for one outside it);
+//                 arrivals written into their drawn slots of the LDS
+//                 population (later directions overwrite earlier ones); the
+//                 drawn emigrant (post-immigration) copied to the LDS outbox
+//                 of parity t&1 and, for an island with a neighbour outside
+//                 the tile, to the HBM outbox;
+//   publish       once every island-pass store has completed, the tile's
+//                 progress word becomes t+1: its emissions of t are readable
+//                 and it has finished reading its neighbours' emissions of t-1;
+//   iterations    lanes are agent slots, 64/N islands per wavefront
+//                 iteration, tournament / copy / mutation / deposit (`breed`)
+//                 in registers, children written back in place;
+//   wait          before the island pass of t+1, wavefront 0 waits until each
+//                 neighbouring tile's progress word reaches t+1.
+// The emissions of t are fixed by the island pass, before the iterations, so
+// a tile publishes them early and its neighbours' waits for generation t+1
+// overlap its iterations of t. The wait also guarantees that a neighbour has
+// finished reading the HBM outbox entries of parity (t+1)&1 (its island pass
+// of t) before this tile overwrites them in generation t+1.
+//
+// Every tile's workgroup must be resident at once (the host sizes the tiling
+// by the occupancy query); each wait is bounded, and a wait that gave up is
+// counted, which the host reports as an error when the state is read.
+#include "ga_device.hpp"
+
+namespace ga {
+namespace {
+
+extern __shared__ uint32_t tile_lds[];
+
+// LDS words of a tile: population planes (f, T, surface words, string words)
+// of TA agents each, the packed (x, y) table of TA / N islands, and the outbox
+// for both parities (TI entries of ob_stride words each).
+__host__ __device__ inline uint32_t tile_agents_padded(uint32_t ti_full, uint32_t log2n) {
+  return ((ti_full << log2n) + 63u) & ~63u;
+}
+__host__ __device__ inline uint32_t tile_planes(uint32_t words, bool strings) {
+  return 2u + words + (strings ? 2u : 0u);
+}
+// the (x, y) table, padded so the outbox after it is 16-byte aligned
+__host__ __device__ inline uint32_t tile_table_words(uint32_t ta, uint32_t log2n) {
+  return ((ta >> log2n) + 3u) & ~3u;
+}
+
+template <int LC, int SWC, typename Model, bool WIDE>
+__global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) {
+  constexpr uint32_t L = (uint32_t)LC;
+  constexpr uint32_t SW = (uint32_t)SWC;
+  constexpr uint32_t N = 1u << L;
+  constexpr bool kStr = Model::kString;
+  constexpr uint32_t kPlanes = 2u + SW + (kStr ? 2u : 0u);
+  const uint32_t tid = threadIdx.x, nthreads = blockDim.x;
+  const uint32_t lane = __lane_id();
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t nwaves = nthreads >> 6;
+
+  // this workgroup's tile and its actual extent
+  const uint32_t tile = xcd_band_group();
+  const uint32_t tx = tile % v.tiles_x, ty = tile / v.tiles_x;
+  const uint32_t x0 = tx * v.tile_w, y0 = ty * v.tile_h;
+  const uint32_t w = min(v.tile_w, v.width - x0), h = min(v.tile_h, v.height - y0);
+  const uint32_t ti = w * h;
+  const uint32_t TI = v.tile_w * v.tile_h;
+  const uint32_t TA = tile_agents_padded(TI, L);
+  const uint32_t TIP = TA >> L;  // islands covered by whole iterations
+  // words per outbox entry (f, T, surface, header; with a string f, T, D0,
+  // D1, P0, P1, header) and the header's word, as in the HBM outbox
+  constexpr uint32_t obs = (SW == 1 && !kStr) ? 4u : 8u;
+  constexpr uint32_t ob_hdr = kStr ? 6u : 2u + SW;
+
+  uint32_t* lpl = tile_lds;                 // planes: [k * TA + a]
+  uint32_t* lxy = lpl + kPlanes * TA;       // [li]: x | y << 16
+  uint32_t* lob = lxy + tile_table_words(TA, L);  // [(p * TI + li) * obs + k]
+  auto plane = [&](uint32_t k) { return lpl + k * TA; };
+
+  // ---- load: island table, population, pending outbox ----------------------
+  for (uint32_t li = tid; li < TIP; li += nthreads) {
+    const uint32_t r = li < ti ? li : 0u;
+    const uint32_t ly = r / w, lx = r - ly * w;
+    lxy[li] = (x0 + lx) | ((y0 + ly) << 16);
+  }
+  __syncthreads();
+  const uint64_t t0 = *v.gen;
+  {
+    const uint32_t* gpl[6] = {reinterpret_cast<const uint32_t*>(v.pop_f), v.pop_T, v.pop_D,
+                              v.pop_D + v.agent_stride, v.pop_P, v.pop_P + v.agent_stride};
+    for (uint32_t la = tid; la < TA; la += nthreads) {
+      const uint32_t li = la >> L;
+      const uint32_t xy = lxy[li];
+      const uint32_t a = (((xy >> 16) * v.width + (xy & 0xFFFFu)) << L) + (la & (N - 1u));
+      const bool ok = li < ti;
+      plane(0)[la] = ok ? gpl[0][a] : 0u;
+      plane(1)[la] = ok ? gpl[1][a] : 0u;
+      plane(2)[la] = ok ? gpl[2][a] : 0u;
+      if (SW > 1) plane(3)[la] = ok ? gpl[3][a] : 0u;
+      if (kStr) {
+        plane(2 + SW)[la] = ok ? gpl[4][a] : 0u;
+        plane(3 + SW)[la] = ok ? gpl[5][a] : 0u;
+      }
+    }
+    const uint32_t p_in = ((uint32_t)t0 & 1u) ^ 1u;
+    const uint32_t* gob = v.ob[p_in];
+    for (uint32_t k = tid; k < ti * obs; k += nthreads) {
+      const uint32_t li = k / obs, j = k - li * obs;
+      const uint32_t xy = lxy[li];
+      const uint32_t island = (xy >> 16) * v.width + (xy & 0xFFFFu);
+      lob[(p_in * TI + li) * obs + j] = gob[(size_t)island * obs + j];
+    }
+  }
+  __syncthreads();
+
+  // neighbouring tiles this one waits on (lanes 0..3 of wavefront 0: N, E, S, W)
+  uint32_t nb_tile = tile;
+  if (lane < 4u) {
+    const uint32_t gx = v.tiles_x, gy = v.tiles_y;
+    const uint32_t ntx = lane == 1u ? (tx + 1u == gx ? 0u : tx + 1u)
+                                    : (lane == 3u ? (tx == 0u ? gx : tx) - 1u : tx);
+    const uint32_t nty = lane == 2u ? (ty + 1u == gy ? 0u : ty + 1u)
+                                    : (lane == 0u ? (ty == 0u ? gy : ty) - 1u : ty);
+    nb_tile = nty * gx + ntx;
+  }
+  const bool waits_on = lane < 4u && nb_tile != tile;
+  uint32_t gave_up = 0u;
+
+  for (uint64_t g = 0; g < n_gens; ++g) {
+    const uint64_t t = t0 + g;
+    const uint32_t t_lo = (uint32_t)t;
+    const uint32_t t_hi4 = (uint32_t)(t >> 32) << 2;
+    const uint32_t p_out = t_lo & 1u, p_in = p_out ^ 1u;
+    const uint32_t* __restrict__ in_ob = v.ob[p_in];
+    uint32_t* __restrict__ out_ob = v.ob[p_out];
+
+    // ---- island pass --------------------------------------------------------
+    for (uint32_t li = tid; li < ti; li += nthreads) {
+      const uint32_t xy = lxy[li];
+      const uint32_t x = xy & 0xFFFFu, y = xy >> 16;
+      const uint32_t island = y * v.width + x;
+      const Block mig = philox10(0u, island, t_lo, t_hi4 | kStreamMigrate, v.seed, v.run_id);
+      const uint32_t emig = L ? (mig.x >> (32u - L)) : 0u;
+      bool edge = false;
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        uint32_t nx, ny;
+        torus_xy(x, y, q, v.width, v.height, &nx, &ny);
+        const bool inside = nx - x0 < w && ny - y0 < h;
+        edge |= !inside;
+        uint32_t e[8];
+        if (inside) {
+          const uint4* src =
+              reinterpret_cast<const uint4*>(lob + (p_in * TI + (ny - y0) * w + (nx - x0)) * obs);
+#pragma unroll
+          for (uint32_t k = 0; k < obs; k += 4) {
+            const uint4 u = src[k >> 2];
+            e[k] = u.x;
+            e[k + 1] = u.y;
+            e[k + 2] = u.z;
+            e[k + 3] = u.w;
+          }
+        } else {
+          const uint32_t* src = in_ob + (size_t)(ny * v.width + nx) * obs;
+#pragma unroll
+          for (uint32_t k = 0; k < 8; k += 2)
+            if (k < obs) {
+              const uint2 two = load_agent2(src + k);
+              e[k] = two.x;
+              e[k + 1] = two.y;
+            }
+        }
+        if (e[ob_hdr] == (kMetaValid | (q ^ 2u))) {
+          const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
+          const uint32_t a = (li << L) + slot;
+          plane(0)[a] = e[0];
+          plane(1)[a] = e[1];
+          plane(2)[a] = e[2];
+          if (SW > 1) plane(3)[a] = e[3];
+          if (kStr) {
+            plane(2 + SW)[a] = e[4];
+            plane(3 + SW)[a] = e[5];
+          }
+        }
+      }
+      // the emission: the drawn member after immigration
+      uint32_t o[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+      const uint32_t a = (li << L) + emig;
+      o[0] = plane(0)[a];
+      o[1] = plane(1)[a];
+      o[2] = plane(2)[a];
+      if (SW > 1) o[3] = plane(3)[a];
+      if (kStr) {
+        o[4] = plane(2 + SW)[a];
+        o[5] = plane(3 + SW)[a];
+      }
+      o[ob_hdr] = v.migration ? (kMetaValid | (mig.y >> 30)) : 0u;
+      uint4* dst = reinterpret_cast<uint4*>(lob + (p_out * TI + li) * obs);
+#pragma unroll
+      for (uint32_t k = 0; k < obs; k += 4) dst[k >> 2] = make_uint4(o[k], o[k + 1], o[k + 2], o[k + 3]);
+      if (edge) {
+        uint32_t* gdst = out_ob + (size_t)island * obs;
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k += 2)
+          if (k < obs) store_agent2(gdst + k, o[k], o[k + 1]);
+      }
+    }
+    // publish: every store of the island pass has completed
+    drain_memory();
+    __syncthreads();
+    if (tid == 0u) store_agent(v.prog + tile, t_lo + 1u);
+
+    // ---- iterations: lanes are agent slots ----------------------------------
+    const BreedLane bl = breed_lane<LC>(v, t);
+    for (uint32_t it = wave; it < (TA >> 6); it += nwaves) {
+      const uint32_t la = (it << 6) + lane;
+      const uint32_t li = la >> L;
+      const uint32_t xy = lxy[li];
+      const uint32_t island = (xy >> 16) * v.width + (xy & 0xFFFFu);
+      Genome gn;
+      gn.f = __uint_as_float(plane(0)[la]);
+      gn.T = plane(1)[la];
+      gn.D0 = plane(2)[la];
+      if (SW > 1) gn.D1 = plane(3)[la];
+      if (kStr) {
+        gn.P0 = plane(2 + SW)[la];
+        gn.P1 = plane(3 + SW)[la];
+      }
+      const Genome c = breed<LC, SWC, Model, WIDE>(v, bl, gn, island);
+      if (li < ti) {
+        plane(0)[la] = __float_as_uint(c.f);
+        plane(1)[la] = c.T;
+        plane(2)[la] = c.D0;
+        if (SW > 1) plane(3)[la] = c.D1;
+        if (kStr) {
+          plane(2 + SW)[la] = c.P0;
+          plane(3 + SW)[la] = c.P1;
+        }
+      }
+    }
+
+    // ---- wait for the neighbouring tiles' island pass of t + 1 -------------
+    if (wave == 0u && g + 1u < n_gens) {
+      const uint32_t due = t_lo + 1u;
+      for (uint32_t spin = 0;; ++spin) {
+        bool behind = false;
+        if (waits_on) behind = (int32_t)(load_agent(v.prog + nb_tile) - due) < 0;
+        if (__ballot(behind) == 0ull) break;
+        if (spin == kLockSpins) {
+          ++gave_up;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- store: population and the last generation's outbox -------------------
+  {
+    uint32_t* gpl[6] = {reinterpret_cast<uint32_t*>(v.pop_f), v.pop_T, v.pop_D,
+                        v.pop_D + v.agent_stride, v.pop_P, v.pop_P + v.agent_stride};
+    for (uint32_t la = tid; la < (ti << L); la += nthreads) {
+      const uint32_t li = la >> L;
+      const uint32_t xy = lxy[li];
+      const uint32_t a = (((xy >> 16) * v.width + (xy & 0xFFFFu)) << L) + (la & (N - 1u));
+      gpl[0][a] = plane(0)[la];
+      gpl[1][a] = plane(1)[la];
+      gpl[2][a] = plane(2)[la];
+      if (SW > 1) gpl[3][a] = plane(3)[la];
+      if (kStr) {
+        gpl[4][a] = plane(2 + SW)[la];
+        gpl[5][a] = plane(3 + SW)[la];
+      }
+    }
+    if (n_gens > 0) {
+      const uint32_t p_last = (uint32_t)(t0 + n_gens - 1u) & 1u;
+      uint32_t* gob = v.ob[p_last];
+      for (uint32_t k = tid; k < ti * obs; k += nthreads) {
+        const uint32_t li = k / obs, j = k - li * obs;
+        const uint32_t xy = lxy[li];
+        const uint32_t island = (xy >> 16) * v.width + (xy & 0xFFFFu);
+        gob[(size_t)island * obs + j] = lob[(p_last * TI + li) * obs + j];
+      }
+    }
+  }
+  if (tid == 0u && gave_up)
+    __hip_atomic_fetch_add(v.waits, (unsigned long long)gave_up, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace
+
+size_t tile_lds_bytes(uint32_t tile_w, uint32_t tile_h, uint32_t log2n, uint32_t words,
+                      uint32_t model, uint32_t ob_stride) {
+  const uint32_t TI = tile_w * tile_h;
+  const uint32_t TA = tile_agents_padded(TI, log2n);
+  return 4u * ((size_t)tile_planes(words, model_has_string(model)) * TA +
+               tile_table_words(TA, log2n) + 2u * (size_t)TI * ob_stride);
+}
+
+uint32_t tile_threads(uint32_t tile_w, uint32_t tile_h, uint32_t log2n) {
+  const uint32_t iters = tile_agents_padded(tile_w * tile_h, log2n) >> 6;
+  return 64u * (iters < 16u ? iters : 16u);
+}
+
+hipError_t tile_occupancy(const RunView& v, uint32_t threads, size_t lds, int* groups_per_cu) {
+  return dispatch(v, [&](auto LC, auto SWC, auto M, auto WD) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        groups_per_cu, tile_kernel<GA_SHAPE_ARGS(LC, SWC, M, WD)>, (int)threads, lds);
+  });
+}
+
+hipError_t launch_tiles(const RunView& v, uint64_t n_gens, hipStream_t stream) {
+  if (n_gens == 0) return hipSuccess;
+  const uint32_t n_tiles = v.tiles_x * v.tiles_y;
+  const uint32_t threads = tile_threads(v.tile_w, v.tile_h, v.log2n);
+  const size_t lds = tile_lds_bytes(v.tile_w, v.tile_h, v.log2n, v.words, v.model, v.ob_stride);
+  return dispatch(v, [&](auto LC, auto SWC, auto M, auto WD) {
+    tile_kernel<GA_SHAPE_ARGS(LC, SWC, M, WD)><<<dim3(n_tiles), dim3(threads), lds, stream>>>(
+        v, n_gens);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace ga

@@ -92,6 +92,16 @@ class GARun:
     def set_graph_block(self, gens: int):
         check(load().ga_set_graph_block(self._h, gens))
 
+    def set_tiles(self, tile_w: int = 0, tile_h: int = 0):
+        """Tile shape of the LDS-resident form (0, 0: the library's choice)."""
+        check(load().ga_set_tiles(self._h, int(tile_w), int(tile_h)))
+
+    def tiles(self) -> tuple:
+        """(tile_w, tile_h, tiles) that ga_step uses; zeros for the streaming form."""
+        w, h, n = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        check(load().ga_get_tiles(self._h, ctypes.byref(w), ctypes.byref(h), ctypes.byref(n)))
+        return int(w.value), int(h.value), int(n.value)
+
     def set_async(self, max_wavefronts: int = 0, max_lead: int = 0, skew: int = 0):
         """Asynchronous runs: cap on wavefronts (0 = fill the GPU), how many
         generations an island may lead a neighbour (ASYNC_UNPACED = no bound),

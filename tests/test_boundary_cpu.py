@@ -41,7 +41,8 @@ def test_state_bytes_layout(lib):
     # Planes are padded to roundup(islands, 64) + 128 islands.
     # The asynchronous schedule has eight buffers (direction x parity), four
     # stamps, a progress word and eight lockstep headers per island instead of
-    # the two outboxes.
+    # the two outboxes; the synchronous one a progress word per resident-form
+    # tile (at most 8,192 tiles, never more than islands).
     def expect(c):
         I = (c["width"] * c["height"] + 63) // 64 * 64 + 128
         A = I * c["pop"]
@@ -55,7 +56,7 @@ def test_state_bytes_layout(lib):
             ob = 8
         exchange = ((al(4 * 8 * I * ob) + al(4 * 4 * I) + al(4 * I) + al(4 * 8 * I))
                     if c.get("schedule")
-                    else 2 * al(4 * I * ob))
+                    else 2 * al(4 * I * ob) + al(4 * min(8192, c["width"] * c["height"])))
         return (al(4 * A) * 2 + al(4 * A * W) + (al(4 * A * 2) if strings else 0) + exchange
                 + 256 + 2 * al(4 * I) + al(4 * I * W))
     for c in (TINY, MID, PAPER, run_config(width=3, height=5, pop=1, sites=32)):
