@@ -440,6 +440,22 @@ int ga_mrca_matrix_ex(const uint32_t* T, const uint32_t* surface_words, size_t n
                       uint32_t kc, void* workspace, size_t workspace_bytes, uint32_t* L,
                       uint32_t* U, void* hip_stream);
 
+/* ga_mrca_matrix_ex without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the steady policy's normalised surfaces
+ * go to a static device array inside the library (65,536 entries of 16 bytes:
+ * 1 MiB per GPU the library runs on, held until the process ends). Nothing is allocated and nothing needs clearing: every entry
+ * the call reads it has written first. All calls on one GPU share that array,
+ * so calls that overlap on one GPU (on different streams or host threads)
+ * race and must be serialised by the caller. The current device must be the
+ * one the pointers and the stream belong to. n <= 65,535 as for
+ * ga_mrca_matrix_ex (GA_EINVAL above, and for every argument that call
+ * rejects). Same results as ga_mrca_matrix_ex. */
+int ga_mrca_matrix_noalloc(const uint32_t* T, const uint32_t* surface_words, size_t n,
+                           uint32_t surface_sites, uint32_t differentia_bits,
+                           uint32_t surface_policy, uint32_t kc, uint32_t* L, uint32_t* U,
+                           void* hip_stream);
+
 /* Message for a return code, and the calling thread's last error message. */
 const char* ga_strerror(int code);
 const char* ga_last_error(void);

@@ -107,6 +107,7 @@ SIGNATURES = {
     "ga_mrca_workspace_bytes": (sz, [sz]),
     "ga_mrca_matrix": (i32, [P, P, sz, u32, u32, P, sz, P, P, P]),
     "ga_mrca_matrix_ex": (i32, [P, P, sz, u32, u32, u32, u32, P, sz, P, P, P]),
+    "ga_mrca_matrix_noalloc": (i32, [P, P, sz, u32, u32, u32, u32, P, P, P]),
     "ga_strerror": (ctypes.c_char_p, [i32]),
     "ga_last_error": (ctypes.c_char_p, []),
 }

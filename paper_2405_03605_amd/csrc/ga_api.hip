@@ -1324,11 +1324,12 @@ void ga_pool_destroy(ga_pool* p) {
 
 size_t ga_mrca_workspace_bytes(size_t n) { return ga::mrca_workspace_bytes(n); }
 
-int ga_mrca_matrix_ex(const uint32_t* T, const uint32_t* surface_words, size_t n,
-                      uint32_t surface_sites, uint32_t differentia_bits, uint32_t surface_policy,
-                      uint32_t kc, void* workspace, size_t workspace_bytes, uint32_t* L,
-                      uint32_t* U, void* hip_stream) {
-  if (n == 0) return GA_OK;
+namespace {
+
+// Argument checks shared by the relatedness calls.
+int mrca_args_ok(const uint32_t* T, const uint32_t* surface_words, size_t n,
+                 uint32_t surface_sites, uint32_t differentia_bits, uint32_t surface_policy,
+                 uint32_t kc, const uint32_t* L, const uint32_t* U) {
   if (n > 65535) return fail(GA_EINVAL, "n must be <= 65535");
   if (!surface_ok(surface_sites, differentia_bits))
     return fail(GA_EINVAL, "surface_sites x differentia_bits must be 32 or 64 bits");
@@ -1337,6 +1338,19 @@ int ga_mrca_matrix_ex(const uint32_t* T, const uint32_t* surface_words, size_t n
     return fail(GA_EINVAL, why);
   if (kc < 1) return fail(GA_EINVAL, "kc must be >= 1");
   if (!T || !surface_words || !L || !U) return fail(GA_EINVAL, "NULL pointer");
+  return GA_OK;
+}
+
+}  // namespace
+
+int ga_mrca_matrix_ex(const uint32_t* T, const uint32_t* surface_words, size_t n,
+                      uint32_t surface_sites, uint32_t differentia_bits, uint32_t surface_policy,
+                      uint32_t kc, void* workspace, size_t workspace_bytes, uint32_t* L,
+                      uint32_t* U, void* hip_stream) {
+  if (n == 0) return GA_OK;
+  const int rc = mrca_args_ok(T, surface_words, n, surface_sites, differentia_bits,
+                              surface_policy, kc, L, U);
+  if (rc != GA_OK) return rc;
   if (surface_policy == GA_POLICY_STEADY) {
     if (!workspace) return fail(GA_EINVAL, "NULL workspace");
     if (workspace_bytes < ga::mrca_workspace_bytes(n)) return fail(GA_ENOMEM, "workspace too small");
@@ -1345,6 +1359,23 @@ int ga_mrca_matrix_ex(const uint32_t* T, const uint32_t* surface_words, size_t n
                                 log2u(differentia_bits), surface_policy, kc, workspace, L, U,
                                 static_cast<hipStream_t>(hip_stream)),
          "mrca launch");
+  return GA_OK;
+}
+
+int ga_mrca_matrix_noalloc(const uint32_t* T, const uint32_t* surface_words, size_t n,
+                           uint32_t surface_sites, uint32_t differentia_bits,
+                           uint32_t surface_policy, uint32_t kc, uint32_t* L, uint32_t* U,
+                           void* hip_stream) {
+  if (n == 0) return GA_OK;
+  if (n > ga::kScratchSurfaces)
+    return fail(GA_EINVAL, "n exceeds the 65,536 surfaces of the static workspace");
+  const int rc = mrca_args_ok(T, surface_words, n, surface_sites, differentia_bits,
+                              surface_policy, kc, L, U);
+  if (rc != GA_OK) return rc;
+  GA_HIP(ga::launch_mrca_matrix_noalloc(T, surface_words, (uint32_t)n, log2u(surface_sites),
+                                        log2u(differentia_bits), surface_policy, kc, L, U,
+                                        static_cast<hipStream_t>(hip_stream)),
+         "mrca launch (static workspace)");
   return GA_OK;
 }
 

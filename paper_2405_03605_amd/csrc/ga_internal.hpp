@@ -127,6 +127,13 @@ hipError_t launch_batch_advance(const RunView* views, uint32_t n_runs, uint64_t 
                                 hipStream_t stream);
 
 size_t mrca_workspace_bytes(size_t n);
+// Most surfaces the allocation-free relatedness call takes (its workspace is a
+// static device array of this many normalised surfaces, 16 bytes each).
+constexpr uint32_t kScratchSurfaces = 65536;
+// launch_mrca_matrix with that static array as its workspace.
+hipError_t launch_mrca_matrix_noalloc(const uint32_t* T, const uint32_t* D, uint32_t n,
+                                      uint32_t s_log, uint32_t dlog, uint32_t policy, uint32_t kc,
+                                      uint32_t* L, uint32_t* U, hipStream_t stream);
 hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, uint32_t s_log,
                               uint32_t dlog, uint32_t policy, uint32_t kc, void* workspace,
                               uint32_t* L, uint32_t* U, hipStream_t stream);

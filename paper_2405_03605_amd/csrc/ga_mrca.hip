@@ -17,6 +17,8 @@
 // every 2^(e - e(T))-th bit of each string (stride compaction), XORs them and
 // takes the lowest set bit, O(1) per pair; wider fields are compared field by
 // field up to the first mismatch (at most S <= 32 of them). Integer only.
+#include <mutex>
+
 #include "ga_internal.hpp"
 
 namespace ga {
@@ -421,6 +423,36 @@ __global__ __launch_bounds__(256) void pairs_hybrid_tile_kernel(const uint32_t* 
 
 size_t mrca_workspace_bytes(size_t n) { return n * sizeof(Normalized); }
 
+// Workspace of the allocation-free relatedness call: one normalised surface
+// per sample for up to kScratchSurfaces samples, in a file-scope device array.
+// Each GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` only names the symbol: its device address, per
+// device, comes from hipGetSymbolAddress.
+static __device__ __align__(256) Normalized scratch[kScratchSurfaces];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+void* scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (with that device current) and kept.
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> hold(scratch_mutex);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
+}
+
 hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, uint32_t s_log,
                               uint32_t dlog, uint32_t policy, uint32_t kc, void* workspace,
                               uint32_t* L, uint32_t* U, hipStream_t stream) {
@@ -446,6 +478,20 @@ hipError_t launch_mrca_matrix(const uint32_t* T, const uint32_t* D, uint32_t n, 
   if (e != hipSuccess) return e;
   pairs_kernel<<<dim3((n + 2047) / 2048, n), dim3(256), 0, stream>>>(nz, n, dlog, kc, L, U);
   return hipGetLastError();
+}
+
+hipError_t launch_mrca_matrix_noalloc(const uint32_t* T, const uint32_t* D, uint32_t n,
+                                      uint32_t s_log, uint32_t dlog, uint32_t policy, uint32_t kc,
+                                      uint32_t* L, uint32_t* U, hipStream_t stream) {
+  if (n > kScratchSurfaces) return hipErrorInvalidValue;
+  void* ws = nullptr;
+  if (n != 0 && policy == 0u) {
+    // the normalise pass writes every one of the n entries it reads back,
+    // so nothing left from an earlier call needs clearing
+    const hipError_t e = scratch_address(&ws);
+    if (e != hipSuccess) return e;
+  }
+  return launch_mrca_matrix(T, D, n, s_log, dlog, policy, kc, ws, L, U, stream);
 }
 
 }  // namespace ga
