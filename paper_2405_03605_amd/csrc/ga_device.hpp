@@ -275,18 +275,17 @@ __device__ __forceinline__ Genome breed(const RunView& v, const BreedLane& b, co
   const Block r = b.sel.block(island);
   uint32_t best = b.lane0_addr + (((r.x & 0xFFu) >> (8u - L)) << 2);
   float fbest = permute(g.f, best);
-  if (v.selection) {
-#pragma unroll
-    for (uint32_t m = 1; m < 8; ++m) {
-      if (m < v.k) {
-        const uint32_t byte = ((m < 4 ? r.x : r.y) >> (8u * (m & 3u))) & 0xFFu;
-        const uint32_t cand = b.lane0_addr + ((byte >> (8u - L)) << 2);
-        const float fc = permute(g.f, cand);
-        if (fc > fbest) {
-          best = cand;
-          fbest = fc;
-        }
-      }
+  // entrants 1..k-1: bytes 1..7 of (w0, w1), little-endian; a uniform loop
+  // (no per-entrant condition kept live across the caller's loop)
+  const uint32_t k = v.selection ? v.k : 1u;
+  uint64_t rest = (((uint64_t)r.y << 32) | r.x) >> 8;
+  for (uint32_t m = 1; m < k; ++m) {
+    const uint32_t cand = b.lane0_addr + ((((uint32_t)rest & 0xFFu) >> (8u - L)) << 2);
+    rest >>= 8;
+    const float fc = permute(g.f, cand);
+    if (fc > fbest) {
+      best = cand;
+      fbest = fc;
     }
   }
   Genome c;

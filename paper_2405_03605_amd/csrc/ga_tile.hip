@@ -11,26 +11,31 @@
 // Generation t in one workgroup, with the same results as the per-generation
 // streaming kernel (and the oracle):
 //   island pass   one thread per island: the migration draw; the four
-//                 neighbours' emissions of generation t-1 (LDS outbox for a
-//                 neighbour in the tile, the HBM outbox for one outside it);
-//                 arrivals written into their drawn slots of the LDS
-//                 population (later directions overwrite earlier ones); the
-//                 drawn emigrant (post-immigration) copied to the LDS outbox
-//                 of parity t&1 and, for an island with a neighbour outside
-//                 the tile, to the HBM outbox;
-//   publish       once every island-pass store has completed, the tile's
-//                 progress word becomes t+1: its emissions of t are readable
-//                 and it has finished reading its neighbours' emissions of t-1;
+//                 neighbours' emissions of generation t-1 (the LDS outbox for
+//                 a neighbour in the tile, the LDS halo staging for one
+//                 outside it); arrivals written into their drawn slots of the
+//                 LDS population (later directions overwrite earlier ones);
+//                 the drawn emigrant (post-immigration) copied to the LDS
+//                 outbox of parity t&1 and, for an island with a neighbour
+//                 outside the tile, to the HBM outbox;
 //   iterations    lanes are agent slots, 64/N islands per wavefront
 //                 iteration, tournament / copy / mutation / deposit (`breed`)
 //                 in registers, children written back in place;
-//   wait          before the island pass of t+1, wavefront 0 waits until each
-//                 neighbouring tile's progress word reaches t+1.
+//   publish       after its first iteration each wavefront drains its HBM
+//                 stores and arrives on an LDS counter; the last one sets the
+//                 tile's progress word to t+1: its emissions of t are readable
+//                 and it has finished reading its neighbours' emissions of t-1;
+//   halo          wavefront 0, halfway through its iterations, polls the four
+//                 neighbouring tiles' progress words and, once they read t+1,
+//                 loads their edge emissions of t (the halo of generation t+1)
+//                 into registers, staged in LDS after its last iteration (a
+//                 bounded wait there if they are late).
 // The emissions of t are fixed by the island pass, before the iterations, so
-// a tile publishes them early and its neighbours' waits for generation t+1
-// overlap its iterations of t. The wait also guarantees that a neighbour has
-// finished reading the HBM outbox entries of parity (t+1)&1 (its island pass
-// of t) before this tile overwrites them in generation t+1.
+// the HBM round trips of the exchange (the drain of a tile's edge stores, the
+// neighbours' loads of them) overlap the iterations instead of following
+// them. A neighbour has finished reading the HBM outbox entries of parity
+// (t+1)&1 (its island pass of t) when its progress word reads t+1, before
+// this tile overwrites them in generation t+1.
 //
 // Every tile's workgroup must be resident at once (the host sizes the tiling
 // by the occupancy query); each wait is bounded, and a wait that gave up is
@@ -43,8 +48,10 @@ namespace {
 extern __shared__ uint32_t tile_lds[];
 
 // LDS words of a tile: population planes (f, T, surface words, string words)
-// of TA agents each, the packed (x, y) table of TA / N islands, and the outbox
-// for both parities (TI entries of ob_stride words each).
+// of TA agents each, the packed (x, y) table of TA / N islands, the outbox for
+// both parities (TI entries of ob_stride words each), the halo staging (one
+// entry per edge island and outward direction, at most 2 (tile_w + tile_h)),
+// the neighbour island each such pair reads, and one arrival counter.
 __host__ __device__ inline uint32_t tile_agents_padded(uint32_t ti_full, uint32_t log2n) {
   return ((ti_full << log2n) + 63u) & ~63u;
 }
@@ -56,6 +63,38 @@ __host__ __device__ inline uint32_t tile_table_words(uint32_t ta, uint32_t log2n
   return ((ta >> log2n) + 3u) & ~3u;
 }
 
+// Edge pairs of a tile of w x h islands on a W x H torus: (island, direction)
+// whose neighbour lies in another tile. Indices: the north row's islands
+// (0..w-1) and the south row's (w..2w-1) when the tile does not span the
+// torus's height (h < H), then the west column's (..+h-1) and the east
+// column's when it does not span the width.
+struct EdgePairs {
+  uint32_t w, h, n_ns, count;
+  __device__ EdgePairs(uint32_t w_, uint32_t h_, uint32_t W, uint32_t H) : w(w_), h(h_) {
+    n_ns = h < H ? 2u * w : 0u;
+    count = n_ns + (w < W ? 2u * h : 0u);
+  }
+  // index of the pair (lx, ly, q); q's neighbour must lie outside the tile
+  __device__ uint32_t index(uint32_t lx, uint32_t ly, uint32_t q) const {
+    return q == 0u ? lx : q == 2u ? w + lx : q == 3u ? n_ns + ly : n_ns + h + ly;
+  }
+  // the pair's local island and direction
+  __device__ void of(uint32_t p, uint32_t* lx, uint32_t* ly, uint32_t* q) const {
+    if (p < n_ns) {
+      const bool south = p >= w;
+      *lx = south ? p - w : p;
+      *ly = south ? h - 1u : 0u;
+      *q = south ? 2u : 0u;
+    } else {
+      const uint32_t r = p - n_ns;
+      const bool east = r >= h;
+      *ly = east ? r - h : r;
+      *lx = east ? w - 1u : 0u;
+      *q = east ? 1u : 3u;
+    }
+  }
+};
+
 template <int LC, int SWC, typename Model, bool WIDE>
 __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) {
   constexpr uint32_t L = (uint32_t)LC;
@@ -63,36 +102,55 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
   constexpr uint32_t N = 1u << L;
   constexpr bool kStr = Model::kString;
   constexpr uint32_t kPlanes = 2u + SW + (kStr ? 2u : 0u);
+  // words per outbox entry (f, T, surface, header; with a string f, T, D0,
+  // D1, P0, P1, header) and the header's word, as in the HBM outbox
+  constexpr uint32_t obs = (SW == 1 && !kStr) ? 4u : 8u;
+  constexpr uint32_t ob_hdr = kStr ? 6u : 2u + SW;
   const uint32_t tid = threadIdx.x, nthreads = blockDim.x;
   const uint32_t lane = __lane_id();
   const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t nwaves = nthreads >> 6;
+  const uint32_t W = v.width, H = v.height;
 
   // this workgroup's tile and its actual extent
   const uint32_t tile = xcd_band_group();
   const uint32_t tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const uint32_t x0 = tx * v.tile_w, y0 = ty * v.tile_h;
-  const uint32_t w = min(v.tile_w, v.width - x0), h = min(v.tile_h, v.height - y0);
+  const uint32_t w = min(v.tile_w, W - x0), h = min(v.tile_h, H - y0);
   const uint32_t ti = w * h;
   const uint32_t TI = v.tile_w * v.tile_h;
   const uint32_t TA = tile_agents_padded(TI, L);
   const uint32_t TIP = TA >> L;  // islands covered by whole iterations
-  // words per outbox entry (f, T, surface, header; with a string f, T, D0,
-  // D1, P0, P1, header) and the header's word, as in the HBM outbox
-  constexpr uint32_t obs = (SW == 1 && !kStr) ? 4u : 8u;
-  constexpr uint32_t ob_hdr = kStr ? 6u : 2u + SW;
+  const uint32_t n_iter = TA >> 6;
+  const EdgePairs edges(w, h, W, H);
 
-  uint32_t* lpl = tile_lds;                 // planes: [k * TA + a]
-  uint32_t* lxy = lpl + kPlanes * TA;       // [li]: x | y << 16
-  uint32_t* lob = lxy + tile_table_words(TA, L);  // [(p * TI + li) * obs + k]
+  uint32_t* lpl = tile_lds;                                // planes: [k * TA + a]
+  uint32_t* lxy = lpl + kPlanes * TA;                      // [li]: x | y << 16
+  uint32_t* lob = lxy + tile_table_words(TA, L);           // [(p * TI + li) * obs + k]
+  uint32_t* halo = lob + 2u * TI * obs;                    // [pair * obs + k]
+  uint32_t* halo_isl = halo + 2u * (v.tile_w + v.tile_h) * obs;  // [pair]: neighbour island
+  uint32_t* arrivals = halo_isl + 2u * (v.tile_w + v.tile_h);
+  const uint32_t n_pairs = edges.count;
   auto plane = [&](uint32_t k) { return lpl + k * TA; };
+  auto island_of = [&](uint32_t xy) { return (xy >> 16) * W + (xy & 0xFFFFu); };
+  // the HBM outbox entry (of plane `ob`) that edge pair p reads
+  auto halo_src = [&](const uint32_t* ob, uint32_t p) {
+    return ob + (size_t)halo_isl[p] * obs;
+  };
 
-  // ---- load: island table, population, pending outbox ----------------------
+  // ---- load: island table, population, pending outbox, halo ----------------
   for (uint32_t li = tid; li < TIP; li += nthreads) {
     const uint32_t r = li < ti ? li : 0u;
     const uint32_t ly = r / w, lx = r - ly * w;
     lxy[li] = (x0 + lx) | ((y0 + ly) << 16);
   }
+  for (uint32_t p = tid; p < n_pairs; p += nthreads) {
+    uint32_t lx, ly, q, nx, ny;
+    edges.of(p, &lx, &ly, &q);
+    torus_xy(x0 + lx, y0 + ly, q, W, H, &nx, &ny);
+    halo_isl[p] = ny * W + nx;
+  }
+  if (tid == 0u) *arrivals = 0u;
   __syncthreads();
   const uint64_t t0 = *v.gen;
   {
@@ -100,8 +158,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
                               v.pop_D + v.agent_stride, v.pop_P, v.pop_P + v.agent_stride};
     for (uint32_t la = tid; la < TA; la += nthreads) {
       const uint32_t li = la >> L;
-      const uint32_t xy = lxy[li];
-      const uint32_t a = (((xy >> 16) * v.width + (xy & 0xFFFFu)) << L) + (la & (N - 1u));
+      const uint32_t a = (island_of(lxy[li]) << L) + (la & (N - 1u));
       const bool ok = li < ti;
       plane(0)[la] = ok ? gpl[0][a] : 0u;
       plane(1)[la] = ok ? gpl[1][a] : 0u;
@@ -116,9 +173,11 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
     const uint32_t* gob = v.ob[p_in];
     for (uint32_t k = tid; k < ti * obs; k += nthreads) {
       const uint32_t li = k / obs, j = k - li * obs;
-      const uint32_t xy = lxy[li];
-      const uint32_t island = (xy >> 16) * v.width + (xy & 0xFFFFu);
-      lob[(p_in * TI + li) * obs + j] = gob[(size_t)island * obs + j];
+      lob[(p_in * TI + li) * obs + j] = gob[(size_t)island_of(lxy[li]) * obs + j];
+    }
+    for (uint32_t k = tid; k < n_pairs * obs; k += nthreads) {
+      const uint32_t p = k / obs, j = k - p * obs;
+      halo[k] = halo_src(gob, p)[j];
     }
   }
   __syncthreads();
@@ -135,50 +194,44 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
   }
   const bool waits_on = lane < 4u && nb_tile != tile;
   uint32_t gave_up = 0u;
+  // this wavefront's iterations per generation (at least one: the launch
+  // has no more wavefronts than iterations)
+  const uint32_t my_iters = (n_iter - wave + nwaves - 1u) / nwaves;
 
   for (uint64_t g = 0; g < n_gens; ++g) {
     const uint64_t t = t0 + g;
     const uint32_t t_lo = (uint32_t)t;
     const uint32_t t_hi4 = (uint32_t)(t >> 32) << 2;
     const uint32_t p_out = t_lo & 1u, p_in = p_out ^ 1u;
-    const uint32_t* __restrict__ in_ob = v.ob[p_in];
     uint32_t* __restrict__ out_ob = v.ob[p_out];
 
-    // ---- island pass --------------------------------------------------------
+    // ---- island pass: one thread per island ---------------------------------
     for (uint32_t li = tid; li < ti; li += nthreads) {
       const uint32_t xy = lxy[li];
       const uint32_t x = xy & 0xFFFFu, y = xy >> 16;
-      const uint32_t island = y * v.width + x;
+      const uint32_t lx = x - x0, ly = y - y0;
+      const uint32_t island = y * W + x;
       const Block mig = philox10(0u, island, t_lo, t_hi4 | kStreamMigrate, v.seed, v.run_id);
       const uint32_t emig = L ? (mig.x >> (32u - L)) : 0u;
       bool edge = false;
 #pragma unroll
       for (uint32_t q = 0; q < 4; ++q) {
         uint32_t nx, ny;
-        torus_xy(x, y, q, v.width, v.height, &nx, &ny);
+        torus_xy(x, y, q, W, H, &nx, &ny);
         const bool inside = nx - x0 < w && ny - y0 < h;
         edge |= !inside;
-        uint32_t e[8];
-        if (inside) {
-          const uint4* src =
-              reinterpret_cast<const uint4*>(lob + (p_in * TI + (ny - y0) * w + (nx - x0)) * obs);
+        // a neighbour in the tile: its LDS outbox entry of parity (t-1)&1; one
+        // outside: the staged copy of its HBM outbox entry
+        const uint32_t* src = inside ? lob + (p_in * TI + (ny - y0) * w + (nx - x0)) * obs
+                                     : halo + edges.index(lx, ly, q) * obs;
+        uint32_t e[obs];
 #pragma unroll
-          for (uint32_t k = 0; k < obs; k += 4) {
-            const uint4 u = src[k >> 2];
-            e[k] = u.x;
-            e[k + 1] = u.y;
-            e[k + 2] = u.z;
-            e[k + 3] = u.w;
-          }
-        } else {
-          const uint32_t* src = in_ob + (size_t)(ny * v.width + nx) * obs;
-#pragma unroll
-          for (uint32_t k = 0; k < 8; k += 2)
-            if (k < obs) {
-              const uint2 two = load_agent2(src + k);
-              e[k] = two.x;
-              e[k + 1] = two.y;
-            }
+        for (uint32_t k = 0; k < obs; k += 4) {
+          const uint4 u = *reinterpret_cast<const uint4*>(src + k);
+          e[k] = u.x;
+          e[k + 1] = u.y;
+          e[k + 2] = u.z;
+          e[k + 3] = u.w;
         }
         if (e[ob_hdr] == (kMetaValid | (q ^ 2u))) {
           const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
@@ -194,7 +247,9 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
         }
       }
       // the emission: the drawn member after immigration
-      uint32_t o[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+      uint32_t o[obs];
+#pragma unroll
+      for (uint32_t k = 0; k < obs; ++k) o[k] = 0u;
       const uint32_t a = (li << L) + emig;
       o[0] = plane(0)[a];
       o[1] = plane(1)[a];
@@ -209,24 +264,33 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
 #pragma unroll
       for (uint32_t k = 0; k < obs; k += 4) dst[k >> 2] = make_uint4(o[k], o[k + 1], o[k + 2], o[k + 3]);
       if (edge) {
+        // completed (drained) before the tile's progress word moves on
         uint32_t* gdst = out_ob + (size_t)island * obs;
 #pragma unroll
-        for (uint32_t k = 0; k < 8; k += 2)
-          if (k < obs) store_agent2(gdst + k, o[k], o[k + 1]);
+        for (uint32_t k = 0; k < obs; k += 2) store_agent2(gdst + k, o[k], o[k + 1]);
       }
     }
-    // publish: every store of the island pass has completed
-    drain_memory();
     __syncthreads();
-    if (tid == 0u) store_agent(v.prog + tile, t_lo + 1u);
 
     // ---- iterations: lanes are agent slots ----------------------------------
+    // After its first iteration each wavefront drains its island-pass stores
+    // and arrives on the LDS counter; the last to arrive publishes the tile's
+    // progress (t + 1). Wavefront 0 meanwhile polls the neighbouring tiles'
+    // progress and, once they have published t + 1, prefetches the halo of
+    // generation t + 1 (their edge emissions of t) into registers, staged in
+    // LDS after its last iteration.
+    const bool next = g + 1u < n_gens;
+    const uint32_t due = t_lo + 1u;
+    uint32_t pf[obs];
+    bool fetching = false;
+    uint32_t polled = 0u, flag = 0u;
+    const uint32_t poll_at = my_iters / 2u;
     const BreedLane bl = breed_lane<LC>(v, t);
-    for (uint32_t it = wave; it < (TA >> 6); it += nwaves) {
+    uint32_t k = 0;
+    for (uint32_t it = wave; it < n_iter; it += nwaves, ++k) {
       const uint32_t la = (it << 6) + lane;
       const uint32_t li = la >> L;
-      const uint32_t xy = lxy[li];
-      const uint32_t island = (xy >> 16) * v.width + (xy & 0xFFFFu);
+      const uint32_t island = island_of(lxy[li]);
       Genome gn;
       gn.f = __uint_as_float(plane(0)[la]);
       gn.T = plane(1)[la];
@@ -247,20 +311,77 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
           plane(3 + SW)[la] = c.P1;
         }
       }
+      if (k == 0u) {
+        drain_memory();
+        if (lane == 0u) {
+          const uint32_t before = __hip_atomic_fetch_add(arrivals, 1u, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (before == (uint32_t)(g + 1u) * nwaves - 1u) store_agent(v.prog + tile, due);
+        }
+      }
+      if (wave == 0u && next && !fetching && k >= poll_at) {
+        // a poll issued one iteration ago is read now; a fresh one goes out
+        if (polled) {
+          drain_memory();
+          if (__ballot(waits_on && (int32_t)(flag - due) < 0) == 0ull) {
+            fetching = true;
+            if (lane < n_pairs) {
+              const uint32_t* src = halo_src(out_ob, lane);
+#pragma unroll
+              for (uint32_t j = 0; j < obs; j += 2) {
+                const uint2 two = load_agent2(src + j);
+                pf[j] = two.x;
+                pf[j + 1] = two.y;
+              }
+            }
+          }
+        }
+        if (!fetching) {
+          flag = waits_on ? load_agent(v.prog + nb_tile) : due;
+          polled = 1u;
+        }
+      }
     }
 
-    // ---- wait for the neighbouring tiles' island pass of t + 1 -------------
-    if (wave == 0u && g + 1u < n_gens) {
-      const uint32_t due = t_lo + 1u;
-      for (uint32_t spin = 0;; ++spin) {
-        bool behind = false;
-        if (waits_on) behind = (int32_t)(load_agent(v.prog + nb_tile) - due) < 0;
-        if (__ballot(behind) == 0ull) break;
-        if (spin == kLockSpins) {
-          ++gave_up;
-          break;
+    // ---- wavefront 0: finish the wait and stage the halo of t + 1 ------------
+    if (wave == 0u && next) {
+      if (!fetching) {
+        for (uint32_t spin = 0;; ++spin) {
+          bool behind = false;
+          if (waits_on) behind = (int32_t)(load_agent(v.prog + nb_tile) - due) < 0;
+          if (__ballot(behind) == 0ull) break;
+          if (spin == kLockSpins) {
+            ++gave_up;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
         }
-        __builtin_amdgcn_s_sleep(1);
+        if (lane < n_pairs) {
+          const uint32_t* src = halo_src(out_ob, lane);
+#pragma unroll
+          for (uint32_t j = 0; j < obs; j += 2) {
+            const uint2 two = load_agent2(src + j);
+            pf[j] = two.x;
+            pf[j + 1] = two.y;
+          }
+        }
+      }
+      drain_memory();
+      if (lane < n_pairs) {
+#pragma unroll
+        for (uint32_t j = 0; j < obs; j += 4)
+          *reinterpret_cast<uint4*>(halo + lane * obs + j) =
+              make_uint4(pf[j], pf[j + 1], pf[j + 2], pf[j + 3]);
+      }
+      // pairs beyond the first 64, loaded and staged now
+      for (uint32_t p = 64u + lane; p < n_pairs; p += 64u) {
+        const uint32_t* src = halo_src(out_ob, p);
+#pragma unroll
+        for (uint32_t j = 0; j < obs; j += 2) {
+          const uint2 two = load_agent2(src + j);
+          halo[p * obs + j] = two.x;
+          halo[p * obs + j + 1] = two.y;
+        }
       }
     }
     __syncthreads();
@@ -272,8 +393,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
                         v.pop_D + v.agent_stride, v.pop_P, v.pop_P + v.agent_stride};
     for (uint32_t la = tid; la < (ti << L); la += nthreads) {
       const uint32_t li = la >> L;
-      const uint32_t xy = lxy[li];
-      const uint32_t a = (((xy >> 16) * v.width + (xy & 0xFFFFu)) << L) + (la & (N - 1u));
+      const uint32_t a = (island_of(lxy[li]) << L) + (la & (N - 1u));
       gpl[0][a] = plane(0)[la];
       gpl[1][a] = plane(1)[la];
       gpl[2][a] = plane(2)[la];
@@ -288,9 +408,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
       uint32_t* gob = v.ob[p_last];
       for (uint32_t k = tid; k < ti * obs; k += nthreads) {
         const uint32_t li = k / obs, j = k - li * obs;
-        const uint32_t xy = lxy[li];
-        const uint32_t island = (xy >> 16) * v.width + (xy & 0xFFFFu);
-        gob[(size_t)island * obs + j] = lob[(p_last * TI + li) * obs + j];
+        gob[(size_t)island_of(lxy[li]) * obs + j] = lob[(p_last * TI + li) * obs + j];
       }
     }
   }
@@ -306,7 +424,8 @@ size_t tile_lds_bytes(uint32_t tile_w, uint32_t tile_h, uint32_t log2n, uint32_t
   const uint32_t TI = tile_w * tile_h;
   const uint32_t TA = tile_agents_padded(TI, log2n);
   return 4u * ((size_t)tile_planes(words, model_has_string(model)) * TA +
-               tile_table_words(TA, log2n) + 2u * (size_t)TI * ob_stride);
+               tile_table_words(TA, log2n) + 2u * (size_t)TI * ob_stride +
+               2u * (size_t)(tile_w + tile_h) * (ob_stride + 1u) + 1u);
 }
 
 uint32_t tile_threads(uint32_t tile_w, uint32_t tile_h, uint32_t log2n) {
