@@ -275,17 +275,26 @@ __device__ __forceinline__ Genome breed(const RunView& v, const BreedLane& b, co
   const Block r = b.sel.block(island);
   uint32_t best = b.lane0_addr + (((r.x & 0xFFu) >> (8u - L)) << 2);
   float fbest = permute(g.f, best);
-  // entrants 1..k-1: bytes 1..7 of (w0, w1), little-endian; a uniform loop
-  // (no per-entrant condition kept live across the caller's loop)
+  // entrants 1..k-1: bytes 1..7 of (w0, w1), little-endian. Entrant 1 is
+  // taken apart (k = 2 is the common size), the rest in a uniform loop (no
+  // per-entrant condition kept live across the caller's loop).
   const uint32_t k = v.selection ? v.k : 1u;
-  uint64_t rest = (((uint64_t)r.y << 32) | r.x) >> 8;
-  for (uint32_t m = 1; m < k; ++m) {
-    const uint32_t cand = b.lane0_addr + ((((uint32_t)rest & 0xFFu) >> (8u - L)) << 2);
-    rest >>= 8;
+  if (k > 1u) {
+    const uint32_t cand = b.lane0_addr + ((((r.x >> 8) & 0xFFu) >> (8u - L)) << 2);
     const float fc = permute(g.f, cand);
     if (fc > fbest) {
       best = cand;
       fbest = fc;
+    }
+    uint64_t rest = (((uint64_t)r.y << 32) | r.x) >> 16;
+    for (uint32_t m = 2; m < k; ++m) {
+      const uint32_t cand_m = b.lane0_addr + ((((uint32_t)rest & 0xFFu) >> (8u - L)) << 2);
+      rest >>= 8;
+      const float fm = permute(g.f, cand_m);
+      if (fm > fbest) {
+        best = cand_m;
+        fbest = fm;
+      }
     }
   }
   Genome c;

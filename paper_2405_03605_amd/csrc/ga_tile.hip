@@ -47,18 +47,21 @@ namespace {
 
 extern __shared__ uint32_t tile_lds[];
 
-// LDS words of a tile: population planes (f, T, surface words, string words)
-// of TA agents each, the packed (x, y) table of TA / N islands, the outbox for
+// LDS words of a tile: the population as TA agent records (and TA string
+// records), the island-id and packed (x, y) tables of TA / N islands, the outbox for
 // both parities (TI entries of ob_stride words each), the halo staging (one
 // entry per edge island and outward direction, at most 2 (tile_w + tile_h)),
 // the neighbour island each such pair reads, and one arrival counter.
 __host__ __device__ inline uint32_t tile_agents_padded(uint32_t ti_full, uint32_t log2n) {
   return ((ti_full << log2n) + 63u) & ~63u;
 }
-__host__ __device__ inline uint32_t tile_planes(uint32_t words, bool strings) {
-  return 2u + words + (strings ? 2u : 0u);
+// words per agent: a 16-byte record (fitness, T, surface word 0, surface
+// word 1 or 0) and, for a genome model with a string, an 8-byte one
+__host__ __device__ inline uint32_t tile_agent_words(bool strings) {
+  return 4u + (strings ? 2u : 0u);
 }
-// the (x, y) table, padded so the outbox after it is 16-byte aligned
+// the island-id and (x, y) tables, each padded to a multiple of 4 words so
+// what follows stays 16-byte aligned
 __host__ __device__ inline uint32_t tile_table_words(uint32_t ta, uint32_t log2n) {
   return ((ta >> log2n) + 3u) & ~3u;
 }
@@ -101,7 +104,6 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
   constexpr uint32_t SW = (uint32_t)SWC;
   constexpr uint32_t N = 1u << L;
   constexpr bool kStr = Model::kString;
-  constexpr uint32_t kPlanes = 2u + SW + (kStr ? 2u : 0u);
   // words per outbox entry (f, T, surface, header; with a string f, T, D0,
   // D1, P0, P1, header) and the header's word, as in the HBM outbox
   constexpr uint32_t obs = (SW == 1 && !kStr) ? 4u : 8u;
@@ -124,15 +126,15 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
   const uint32_t n_iter = TA >> 6;
   const EdgePairs edges(w, h, W, H);
 
-  uint32_t* lpl = tile_lds;                                // planes: [k * TA + a]
-  uint32_t* lxy = lpl + kPlanes * TA;                      // [li]: x | y << 16
+  uint4* pop = reinterpret_cast<uint4*>(tile_lds);         // [a]: f, T, D0, D1
+  uint2* pstr = reinterpret_cast<uint2*>(pop + TA);        // [a]: P0, P1 (strings)
+  uint32_t* lisl = tile_lds + TA * tile_agent_words(kStr);  // [li]: island id
+  uint32_t* lxy = lisl + tile_table_words(TA, L);          // [li]: x | y << 16
   uint32_t* lob = lxy + tile_table_words(TA, L);           // [(p * TI + li) * obs + k]
   uint32_t* halo = lob + 2u * TI * obs;                    // [pair * obs + k]
   uint32_t* halo_isl = halo + 2u * (v.tile_w + v.tile_h) * obs;  // [pair]: neighbour island
   uint32_t* arrivals = halo_isl + 2u * (v.tile_w + v.tile_h);
   const uint32_t n_pairs = edges.count;
-  auto plane = [&](uint32_t k) { return lpl + k * TA; };
-  auto island_of = [&](uint32_t xy) { return (xy >> 16) * W + (xy & 0xFFFFu); };
   // the HBM outbox entry (of plane `ob`) that edge pair p reads
   auto halo_src = [&](const uint32_t* ob, uint32_t p) {
     return ob + (size_t)halo_isl[p] * obs;
@@ -143,6 +145,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
     const uint32_t r = li < ti ? li : 0u;
     const uint32_t ly = r / w, lx = r - ly * w;
     lxy[li] = (x0 + lx) | ((y0 + ly) << 16);
+    lisl[li] = (y0 + ly) * W + x0 + lx;
   }
   for (uint32_t p = tid; p < n_pairs; p += nthreads) {
     uint32_t lx, ly, q, nx, ny;
@@ -158,22 +161,17 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
                               v.pop_D + v.agent_stride, v.pop_P, v.pop_P + v.agent_stride};
     for (uint32_t la = tid; la < TA; la += nthreads) {
       const uint32_t li = la >> L;
-      const uint32_t a = (island_of(lxy[li]) << L) + (la & (N - 1u));
+      const uint32_t a = (lisl[li] << L) + (la & (N - 1u));
       const bool ok = li < ti;
-      plane(0)[la] = ok ? gpl[0][a] : 0u;
-      plane(1)[la] = ok ? gpl[1][a] : 0u;
-      plane(2)[la] = ok ? gpl[2][a] : 0u;
-      if (SW > 1) plane(3)[la] = ok ? gpl[3][a] : 0u;
-      if (kStr) {
-        plane(2 + SW)[la] = ok ? gpl[4][a] : 0u;
-        plane(3 + SW)[la] = ok ? gpl[5][a] : 0u;
-      }
+      pop[la] = ok ? make_uint4(gpl[0][a], gpl[1][a], gpl[2][a], SW > 1 ? gpl[3][a] : 0u)
+                   : make_uint4(0u, 0u, 0u, 0u);
+      if (kStr) pstr[la] = ok ? make_uint2(gpl[4][a], gpl[5][a]) : make_uint2(0u, 0u);
     }
     const uint32_t p_in = ((uint32_t)t0 & 1u) ^ 1u;
     const uint32_t* gob = v.ob[p_in];
     for (uint32_t k = tid; k < ti * obs; k += nthreads) {
       const uint32_t li = k / obs, j = k - li * obs;
-      lob[(p_in * TI + li) * obs + j] = gob[(size_t)island_of(lxy[li]) * obs + j];
+      lob[(p_in * TI + li) * obs + j] = gob[(size_t)lisl[li] * obs + j];
     }
     for (uint32_t k = tid; k < n_pairs * obs; k += nthreads) {
       const uint32_t p = k / obs, j = k - p * obs;
@@ -236,14 +234,8 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
         if (e[ob_hdr] == (kMetaValid | (q ^ 2u))) {
           const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
           const uint32_t a = (li << L) + slot;
-          plane(0)[a] = e[0];
-          plane(1)[a] = e[1];
-          plane(2)[a] = e[2];
-          if (SW > 1) plane(3)[a] = e[3];
-          if (kStr) {
-            plane(2 + SW)[a] = e[4];
-            plane(3 + SW)[a] = e[5];
-          }
+          pop[a] = make_uint4(e[0], e[1], e[2], SW > 1 ? e[3] : 0u);
+          if (kStr) pstr[a] = make_uint2(e[4], e[5]);
         }
       }
       // the emission: the drawn member after immigration
@@ -251,13 +243,15 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
 #pragma unroll
       for (uint32_t k = 0; k < obs; ++k) o[k] = 0u;
       const uint32_t a = (li << L) + emig;
-      o[0] = plane(0)[a];
-      o[1] = plane(1)[a];
-      o[2] = plane(2)[a];
-      if (SW > 1) o[3] = plane(3)[a];
+      const uint4 em = pop[a];
+      o[0] = em.x;
+      o[1] = em.y;
+      o[2] = em.z;
+      if (SW > 1) o[3] = em.w;
       if (kStr) {
-        o[4] = plane(2 + SW)[a];
-        o[5] = plane(3 + SW)[a];
+        const uint2 es = pstr[a];
+        o[4] = es.x;
+        o[5] = es.y;
       }
       o[ob_hdr] = v.migration ? (kMetaValid | (mig.y >> 30)) : 0u;
       uint4* dst = reinterpret_cast<uint4*>(lob + (p_out * TI + li) * obs);
@@ -290,26 +284,22 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
     for (uint32_t it = wave; it < n_iter; it += nwaves, ++k) {
       const uint32_t la = (it << 6) + lane;
       const uint32_t li = la >> L;
-      const uint32_t island = island_of(lxy[li]);
+      const uint32_t island = lisl[li];
+      const uint4 rec = pop[la];
       Genome gn;
-      gn.f = __uint_as_float(plane(0)[la]);
-      gn.T = plane(1)[la];
-      gn.D0 = plane(2)[la];
-      if (SW > 1) gn.D1 = plane(3)[la];
+      gn.f = __uint_as_float(rec.x);
+      gn.T = rec.y;
+      gn.D0 = rec.z;
+      gn.D1 = rec.w;
       if (kStr) {
-        gn.P0 = plane(2 + SW)[la];
-        gn.P1 = plane(3 + SW)[la];
+        const uint2 sr = pstr[la];
+        gn.P0 = sr.x;
+        gn.P1 = sr.y;
       }
       const Genome c = breed<LC, SWC, Model, WIDE>(v, bl, gn, island);
       if (li < ti) {
-        plane(0)[la] = __float_as_uint(c.f);
-        plane(1)[la] = c.T;
-        plane(2)[la] = c.D0;
-        if (SW > 1) plane(3)[la] = c.D1;
-        if (kStr) {
-          plane(2 + SW)[la] = c.P0;
-          plane(3 + SW)[la] = c.P1;
-        }
+        pop[la] = make_uint4(__float_as_uint(c.f), c.T, c.D0, c.D1);
+        if (kStr) pstr[la] = make_uint2(c.P0, c.P1);
       }
       if (k == 0u) {
         drain_memory();
@@ -392,15 +382,16 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
     uint32_t* gpl[6] = {reinterpret_cast<uint32_t*>(v.pop_f), v.pop_T, v.pop_D,
                         v.pop_D + v.agent_stride, v.pop_P, v.pop_P + v.agent_stride};
     for (uint32_t la = tid; la < (ti << L); la += nthreads) {
-      const uint32_t li = la >> L;
-      const uint32_t a = (island_of(lxy[li]) << L) + (la & (N - 1u));
-      gpl[0][a] = plane(0)[la];
-      gpl[1][a] = plane(1)[la];
-      gpl[2][a] = plane(2)[la];
-      if (SW > 1) gpl[3][a] = plane(3)[la];
+      const uint32_t a = (lisl[la >> L] << L) + (la & (N - 1u));
+      const uint4 rec = pop[la];
+      gpl[0][a] = rec.x;
+      gpl[1][a] = rec.y;
+      gpl[2][a] = rec.z;
+      if (SW > 1) gpl[3][a] = rec.w;
       if (kStr) {
-        gpl[4][a] = plane(2 + SW)[la];
-        gpl[5][a] = plane(3 + SW)[la];
+        const uint2 sr = pstr[la];
+        gpl[4][a] = sr.x;
+        gpl[5][a] = sr.y;
       }
     }
     if (n_gens > 0) {
@@ -408,7 +399,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
       uint32_t* gob = v.ob[p_last];
       for (uint32_t k = tid; k < ti * obs; k += nthreads) {
         const uint32_t li = k / obs, j = k - li * obs;
-        gob[(size_t)island_of(lxy[li]) * obs + j] = lob[(p_last * TI + li) * obs + j];
+        gob[(size_t)lisl[li] * obs + j] = lob[(p_last * TI + li) * obs + j];
       }
     }
   }
@@ -421,10 +412,11 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
 
 size_t tile_lds_bytes(uint32_t tile_w, uint32_t tile_h, uint32_t log2n, uint32_t words,
                       uint32_t model, uint32_t ob_stride) {
+  (void)words;  // one 16-byte record per agent whatever the surface words
   const uint32_t TI = tile_w * tile_h;
   const uint32_t TA = tile_agents_padded(TI, log2n);
-  return 4u * ((size_t)tile_planes(words, model_has_string(model)) * TA +
-               tile_table_words(TA, log2n) + 2u * (size_t)TI * ob_stride +
+  return 4u * ((size_t)tile_agent_words(model_has_string(model)) * TA +
+               2u * tile_table_words(TA, log2n) + 2u * (size_t)TI * ob_stride +
                2u * (size_t)(tile_w + tile_h) * (ob_stride + 1u) + 1u);
 }
 
