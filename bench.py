@@ -1,15 +1,17 @@
 """Benchmark: agent-generations per second of the island-model GA generation
 step on one MI355X, at 16.8M agents (1024 x 512 islands x 32 agents, 32-site
 surfaces, tournament 2, mutation p = 0.1), plus batched vs plain throughput on
-64 uneven runs.
+64 uneven runs, the served stream, and the LDS-resident tile form on one GPU's
+256 x 256 tile.
 
 A step is one generation of the whole population: absorb, emit, evaluate,
 tournament, copy, mutate and deposit for every island and agent. The state is
 resident in HBM before timing starts. Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--batched-gens G]
-                  [--no-cpu-baseline] [--no-batched] [--workload paper|shard]
-                  [--schedule async [--max-lead N|unpaced]]
+                  [--served-requests R] [--resident-gens G] [--no-cpu-baseline]
+                  [--no-batched] [--no-resident] [--workload paper|shard]
+                  [--form auto|streaming|resident] [--schedule async [--max-lead N|unpaced]]
 
 The default is the synchronous schedule. --schedule async times the
 barrier-free asynchronous schedule on the same workload instead (and adds the
@@ -19,7 +21,6 @@ freshness of the exchanged genomes to the line). --workload shard times the
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -31,64 +32,84 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBPS = 8000.0          # MI355X HBM3E
 CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_LANE_OPS = CUS * LANES_PER_CU * CLOCK_HZ   # full-rate 32-bit VALU lane-ops/s
-KERNEL_SRC = os.path.join(ROOT, "paper_2405_03605_amd", "csrc", "ga_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_generation_kernel_paper.json")
+PROFILES = os.path.join(ROOT, "profiles")
+COUNTER_FILES = {"paper-streaming": os.path.join(PROFILES, "counters_generation_kernel_paper.json"),
+                 "mid-tiles": os.path.join(PROFILES, "counters_tile_kernel_mid.json")}
 
 
 def algorithmic_bytes_per_generation(cfg: dict) -> int:
-    """HBM bytes one generation must move: every agent's genome read and
-    written once (fitness, T, S/32 surface words), and per island one outbox
-    entry written and one read (header, fitness, T, surface words)."""
+    """HBM bytes one generation of the streaming form must move: every agent's
+    genome read and written once (fitness, T, S/32 surface words), and per
+    island one outbox entry written and one read (header, fitness, T, surface
+    words)."""
     I = cfg["width"] * cfg["height"]
     A = I * cfg["pop"]
     genome = 8 + cfg["sites"] // 8
     return 2 * genome * A + 2 * (4 + genome) * I
 
 
-def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+def algorithmic_lane_ops_per_agent_generation(cfg: dict) -> float:
+    """32-bit VALU lane operations one agent-generation needs at least, the
+    work of the LDS-resident form (its memory traffic is the population once
+    per launch plus the tiles' edge emissions):
+      per child: one Philox4x32-10 block, 10 rounds of two 32x32->64 products
+        and two three-input XORs (40); k entrant indices (k) and k-1 strict
+        comparisons each selecting fitness and address (3 (k-1)); the mutation
+        test, delta index, conversion and add (5); the deposit's rank test
+        (4), bit insert (3) and T + 1 (1);
+      per island (1/N of it per agent): the migration block (40), four arrival
+        tests and slot extractions (8), the emigrant's slot and header (2)."""
+    k = cfg["k"] if cfg.get("selection", 1) else 1
+    child = 40 + k + 3 * (k - 1) + 5 + 8
+    island = 40 + 8 + 2
+    return child + island / cfg["pop"]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
-    if the kernel source has changed since they were taken."""
+def counter_record(mode: str):
+    """The committed counter record of a kernel, or None if its sources have
+    changed since the counters were taken."""
+    from paper_2405_03605_amd.counters import source_hash
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(COUNTER_FILES[mode]) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    return rec.get("bytes_per_launch")
+    return rec if rec.get("kernel_source_sha256") == source_hash(mode) else None
+
+
+def _timed(run, steps, warmup, torch):
+    """Wall time and HIP-event time (on the launch stream) of `steps`
+    generations after `warmup` untimed ones."""
+    stream = torch.cuda.current_stream()
+    run.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    run.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, ev0.elapsed_time(ev1)
 
 
 def bench_single(args, torch):
-    from paper_2405_03605_amd import GARun
+    from paper_2405_03605_amd import FORM_AUTO, FORM_RESIDENT, FORM_STREAMING, GARun
     from paper_2405_03605_amd.workloads import MID, PAPER
 
     cfg = dict(PAPER if args.workload == "paper" else MID)
     if args.schedule == "async":
         cfg["schedule"] = 1
     run = GARun(cfg)
-    if args.ipw or args.wpg:
-        run.set_launch(args.ipw, args.wpg)
+    form = {"auto": FORM_AUTO, "streaming": FORM_STREAMING, "resident": FORM_RESIDENT}[args.form]
+    if args.ipw or args.wpg or form:
+        run.set_launch(args.ipw, args.wpg, form)
     if args.schedule == "async":
         run.set_async(0, args.max_lead)
     if args.graph_block is not None:
         run.set_graph_block(args.graph_block)
-    stream = torch.cuda.current_stream()
-    run.step(args.warmup)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    run.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = ev0.elapsed_time(ev1)
+    tiles = run.tiles() if args.schedule == "sync" else (0, 0, 0)
+    wall, ev_ms = _timed(run, args.steps, args.warmup, torch)
     gen = run.read(outbox=False)["generation"]
     assert gen == args.warmup + args.steps, (gen, args.warmup, args.steps)
     extra = None
@@ -100,7 +121,60 @@ def bench_single(args, torch):
                  "last_taken_age_p50_p99_max": [float(np.percentile(age, 50)),
                                                 float(np.percentile(age, 99)), int(age.max())]}
     run.close()
-    return cfg, wall, ev_ms, extra
+    return cfg, wall, ev_ms, extra, tiles
+
+
+def roofline_streaming(cfg, us_per_gen, counters):
+    bytes_gen = algorithmic_bytes_per_generation(cfg)
+    achieved = bytes_gen / (us_per_gen * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+            "traffic": counters["bytes_per_generation"] if counters else None,
+            "valu_issue_frac": counters["valu_issue_frac"] if counters else None,
+            "kernel": "generation_kernel<5,1,FitnessModel,false>", "bytes_per_launch": bytes_gen,
+            "launch_us": round(us_per_gen, 2)}
+
+
+def roofline_tiles(cfg, us_per_gen, counters, tiles):
+    agents = cfg["width"] * cfg["height"] * cfg["pop"]
+    ops = algorithmic_lane_ops_per_agent_generation(cfg)
+    achieved = ops * agents / (us_per_gen * 1e-6) / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2),
+            "unit": "T lane-op/s", "frac": round(achieved / peak, 4),
+            "traffic": counters["bytes_per_generation"] if counters else None,
+            "valu_issue_frac": counters["valu_issue_frac"] if counters else None,
+            "kernel": "tile_kernel<5,1,FitnessModel,false>",
+            "lane_ops_per_agent_generation": round(ops, 2),
+            "tiles": {"tile_w": tiles[0], "tile_h": tiles[1], "count": tiles[2]},
+            "us_per_generation": round(us_per_gen, 2)}
+
+
+def bench_resident(gens: int, torch):
+    """The 256 x 256 x 32 workload (one GPU's tile of the 16.8M grid) in the
+    LDS-resident tile form against the per-generation streaming form."""
+    from paper_2405_03605_amd import FORM_RESIDENT, FORM_STREAMING, GARun
+    from paper_2405_03605_amd.workloads import MID
+
+    agents = MID["width"] * MID["height"] * MID["pop"]
+    out = {"workload": "256x256 islands x 32 agents (2.1M), 32-site surface, tournament 2",
+           "generations": gens}
+    for name, form in (("resident", FORM_RESIDENT), ("streaming", FORM_STREAMING)):
+        run = GARun(MID)
+        run.set_launch(form=form)
+        tiles = run.tiles()
+        wall, ev_ms = _timed(run, gens, 100, torch)
+        run.close()
+        us = ev_ms * 1e3 / gens
+        out[f"{name}_agent_gens_per_s"] = agents * gens / wall
+        out[f"{name}_us_per_generation"] = round(us, 3)
+        if name == "resident":
+            out["roofline"] = roofline_tiles(MID, us, counter_record("mid-tiles"), tiles)
+        else:
+            out["streaming_hbm_frac"] = round(
+                algorithmic_bytes_per_generation(MID) / (us * 1e-6) / 1e9 / PEAK_HBM_GBPS, 4)
+    out["speedup"] = out["resident_agent_gens_per_s"] / out["streaming_agent_gens_per_s"]
+    return out
 
 
 def bench_batched(gens: int, torch):
@@ -213,10 +287,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--batched-gens", type=int, default=1000)
+    ap.add_argument("--batched-gens", type=int, default=20000,
+                    help="generations of the 64-run batched workload (its full length)")
+    ap.add_argument("--resident-gens", type=int, default=2000,
+                    help="generations of the 256x256 tile in each form (0 skips that leg)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=150,
+    ap.add_argument("--no-resident", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=2000,
                     help="requests of the served stream to run (0 skips the served leg)")
     ap.add_argument("--ipw", type=int, default=0, help="islands per wavefront (0: library default)")
     ap.add_argument("--wpg", type=int, default=0, help="wavefronts per workgroup (0: default)")
@@ -225,6 +303,8 @@ def main():
     ap.add_argument("--workload", choices=("paper", "shard"), default="paper",
                     help="paper: 1024x512 islands x 32 (16.8M agents); shard: 256x256 x 32 "
                          "(2.1M agents), one GPU's tile of the paper grid cut 4 x 2")
+    ap.add_argument("--form", choices=("auto", "streaming", "resident"), default="auto",
+                    help="launch form of the main line (auto: resident when the run fits LDS)")
     ap.add_argument("--schedule", choices=("sync", "async"), default="sync")
     ap.add_argument("--max-lead", default="0",
                     help="async: generations an island may lead a neighbour, or 'unpaced'")
@@ -241,23 +321,22 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
 
-    cfg, wall, ev_ms, async_info = bench_single(args, torch)
+    cfg, wall, ev_ms, async_info, tiles = bench_single(args, torch)
     agents = cfg["width"] * cfg["height"] * cfg["pop"]
     value = agents * args.steps / wall
-    kernel_s = ev_ms * 1e-3 / args.steps
-    bytes_gen = algorithmic_bytes_per_generation(cfg)
-    achieved = bytes_gen / kernel_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                "traffic": measured_traffic() if args.workload == "paper" else None,
-                "kernel": "generation_kernel<5,1>", "bytes_per_launch": bytes_gen,
-                "launch_us": round(kernel_s * 1e6, 2)}
+    us_per_gen = ev_ms * 1e3 / args.steps
     if async_info is not None:
-        # one persistent launch covers many generations: per-generation figures
+        roofline = roofline_streaming(cfg, us_per_gen, None)
         kernel = "lockstep_kernel<5,1>" if args.max_lead == 0 else "async_kernel<5,1>"
-        roofline.update({"kernel": kernel, "traffic": None,
-                         "bytes_per_launch": None, "bytes_per_generation": bytes_gen,
-                         "launch_us": None, "us_per_generation": round(kernel_s * 1e6, 2)})
+        roofline.update({"kernel": kernel, "bytes_per_launch": None,
+                         "bytes_per_generation": roofline["bytes_per_launch"],
+                         "launch_us": None, "us_per_generation": round(us_per_gen, 2)})
+    elif tiles[2]:
+        mode = "mid-tiles" if args.workload == "shard" else None
+        roofline = roofline_tiles(cfg, us_per_gen, counter_record(mode) if mode else None, tiles)
+    else:
+        mode = "paper-streaming" if args.workload == "paper" else None
+        roofline = roofline_streaming(cfg, us_per_gen, counter_record(mode) if mode else None)
     shape = (f"{cfg['width']}x{cfg['height']} islands x {cfg['pop']} agents "
              f"({agents / 1e6:.1f}M)")
     metric = ("agent-generations/sec at 16.8M agents; batched vs plain throughput"
@@ -271,10 +350,13 @@ def main():
            "config": {"workload": f"island GA {shape}, 32-site surface, tournament 2, "
                                   "mutation p=0.1, migration 1/island/gen",
                       "islands": cfg["width"] * cfg["height"], "agents": agents,
-                      "step": "one generation", "schedule": args.schedule},
+                      "step": "one generation", "schedule": args.schedule,
+                      "form": "resident" if tiles[2] else "streaming"},
            "roofline": roofline}
     if async_info is not None:
         out["async"] = async_info
+    if not args.no_resident and args.resident_gens > 0:
+        out["resident"] = bench_resident(args.resident_gens, torch)
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_gens, torch)
         if args.served_requests > 0:

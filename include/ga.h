@@ -456,6 +456,29 @@ int ga_mrca_matrix_noalloc(const uint32_t* T, const uint32_t* surface_words, siz
                            uint32_t surface_policy, uint32_t kc, uint32_t* L, uint32_t* U,
                            void* hip_stream);
 
+/* ---------------------------------------------------------------------- */
+/* Roof microbenchmarks: the limits the generation step is measured       */
+/* against (measurement only; all enqueued on hip_stream, device buffers  */
+/* owned by the caller).                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* HBM roof of the streaming form: n_planes (1..8) planes of words_per_plane
+ * u32 each (a multiple of 4; 16-byte aligned, consecutive) are read and
+ * written back incremented, 16 bytes per access: 8 * n_planes * words bytes
+ * moved, the traffic of a generation that updates the population planes in
+ * place. */
+int ga_roof_inplace(void* planes, size_t words_per_plane, uint32_t n_planes, void* hip_stream);
+/* RNG roof: `threads` threads (a multiple of 256) each draw blocks_per_thread
+ * full Philox4x32-10 blocks (the block every child of a generation draws,
+ * Sec. 2's selection and mutation randomness) and write one folded word to
+ * out[thread]. */
+int ga_roof_philox(uint32_t* out, uint32_t threads, uint32_t blocks_per_thread, void* hip_stream);
+/* Issue rate of one instruction kind: `threads` threads (a multiple of 256)
+ * run eight coupled chains of `iters` steps: kind 0 one three-input XOR per
+ * step, kind 1 one 32x32->64 multiply-add plus one XOR per step. One word per
+ * thread to out[thread]. */
+int ga_roof_valu(uint32_t* out, uint32_t threads, uint32_t iters, uint32_t kind, void* hip_stream);
+
 /* Message for a return code, and the calling thread's last error message. */
 const char* ga_strerror(int code);
 const char* ga_last_error(void);

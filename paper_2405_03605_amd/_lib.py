@@ -13,7 +13,7 @@ ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libga_hip.so")
 HEADER = os.path.join(ROOT, "include", "ga.h")
 SOURCES = [os.path.join(_HERE, "csrc", n)
-           for n in ("ga_kernels.hip", "ga_tile.hip", "ga_mrca.hip", "ga_api.hip")]
+           for n in ("ga_kernels.hip", "ga_tile.hip", "ga_mrca.hip", "ga_roofs.hip", "ga_api.hip")]
 BUILD_DIR = os.path.join(_HERE, "_build")
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -108,6 +108,9 @@ SIGNATURES = {
     "ga_mrca_matrix": (i32, [P, P, sz, u32, u32, P, sz, P, P, P]),
     "ga_mrca_matrix_ex": (i32, [P, P, sz, u32, u32, u32, u32, P, sz, P, P, P]),
     "ga_mrca_matrix_noalloc": (i32, [P, P, sz, u32, u32, u32, u32, P, P, P]),
+    "ga_roof_inplace": (i32, [P, sz, u32, P]),
+    "ga_roof_philox": (i32, [P, u32, u32, P]),
+    "ga_roof_valu": (i32, [P, u32, u32, u32, P]),
     "ga_strerror": (ctypes.c_char_p, [i32]),
     "ga_last_error": (ctypes.c_char_p, []),
 }

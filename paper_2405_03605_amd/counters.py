@@ -1,0 +1,151 @@
+"""Hardware-counter record of one kernel on one workload, for the roofline
+fields of bench.py: HBM bytes per dispatch (FETCH_SIZE, WRITE_SIZE, each
+scaled by what the counter reads for an in-place update of known size) and VALU
+issue (SQ counters). Each counter set is one rocprofv3 pass over a committed
+command, run as a child process (this process never touches the GPU). The
+scale factors come from the library's in-place update roof kernel, whose
+bytes are exact.
+
+  python -m paper_2405_03605_amd.counters paper-streaming --out profiles/counters_generation_kernel_paper.json
+  python -m paper_2405_03605_amd.counters mid-tiles --out profiles/counters_tile_kernel_mid.json
+
+The record holds the sha256 of the kernel's sources; bench.py reports its
+figures only while the sources are unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+from .roofs import INPLACE_BYTES_EACH_WAY
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+
+# Sources each kernel family is compiled from (the hash bench.py compares).
+COMMON = ["ga_device.hpp", "ga_internal.hpp", "models/models.hpp", "models/fitness.hpp",
+          "models/strings.hpp", "models/onemax.hpp", "models/trap4.hpp"]
+KERNELS = {
+    "paper-streaming": {"kernel": "generation_kernel", "sources": ["ga_kernels.hip"] + COMMON,
+                        "name": "generation_kernel<5,1,FitnessModel,false>",
+                        "workload": "1024x512 islands x 32 agents, 32-site surface, tournament 2",
+                        "gens_per_dispatch": 1},
+    "mid-tiles": {"kernel": "tile_kernel", "sources": ["ga_tile.hip"] + COMMON,
+                  "name": "tile_kernel<5,1,FitnessModel,false>",
+                  "workload": "256x256 islands x 32 agents, 32-site surface, tournament 2, "
+                              "256 tiles of 16x16 islands",
+                  "gens_per_dispatch": 200},
+}
+SQ_SET = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_VALU",
+          "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU_INT64", "GRBM_GUI_ACTIVE"]
+SIMDS = 1024
+
+
+def source_hash(mode: str) -> str:
+    h = hashlib.sha256()
+    for name in KERNELS[mode]["sources"]:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _pass(counters, cmd, kernel, tmp, tag):
+    """One rocprofv3 pass: per-dispatch counter values of `kernel` dispatches."""
+    out_dir = os.path.join(tmp, tag)
+    prof = ["rocprofv3", "--pmc"] + counters + ["--output-format", "csv", "-d", out_dir,
+                                                "-o", "run", "--"]
+    print(f"[counters] {tag}: {' '.join(counters)}", flush=True)
+    subprocess.run(prof + cmd, check=True, timeout=300, cwd=ROOT)
+    files = glob.glob(os.path.join(out_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise RuntimeError(f"no counter file under {out_dir}")
+    per = {}
+    for path in files:
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if kernel not in row.get("Kernel_Name", ""):
+                    continue
+                d = per.setdefault(row["Dispatch_Id"], {})
+                name = row["Counter_Name"]
+                d[name] = d.get(name, 0.0) + float(row["Counter_Value"])
+    if not per:
+        raise RuntimeError(f"no {kernel} dispatch in {files}")
+    return [per[k] for k in sorted(per, key=int)]
+
+
+def _mean(dispatches, name, skip_first=True):
+    vals = [d[name] for d in dispatches]
+    if skip_first and len(vals) > 1:
+        vals = vals[1:]
+    return sum(vals) / len(vals)
+
+
+def collect(mode: str) -> dict:
+    spec = KERNELS[mode]
+    py = sys.executable
+    cmd = [py, "-m", "paper_2405_03605_amd.profile_run", mode]
+    calib = [py, "-m", "paper_2405_03605_amd.roofs", "--only", "inplace", "--reps", "2"]
+    tmp = tempfile.mkdtemp(prefix="counters_", dir=os.environ.get("TMPDIR", "/tmp"))
+    try:
+        # the in-place update reads and writes exactly INPLACE_BYTES_EACH_WAY
+        cf = _pass(["FETCH_SIZE"], calib, "inplace_kernel", tmp, "calib_fetch")
+        cw = _pass(["WRITE_SIZE"], calib, "inplace_kernel", tmp, "calib_write")
+        kib = INPLACE_BYTES_EACH_WAY / 1024.0
+        fetch_scale = kib / _mean(cf, "FETCH_SIZE")
+        write_scale = kib / _mean(cw, "WRITE_SIZE")
+        f = _pass(["FETCH_SIZE"], cmd, spec["kernel"], tmp, "fetch")
+        w = _pass(["WRITE_SIZE"], cmd, spec["kernel"], tmp, "write")
+        sq = _pass(SQ_SET, cmd, spec["kernel"], tmp, "sq")
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    gens = spec["gens_per_dispatch"]
+    fetch_kib, write_kib = _mean(f, "FETCH_SIZE"), _mean(w, "WRITE_SIZE")
+    read_b = fetch_kib * 1024.0 * fetch_scale
+    write_b = write_kib * 1024.0 * write_scale
+    valu = _mean(sq, "SQ_INSTS_VALU")
+    gui = _mean(sq, "GRBM_GUI_ACTIVE")
+    # GRBM_GUI_ACTIVE sums the busy cycles of the 8 XCDs: per-XCD cycles x 1,024 SIMDs
+    simd_cycles = gui / 8.0 * SIMDS
+    rec = {
+        "kernel": spec["name"], "workload": spec["workload"], "mode": mode,
+        "kernel_source_sha256": source_hash(mode),
+        "generations_per_dispatch": gens, "dispatches": len(sq),
+        "fetch_scale": round(fetch_scale, 4), "write_scale": round(write_scale, 4),
+        "fetch_kib_per_dispatch": round(fetch_kib, 1), "write_kib_per_dispatch": round(write_kib, 1),
+        "read_bytes_per_generation": round(read_b / gens),
+        "write_bytes_per_generation": round(write_b / gens),
+        "bytes_per_generation": round((read_b + write_b) / gens),
+        "sq_per_dispatch": {n: _mean(sq, n) for n in SQ_SET},
+        "valu_wave_insts_per_generation": round(valu / gens),
+        # issue slots used: a wave64 VALU instruction holds a SIMD for 4 cycles
+        "valu_issue_frac": round(4.0 * valu / simd_cycles, 4),
+        "commands": {"workload": " ".join(["python3"] + cmd[1:]),
+                     "calibration": "python3 -m paper_2405_03605_amd.roofs --only inplace --reps 2",
+                     "passes": ["rocprofv3 --pmc FETCH_SIZE", "rocprofv3 --pmc WRITE_SIZE",
+                                "rocprofv3 --pmc " + " ".join(SQ_SET)]},
+    }
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=sorted(KERNELS))
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args()
+    rec = collect(args.mode)
+    with open(args.out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1319,6 +1319,37 @@ void ga_pool_destroy(ga_pool* p) {
 }
 
 // ---------------------------------------------------------------------------
+// Roof microbenchmarks
+// ---------------------------------------------------------------------------
+
+int ga_roof_inplace(void* planes, size_t words_per_plane, uint32_t n_planes, void* hip_stream) {
+  if (!planes) return fail(GA_EINVAL, "planes is NULL");
+  if (reinterpret_cast<uintptr_t>(planes) % 16 || words_per_plane % 4)
+    return fail(GA_EINVAL, "planes must be 16-byte aligned and words_per_plane a multiple of 4");
+  if (n_planes < 1 || n_planes > 8) return fail(GA_EINVAL, "n_planes must be in [1, 8]");
+  GA_HIP(ga::launch_roof_inplace(planes, words_per_plane, n_planes,
+                                 static_cast<hipStream_t>(hip_stream)), "roof launch");
+  return GA_OK;
+}
+
+int ga_roof_philox(uint32_t* out, uint32_t threads, uint32_t blocks_per_thread, void* hip_stream) {
+  if (!out) return fail(GA_EINVAL, "out is NULL");
+  if (threads % 256) return fail(GA_EINVAL, "threads must be a multiple of 256");
+  GA_HIP(ga::launch_roof_philox(out, threads, blocks_per_thread,
+                                static_cast<hipStream_t>(hip_stream)), "roof launch");
+  return GA_OK;
+}
+
+int ga_roof_valu(uint32_t* out, uint32_t threads, uint32_t iters, uint32_t kind, void* hip_stream) {
+  if (!out) return fail(GA_EINVAL, "out is NULL");
+  if (threads % 256) return fail(GA_EINVAL, "threads must be a multiple of 256");
+  if (kind > 1) return fail(GA_EINVAL, "kind must be 0 (three-input XOR) or 1 (64-bit multiply-add)");
+  GA_HIP(ga::launch_roof_valu(out, threads, iters, kind, static_cast<hipStream_t>(hip_stream)),
+         "roof launch");
+  return GA_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Post hoc relatedness
 // ---------------------------------------------------------------------------
 

@@ -126,6 +126,13 @@ hipError_t launch_batch_generation(const RunView* views, const Tile* tiles, uint
 hipError_t launch_batch_advance(const RunView* views, uint32_t n_runs, uint64_t block,
                                 hipStream_t stream);
 
+// Roof microbenchmarks (ga_roofs.hip).
+hipError_t launch_roof_inplace(void* base, size_t words_per_plane, uint32_t planes,
+                               hipStream_t stream);
+hipError_t launch_roof_philox(uint32_t* out, uint32_t threads, uint32_t blocks, hipStream_t stream);
+hipError_t launch_roof_valu(uint32_t* out, uint32_t threads, uint32_t iters, uint32_t kind,
+                            hipStream_t stream);
+
 size_t mrca_workspace_bytes(size_t n);
 // Most surfaces the allocation-free relatedness call takes (its workspace is a
 // static device array of this many normalised surfaces, 16 bytes each).
