@@ -34,7 +34,8 @@ CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_LANE_OPS = CUS * LANES_PER_CU * CLOCK_HZ   # full-rate 32-bit VALU lane-ops/s
 PROFILES = os.path.join(ROOT, "profiles")
 COUNTER_FILES = {"paper-streaming": os.path.join(PROFILES, "counters_generation_kernel_paper.json"),
-                 "mid-tiles": os.path.join(PROFILES, "counters_tile_kernel_mid.json")}
+                 "mid-tiles": os.path.join(PROFILES, "counters_tile_kernel_mid.json"),
+                 "batch": os.path.join(PROFILES, "counters_batch_all_kernel_64runs.json")}
 
 
 def algorithmic_bytes_per_generation(cfg: dict) -> int:
@@ -75,6 +76,11 @@ def counter_record(mode: str):
     except (OSError, ValueError):
         return None
     return rec if rec.get("kernel_source_sha256") == source_hash(mode) else None
+
+
+def progress(msg: str):
+    """One progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def _timed(run, steps, warmup, torch):
@@ -177,12 +183,13 @@ def bench_resident(gens: int, torch):
     return out
 
 
-def bench_batched(gens: int, torch):
+def bench_batched(gens: int, torch, tune: bool = True):
     from paper_2405_03605_amd import GABatch, GARun
     from paper_2405_03605_amd.workloads import batched_configs
 
     cfgs = batched_configs()
     agents = sum(c["width"] * c["height"] * c["pop"] for c in cfgs)
+    progress(f"batched leg: 64 runs alone, {gens} generations each")
     # plain: one run per launch sequence, runs one after another
     runs = [GARun(c) for c in cfgs]
     for r in runs:
@@ -195,11 +202,18 @@ def bench_batched(gens: int, torch):
     plain = time.perf_counter() - t0
     for r in runs:
         r.close()
-    # batched: every run in one launch per generation, 100-generation graph blocks
+    # batched: one launch per generation over every member's islands in
+    # 100-generation graph blocks, launch shape chosen by the autotuner (timed
+    # on scratch runs of the same shapes before the timed region)
+    from paper_2405_03605_amd.autotune import autotune_batch
+    progress(f"batched leg: plain {agents * gens / plain:.3e} agent-gen/s; autotuning the batch")
     runs = [GARun(c) for c in cfgs]
     batch = GABatch()
     for r in runs:
         batch.add(r, gens + 100)
+    chosen = autotune_batch(batch, cfgs) if tune else dict(
+        {k: batch.class_launch(*k)[0] for k in batch.classes()}, waves_per_group=4)
+    progress(f"batched leg: shapes {chosen}; timing {gens} generations")
     batch.step(100)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -213,14 +227,23 @@ def bench_batched(gens: int, torch):
     # (graph replays and the per-block advance included)
     bytes_gen = sum(algorithmic_bytes_per_generation(c) for c in cfgs)
     achieved = bytes_gen * gens / batched / 1e9
+    counters = counter_record("batch")
+    shapes = {"waves_per_group": chosen["waves_per_group"]}
+    shapes.update({f"N={1 << k[0]},words={k[1]}": {"islands_per_wave": v}
+                   for k, v in sorted((k, v) for k, v in chosen.items() if k != "waves_per_group")})
     return {"runs": len(cfgs), "agents": agents, "generations": gens,
+            "plain_form": "each run alone in the library's default form (LDS-resident tiles "
+                          "where it fits, else streaming)",
+            "autotuned_shapes": shapes,
             "batched_agent_gens_per_s": agents * gens / batched,
             "plain_agent_gens_per_s": agents * gens / plain,
             "speedup": plain / batched,
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
                          "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
                          "bytes_per_generation": bytes_gen,
-                         "kernel": "batch_generation_kernel"}}
+                         "traffic": counters["bytes_per_generation"] if counters else None,
+                         "valu_issue_frac": counters["valu_issue_frac"] if counters else None,
+                         "kernel": "batch_all_kernel"}}
 
 
 def bench_served(n_requests: int, capacity: float, torch):
@@ -238,8 +261,14 @@ def bench_served(n_requests: int, capacity: float, torch):
     free, _ = torch.cuda.mem_get_info()
     budget = int(free - 8e9)
     srv = Server(budget, max_slots=256, block=100)
+    progress(f"served leg: {n_requests} requests at {rate:.2f}/s")
+
+    def report(server, elapsed):
+        progress(f"served leg: {elapsed:.0f} s, done {len(server.done)}, live "
+                 f"{len(server.live)}, waiting {len(server.waiting)}")
+
     t0 = time.perf_counter()
-    srv.drain(arrivals)
+    srv.drain(arrivals, progress=report, progress_every=10.0)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     rep = srv.report(wall)
@@ -293,6 +322,8 @@ def main():
                     help="generations of the 256x256 tile in each form (0 skips that leg)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-batch-autotune", action="store_true",
+                    help="batched leg: the default launch shape of every class")
     ap.add_argument("--no-resident", action="store_true")
     ap.add_argument("--served-requests", type=int, default=2000,
                     help="requests of the served stream to run (0 skips the served leg)")
@@ -321,6 +352,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
 
+    progress(f"main line: {args.workload} workload, {args.steps} generations")
     cfg, wall, ev_ms, async_info, tiles = bench_single(args, torch)
     agents = cfg["width"] * cfg["height"] * cfg["pop"]
     value = agents * args.steps / wall
@@ -356,13 +388,16 @@ def main():
     if async_info is not None:
         out["async"] = async_info
     if not args.no_resident and args.resident_gens > 0:
+        progress("resident leg: 256x256x32, tiles and streaming")
         out["resident"] = bench_resident(args.resident_gens, torch)
     if not args.no_batched:
-        out["batched"] = bench_batched(args.batched_gens, torch)
+        out["batched"] = bench_batched(args.batched_gens, torch,
+                                       tune=not args.no_batch_autotune)
         if args.served_requests > 0:
             out["served"] = bench_served(args.served_requests,
                                          out["batched"]["batched_agent_gens_per_s"], torch)
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
 

@@ -329,28 +329,42 @@ int ga_async_last_taken(ga_run* run, int64_t* sent);
 int ga_set_graph_block(ga_run* run, uint32_t gens_per_block);
 
 /* ---------------------------------------------------------------------- */
-/* Batched form: many independent runs of uneven shape advanced together, */
-/* one kernel launch per generation covering every member's islands, with */
-/* blocks of generations captured in a HIP graph. Each member gives the   */
-/* bits it would give alone.                                              */
+/* Batched form: many independent runs of uneven shape advanced together  */
+/* (Sec. 3 runs replicates and treatments as independent runs): one       */
+/* kernel launch per generation over every member's islands, each         */
+/* wavefront running the body compiled for its member's class (island     */
+/* size, surface words), blocks of generations replayed from a HIP graph. */
+/* Members and their budgets live in device tables that the graph reads,  */
+/* so members come and go without a new graph or a wait for the stream    */
+/* (a new graph only when the tiles outgrow the launch's headroom or the  */
+/* launch shape changes). Each member gives the bits it would give alone. */
 /* ---------------------------------------------------------------------- */
 typedef struct ga_batch ga_batch;
 
 /* Create an empty batch bound to hip_stream. The batch allocates its own
- * small descriptor tables in device memory. */
+ * small descriptor tables in device memory (and pinned host staging for
+ * them), growing them, with a wait for the stream, when the members outgrow
+ * them. */
 int ga_batch_create(void* hip_stream, ga_batch** out);
 /* Add a run (created by ga_init, bound to any stream; from now on it is
  * advanced only through the batch) with a generation budget: the batch stops
- * advancing it after budget more generations. Returns GA_OK; GA_EINVAL for an
+ * advancing it after budget more generations. Enqueued: the run's earlier
+ * work on its own stream comes first. Returns GA_OK; GA_EINVAL for an
  * asynchronous run, a genome model with a string, differentia_bits > 1 or a
  * surface policy other than steady; GA_ESTATE if the run is already in a batch. */
 int ga_batch_add(ga_batch* batch, ga_run* run, uint64_t budget);
-/* Remove a member (after waiting for the batch's stream). */
+/* Remove a member. Enqueued, no wait: work later enqueued on the run's own
+ * stream follows the batch's work so far; ga_generation is exact at once
+ * (the batch keeps the host mirror). */
 int ga_batch_remove(ga_batch* batch, ga_run* run);
 /* Enqueue up to n_gens generations for every member with budget left. */
 int ga_batch_step(ga_batch* batch, uint64_t n_gens);
 /* Generations still owed to a member (host mirror). */
 uint64_t ga_batch_remaining(const ga_batch* batch, const ga_run* run);
+/* Whether a member's last generation has run on the GPU (*settled 1), not
+ * only been enqueued (0; also 0 while it has budget left). Waits for nothing.
+ * GA_EINVAL for a run that is not a member. */
+int ga_batch_settled(ga_batch* batch, const ga_run* run, int* settled);
 /* Members; waits for nothing. */
 size_t ga_batch_size(const ga_batch* batch);
 /* Generations per graph replay for the batch (default 100; 0 disables). */
@@ -361,6 +375,15 @@ int ga_batch_set_graph_block(ga_batch* batch, uint32_t gens_per_block);
  * wavefronts per workgroup (1..16; 0 keeps the current value, default 4).
  * Results do not depend on either. */
 int ga_batch_set_launch(ga_batch* batch, uint32_t islands_per_wave, uint32_t waves_per_group);
+/* Islands per wavefront of one class of members (log2 N in 0..6, surface
+ * words 1 or 2), overriding ga_batch_set_launch for it: 0 = the batch's
+ * rule, else a multiple of 64/N in [64/N, 64]. Results do not depend on it. */
+int ga_batch_set_class_launch(ga_batch* batch, uint32_t log2n, uint32_t words,
+                              uint32_t islands_per_wave);
+/* The islands per wavefront a class uses and how many wavefront tiles its
+ * current members make (either output may be NULL). */
+int ga_batch_class_launch(ga_batch* batch, uint32_t log2n, uint32_t words,
+                          uint32_t* islands_per_wave, uint32_t* tiles);
 void ga_batch_destroy(ga_batch* batch);
 
 /* ---------------------------------------------------------------------- */
@@ -392,12 +415,20 @@ int ga_pool_remaining(const ga_pool* pool, uint64_t ticket, uint64_t* left);
 /* Tickets of the runs whose budget is spent: up to cap of them in tickets
  * (may be NULL), in ticket order; *n_done receives how many there are. */
 int ga_pool_poll(const ga_pool* pool, uint64_t* tickets, size_t cap, size_t* n_done);
+/* ga_pool_poll restricted, if settled_only, to runs whose last generation has
+ * already run on the GPU (ga_batch_settled): retiring those waits for no
+ * block still running. */
+int ga_pool_poll_settled(const ga_pool* pool, uint64_t* tickets, size_t cap, size_t* n_done,
+                         int settled_only);
 /* Remove a run (finished or not) and release its memory. Unless all three
  * outputs are NULL, first sample its end population as ga_extract_surfaces
  * does with agent_ids NULL: one agent per island from the sampling stream,
  * ids_out[islands], T_out[islands], surface_words_out[islands * S*b/32]
- * (Sec. 3: one genome sampled per island). A failure leaves the run in the
- * pool. Synchronous. */
+ * (Sec. 3: one genome sampled per island). The sample is taken on a stream of
+ * the pool's own after the work enqueued so far, and the call waits for that
+ * stream only, so blocks already enqueued keep running; later work on the
+ * pool's stream (a run admitted into the freed memory) follows the sampling.
+ * A failure leaves the run in the pool. */
 int ga_pool_retire(ga_pool* pool, uint64_t ticket, uint64_t* ids_out, uint32_t* T_out,
                    uint32_t* surface_words_out);
 /* Bytes held by runs, the largest free block, and the number of runs; any

@@ -94,6 +94,9 @@ SIGNATURES = {
     "ga_batch_size": (sz, [P]),
     "ga_batch_set_graph_block": (i32, [P, u32]),
     "ga_batch_set_launch": (i32, [P, u32, u32]),
+    "ga_batch_set_class_launch": (i32, [P, u32, u32, u32]),
+    "ga_batch_class_launch": (i32, [P, u32, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+    "ga_batch_settled": (i32, [P, P, ctypes.POINTER(i32)]),
     "ga_batch_destroy": (None, [P]),
     "ga_pool_create": (i32, [P, sz, u32, P, ctypes.POINTER(P)]),
     "ga_pool_admit": (i32, [P, P, u64, ctypes.POINTER(u64)]),
@@ -101,6 +104,7 @@ SIGNATURES = {
     "ga_pool_set_graph_block": (i32, [P, u32]),
     "ga_pool_remaining": (i32, [P, u64, ctypes.POINTER(u64)]),
     "ga_pool_poll": (i32, [P, P, sz, ctypes.POINTER(sz)]),
+    "ga_pool_poll_settled": (i32, [P, P, sz, ctypes.POINTER(sz), i32]),
     "ga_pool_retire": (i32, [P, u64, P, P, P]),
     "ga_pool_usage": (i32, [P, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(u32)]),
     "ga_pool_destroy": (None, [P]),

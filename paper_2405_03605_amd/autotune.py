@@ -1,45 +1,71 @@
-"""Launch-shape autotuner: islands per wavefront, wavefronts per workgroup and
-launch form for a run shape, chosen by timing a scratch run of the same shape.
+"""Launch-shape autotuner. Every candidate computes the same bits (the RNG is
+keyed by island, generation and slot, never by the launch shape), so the
+choice only moves time.
 
-Every candidate computes the same bits (the RNG is keyed by island, generation
-and slot, never by the launch shape), so the choice only moves time.
+Single runs: islands per wavefront and wavefronts per workgroup of the
+streaming form, the LDS-resident form (its tile shapes), chosen by timing a
+scratch run of the same shape.
+
+Batches: per class of members (log2 N, surface words), the class kernel's
+islands per wavefront and wavefronts per workgroup, chosen by timing a scratch
+batch of that class's member shapes; cached by the class and its shapes.
 """
 from __future__ import annotations
 
 import time
 
 from ._lib import FORM_RESIDENT, FORM_STREAMING
-from .run import GARun
+from .run import GABatch, GARun
 
 SHAPE_FIELDS = ("width", "height", "pop", "sites", "k", "selection", "migration")
 _cache: dict = {}
+_batch_cache: dict = {}
 
 
 def shape_key(cfg: dict) -> tuple:
     return tuple(int(cfg[f]) for f in SHAPE_FIELDS)
 
 
-def candidates(cfg: dict) -> list[tuple[int, int, int]]:
-    """(islands_per_wave, waves_per_group, form) candidates for a run shape."""
+def candidates(cfg: dict) -> list[tuple]:
+    """Candidates for a single run: (islands_per_wave, waves_per_group,
+    FORM_STREAMING) and (tile_w, tile_h, FORM_RESIDENT) (0, 0: the library's
+    tiling)."""
     per_iter = 64 // cfg["pop"]
-    islands = cfg["width"] * cfg["height"]
     out = []
     ipw = per_iter
     while ipw <= 64:
         for wpg in (1, 2, 4, 8):
             out.append((ipw, wpg, FORM_STREAMING))
         ipw *= 2
-    # resident: one workgroup, only for runs that fit 16 wavefronts
-    res_ipw = max(per_iter, -(-islands // 16))
-    res_ipw = -(-res_ipw // per_iter) * per_iter
-    if res_ipw <= 64 and -(-islands // res_ipw) <= 16:
-        out.append((0, 0, FORM_RESIDENT))
+    out.append((0, 0, FORM_RESIDENT))
+    W, H = cfg["width"], cfg["height"]
+    for tw, th in ((W, H), (max(1, W // 2), max(1, H // 2)), (max(1, W // 4), max(1, H // 4))):
+        if tile_lds_estimate(tw, th, cfg) <= 160 * 1024 and (tw, th, FORM_RESIDENT) not in out:
+            out.append((tw, th, FORM_RESIDENT))
     return out
 
 
+def tile_lds_estimate(tw: int, th: int, cfg: dict) -> int:
+    """LDS bytes of a tile of tw x th islands (16-byte agent records, 8 more
+    with a string; the island tables, both outbox parities, the halo)."""
+    words = cfg["sites"] * cfg.get("dbits", 1) // 32
+    strings = cfg.get("model", 0) != 0
+    ob = 4 if words == 1 and not strings else 8
+    agents = -(-tw * th * cfg["pop"] // 64) * 64
+    return agents * (24 if strings else 16) + 8 * tw * th + 8 * tw * th * ob + 8 * (tw + th) * (ob + 1) + 16
+
+
+def apply(run: GARun, choice):
+    a, b, form = choice
+    if form == FORM_RESIDENT:
+        run.set_launch(form=FORM_RESIDENT)
+        run.set_tiles(a, b)
+    else:
+        run.set_launch(a, b, form)
+
+
 def time_candidate(run: GARun, cand, gens: int, torch) -> float:
-    ipw, wpg, form = cand
-    run.set_launch(ipw, wpg, form)
+    apply(run, cand)
     run.step(2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -49,8 +75,9 @@ def time_candidate(run: GARun, cand, gens: int, torch) -> float:
 
 
 def autotune(cfg: dict, gens: int | None = None, use_cache: bool = True):
-    """Fastest (islands_per_wave, waves_per_group, form) for cfg's shape."""
+    """Fastest candidate for cfg's shape (candidates that do not fit are skipped)."""
     import torch
+    from ._lib import GAError
     key = shape_key(cfg)
     if use_cache and key in _cache:
         return _cache[key]
@@ -60,7 +87,10 @@ def autotune(cfg: dict, gens: int | None = None, use_cache: bool = True):
     scratch = GARun(dict(cfg, seed=0x5eed, run_id=0xA070))
     best, best_t = None, float("inf")
     for cand in candidates(cfg):
-        t = time_candidate(scratch, cand, gens, torch)
+        try:
+            t = time_candidate(scratch, cand, gens, torch)
+        except GAError:
+            continue            # a tiling that does not fit
         if t < best_t:
             best, best_t = cand, t
     scratch.close()
@@ -68,6 +98,80 @@ def autotune(cfg: dict, gens: int | None = None, use_cache: bool = True):
     return best
 
 
-def apply(run: GARun, choice):
-    ipw, wpg, form = choice
-    run.set_launch(ipw, wpg, form)
+# ---- batches -----------------------------------------------------------------
+
+def class_of(cfg: dict) -> tuple:
+    return ((cfg["pop"]).bit_length() - 1, cfg["sites"] * cfg.get("dbits", 1) // 32)
+
+
+def batch_candidates(log2n: int) -> list[int]:
+    """Islands-per-wavefront candidates of one class: 64 to 2,048 agents per
+    wavefront, multiples of one iteration (64/N islands)."""
+    per_iter = 64 >> log2n
+    out = []
+    ipw = per_iter
+    while ipw <= 64:
+        if 64 <= ipw << log2n <= 2048:
+            out.append(ipw)
+        ipw *= 2
+    return out
+
+
+WPG_CANDIDATES = (2, 4, 8)
+
+
+def _batch_key(cfgs: list) -> tuple:
+    return tuple(sorted((c["width"], c["height"], c["pop"], c["sites"]) for c in cfgs))
+
+
+def _time_batch(batch: GABatch, gens: int, torch) -> float:
+    batch.step(gens)                 # new tables (and graph, if the shape changed), warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(gens)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def autotune_batch(batch: GABatch, cfgs: list, gens: int = 100, use_cache: bool = True) -> dict:
+    """Choose and apply the launch shape of a batch of runs with configurations
+    cfgs: the batch-wide wavefronts per workgroup, then each class's islands
+    per wavefront with the others held (coordinate descent), every candidate
+    timed on a scratch batch of the same shapes in one launch per generation,
+    as the batch runs. Returns {"waves_per_group": w, (log2 N, words): ipw}."""
+    import torch
+    key = _batch_key(cfgs)
+    if not (use_cache and key in _batch_cache):
+        classes = sorted({class_of(c) for c in cfgs})
+        runs = [GARun(dict(c, seed=0x5eed, run_id=0xB000 + i)) for i, c in enumerate(cfgs)]
+        scratch = GABatch()
+        for r in runs:
+            scratch.add(r, 1 << 40)
+        chosen = {k: scratch.class_launch(*k)[0] for k in classes}
+        best_w, best_t = 4, float("inf")
+        for w in WPG_CANDIDATES:
+            scratch.set_launch(0, w)
+            t = _time_batch(scratch, gens, torch)
+            if t < best_t:
+                best_w, best_t = w, t
+        scratch.set_launch(0, best_w)
+        for k in classes:
+            best_i, best_t = chosen[k], float("inf")
+            for ipw in batch_candidates(k[0]):
+                scratch.set_class_launch(k[0], k[1], ipw)
+                t = _time_batch(scratch, gens, torch)
+                if t < best_t:
+                    best_i, best_t = ipw, t
+            scratch.set_class_launch(k[0], k[1], best_i)
+            chosen[k] = best_i
+        chosen["waves_per_group"] = best_w
+        scratch.close()
+        for r in runs:
+            r.close()
+        _batch_cache[key] = chosen
+    chosen = _batch_cache[key]
+    batch.set_launch(0, chosen["waves_per_group"])
+    for k, ipw in chosen.items():
+        if k != "waves_per_group":
+            batch.set_class_launch(k[0], k[1], ipw)
+    return dict(chosen)

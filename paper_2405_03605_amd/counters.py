@@ -8,6 +8,8 @@ bytes are exact.
 
   python -m paper_2405_03605_amd.counters paper-streaming --out profiles/counters_generation_kernel_paper.json
   python -m paper_2405_03605_amd.counters mid-tiles --out profiles/counters_tile_kernel_mid.json
+  python -m paper_2405_03605_amd.counters batch --out profiles/counters_batch_all_kernel_64runs.json
+  python -m paper_2405_03605_amd.counters batch-classes --out profiles/counters_batch_classes.json
 
 The record holds the sha256 of the kernel's sources; bench.py reports its
 figures only while the sources are unchanged.
@@ -44,6 +46,10 @@ KERNELS = {
                   "workload": "256x256 islands x 32 agents, 32-site surface, tournament 2, "
                               "256 tiles of 16x16 islands",
                   "gens_per_dispatch": 200},
+    "batch": {"kernel": "batch_all_kernel", "sources": ["ga_kernels.hip"] + COMMON,
+              "name": "batch_all_kernel",
+              "workload": "64 uneven runs, 8,597,368 agents, one launch per generation",
+              "gens_per_dispatch": 1},
 }
 SQ_SET = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_VALU",
           "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU_INT64", "GRBM_GUI_ACTIVE"]
@@ -136,12 +142,69 @@ def collect(mode: str) -> dict:
     return rec
 
 
+CLASS_SET = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_SMEM", "SQ_INSTS_LDS",
+             "SQ_INSTS_VALU_INT64", "GRBM_GUI_ACTIVE"]
+
+
+def collect_classes(gens: int = 12) -> dict:
+    """Instruction counts of the batch kernel against the kernel compiled for
+    one run, class by class: one run per class advanced alone, then as a batch
+    of one (profile_run batch-classes), one SQ pass."""
+    from .profile_run import CLASS_RUNS, class_config
+    py = sys.executable
+    cmd = [py, "-m", "paper_2405_03605_amd.profile_run", "batch-classes", "--gens", str(gens)]
+    tmp = tempfile.mkdtemp(prefix="counters_", dir=os.environ.get("TMPDIR", "/tmp"))
+    try:
+        out_dir = os.path.join(tmp, "classes")
+        prof = ["rocprofv3", "--pmc"] + CLASS_SET + ["--output-format", "csv", "-d", out_dir,
+                                                     "-o", "run", "--"]
+        print(f"[counters] classes: {' '.join(CLASS_SET)}", flush=True)
+        subprocess.run(prof + cmd, check=True, timeout=300, cwd=ROOT)
+        files = glob.glob(os.path.join(out_dir, "**", "*counter_collection.csv"), recursive=True)
+        per = {}
+        for path in files:
+            with open(path) as fh:
+                for row in csv.DictReader(fh):
+                    name = row.get("Kernel_Name", "")
+                    if "generation_kernel" not in name and "batch_all_kernel" not in name:
+                        continue
+                    d = per.setdefault(int(row["Dispatch_Id"]), {"kernel": name})
+                    c = row["Counter_Name"]
+                    d[c] = d.get(c, 0.0) + float(row["Counter_Value"])
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    seq = [per[k] for k in sorted(per)]
+    if len(seq) != 2 * gens * len(CLASS_RUNS):
+        raise RuntimeError(f"expected {2 * gens * len(CLASS_RUNS)} dispatches, got {len(seq)}")
+    rows = []
+    for i, (l, w) in enumerate(CLASS_RUNS):
+        plain = seq[2 * gens * i: 2 * gens * i + gens]
+        batch = seq[2 * gens * i + gens: 2 * gens * (i + 1)]
+        assert all("generation_kernel" in d["kernel"] for d in plain)
+        assert all("batch_all_kernel" in d["kernel"] for d in batch)
+        cfg = class_config(l, w)
+        row = {"N": 1 << l, "surface_words": w,
+               "run": f"{cfg['width']}x{cfg['height']}x{cfg['pop']}, S={cfg['sites']}",
+               "plain_kernel": plain[0]["kernel"].split("(")[0]}
+        for name in CLASS_SET:
+            row["plain_" + name] = _mean(plain, name)
+            row["batch_" + name] = _mean(batch, name)
+        row["valu_ratio"] = round(row["batch_SQ_INSTS_VALU"] / row["plain_SQ_INSTS_VALU"], 4)
+        row["salu_ratio"] = round(row["batch_SQ_INSTS_SALU"] / row["plain_SQ_INSTS_SALU"], 4)
+        rows.append(row)
+    return {"kernel": "batch_all_kernel", "mode": "batch-classes",
+            "kernel_source_sha256": source_hash("batch"), "generations_per_class": gens,
+            "classes": rows,
+            "commands": {"workload": " ".join(["python3"] + cmd[1:]),
+                         "pass": "rocprofv3 --pmc " + " ".join(CLASS_SET)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=sorted(KERNELS))
+    ap.add_argument("mode", choices=sorted(KERNELS) + ["batch-classes"])
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
-    rec = collect(args.mode)
+    rec = collect_classes() if args.mode == "batch-classes" else collect(args.mode)
     with open(args.out, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec), flush=True)

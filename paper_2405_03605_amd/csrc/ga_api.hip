@@ -214,21 +214,42 @@ struct ga_run {
   std::string tile_why;          // why no tiling fits
 };
 
+// Per-class settings of a batch: one class per (log2 N, surface words).
+struct BatchClass {
+  uint32_t ipw = 0;      // islands per wavefront (0: the batch's default rule)
+  uint32_t n_tiles = 0;  // tiles of the current members
+};
+
 struct ga_batch {
   hipStream_t stream = nullptr;
   std::vector<ga_run*> members;
   std::vector<uint64_t> remaining;
-  ga::RunView* d_views = nullptr;
-  ga::Tile* d_tiles = nullptr;
-  size_t cap_views = 0, cap_tiles = 0;
-  uint32_t n_tiles = 0;
-  uint32_t max_ipw = 1;
-  uint32_t wpg = 4;
-  uint32_t ipw_override = 0;
+  std::vector<uint64_t> finished_step;  // step call at which the member's budget ran out
+  // device tables: [views: view_cap RunViews][tiles: tile_cap][tile count, member count]
+  uint8_t* d_tab = nullptr;
+  uint32_t view_cap = 0, tile_cap = 0;
+  // pinned staging for the table uploads, two buffers used in turn, each free
+  // again once its copy's event has completed
+  uint8_t* h_stage[2] = {nullptr, nullptr};
+  hipEvent_t stage_done[2] = {nullptr, nullptr};
+  size_t stage_bytes = 0;
+  int stage_next = 0;
+  BatchClass cls[ga::kBatchClasses];
+  uint32_t wpg = 4;            // wavefronts per group of the batch launch
+  uint32_t ipw_override = 0;   // default islands per wavefront (0: about 512 agents per wavefront)
   uint32_t graph_block = 100;
-  bool dirty = true;
+  // the launch the graph was captured with: wavefronts covered (with
+  // headroom), largest islands per wavefront (sizes the LDS), group size
+  uint32_t grid_waves = 0, use_max_ipw = 0, use_wpg = 0;
+  bool dirty = true;           // membership or shapes changed since the last upload
+  bool graph_stale = true;     // the captured graph no longer matches
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph = nullptr;
+  // one event per step call (ring): a member whose budget ran out at step s is
+  // settled once the event of step s (or of a later step) has completed
+  static constexpr int kStepEvents = 8;
+  hipEvent_t step_done[kStepEvents] = {};
+  uint64_t steps = 0;          // step calls so far
 };
 
 // A run pool: runs sub-allocated from one caller-owned device buffer and
@@ -248,6 +269,10 @@ struct ga_pool {
   std::map<uint64_t, Member> members;
   uint64_t next_ticket = 1;
   size_t used = 0;
+  // retirement samples a finished run on a stream of its own, so the batch
+  // stream keeps running the next block meanwhile
+  hipStream_t side = nullptr;
+  hipEvent_t batch_mark = nullptr, side_mark = nullptr;
 };
 
 namespace {
@@ -431,8 +456,10 @@ int step_tiles(ga_run* r, uint64_t n) {
   return GA_OK;
 }
 
+// Destroy the run's graph once its stream has finished any launch of it.
 void drop_graph(ga_run* r) {
   if (r->graph) {
+    (void)hipStreamSynchronize(r->stream);
     (void)hipGraphExecDestroy(r->graph);
     r->graph = nullptr;
   }
@@ -971,7 +998,7 @@ size_t ga_batch_size(const ga_batch* b) { return b ? b->members.size() : 0; }
 int ga_batch_set_graph_block(ga_batch* b, uint32_t gens) {
   if (!b) return fail(GA_EINVAL, "batch is NULL");
   if (gens > 100000) return fail(GA_EINVAL, "graph block too long");
-  if (gens != b->graph_block) b->dirty = true;
+  if (gens != b->graph_block) b->graph_stale = true;
   b->graph_block = gens;
   return GA_OK;
 }
@@ -986,6 +1013,17 @@ int ga_batch_set_launch(ga_batch* b, uint32_t ipw, uint32_t wpg) {
   return GA_OK;
 }
 
+int ga_batch_set_class_launch(ga_batch* b, uint32_t log2n, uint32_t words, uint32_t ipw) {
+  if (!b) return fail(GA_EINVAL, "batch is NULL");
+  if (log2n > 6 || words < 1 || words > 2) return fail(GA_EINVAL, "no such class");
+  const uint32_t g = 64u >> log2n;
+  if (ipw && (ipw < g || ipw > 64 || ipw % g))
+    return fail(GA_EINVAL, "islands_per_wave must be 0 or a multiple of 64/N in [64/N, 64]");
+  b->cls[log2n * 2 + words - 1].ipw = ipw;
+  b->dirty = true;
+  return GA_OK;
+}
+
 int ga_batch_add(ga_batch* b, ga_run* r, uint64_t budget) {
   if (!b || !r) return fail(GA_EINVAL, "batch or run is NULL");
   if (r->cfg.schedule == GA_SCHEDULE_ASYNC)
@@ -995,12 +1033,21 @@ int ga_batch_add(ga_batch* b, ga_run* r, uint64_t budget) {
   if (r->view.dlog != 0u || r->view.policy != GA_POLICY_STEADY)
     return fail(GA_EINVAL, "a batch advances one-bit differentia on the steady policy only");
   if (r->batch) return fail(GA_ESTATE, "run is already in a batch");
-  GA_HIP(hipStreamSynchronize(r->stream), "stream sync");
-  unsigned long long left = budget;
-  GA_HIP(hipMemcpy(r->view.left, &left, sizeof(left), hipMemcpyHostToDevice), "write budget");
+  // the run's own work (its founders, earlier steps) comes first in the
+  // batch's stream order; then its budget is set on the device
+  if (r->stream != b->stream) {
+    hipEvent_t ev = nullptr;
+    GA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+    hipError_t e = hipEventRecord(ev, r->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ev, 0);
+    (void)hipEventDestroy(ev);
+    GA_HIP(e, "order the run before the batch");
+  }
+  GA_HIP(ga::launch_store_u64(r->view.left, budget, b->stream), "write budget");
   r->batch = b;
   b->members.push_back(r);
   b->remaining.push_back(budget);
+  b->finished_step.push_back(budget == 0 ? b->steps : UINT64_MAX);
   b->dirty = true;
   return GA_OK;
 }
@@ -1009,13 +1056,19 @@ int ga_batch_remove(ga_batch* b, ga_run* r) {
   if (!b || !r) return fail(GA_EINVAL, "batch or run is NULL");
   auto it = std::find(b->members.begin(), b->members.end(), r);
   if (it == b->members.end()) return fail(GA_EINVAL, "run is not a member");
-  GA_HIP(hipStreamSynchronize(b->stream), "stream sync");
   const size_t idx = (size_t)(it - b->members.begin());
   b->members.erase(it);
   b->remaining.erase(b->remaining.begin() + (long)idx);
-  unsigned long long t = 0;
-  GA_HIP(hipMemcpy(&t, r->view.gen, sizeof(t), hipMemcpyDeviceToHost), "read generation");
-  r->gen_host = t;
+  b->finished_step.erase(b->finished_step.begin() + (long)idx);
+  // later work on the run's own stream follows the batch's work so far
+  if (r->stream != b->stream) {
+    hipEvent_t ev = nullptr;
+    GA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+    hipError_t e = hipEventRecord(ev, b->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(r->stream, ev, 0);
+    (void)hipEventDestroy(ev);
+    GA_HIP(e, "order the batch before the run");
+  }
   r->batch = nullptr;
   b->dirty = true;
   return GA_OK;
@@ -1028,18 +1081,44 @@ uint64_t ga_batch_remaining(const ga_batch* b, const ga_run* r) {
   return 0;
 }
 
+int ga_batch_settled(ga_batch* b, const ga_run* r, int* settled) {
+  if (!b || !settled) return fail(GA_EINVAL, "batch or settled is NULL");
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    if (b->members[i] != r) continue;
+    const uint64_t s = b->finished_step[i];
+    *settled = 0;
+    if (s == UINT64_MAX) return GA_OK;
+    if (s == 0) {  // never advanced
+      *settled = 1;
+      return GA_OK;
+    }
+    // slot (s - 1) mod the ring holds step s or a later step: its completion
+    // implies step s's (conservative once the ring has wrapped)
+    const hipEvent_t ev = b->step_done[(s - 1) % ga_batch::kStepEvents];
+    const hipError_t q = ev ? hipEventQuery(ev) : hipSuccess;
+    if (q == hipSuccess) *settled = 1;
+    else if (q != hipErrorNotReady) return hip_fail(q, "event query");
+    return GA_OK;
+  }
+  return fail(GA_EINVAL, "run is not a member");
+}
+
 namespace {
 
-// Islands per wavefront for a member: the batch setting, else about 512
-// agents per wavefront whatever the island size (a batch has wavefronts
-// enough, so small members need no finer chunks, and short wavefronts would
-// spend their time in the per-wavefront set-up).
-uint32_t batch_ipw(const ga_batch* b, const ga_run* r) {
-  const uint32_t g = per_iter(r);
-  uint32_t ipw = b->ipw_override ? b->ipw_override : std::max(1u, 512u >> r->view.log2n);
+// Islands per wavefront of a class: its own setting, else the batch's, else
+// about 512 agents per wavefront whatever the island size (a batch has
+// wavefronts enough, so small members need no finer chunks, and short
+// wavefronts would spend their time in the per-wavefront set-up).
+uint32_t class_ipw(const ga_batch* b, uint32_t c) {
+  const uint32_t log2n = c / 2;
+  const uint32_t g = 64u >> log2n;
+  uint32_t ipw = b->cls[c].ipw ? b->cls[c].ipw
+                               : (b->ipw_override ? b->ipw_override : std::max(1u, 512u >> log2n));
   ipw = std::max(g, ipw / g * g);
   return std::min(64u, ipw);
 }
+
+uint32_t class_of(const ga::RunView& v) { return v.log2n * 2u + v.words - 1u; }
 
 extern "C++" {
 namespace {
@@ -1062,82 +1141,135 @@ void to_table(ga::RunView& v, const void* table) {
 }  // namespace
 }  // extern "C++"
 
+size_t tab_tiles_off(const ga_batch* b) { return align_up((size_t)b->view_cap * sizeof(ga::RunView)); }
+size_t tab_counts_off(const ga_batch* b) {
+  return tab_tiles_off(b) + align_up((size_t)b->tile_cap * sizeof(ga::Tile));
+}
+// the counts: live tiles, then members
+size_t tab_bytes(const ga_batch* b) { return tab_counts_off(b) + align_up(2 * 4); }
+
+uint32_t pow2_at_least(uint32_t v) {
+  uint32_t p = 256;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Rebuild the device tables for the current members and upload them in the
+// batch's stream order (no wait: a kernel already enqueued keeps reading the
+// old contents until the copy runs after it). Capacities grow (with a wait
+// for the stream and a new graph) only when the members outgrow them.
 int rebuild_tables(ga_batch* b) {
   std::vector<ga::RunView> views;
   std::vector<ga::Tile> tiles;
   views.reserve(b->members.size());
+  uint32_t max_ipw = 1;
   for (uint32_t m = 0; m < b->members.size(); ++m) {
-    ga_run* r = b->members[m];
-    ga::RunView v = r->view;
-    v.ipw = batch_ipw(b, r);
+    ga::RunView v = b->members[m]->view;
+    v.ipw = class_ipw(b, class_of(v));
+    max_ipw = std::max(max_ipw, v.ipw);
     views.push_back(v);
     for (uint32_t first = 0; first < v.islands; first += v.ipw) tiles.push_back({m, first});
   }
-  // Wavefronts of one specialised body (island size, surface words) side by
-  // side: neighbouring wavefronts on a CU then share instruction-cache lines.
+  // wavefronts of one class side by side: neighbouring wavefronts on a CU
+  // then run the same shape and share instruction-cache lines
   std::stable_sort(tiles.begin(), tiles.end(), [&](const ga::Tile& a, const ga::Tile& c) {
-    return views[a.run].log2n * 2u + views[a.run].words < views[c.run].log2n * 2u + views[c.run].words;
+    return class_of(views[a.run]) < class_of(views[c.run]);
   });
-  if (views.size() > b->cap_views) {
-    if (b->d_views) GA_HIP(hipFree(b->d_views), "free views");
-    b->d_views = nullptr;
-    b->cap_views = 0;
-    const size_t cap = std::max<size_t>(64, views.size() * 2);
-    GA_HIP(hipMalloc(&b->d_views, cap * sizeof(ga::RunView)), "alloc views");
-    b->cap_views = cap;
+  for (BatchClass& k : b->cls) k.n_tiles = 0;
+  for (const ga::Tile& t : tiles) b->cls[class_of(views[t.run])].n_tiles += 1;
+  if (views.size() > b->view_cap || tiles.size() > b->tile_cap || !b->d_tab) {
+    GA_HIP(hipStreamSynchronize(b->stream), "stream sync");
+    if (b->d_tab) GA_HIP(hipFree(b->d_tab), "free tables");
+    b->d_tab = nullptr;
+    b->view_cap = std::max<uint32_t>({64u, b->view_cap, (uint32_t)views.size() * 2});
+    b->tile_cap = std::max<uint32_t>({4096u, b->tile_cap, (uint32_t)tiles.size() * 2});
+    GA_HIP(hipMalloc(&b->d_tab, tab_bytes(b)), "alloc tables");
+    for (int i = 0; i < 2; ++i) {
+      if (b->h_stage[i]) GA_HIP(hipHostFree(b->h_stage[i]), "free staging");
+      b->h_stage[i] = nullptr;
+      GA_HIP(hipHostMalloc(reinterpret_cast<void**>(&b->h_stage[i]), tab_bytes(b)), "alloc staging");
+      if (!b->stage_done[i])
+        GA_HIP(hipEventCreateWithFlags(&b->stage_done[i], hipEventDisableTiming), "event");
+    }
+    b->stage_bytes = tab_bytes(b);
+    b->graph_stale = true;
   }
-  if (tiles.size() > b->cap_tiles) {
-    if (b->d_tiles) GA_HIP(hipFree(b->d_tiles), "free tiles");
-    b->d_tiles = nullptr;
-    b->cap_tiles = 0;
-    const size_t cap = std::max<size_t>(1024, tiles.size() * 2);
-    GA_HIP(hipMalloc(&b->d_tiles, cap * sizeof(ga::Tile)), "alloc tiles");
-    b->cap_tiles = cap;
-  }
-  // the device table holds each run's pointers as byte offsets from the table
-  for (ga::RunView& v : views) to_table(v, b->d_views);
-  if (!views.empty())
-    GA_HIP(hipMemcpyAsync(b->d_views, views.data(), views.size() * sizeof(ga::RunView),
-                          hipMemcpyHostToDevice, b->stream), "upload views");
+  // a staging buffer is reused once its previous copy has completed
+  uint8_t* st = b->h_stage[b->stage_next];
+  GA_HIP(hipEventSynchronize(b->stage_done[b->stage_next]), "staging free");
+  std::memset(st, 0, b->stage_bytes);
+  for (ga::RunView& v : views) to_table(v, b->d_tab);
+  if (!views.empty()) std::memcpy(st, views.data(), views.size() * sizeof(ga::RunView));
   if (!tiles.empty())
-    GA_HIP(hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(ga::Tile),
-                          hipMemcpyHostToDevice, b->stream), "upload tiles");
-  GA_HIP(hipStreamSynchronize(b->stream), "stream sync");
-  b->n_tiles = (uint32_t)tiles.size();
-  b->max_ipw = 1;
-  for (const ga::RunView& v : views) b->max_ipw = std::max(b->max_ipw, v.ipw);
-  if (b->graph) {
-    (void)hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
+    std::memcpy(st + tab_tiles_off(b), tiles.data(), tiles.size() * sizeof(ga::Tile));
+  uint32_t* counts = reinterpret_cast<uint32_t*>(st + tab_counts_off(b));
+  counts[0] = (uint32_t)tiles.size();
+  counts[1] = (uint32_t)views.size();
+  // the graph covers the tiles with headroom; it is captured again only when
+  // they outgrow it or the launch shape changes (the largest islands per
+  // wavefront sizes each wavefront's LDS)
+  if (tiles.size() > b->grid_waves) {
+    b->grid_waves = pow2_at_least((uint32_t)tiles.size());
+    b->graph_stale = true;
   }
+  if (max_ipw != b->use_max_ipw || b->wpg != b->use_wpg) b->graph_stale = true;
+  b->use_max_ipw = max_ipw;
+  b->use_wpg = b->wpg;
+  GA_HIP(hipMemcpyAsync(b->d_tab, st, b->stage_bytes, hipMemcpyHostToDevice, b->stream),
+         "upload tables");
+  GA_HIP(hipEventRecord(b->stage_done[b->stage_next], b->stream), "staging event");
+  b->stage_next ^= 1;
   b->dirty = false;
   return GA_OK;
 }
 
+const ga::RunView* tab_views(const ga_batch* b) {
+  return reinterpret_cast<const ga::RunView*>(b->d_tab);
+}
+const ga::Tile* tab_tiles(const ga_batch* b) {
+  return reinterpret_cast<const ga::Tile*>(b->d_tab + tab_tiles_off(b));
+}
+const uint32_t* tab_count(const ga_batch* b, uint32_t i) {
+  return reinterpret_cast<const uint32_t*>(b->d_tab + tab_counts_off(b)) + i;
+}
+
+hipError_t launch_gen(ga_batch* b, uint32_t gen_offset, hipStream_t s) {
+  return ga::launch_batch_all(tab_views(b), tab_tiles(b), tab_count(b, 0), b->grid_waves,
+                              gen_offset, b->use_max_ipw, b->use_wpg, s);
+}
+
 int batch_direct(ga_batch* b, uint64_t n) {
-  const uint32_t runs = (uint32_t)b->members.size();
   while (n > 0) {
     const uint64_t slice = std::min<uint64_t>(n, 1u << 20);
     for (uint64_t g = 0; g < slice; ++g)
-      GA_HIP(ga::launch_batch_generation(b->d_views, b->d_tiles, b->n_tiles, (uint32_t)g, b->wpg,
-                                         b->max_ipw, b->stream), "batch launch");
-    GA_HIP(ga::launch_batch_advance(b->d_views, runs, slice, b->stream), "batch advance");
+      GA_HIP(launch_gen(b, (uint32_t)g, b->stream), "batch launch");
+    GA_HIP(ga::launch_batch_advance(tab_views(b), tab_count(b, 1), b->view_cap, slice, b->stream),
+           "batch advance");
     n -= slice;
   }
   return GA_OK;
 }
 
+// One block of graph_block generations: one launch per generation over every
+// member's tiles, then the block's advance. Members are read from the device
+// tables at run time, so the graph outlives membership changes.
 int batch_graph(ga_batch* b) {
-  if (b->graph) return GA_OK;
+  if (b->graph && !b->graph_stale) return GA_OK;
+  if (b->graph) {
+    // the graph may still be running its last launch: it is destroyed only
+    // once the stream has finished it
+    GA_HIP(hipStreamSynchronize(b->stream), "stream sync");
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
   if (!b->capture_stream)
     GA_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking), "capture stream");
   GA_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
   hipError_t err = hipSuccess;
   for (uint32_t g = 0; g < b->graph_block && err == hipSuccess; ++g)
-    err = ga::launch_batch_generation(b->d_views, b->d_tiles, b->n_tiles, g, b->wpg, b->max_ipw,
-                                      b->capture_stream);
+    err = launch_gen(b, g, b->capture_stream);
   if (err == hipSuccess)
-    err = ga::launch_batch_advance(b->d_views, (uint32_t)b->members.size(), b->graph_block,
+    err = ga::launch_batch_advance(tab_views(b), tab_count(b, 1), b->view_cap, b->graph_block,
                                    b->capture_stream);
   hipGraph_t graph = nullptr;
   hipError_t end = hipStreamEndCapture(b->capture_stream, &graph);
@@ -1151,10 +1283,24 @@ int batch_graph(ga_batch* b) {
   (void)hipGraphDestroy(graph);
   if (err != hipSuccess) return hip_fail(err, "graph instantiate");
   b->graph = exec;
+  b->graph_stale = false;
   return GA_OK;
 }
 
 }  // namespace
+
+int ga_batch_class_launch(ga_batch* b, uint32_t log2n, uint32_t words, uint32_t* ipw,
+                          uint32_t* tiles) {
+  if (!b) return fail(GA_EINVAL, "batch is NULL");
+  if (log2n > 6 || words < 1 || words > 2) return fail(GA_EINVAL, "no such class");
+  const uint32_t c = log2n * 2 + words - 1;
+  uint32_t n = 0;
+  for (const ga_run* r : b->members)
+    if (class_of(r->view) == c) n += ceil_div(r->view.islands, class_ipw(b, c));
+  if (ipw) *ipw = class_ipw(b, c);
+  if (tiles) *tiles = n;
+  return GA_OK;
+}
 
 int ga_batch_step(ga_batch* b, uint64_t n) {
   if (!b) return fail(GA_EINVAL, "batch is NULL");
@@ -1174,24 +1320,34 @@ int ga_batch_step(ga_batch* b, uint64_t n) {
   }
   int rc = batch_direct(b, left);
   if (rc != GA_OK) return rc;
-  // host mirror of the budgets: however the n generations are split into
-  // blocks, each member advances by min(n, its remaining budget)
-  for (auto& rem : b->remaining) rem -= std::min<uint64_t>(rem, n);
+  // host mirrors: however the n generations are split into blocks, each
+  // member advances by min(n, its remaining budget)
+  b->steps += 1;
+  hipEvent_t& ev = b->step_done[(b->steps - 1) % ga_batch::kStepEvents];
+  if (!ev) GA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+  GA_HIP(hipEventRecord(ev, b->stream), "step event");
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    const uint64_t adv = std::min<uint64_t>(b->remaining[i], n);
+    b->members[i]->gen_host += adv;
+    b->remaining[i] -= adv;
+    if (adv && b->remaining[i] == 0) b->finished_step[i] = b->steps;
+  }
   return GA_OK;
 }
 
 void ga_batch_destroy(ga_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
-  for (ga_run* r : b->members) {
-    unsigned long long t = 0;
-    if (hipMemcpy(&t, r->view.gen, sizeof(t), hipMemcpyDeviceToHost) == hipSuccess) r->gen_host = t;
-    r->batch = nullptr;
-  }
+  for (ga_run* r : b->members) r->batch = nullptr;
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
-  if (b->d_views) (void)hipFree(b->d_views);
-  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  for (hipEvent_t e : b->step_done)
+    if (e) (void)hipEventDestroy(e);
+  for (int i = 0; i < 2; ++i) {
+    if (b->h_stage[i]) (void)hipHostFree(b->h_stage[i]);
+    if (b->stage_done[i]) (void)hipEventDestroy(b->stage_done[i]);
+  }
+  if (b->d_tab) (void)hipFree(b->d_tab);
   delete b;
 }
 
@@ -1264,16 +1420,62 @@ int ga_pool_remaining(const ga_pool* p, uint64_t ticket, uint64_t* left) {
 }
 
 int ga_pool_poll(const ga_pool* p, uint64_t* tickets, size_t cap, size_t* n_done) {
+  return ga_pool_poll_settled(p, tickets, cap, n_done, 0);
+}
+
+int ga_pool_poll_settled(const ga_pool* p, uint64_t* tickets, size_t cap, size_t* n_done,
+                         int settled_only) {
   if (!p || !n_done) return fail(GA_EINVAL, "pool or n_done is NULL");
   size_t n = 0;
   for (const auto& m : p->members) {
     if (ga_batch_remaining(p->batch, m.second.run) != 0) continue;
+    if (settled_only) {
+      int settled = 0;
+      const int rc = ga_batch_settled(p->batch, m.second.run, &settled);
+      if (rc != GA_OK) return rc;
+      if (!settled) continue;
+    }
     if (tickets && n < cap) tickets[n] = m.first;
     ++n;
   }
   *n_done = n;
   return GA_OK;
 }
+
+namespace {
+
+// One agent per island of run r (sampling stream at its current generation),
+// on the pool's side stream once everything enqueued so far on the batch
+// stream has run; waits for the side stream only.
+int pool_sample(ga_pool* p, ga_run* r, uint64_t* ids_out, uint32_t* T_out,
+                uint32_t* surface_words_out) {
+  if (!p->side) GA_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking), "side stream");
+  if (!p->batch_mark) GA_HIP(hipEventCreateWithFlags(&p->batch_mark, hipEventDisableTiming), "event");
+  if (!p->side_mark) GA_HIP(hipEventCreateWithFlags(&p->side_mark, hipEventDisableTiming), "event");
+  GA_HIP(hipEventRecord(p->batch_mark, p->batch->stream), "mark batch");
+  GA_HIP(hipStreamWaitEvent(p->side, p->batch_mark, 0), "side waits");
+  const ga::RunView& v = r->view;
+  const size_t I = v.islands, W = v.words;
+  uint32_t* st_ids = reinterpret_cast<uint32_t*>(r->base + r->lay.st_ids);
+  uint32_t* st_T = reinterpret_cast<uint32_t*>(r->base + r->lay.st_T);
+  uint32_t* st_D = reinterpret_cast<uint32_t*>(r->base + r->lay.st_D);
+  std::vector<uint32_t> ids32(I), tT(I), tD(I * W);
+  GA_HIP(ga::launch_sample(v, st_ids, p->side), "sample launch");
+  GA_HIP(ga::launch_gather(v, st_ids, (uint32_t)I, st_T, st_D, p->side), "gather launch");
+  GA_HIP(hipMemcpyAsync(ids32.data(), st_ids, I * 4, hipMemcpyDeviceToHost, p->side), "read ids");
+  GA_HIP(hipMemcpyAsync(tT.data(), st_T, I * 4, hipMemcpyDeviceToHost, p->side), "read T");
+  GA_HIP(hipMemcpyAsync(tD.data(), st_D, I * W * 4, hipMemcpyDeviceToHost, p->side), "read surfaces");
+  GA_HIP(hipStreamSynchronize(p->side), "side sync");
+  for (size_t j = 0; j < I; ++j) {
+    if (ids_out) ids_out[j] = ids32[j];
+    if (T_out) T_out[j] = tT[j];
+    if (surface_words_out)
+      for (size_t w = 0; w < W; ++w) surface_words_out[j * W + w] = tD[w * I + j];
+  }
+  return GA_OK;
+}
+
+}  // namespace
 
 int ga_pool_retire(ga_pool* p, uint64_t ticket, uint64_t* ids_out, uint32_t* T_out,
                    uint32_t* surface_words_out) {
@@ -1282,14 +1484,24 @@ int ga_pool_retire(ga_pool* p, uint64_t ticket, uint64_t* ids_out, uint32_t* T_o
   if (it == p->members.end()) return fail(GA_EINVAL, "unknown ticket");
   ga_run* r = it->second.run;
   // sample while the run is still a member (a failure leaves the pool as it was)
-  if (ids_out || T_out || surface_words_out) {
-    const int rc = ga_extract_surfaces(r, nullptr, r->view.islands, ids_out, T_out,
-                                       surface_words_out);
+  const bool sampled = ids_out || T_out || surface_words_out;
+  if (sampled) {
+    const int rc = pool_sample(p, r, ids_out, T_out, surface_words_out);
     if (rc != GA_OK) return rc;
   }
   const int rc = ga_batch_remove(p->batch, r);
   if (rc != GA_OK) return rc;
-  ga_destroy(r);
+  // the run's block returns to the pool; whatever the batch stream runs next
+  // (a new run's founders in that block) follows the sampling
+  if (sampled) {
+    GA_HIP(hipEventRecord(p->side_mark, p->side), "mark side");
+    GA_HIP(hipStreamWaitEvent(p->batch->stream, p->side_mark, 0), "batch waits");
+  }
+  // no wait for the run's stream (the batch stream): the memory is not freed,
+  // and every later use of it is ordered after the batch's work by the stream
+  drop_graph(r);
+  if (r->capture_stream) (void)hipStreamDestroy(r->capture_stream);
+  delete r;
   pool_give(p, it->second.off, it->second.size);
   p->used -= it->second.size;
   p->members.erase(it);
@@ -1315,6 +1527,12 @@ void ga_pool_destroy(ga_pool* p) {
     ga_destroy(m.second.run);
   }
   ga_batch_destroy(p->batch);
+  if (p->side) {
+    (void)hipStreamSynchronize(p->side);
+    (void)hipStreamDestroy(p->side);
+  }
+  if (p->batch_mark) (void)hipEventDestroy(p->batch_mark);
+  if (p->side_mark) (void)hipEventDestroy(p->side_mark);
   delete p;
 }
 

@@ -218,11 +218,13 @@ __device__ __forceinline__ void drain_memory() {
 // g mod 8), each XCD with its own L2. Renumbering the groups so that every XCD
 // takes one contiguous band of the grid keeps an island's four neighbours, and
 // the outbox entries it reads from them, mostly on its own XCD.
-__device__ __forceinline__ uint32_t xcd_band_group() {
-  const uint32_t g = blockIdx.x, n = gridDim.x;
+// The renumbering of groups g < n (a permutation of [0, n)), for grids whose
+// first n groups are the ones with work.
+__device__ __forceinline__ uint32_t xcd_band(uint32_t g, uint32_t n) {
   const uint32_t x = g & 7u, q = n >> 3, r = n & 7u;
   return (x < r ? x * (q + 1u) : r * (q + 1u) + (x - r) * q) + (g >> 3);
 }
+__device__ __forceinline__ uint32_t xcd_band_group() { return xcd_band(blockIdx.x, gridDim.x); }
 
 // Per-lane constants of one generation's children: the lane's slot in its
 // island, the permute address of slot 0 of that island, and the selection

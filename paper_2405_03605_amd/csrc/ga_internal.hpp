@@ -76,6 +76,8 @@ constexpr uint32_t kPaceSpins = 2048;
 constexpr uint32_t kLockSpins = 32768;
 
 // One wavefront's share of a batched launch: islands [first, first + ipw) of run `run`.
+// Batch classes: one per (log2 N, surface words), index log2 N * 2 + words - 1.
+constexpr uint32_t kBatchClasses = 14;
 struct Tile {
   uint32_t run;
   uint32_t first;
@@ -120,11 +122,15 @@ hipError_t launch_fill(uint32_t* p, uint32_t value, size_t words, hipStream_t st
 hipError_t launch_sample(const RunView& v, uint32_t* ids, hipStream_t stream);
 hipError_t launch_gather(const RunView& v, const uint32_t* ids, uint32_t n, uint32_t* T_out,
                          uint32_t* D_out, hipStream_t stream);
-hipError_t launch_batch_generation(const RunView* views, const Tile* tiles, uint32_t n_tiles,
-                                   uint32_t gen_offset, uint32_t waves_per_group,
-                                   uint32_t max_ipw, hipStream_t stream);
-hipError_t launch_batch_advance(const RunView* views, uint32_t n_runs, uint64_t block,
-                                hipStream_t stream);
+// One generation of a batch: grid_waves wavefronts over the members' tiles,
+// of which *n_tiles (device memory) are live; LDS sized for max_ipw.
+hipError_t launch_batch_all(const RunView* views, const Tile* tiles, const uint32_t* n_tiles,
+                            uint32_t grid_waves, uint32_t gen_offset, uint32_t max_ipw,
+                            uint32_t waves_per_group, hipStream_t stream);
+hipError_t launch_store_u64(unsigned long long* p, unsigned long long value, hipStream_t stream);
+// Close a block of a batch: *n_runs members (device count), a grid for cap.
+hipError_t launch_batch_advance(const RunView* views, const uint32_t* n_runs, uint32_t cap,
+                                uint64_t block, hipStream_t stream);
 
 // Roof microbenchmarks (ga_roofs.hip).
 hipError_t launch_roof_inplace(void* base, size_t words_per_plane, uint32_t planes,

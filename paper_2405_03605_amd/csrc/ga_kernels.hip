@@ -634,47 +634,56 @@ __device__ __forceinline__ void from_table(RunView& v, const RunView* table) {
   v.left = table_ptr(table, v.left);
 }
 
-// Batched form: wavefront i works on tiles[i]; members whose budget for this
-// block is spent sit the generation out. Members are fitness-valued genomes
-// with one-bit differentia.
-// eight wavefronts per SIMD: the specialised bodies must fit 64 registers
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
-void batch_generation_kernel(const RunView* __restrict__ views,
-                                                                const Tile* __restrict__ tiles,
-                                                                uint32_t n_tiles,
-                                                                uint32_t gen_offset,
-                                                                uint32_t max_ipw) {
+// Batched form, one launch per generation over every member's tiles (sorted by
+// class, so neighbouring wavefronts run the same shape). The grid has headroom
+// past the live tiles (*n_tiles, device memory, so a captured launch follows
+// membership changes): only its first live_groups groups work, renumbered
+// over that count so that all eight XCDs share them. Each wavefront branches
+// (uniformly) to the body compiled for its member's log2 N and surface words.
+__global__ __launch_bounds__(1024) void batch_all_kernel(const RunView* __restrict__ views,
+                                                         const Tile* __restrict__ tiles,
+                                                         const uint32_t* __restrict__ n_tiles,
+                                                         uint32_t gen_offset, uint32_t max_ipw) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t wave = xcd_band_group() * (blockDim.x >> 6) + wig;
-  if (wave >= n_tiles) return;
+  const uint32_t wpg = blockDim.x >> 6;
+  const uint32_t n = *n_tiles;
+  const uint32_t live_groups = (n + wpg - 1) / wpg;
+  if (blockIdx.x >= live_groups) return;
+  const uint32_t wave = xcd_band(blockIdx.x, live_groups) * wpg + wig;
+  if (wave >= n) return;
   const Tile tile = tiles[wave];
-  RunView v = views[tile.run];
-  from_table(v, views);
-  if (*v.left <= gen_offset) return;
-  const uint64_t t = *v.gen + gen_offset;
-  uint4* arr = wave_lds(wig, max_ipw, 1u);
-  // wavefront-uniform dispatch to the specialised bodies
-  switch (v.log2n * 2u + v.words - 1u) {
-    case 0: chunk_generation<0, 1>(v, tile.first, t, arr); break;
-    case 1: chunk_generation<0, 2>(v, tile.first, t, arr); break;
-    case 2: chunk_generation<1, 1>(v, tile.first, t, arr); break;
-    case 3: chunk_generation<1, 2>(v, tile.first, t, arr); break;
-    case 4: chunk_generation<2, 1>(v, tile.first, t, arr); break;
-    case 5: chunk_generation<2, 2>(v, tile.first, t, arr); break;
-    case 6: chunk_generation<3, 1>(v, tile.first, t, arr); break;
-    case 7: chunk_generation<3, 2>(v, tile.first, t, arr); break;
-    case 8: chunk_generation<4, 1>(v, tile.first, t, arr); break;
-    case 9: chunk_generation<4, 2>(v, tile.first, t, arr); break;
-    case 10: chunk_generation<5, 1>(v, tile.first, t, arr); break;
-    case 11: chunk_generation<5, 2>(v, tile.first, t, arr); break;
-    case 12: chunk_generation<6, 1>(v, tile.first, t, arr); break;
-    default: chunk_generation<6, 2>(v, tile.first, t, arr); break;
+  const RunView* vp = views + tile.run;
+  uint4* lds = wave_lds(wig, max_ipw, 1u);
+  // only the class is read before the branch; each body loads the rest of
+  // the view itself, so nothing of it stays live across the branch
+  const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane(vp->log2n * 2u + vp->words - 1u);
+  switch (c) {
+#define GA_BATCH_CASE(L, S)                                  \
+  case L * 2 + S - 1: {                                      \
+    RunView v = *vp;                                         \
+    from_table(v, views);                                    \
+    if (*v.left <= gen_offset) return;                       \
+    chunk_generation<L, S>(v, tile.first, *v.gen + gen_offset, lds); \
+    break;                                                   \
+  }
+    GA_BATCH_CASE(0, 1) GA_BATCH_CASE(0, 2) GA_BATCH_CASE(1, 1) GA_BATCH_CASE(1, 2)
+    GA_BATCH_CASE(2, 1) GA_BATCH_CASE(2, 2) GA_BATCH_CASE(3, 1) GA_BATCH_CASE(3, 2)
+    GA_BATCH_CASE(4, 1) GA_BATCH_CASE(4, 2) GA_BATCH_CASE(5, 1) GA_BATCH_CASE(5, 2)
+    GA_BATCH_CASE(6, 1) GA_BATCH_CASE(6, 2)
+#undef GA_BATCH_CASE
+    default: break;  // no such class: members are validated on admission
   }
 }
 
-__global__ void batch_advance_kernel(const RunView* views, uint32_t n_runs, uint64_t block) {
+__global__ void store_u64_kernel(unsigned long long* p, unsigned long long value) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p = value;
+}
+
+// Close a block: each member's counter advances by what it ran of the block.
+// The member count lives in device memory (the grid covers the table's capacity).
+__global__ void batch_advance_kernel(const RunView* views, const uint32_t* n_runs, uint64_t block) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_runs) return;
+  if (i >= *n_runs) return;
   RunView v = views[i];
   from_table(v, views);
   const unsigned long long left = *v.left;
@@ -795,21 +804,26 @@ hipError_t launch_gather(const RunView& v, const uint32_t* ids, uint32_t n, uint
   return hipGetLastError();
 }
 
-hipError_t launch_batch_generation(const RunView* views, const Tile* tiles, uint32_t n_tiles,
-                                   uint32_t gen_offset, uint32_t waves_per_group,
-                                   uint32_t max_ipw, hipStream_t stream) {
-  if (n_tiles == 0) return hipSuccess;
-  const uint32_t groups = (n_tiles + waves_per_group - 1) / waves_per_group;
+hipError_t launch_batch_all(const RunView* views, const Tile* tiles, const uint32_t* n_tiles,
+                            uint32_t grid_waves, uint32_t gen_offset, uint32_t max_ipw,
+                            uint32_t waves_per_group, hipStream_t stream) {
+  if (grid_waves == 0) return hipSuccess;
+  const uint32_t groups = (grid_waves + waves_per_group - 1) / waves_per_group;
   const size_t lds = lds_bytes(max_ipw, waves_per_group, 0u);
-  batch_generation_kernel<<<dim3(groups), dim3(64 * waves_per_group), lds, stream>>>(
+  batch_all_kernel<<<dim3(groups), dim3(64 * waves_per_group), lds, stream>>>(
       views, tiles, n_tiles, gen_offset, max_ipw);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_advance(const RunView* views, uint32_t n_runs, uint64_t block,
-                                hipStream_t stream) {
-  if (n_runs == 0) return hipSuccess;
-  batch_advance_kernel<<<dim3((n_runs + 255) / 256), dim3(256), 0, stream>>>(views, n_runs, block);
+hipError_t launch_store_u64(unsigned long long* p, unsigned long long value, hipStream_t stream) {
+  store_u64_kernel<<<1, 64, 0, stream>>>(p, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(const RunView* views, const uint32_t* n_runs, uint32_t cap,
+                                uint64_t block, hipStream_t stream) {
+  if (cap == 0) return hipSuccess;
+  batch_advance_kernel<<<dim3((cap + 255) / 256), dim3(256), 0, stream>>>(views, n_runs, block);
   return hipGetLastError();
 }
 

@@ -233,6 +233,32 @@ class GABatch:
     def set_launch(self, islands_per_wave: int = 0, waves_per_group: int = 0):
         check(load().ga_batch_set_launch(self._h, islands_per_wave, waves_per_group))
 
+    def set_class_launch(self, log2n: int, words: int, islands_per_wave: int = 0):
+        """Islands per wavefront of one class (log2 N, surface words); 0 = the batch's rule."""
+        check(load().ga_batch_set_class_launch(self._h, int(log2n), int(words),
+                                               int(islands_per_wave)))
+
+    def class_launch(self, log2n: int, words: int) -> tuple:
+        """(islands_per_wave, tiles) of a class."""
+        i, t = ctypes.c_uint32(), ctypes.c_uint32()
+        check(load().ga_batch_class_launch(self._h, int(log2n), int(words), ctypes.byref(i),
+                                           ctypes.byref(t)))
+        return int(i.value), int(t.value)
+
+    def classes(self) -> list:
+        """(log2 N, surface words) of every class with members."""
+        out = []
+        for log2n in range(7):
+            for words in (1, 2):
+                if self.class_launch(log2n, words)[1]:
+                    out.append((log2n, words))
+        return out
+
+    def settled(self, run: GARun) -> bool:
+        s = ctypes.c_int()
+        check(load().ga_batch_settled(self._h, run.handle, ctypes.byref(s)))
+        return bool(s.value)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load().ga_batch_destroy(self._h)
@@ -286,12 +312,15 @@ class GAPool:
         check(load().ga_pool_remaining(self._h, int(ticket), ctypes.byref(left)))
         return int(left.value)
 
-    def done(self) -> list:
-        """Tickets of the runs whose budget is spent."""
+    def done(self, settled: bool = False) -> list:
+        """Tickets of the runs whose budget is spent (with settled, only those
+        whose last generation has already run on the GPU)."""
         n = ctypes.c_size_t()
-        check(load().ga_pool_poll(self._h, None, 0, ctypes.byref(n)))
+        lib = load()
+        check(lib.ga_pool_poll_settled(self._h, None, 0, ctypes.byref(n), int(settled)))
         out = np.empty(n.value, dtype=np.uint64)
-        check(load().ga_pool_poll(self._h, _ptr(out), out.size, ctypes.byref(n)))
+        check(lib.ga_pool_poll_settled(self._h, _ptr(out), out.size, ctypes.byref(n),
+                                       int(settled)))
         return [int(t) for t in out[:n.value]]
 
     def retire(self, ticket: int, sample: bool = True):

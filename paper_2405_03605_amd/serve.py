@@ -11,6 +11,10 @@ pool takes them. Each run's result is bit-identical to running it alone,
 because its random stream depends only on (seed, run_id, island, generation,
 slot).
 
+Each round enqueues the next block before it retires anything, and retires
+only runs whose last block has already run (their sampling waits for no
+block still on the GPU), so the host's bookkeeping overlaps the GPU's work.
+
 Memory, slots and the batch belong to the pool: by default the native run pool
 (`GAPool`, ga_pool_* in the C ABI: runs sub-allocated first fit from one device
 buffer of the budget's size). The pool is injected (`make_pool`), so the
@@ -90,10 +94,12 @@ class Server:
             n += 1
         return n
 
-    def retire(self) -> int:
-        """Retire runs whose generation budget is spent; sample their surfaces."""
+    def retire(self, settled: bool = False) -> int:
+        """Retire runs whose generation budget is spent; sample their surfaces.
+        With settled, only runs whose last generation has already run on the
+        GPU: their sampling then waits for no block still running."""
         n = 0
-        for ticket in self.pool.done():
+        for ticket in (self.pool.done(settled=True) if settled else self.pool.done()):
             req, _ = self.live.pop(ticket)
             req.result = self.pool.retire(ticket)
             req.finished = self.clock()
@@ -133,8 +139,14 @@ class Server:
                 if pending:
                     time.sleep(min(0.001, max(0.0, pending[0][0] - now)))
                 continue
-            self.advance()
-            self.retire()
+            if any(self.pool.remaining(t) for t in self.live):
+                # the next block goes in before this round's retirements, so
+                # the GPU runs it while the host samples the runs the block
+                # before finished and admits the next requests
+                self.advance()
+                self.retire(settled=True)
+            else:
+                self.retire()
         return self.done
 
     def close(self):

@@ -5,8 +5,9 @@ import pytest
 
 import oracle
 from gpu_helpers import assert_same_state, oracle_after, say
-from paper_2405_03605_amd import FORM_STREAMING, GABatch, GARun
-from paper_2405_03605_amd.autotune import autotune, candidates
+from paper_2405_03605_amd import FORM_STREAMING, GABatch, GAError, GARun
+from paper_2405_03605_amd.autotune import (apply, autotune, autotune_batch, batch_candidates,
+                                           candidates, class_of)
 from paper_2405_03605_amd.serve import Server
 from paper_2405_03605_amd.workloads import batched_configs, run_config
 
@@ -109,12 +110,74 @@ def test_autotune_candidates_are_bit_identical():
     assert len(cands) >= 8
     for cand in cands:
         run = GARun(cfg)
-        run.set_launch(*cand)
+        try:
+            apply(run, cand)
+        except GAError:      # a tiling the GPU cannot hold at once
+            run.close()
+            continue
         run.step(60)
         assert_same_state(run.read(), ref, f"candidate {cand}")
         run.close()
     best = autotune(cfg, gens=10, use_cache=False)
     assert best in cands
+
+
+def test_batch_class_candidates_are_bit_identical():
+    # every islands-per-wavefront candidate of every class present, the j-th
+    # candidate of each class in the j-th batch with the j-th group size,
+    # against the oracle; then the autotuner's choice
+    from paper_2405_03605_amd.autotune import WPG_CANDIDATES
+    refs = [oracle_after(c, b) for c, b in zip(UNEVEN, BUDGETS)]
+    classes = sorted({class_of(c) for c in UNEVEN})
+    cands = {k: batch_candidates(k[0]) for k in classes}
+    rounds = max(len(v) for v in cands.values())
+    say(f"{len(classes)} classes, up to {rounds} candidates each")
+    for j in range(rounds):
+        runs = [GARun(c) for c in UNEVEN]
+        batch = GABatch()
+        for r, b in zip(runs, BUDGETS):
+            batch.add(r, b)
+        batch.set_launch(0, WPG_CANDIDATES[j % len(WPG_CANDIDATES)])
+        for (log2n, words), cl in cands.items():
+            ipw = cl[j % len(cl)]
+            batch.set_class_launch(log2n, words, ipw)
+            assert batch.class_launch(log2n, words)[0] == ipw
+        batch.step(120)
+        batch.step(200)
+        for r, c, ref in zip(runs, UNEVEN, refs):
+            assert_same_state(r.read(), ref, f"round {j} member {c['run_id']}")
+        batch.close()
+        for r in runs:
+            r.close()
+    runs = [GARun(c) for c in UNEVEN]
+    batch = GABatch()
+    for r, b in zip(runs, BUDGETS):
+        batch.add(r, b)
+    chosen = autotune_batch(batch, UNEVEN, gens=20, use_cache=False)
+    assert chosen["waves_per_group"] in WPG_CANDIDATES
+    for k in classes:
+        assert chosen[k] in cands[k]
+    batch.step(320)
+    for r, c, ref in zip(runs, UNEVEN, refs):
+        assert_same_state(r.read(), ref, f"autotuned member {c['run_id']}")
+    batch.close()
+
+
+def test_settled_follows_the_gpu():
+    # a member whose budget ran out is settled once its last block has run
+    import torch
+    run = GARun(UNEVEN[2])
+    batch = GABatch()
+    batch.add(run, 150)
+    assert not batch.settled(run)
+    batch.step(200)
+    torch.cuda.synchronize()
+    assert batch.remaining(run) == 0 and batch.settled(run)
+    assert run.generation == 150
+    batch.remove(run)
+    assert run.generation == 150
+    assert_same_state(run.read(), oracle_after(UNEVEN[2], 150), "settled member")
+    batch.close()
 
 
 def test_served_results_equal_alone_and_oracle():

@@ -13,7 +13,7 @@ class FakePool:
 
     def __init__(self, budget, slots):
         self.budget, self.slots = budget, slots
-        self.left, self.size, self.cfgs = {}, {}, {}
+        self.left, self.size, self.cfgs, self.finished = {}, {}, {}, {}
         self.next = 1
         self.steps = 0
         self.block = None
@@ -41,10 +41,15 @@ class FakePool:
     def step(self, n):
         self.steps += 1
         for t in self.left:
-            self.left[t] -= min(n, self.left[t])
+            before = self.left[t]
+            self.left[t] -= min(n, before)
+            if before and not self.left[t]:
+                self.finished[t] = self.steps
 
-    def done(self):
-        return sorted(t for t, v in self.left.items() if v == 0)
+    def done(self, settled=False):
+        # a run settles once a later step has been enqueued after its last one
+        return sorted(t for t, v in self.left.items()
+                      if v == 0 and (not settled or self.finished.get(t, 0) < self.steps))
 
     def retire(self, t, sample=True):
         cfg = self.cfgs.pop(t)
