@@ -318,6 +318,15 @@ int ga_set_async(ga_run* run, uint32_t max_wavefronts, uint32_t max_lead, uint32
 /* Asynchronous runs: how many times so far an island stopped waiting for a
  * neighbour and went on (0 means every pacing wait was met). Synchronous. */
 int ga_async_waits(ga_run* run, uint64_t* gave_up);
+/* Asynchronous runs: genomes the islands have absorbed from their neighbours'
+ * buffers since the run was created (Sec. 2 Methods: an island takes what
+ * has arrived and goes on). With migration on, every island sends one genome
+ * per generation and generation 0 has nothing to take, so after g
+ * generations 1 - taken / (islands * (g - 1)) is the share of genomes
+ * overwritten before they were read (0 in lockstep).
+ * GA_EINVAL for a synchronous run (which absorbs every genome sent).
+ * Synchronous. */
+int ga_async_taken(ga_run* run, uint64_t* taken);
 /* Asynchronous runs: for island i and direction q, sent[i*4 + q] receives the
  * generation in which the last genome island i took from that side was sent
  * (t - 1 where t is the generation of the run or of the last

@@ -85,6 +85,7 @@ SIGNATURES = {
     "ga_get_tiles": (i32, [P, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
     "ga_set_async": (i32, [P, u32, u32, u32]),
     "ga_async_waits": (i32, [P, ctypes.POINTER(u64)]),
+    "ga_async_taken": (i32, [P, ctypes.POINTER(u64)]),
     "ga_async_last_taken": (i32, [P, P]),
     "ga_batch_create": (i32, [P, ctypes.POINTER(P)]),
     "ga_batch_add": (i32, [P, P, u64]),

@@ -181,7 +181,7 @@ Layout layout_of(const ga_config* c) {
     // LDS-resident tiles: a progress word per tile (never more tiles than islands)
     L.prog = take(std::min<size_t>(kMaxTiles, (size_t)c->width * c->height) * 4);
   }
-  L.counters = take(24);  // generation, batch budget, async give-ups
+  L.counters = take(32);  // generation, batch budget, async give-ups, async genomes taken
   L.st_ids = take(islands * 4);
   L.st_T = take(islands * 4);
   L.st_D = take(islands * 4 * words);
@@ -746,6 +746,16 @@ int ga_async_waits(ga_run* r, uint64_t* gave_up) {
   unsigned long long n = 0;
   GA_HIP(hipMemcpy(&n, r->view.waits, sizeof(n), hipMemcpyDeviceToHost), "read waits");
   *gave_up = n;
+  return GA_OK;
+}
+
+int ga_async_taken(ga_run* r, uint64_t* taken) {
+  if (!r || !taken) return fail(GA_EINVAL, "run or taken is NULL");
+  if (r->cfg.schedule != GA_SCHEDULE_ASYNC) return fail(GA_EINVAL, "run is not asynchronous");
+  GA_HIP(hipStreamSynchronize(r->stream), "stream sync");
+  unsigned long long n = 0;
+  GA_HIP(hipMemcpy(&n, r->view.waits + 1, sizeof(n), hipMemcpyDeviceToHost), "read taken");
+  *taken = n;
   return GA_OK;
 }
 

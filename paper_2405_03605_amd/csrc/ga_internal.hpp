@@ -46,7 +46,8 @@ struct RunView {
   //     buffer toward direction d for sending generations of parity p:
   //     2 * (g + 1) if it sent a genome that way in generation g, else
   //     2 * (g + 1) + 1;
-  //   waits: how often a wavefront stopped waiting for a neighbour and went on.
+  //   waits[0]: how often a wavefront stopped waiting for a neighbour and went
+  //     on; waits[1]: genomes absorbed from the buffers.
   uint32_t* mail;
   uint32_t* seen;
   uint32_t* prog;

@@ -60,7 +60,24 @@ __device__ __forceinline__ Genome load_genome(const float* pf, const uint32_t* p
 struct AsyncCtx {
   uint32_t lead;     // how many generations an island may run ahead of a neighbour
   uint32_t gave_up;  // waits for a neighbour that hit the spin limit
+  uint32_t taken;    // this lane's islands: genomes absorbed (per lane)
 };
+
+// Flush a wavefront's asynchronous counters: give-ups to waits[0], genomes
+// absorbed (summed over the lanes) to waits[1].
+__device__ __forceinline__ void flush_async(const RunView& v, const AsyncCtx& ax) {
+  uint32_t n = ax.taken;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) n += (uint32_t)__shfl_xor((int)n, m, 64);
+  if (__lane_id() == 0u) {
+    if (ax.gave_up)
+      __hip_atomic_fetch_add(v.waits, (unsigned long long)ax.gave_up, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    if (n)
+      __hip_atomic_fetch_add(v.waits + 1, (unsigned long long)n, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
 
 // One generation for islands [base, base + v.ipw) of a run, by one wavefront.
 // LC / SWC: log2 N and surface words fixed at compile time, or -1 to read them
@@ -175,6 +192,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
       __builtin_amdgcn_s_sleep(8);
     }
     hits = own_ok ? hits : 0u;
+    ax->taken += (uint32_t)__builtin_popcount(hits);
     // the entries, each with its stamp (the last one taken, as recorded)
     uint4 pay[4], pstr[4];
     uint32_t stamp[4];
@@ -287,6 +305,7 @@ __device__ __forceinline__ void chunk_generation(const RunView& v, uint32_t base
     for (uint32_t q = 0; q < 4; ++q) {
       const uint32_t again = load_agent(box[q] + ob_hdr);
       const bool hit = own_ok && ok[q] && again == stamp[q];
+      ax->taken += hit ? 1u : 0u;
       seen_q[q] = hit ? stamp[q] : seen_q[q];
       const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
       desc = hit ? (desc & ~(0xFFu << (8u * q))) | (slot << (8u * q)) : desc;
@@ -523,7 +542,7 @@ void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, ui
   const uint32_t end = min(first + chunks * v.ipw, v.islands);
   const uint64_t t0 = *v.gen;
   uint4* lds = wave_lds(wig, v.ipw, Model::kString ? 2u : 1u);
-  AsyncCtx ax{lead, 0u};
+  AsyncCtx ax{lead, 0u, 0u};
   for (uint64_t step = 0; step < n_gens + skew; ++step) {
     for (uint32_t base = first; base < end; base += v.ipw) {
       const uint64_t lag = skew ? (base / v.ipw) % (skew + 1u) : 0u;
@@ -531,9 +550,7 @@ void async_kernel(RunView v, uint32_t chunks, uint64_t n_gens, uint32_t lead, ui
       chunk_generation<LC, SWC, true, Model, WIDE>(v, base, t0 + step - lag, lds, &ax);
     }
   }
-  if (__lane_id() == 0u && ax.gave_up)
-    __hip_atomic_fetch_add(v.waits, (unsigned long long)ax.gave_up, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+  flush_async(v, ax);
 }
 
 // The asynchronous schedule with no lead and no skew: the lockstep exchange
@@ -549,13 +566,11 @@ void lockstep_kernel(RunView v, uint32_t chunks, uint64_t n_gens) {
   const uint32_t end = min(first + chunks * v.ipw, v.islands);
   const uint64_t t0 = *v.gen;
   uint4* lds = wave_lds(wig, v.ipw, Model::kString ? 2u : 1u);
-  AsyncCtx ax{0u, 0u};
+  AsyncCtx ax{0u, 0u, 0u};
   for (uint64_t step = 0; step < n_gens; ++step)
     for (uint32_t base = first; base < end; base += v.ipw)
       chunk_generation<LC, SWC, true, Model, WIDE, true>(v, base, t0 + step, lds, &ax);
-  if (__lane_id() == 0u && ax.gave_up)
-    __hip_atomic_fetch_add(v.waits, (unsigned long long)ax.gave_up, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+  flush_async(v, ax);
 }
 
 // Before a lockstep launch at generation t0. After one generation under the

@@ -121,6 +121,12 @@ class GARun:
         check(load().ga_async_waits(self._h, ctypes.byref(n)))
         return int(n.value)
 
+    def async_taken(self) -> int:
+        """Genomes absorbed from the neighbours' buffers since creation."""
+        n = ctypes.c_uint64()
+        check(load().ga_async_taken(self._h, ctypes.byref(n)))
+        return int(n.value)
+
     @property
     def asynchronous(self) -> bool:
         return self.cfg["schedule"] == 1

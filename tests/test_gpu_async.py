@@ -9,12 +9,11 @@ invariants every interleaving keeps and, statistically, against the
 synchronous schedule and a no-migration control."""
 import numpy as np
 import pytest
-from scipy import stats
 
 import oracle
 from gpu_helpers import assert_same_state, oracle_after, say
 from paper_2405_03605_amd import ASYNC_UNPACED, GABatch, GARun, GAError
-from paper_2405_03605_amd import phylo
+from paper_2405_03605_amd import async_stats
 from paper_2405_03605_amd.workloads import run_config
 
 pytestmark = pytest.mark.gpu
@@ -334,62 +333,84 @@ def test_async_errors():
 
 
 # --------------------------------------------------------------------------
-# statistics of the free-running schedule
+# statistics of the free-running schedule (the acceptance rule of
+# paper_2405_03605_amd.async_stats, fixed before these runs)
 # --------------------------------------------------------------------------
-STAT_CFG = dict(width=64, height=64, pop=32, sites=64, k=5, p32=429496729)
-STAT_GENS = 1500
-STAT_REPS = 10
+_REPS = {}
 
 
-def _run_stats(schedule, migration, seed, lead=0):
-    cfg = run_config(schedule=schedule, migration=migration, seed=seed, run_id=seed * 7, **STAT_CFG)
+def _reps(kind):
+    if kind not in _REPS:
+        n = async_stats.CONTROL_REPS if kind == "control" else async_stats.REPS
+        say(f"{n} replicates of {kind}, 64x64x32 x {async_stats.GENS} generations")
+        _REPS[kind] = [async_stats.replicate(kind, r) for r in range(n)]
+    return _REPS[kind]
+
+
+def _judged(kind):
+    res = async_stats.judge(_reps("sync"), _reps(kind), _reps("control"))
+    lost = np.mean([x["lost"] for x in _reps(kind)])
+    for key, v in res.items():
+        say(f"{kind} {key}: sync {v['sync_mean']:.4g} +- {v['sync_sd']:.3g}, async "
+            f"{v['async_mean']:.4g} +- {v['async_sd']:.3g}, control {v['control_mean']:.4g}; "
+            f"shift {v['shift_over_effect']:.3f} of the migration effect, "
+            f"{v['shift_over_se']:.2f} SE, KS p {v['ks_p']:.3g} -> "
+            f"{'pass' if v['pass'] else 'MISS'}")
+    say(f"{kind}: {lost:.4f} of sent genomes never absorbed")
+    return res
+
+
+def test_lead2_statistics_match_synchronous():
+    res = _judged("lead2")
+    assert all(v["pass"] for v in res.values()), {k: v["pass"] for k, v in res.items()}
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "finding: unpaced, about 18% of sent genomes are overwritten before they are read and "
+    "mean fitness falls 0.31 of the migration effect below the synchronous schedule "
+    "(85 standard errors); both tree metrics pass the rule"))
+def test_unpaced_statistics_match_synchronous():
+    res = _judged("unpaced")
+    assert all(v["pass"] for v in res.values()), {k: v["pass"] for k, v in res.items()}
+
+
+def test_statistics_have_power():
+    # without migration the islands share no ancestor since the founders: the
+    # trees are far longer, and fitness differs, by much more than the noise
+    sync, control = _reps("sync"), _reps("control")
+    for key in ("sum_branch_length", "mean_evolutionary_distinctiveness"):
+        a = np.array([x[key] for x in sync])
+        c = np.array([x[key] for x in control])
+        assert c.min() > a.max(), key
+
+
+def test_lockstep_absorbs_every_genome():
+    # paced (the lockstep exchange) with every wait met, each island takes the
+    # one genome each neighbour sent it, as the synchronous schedule does: one
+    # per island and generation, except in generation 0 (nothing was sent
+    # before it; what generation 299 sends is still in flight)
+    cfg = run_config(schedule=1, width=37, height=23, pop=16, sites=32)
     run = GARun(cfg)
-    if schedule:
-        run.set_async(0, lead)
-    run.step(STAT_GENS)
-    f = run.read(outbox=False)["f"]
-    ids, T, D = run.extract()
+    run.step(300)
+    assert run.async_waits() == 0
+    assert run.async_taken() == 37 * 23 * 299
     run.close()
-    L, U = phylo.mrca_matrix(T, D, 64)
-    W = STAT_CFG["width"]
-    isl = np.arange(W * STAT_CFG["height"])
-    east = (isl // W) * W + (isl % W + 1) % W
-    far = (isl // W) * W + (isl % W + W // 2) % W
-
-    def depth(j):
-        mid = (L[isl, j].astype(np.float64) + U[isl, j]) / 2
-        return float(np.mean(np.minimum(T[isl], T[j]) - mid))
-    return {"mean_fitness": float(f.mean()), "depth_adjacent": depth(east),
-            "depth_far": depth(far)}
+    with pytest.raises(GAError):
+        sync = GARun(run_config(width=4, height=4, pop=8))
+        try:
+            sync.async_taken()
+        finally:
+            sync.close()
 
 
-def test_loosely_paced_statistics_match_synchronous():
-    # With islands allowed a few generations apart, genomes arrive late or are
-    # overwritten, so the run is a different random process; its statistics
-    # are compared by effect size: the shift from the synchronous schedule must
-    # be a small fraction of what migration itself changes (synchronous against
-    # a no-migration control), or within three standard errors where that
-    # effect is small next to the noise. KS p-values and the unpaced
-    # schedule's shift are reported.
-    say(f"async vs sync statistics, {STAT_REPS} replicates of 64x64x32 x {STAT_GENS} generations")
-    sync = [_run_stats(0, 1, 1000 + r) for r in range(STAT_REPS)]
-    loose = [_run_stats(1, 1, 2000 + r, lead=2) for r in range(STAT_REPS)]
-    unpaced = [_run_stats(1, 1, 3000 + r, lead=ASYNC_UNPACED) for r in range(STAT_REPS // 2)]
-    control = [_run_stats(0, 0, 900 + r) for r in range(2)]
-    for key in ("mean_fitness", "depth_adjacent", "depth_far"):
-        a = np.array([r[key] for r in sync])
-        b = np.array([r[key] for r in loose])
-        u = np.array([r[key] for r in unpaced])
-        c = np.mean([r[key] for r in control])
-        effect = abs(a.mean() - c)
-        rel = abs(b.mean() - a.mean()) / effect
-        say(f"{key}: sync {a.mean():.3f} +- {a.std():.3f}, lead 2 {b.mean():.3f} +- {b.std():.3f} "
-            f"(shift {rel:.3f} of the migration effect, KS p {stats.ks_2samp(a, b).pvalue:.3g}), "
-            f"unpaced {u.mean():.3f} (shift {abs(u.mean() - a.mean()) / effect:.3f}), "
-            f"no migration {c:.3f}")
-        se = np.sqrt(a.var(ddof=1) / a.size + b.var(ddof=1) / b.size)
-        assert rel < 0.25 or abs(b.mean() - a.mean()) < 3 * se, key
-    # the statistics have power: without migration, neighbouring islands share
-    # no recent ancestor at all
-    adj = np.array([r["depth_adjacent"] for r in sync + loose])
-    assert min(r["depth_adjacent"] for r in control) > adj.max() * 2
+def test_lockstep_matches_the_oracle_at_paper_scale():
+    # the paper-scale grid (16.8M agents) in the lockstep launch against the
+    # oracle itself, three generations
+    cfg = run_config(pop=32, sites=32, k=2, width=1024, height=512)
+    say("lockstep vs oracle at 1024x512x32, 3 generations")
+    run = GARun(dict(cfg, schedule=1))
+    run.step(3)
+    got = run.read()
+    assert run.async_waits() == 0
+    run.close()
+    assert_same_state(got, oracle_after(cfg, 3), "lockstep 1024x512x32")
