@@ -18,9 +18,13 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libga_oracle.so")
+# GA_ORACLE_LIB names another build of the same source to load instead (the
+# sanitizer test's instrumented copy).
+LIB_PATH = os.environ.get("GA_ORACLE_LIB") or os.path.join(_HERE, "libga_oracle.so")
 SOURCES = [os.path.join(_HERE, "ga_oracle.c")]
 DISCARD = 0xFFFFFFFF
+_FLAGS = ["-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-fno-fast-math",
+          "-ffp-contract=off"]
 
 
 def build(force: bool = True) -> str:
@@ -28,11 +32,20 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(LIB_PATH):
         return LIB_PATH
     tmp = LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-           "-fno-fast-math", "-ffp-contract=off", "-o", tmp] + SOURCES + ["-lm"]
+    cmd = ["gcc", "-O2"] + _FLAGS + ["-o", tmp] + SOURCES + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
+
+
+def build_sanitized(out: str) -> str:
+    """The same source with AddressSanitizer and UndefinedBehaviorSanitizer
+    (any report aborts), into `out`; load it through GA_ORACLE_LIB with the
+    sanitizer runtimes preloaded."""
+    cmd = (["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+            "-fno-sanitize-recover=all"] + _FLAGS + ["-o", str(out)] + SOURCES + ["-lm"])
+    subprocess.run(cmd, check=True)
+    return str(out)
 
 
 class _Config(ctypes.Structure):
