@@ -255,6 +255,8 @@ struct orc_run {
 static int is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
 uint32_t orc_site_of_policy(uint64_t rank, uint32_t sites, uint32_t policy);
 
+static int model_known(uint32_t model);
+
 int orc_validate(const orc_config* cfg) {
   if (!cfg) return -1;
   if (cfg->width == 0 || cfg->height == 0) return -1;
@@ -270,7 +272,7 @@ int orc_validate(const orc_config* cfg) {
   if (cfg->selection > 1 || cfg->migration > 1) return -1;
   if (cfg->law > 1) return -1;
   if (cfg->law == 1 && (uint64_t)cfg->p_ben32 + cfg->p32 > 0xFFFFFFFFull) return -1;
-  if (cfg->model > 2) return -1;
+  if (!model_known(cfg->model)) return -1;
   if (cfg->model != 0 && cfg->law != 0) return -1;
   return 0;
 }
@@ -293,29 +295,97 @@ static float normal_draw(const uint32_t m[4]) {
 
 /* ----------------------------------------------------------------------- */
 /* Genome models (Sec. 2 Methods: the kernel takes any fixed-length genome  */
-/* through three functions, initialize, mutate and evaluate).               */
+/* through three functions, initialize, mutate and evaluate). Each model   */
+/* below is those three functions and one row of the table MODELS; the     */
+/* generation cycle calls only the table.                                  */
 /*   model 0  the genome is its fitness value (the paper's own runs): no    */
-/*            payload; mutation changes the fitness (law 0 or 1 above).     */
+/*            payload; mutation changes the fitness (law 0 or 1).           */
 /*   model 1  OneMax on a 64-bit string (payload words P0, P1): fitness is  */
 /*            the number of one bits.                                       */
 /*   model 2  Trap-4 on a 64-bit string (Deb and Goldberg's deceptive trap  */
 /*            of order 4): the string is 16 four-bit blocks, block b with u  */
 /*            one bits scores 4 if u = 4, else 3 - u; fitness is the sum.   */
-/* For models 1 and 2: initialize draws the founder's string as words 0 and */
-/* 1 of one block of the sampling stream at the counter's last generation   */
-/* (2^64 - 1, never a real one); mutate, with the same probability p as     */
-/* model 0, flips bit (w3 mod 64) of the child's string, bit b of the       */
-/* string being bit b mod 32 of word b / 32; evaluate runs after every      */
-/* mutation, and the stored fitness always equals evaluate(string).         */
+/* Models 1 and 2 share initialize and mutate: initialize draws the         */
+/* founder's string as words 0 and 1 of one block of the sampling stream at */
+/* the counter's last generation (2^64 - 1, never a real one); mutate, with */
+/* the same probability p as model 0, flips bit (w3 mod 64) of the child's  */
+/* string, bit b of the string being bit b mod 32 of word b / 32, and then  */
+/* evaluates the string, so the stored fitness always equals                */
+/* evaluate(string).                                                        */
 /* ----------------------------------------------------------------------- */
+typedef struct orc_model orc_model;
+struct orc_model {
+  /* founder in slot `slot` of island `island`: its payload P[0..1] and fitness */
+  void (*initialize)(const orc_model* m, const orc_config* cfg, uint32_t slot, uint32_t island,
+                     uint32_t* P, float* f);
+  /* the child in slot `slot` of island `island` at generation t, a copy of its
+   * parent: w is the child's selection block (words 2 and 3 are the mutation
+   * test and its detail) */
+  void (*mutate)(const orc_model* m, const orc_config* cfg, const uint32_t w[4], uint32_t slot,
+                 uint32_t island, uint64_t t, uint32_t* P, float* f);
+  /* fitness of a payload (NULL: the genome is its fitness) */
+  float (*evaluate)(const uint32_t P[2]);
+};
+
+/* model 0: founders +0; law 0 adds a delta from {-1, -0.5, 0, 0.5, 1}; law 1
+ * adds or subtracts a Normal size drawn from the mutation stream */
+static void fitness_initialize(const orc_model* m, const orc_config* cfg, uint32_t slot,
+                               uint32_t island, uint32_t* P, float* f) {
+  (void)m, (void)cfg, (void)slot, (void)island, (void)P;
+  *f = 0.0f;
+}
+
+static void fitness_mutate(const orc_model* m, const orc_config* cfg, const uint32_t w[4],
+                           uint32_t slot, uint32_t island, uint64_t t, uint32_t* P, float* f) {
+  (void)m, (void)P;
+  if (cfg->law == 0) {
+    if (w[2] < cfg->p32) {
+      uint32_t idx = (uint32_t)(((uint64_t)(w[3] & 0x7FFFFFFFu) * 5u) >> 31);
+      float delta = 0.5f * (float)((int)idx - 2);
+      *f = *f + delta;
+    }
+  } else {
+    int beneficial = w[2] < cfg->p_ben32;
+    int deleterious = !beneficial && (uint64_t)w[2] < (uint64_t)cfg->p_ben32 + cfg->p32;
+    if (beneficial || deleterious) {
+      uint32_t d[4];
+      draw(cfg, slot, island, t, TAG_MUTATE, d);
+      float size = fabsf(normal_draw(d));
+      *f = beneficial ? *f + size : *f - size;
+    }
+  }
+}
+
 static uint32_t ones_in(uint32_t v) {
   uint32_t n = 0;
   for (int b = 0; b < 32; ++b) n += (v >> b) & 1u;
   return n;
 }
 
-static float evaluate_model(uint32_t model, const uint32_t P[2]) {
-  if (model == 1) return (float)(ones_in(P[0]) + ones_in(P[1]));
+static void string_initialize(const orc_model* m, const orc_config* cfg, uint32_t slot,
+                              uint32_t island, uint32_t* P, float* f) {
+  uint32_t w[4];
+  draw(cfg, slot, island, UINT64_MAX, TAG_SAMPLE, w);
+  P[0] = w[0];
+  P[1] = w[1];
+  *f = m->evaluate(P);
+}
+
+static void string_mutate(const orc_model* m, const orc_config* cfg, const uint32_t w[4],
+                          uint32_t slot, uint32_t island, uint64_t t, uint32_t* P, float* f) {
+  (void)slot, (void)island, (void)t;
+  if (w[2] < cfg->p32) {
+    const uint32_t bit = w[3] & 63u;
+    P[bit / 32] ^= 1u << (bit % 32);
+    *f = m->evaluate(P);
+  }
+}
+
+static float onemax_evaluate(const uint32_t P[2]) {
+  return (float)(ones_in(P[0]) + ones_in(P[1]));
+}
+
+static float trap4_evaluate(const uint32_t P[2]) {
   uint32_t sum = 0;
   for (int b = 0; b < 16; ++b) {
     const uint32_t u = ones_in((P[b / 8] >> (4 * (b % 8))) & 0xFu);
@@ -324,15 +394,21 @@ static float evaluate_model(uint32_t model, const uint32_t P[2]) {
   return (float)sum;
 }
 
-static void initialize_model(orc_run* r) {
-  uint32_t w[4];
+static const orc_model MODELS[] = {
+    {fitness_initialize, fitness_mutate, NULL},           /* 0: fitness-valued */
+    {string_initialize, string_mutate, onemax_evaluate},  /* 1: OneMax */
+    {string_initialize, string_mutate, trap4_evaluate},   /* 2: Trap-4 */
+};
+#define N_MODELS (sizeof(MODELS) / sizeof(MODELS[0]))
+
+static int model_known(uint32_t model) { return model < N_MODELS; }
+
+static void initialize_founders(orc_run* r) {
+  const orc_model* m = &MODELS[r->cfg.model];
   for (uint64_t i = 0; i < r->islands; ++i)
     for (uint64_t s = 0; s < r->cfg.pop; ++s) {
       const uint64_t a = i * r->cfg.pop + s;
-      draw(&r->cfg, (uint32_t)s, (uint32_t)i, UINT64_MAX, TAG_SAMPLE, w);
-      r->P[a * 2] = w[0];
-      r->P[a * 2 + 1] = w[1];
-      r->f[a] = evaluate_model(r->cfg.model, &r->P[a * 2]);
+      m->initialize(m, &r->cfg, (uint32_t)s, (uint32_t)i, &r->P[a * 2], &r->f[a]);
     }
 }
 
@@ -364,7 +440,7 @@ orc_run* orc_create(const orc_config* cfg, int record_lineage) {
     orc_free(r);
     return NULL;
   }
-  if (cfg->model != 0) initialize_model(r);
+  initialize_founders(r);
   return r;
 }
 
@@ -455,28 +531,8 @@ static void reproduce_island(orc_run* r, uint64_t i, uint64_t t, uint8_t* win_ro
     copy_agent(r, r->f, r->T, r->D, r->P, i * N + best, r->nf, r->nT, r->nD, r->nP, child);
     if (win_row) win_row[child] = (uint8_t)best;
 
-    if (cfg->model != 0) {
-      if (w[2] < cfg->p32) {
-        const uint32_t bit = w[3] & 63u;
-        r->nP[child * 2 + bit / 32] ^= 1u << (bit % 32);
-        r->nf[child] = evaluate_model(cfg->model, &r->nP[child * 2]);
-      }
-    } else if (cfg->law == 0) {
-      if (w[2] < cfg->p32) {
-        uint32_t idx = (uint32_t)(((uint64_t)(w[3] & 0x7FFFFFFFu) * 5u) >> 31);
-        float delta = 0.5f * (float)((int)idx - 2);
-        r->nf[child] = r->nf[child] + delta;
-      }
-    } else {
-      int beneficial = w[2] < cfg->p_ben32;
-      int deleterious = !beneficial && (uint64_t)w[2] < (uint64_t)cfg->p_ben32 + cfg->p32;
-      if (beneficial || deleterious) {
-        uint32_t m[4];
-        draw(cfg, (uint32_t)s, (uint32_t)i, t, TAG_MUTATE, m);
-        float size = fabsf(normal_draw(m));
-        r->nf[child] = beneficial ? r->nf[child] + size : r->nf[child] - size;
-      }
-    }
+    MODELS[cfg->model].mutate(&MODELS[cfg->model], cfg, w, (uint32_t)s, (uint32_t)i, t,
+                              &r->nP[child * 2], &r->nf[child]);
 
     /* the differentia: one bit, the top bit of the selection block's word
      * 3; wider ones, the top dbits bits of word 0 of a block of their own
@@ -713,7 +769,7 @@ void orc_set_payload(orc_run* r, const uint32_t* P) {
 
 float orc_evaluate(uint32_t model, uint32_t p0, uint32_t p1) {
   const uint32_t P[2] = {p0, p1};
-  return model == 0 ? 0.0f : evaluate_model(model, P);
+  return model < N_MODELS && MODELS[model].evaluate ? MODELS[model].evaluate(P) : 0.0f;
 }
 
 void orc_get_population(const orc_run* r, float* f, uint32_t* T, uint32_t* D) {
