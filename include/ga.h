@@ -366,7 +366,9 @@ int ga_batch_add(ga_batch* batch, ga_run* run, uint64_t budget);
  * stream follows the batch's work so far; ga_generation is exact at once
  * (the batch keeps the host mirror). */
 int ga_batch_remove(ga_batch* batch, ga_run* run);
-/* Enqueue up to n_gens generations for every member with budget left. */
+/* Enqueue up to n_gens generations for every member with budget left. At
+ * most two step calls stay in flight: a call returns once the call two before
+ * it has run on the GPU (the one just enqueued keeps the GPU busy meanwhile). */
 int ga_batch_step(ga_batch* batch, uint64_t n_gens);
 /* Generations still owed to a member (host mirror). */
 uint64_t ga_batch_remaining(const ga_batch* batch, const ga_run* run);

@@ -245,10 +245,17 @@ struct ga_batch {
   bool graph_stale = true;     // the captured graph no longer matches
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph = nullptr;
-  // one event per step call (ring): a member whose budget ran out at step s is
-  // settled once the event of step s (or of a later step) has completed
+  // one event per step call (ring; step_of[i] the call whose event slot i
+  // holds): a member whose budget ran out at step s is settled once step s
+  // has completed. At most kStepsInFlight calls are left in flight (a call
+  // waits for the one kStepsInFlight before it), so the host cannot run
+  // ahead of the GPU by more than that, and a slot is reused only after its
+  // step is known complete (done_through: every step up to it has run).
   static constexpr int kStepEvents = 8;
+  static constexpr uint64_t kStepsInFlight = 2;
   hipEvent_t step_done[kStepEvents] = {};
+  uint64_t step_of[kStepEvents] = {};
+  uint64_t done_through = 0;
   uint64_t steps = 0;          // step calls so far
 };
 
@@ -1091,6 +1098,37 @@ uint64_t ga_batch_remaining(const ga_batch* b, const ga_run* r) {
   return 0;
 }
 
+namespace {
+
+// Whether step call s of the batch has completed (wait: block until it has).
+// Steps complete in stream order, so step s implies every earlier one.
+int step_complete(ga_batch* b, uint64_t s, bool wait, bool* done) {
+  *done = false;
+  if (s <= b->done_through) {
+    *done = true;
+    return GA_OK;
+  }
+  const int slot = (int)((s - 1) % ga_batch::kStepEvents);
+  const hipEvent_t ev = b->step_done[slot];
+  if (!ev || b->step_of[slot] < s) return fail(GA_ESTATE, "step not enqueued");
+  // a slot holding a later step is only reused after step s was known complete
+  if (b->step_of[slot] > s) {
+    b->done_through = std::max(b->done_through, s);
+    *done = true;
+    return GA_OK;
+  }
+  const hipError_t q = wait ? hipEventSynchronize(ev) : hipEventQuery(ev);
+  if (q == hipSuccess) {
+    b->done_through = std::max(b->done_through, s);
+    *done = true;
+  } else if (q != hipErrorNotReady) {
+    return hip_fail(q, "step event");
+  }
+  return GA_OK;
+}
+
+}  // namespace
+
 int ga_batch_settled(ga_batch* b, const ga_run* r, int* settled) {
   if (!b || !settled) return fail(GA_EINVAL, "batch or settled is NULL");
   for (size_t i = 0; i < b->members.size(); ++i) {
@@ -1102,12 +1140,10 @@ int ga_batch_settled(ga_batch* b, const ga_run* r, int* settled) {
       *settled = 1;
       return GA_OK;
     }
-    // slot (s - 1) mod the ring holds step s or a later step: its completion
-    // implies step s's (conservative once the ring has wrapped)
-    const hipEvent_t ev = b->step_done[(s - 1) % ga_batch::kStepEvents];
-    const hipError_t q = ev ? hipEventQuery(ev) : hipSuccess;
-    if (q == hipSuccess) *settled = 1;
-    else if (q != hipErrorNotReady) return hip_fail(q, "event query");
+    bool done = false;
+    const int rc = step_complete(b, s, false, &done);
+    if (rc != GA_OK) return rc;
+    *settled = done ? 1 : 0;
     return GA_OK;
   }
   return fail(GA_EINVAL, "run is not a member");
@@ -1333,9 +1369,18 @@ int ga_batch_step(ga_batch* b, uint64_t n) {
   // host mirrors: however the n generations are split into blocks, each
   // member advances by min(n, its remaining budget)
   b->steps += 1;
-  hipEvent_t& ev = b->step_done[(b->steps - 1) % ga_batch::kStepEvents];
+  const int slot = (int)((b->steps - 1) % ga_batch::kStepEvents);
+  hipEvent_t& ev = b->step_done[slot];
   if (!ev) GA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
   GA_HIP(hipEventRecord(ev, b->stream), "step event");
+  b->step_of[slot] = b->steps;
+  // the work just enqueued keeps the GPU busy while the host waits for the
+  // call kStepsInFlight before this one
+  if (b->steps > ga_batch::kStepsInFlight) {
+    bool done = false;
+    const int rc = step_complete(b, b->steps - ga_batch::kStepsInFlight, true, &done);
+    if (rc != GA_OK) return rc;
+  }
   for (size_t i = 0; i < b->members.size(); ++i) {
     const uint64_t adv = std::min<uint64_t>(b->remaining[i], n);
     b->members[i]->gen_host += adv;
@@ -1455,15 +1500,19 @@ int ga_pool_poll_settled(const ga_pool* p, uint64_t* tickets, size_t cap, size_t
 namespace {
 
 // One agent per island of run r (sampling stream at its current generation),
-// on the pool's side stream once everything enqueued so far on the batch
-// stream has run; waits for the side stream only.
-int pool_sample(ga_pool* p, ga_run* r, uint64_t* ids_out, uint32_t* T_out,
+// on the pool's side stream; waits for the side stream only. A settled run
+// (its last generation has run) is sampled at once: the batch's later work
+// only reads its counters and skips it. Otherwise the sampling follows
+// everything enqueued so far on the batch stream.
+int pool_sample(ga_pool* p, ga_run* r, bool settled, uint64_t* ids_out, uint32_t* T_out,
                 uint32_t* surface_words_out) {
   if (!p->side) GA_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking), "side stream");
   if (!p->batch_mark) GA_HIP(hipEventCreateWithFlags(&p->batch_mark, hipEventDisableTiming), "event");
   if (!p->side_mark) GA_HIP(hipEventCreateWithFlags(&p->side_mark, hipEventDisableTiming), "event");
-  GA_HIP(hipEventRecord(p->batch_mark, p->batch->stream), "mark batch");
-  GA_HIP(hipStreamWaitEvent(p->side, p->batch_mark, 0), "side waits");
+  if (!settled) {
+    GA_HIP(hipEventRecord(p->batch_mark, p->batch->stream), "mark batch");
+    GA_HIP(hipStreamWaitEvent(p->side, p->batch_mark, 0), "side waits");
+  }
   const ga::RunView& v = r->view;
   const size_t I = v.islands, W = v.words;
   uint32_t* st_ids = reinterpret_cast<uint32_t*>(r->base + r->lay.st_ids);
@@ -1496,7 +1545,9 @@ int ga_pool_retire(ga_pool* p, uint64_t ticket, uint64_t* ids_out, uint32_t* T_o
   // sample while the run is still a member (a failure leaves the pool as it was)
   const bool sampled = ids_out || T_out || surface_words_out;
   if (sampled) {
-    const int rc = pool_sample(p, r, ids_out, T_out, surface_words_out);
+    int settled = 0;
+    int rc = ga_batch_settled(p->batch, r, &settled);
+    if (rc == GA_OK) rc = pool_sample(p, r, settled != 0, ids_out, T_out, surface_words_out);
     if (rc != GA_OK) return rc;
   }
   const int rc = ga_batch_remove(p->batch, r);
