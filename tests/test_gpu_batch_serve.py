@@ -180,6 +180,26 @@ def test_settled_follows_the_gpu():
     batch.close()
 
 
+def test_settled_with_many_step_calls_enqueued():
+    # a member that finished in the first of many step calls reads settled once
+    # that call has run, however many calls were enqueued after it (a call
+    # returns once the call two before it has run, so after the third call the
+    # first has); its samples then equal the oracle's
+    short, long_ = GARun(UNEVEN[0]), GARun(UNEVEN[1])
+    batch = GABatch()
+    batch.add(short, 3)
+    batch.add(long_, 10 ** 6)
+    for _ in range(20):
+        batch.step(3)
+    assert batch.remaining(short) == 0 and batch.settled(short)
+    assert not batch.settled(long_)
+    batch.remove(short)
+    assert_same_state(short.read(), oracle_after(UNEVEN[0], 3), "member settled early")
+    batch.close()
+    for r in (short, long_):
+        r.close()
+
+
 def test_served_results_equal_alone_and_oracle():
     rng = np.random.default_rng(5)
     stream = []
