@@ -231,7 +231,7 @@ def bench_batched(gens: int, torch, tune: bool = True):
     shapes = {"waves_per_group": chosen["waves_per_group"]}
     shapes.update({f"N={1 << k[0]},words={k[1]}": {"islands_per_wave": v}
                    for k, v in sorted((k, v) for k, v in chosen.items() if k != "waves_per_group")})
-    return {"runs": len(cfgs), "agents": agents, "generations": gens,
+    return chosen, {"runs": len(cfgs), "agents": agents, "generations": gens,
             "plain_form": "each run alone in the library's default form (LDS-resident tiles "
                           "where it fits, else streaming)",
             "autotuned_shapes": shapes,
@@ -246,9 +246,11 @@ def bench_batched(gens: int, torch, tune: bool = True):
                          "kernel": "batch_all_kernel"}}
 
 
-def bench_served(n_requests: int, capacity: float, torch):
+def bench_served(n_requests: int, capacity: float, torch, shapes=None):
     """The served workload's Poisson stream (its first n_requests requests) at
-    80% of the measured batched capacity, full free HBM as budget."""
+    80% of the measured batched capacity, full free HBM as budget, the pool's
+    launch shape the one the autotuner chose for the batched workload (same
+    run mix)."""
     import numpy as np
 
     from paper_2405_03605_amd.serve import Server
@@ -260,7 +262,7 @@ def bench_served(n_requests: int, capacity: float, torch):
     arrivals = [(t / rate, c, g) for t, c, g in reqs]
     free, _ = torch.cuda.mem_get_info()
     budget = int(free - 8e9)
-    srv = Server(budget, max_slots=256, block=100)
+    srv = Server(budget, max_slots=256, block=100, shapes=shapes)
     progress(f"served leg: {n_requests} requests at {rate:.2f}/s")
 
     def report(server, elapsed):
@@ -391,11 +393,12 @@ def main():
         progress("resident leg: 256x256x32, tiles and streaming")
         out["resident"] = bench_resident(args.resident_gens, torch)
     if not args.no_batched:
-        out["batched"] = bench_batched(args.batched_gens, torch,
-                                       tune=not args.no_batch_autotune)
+        shapes, out["batched"] = bench_batched(args.batched_gens, torch,
+                                               tune=not args.no_batch_autotune)
         if args.served_requests > 0:
             out["served"] = bench_served(args.served_requests,
-                                         out["batched"]["batched_agent_gens_per_s"], torch)
+                                         out["batched"]["batched_agent_gens_per_s"], torch,
+                                         shapes=shapes)
     if not args.no_cpu_baseline:
         progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cfg)

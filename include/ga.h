@@ -421,6 +421,12 @@ int ga_pool_admit(ga_pool* pool, const ga_config* cfg, uint64_t n_gens, uint64_t
 int ga_pool_step(ga_pool* pool, uint64_t n_gens);
 /* Generations per graph replay (as ga_batch_set_graph_block). */
 int ga_pool_set_graph_block(ga_pool* pool, uint32_t gens_per_block);
+/* Launch shape of the pool's batch, as ga_batch_set_launch and
+ * ga_batch_set_class_launch (for the classes its runs may fall in; results do
+ * not depend on it). */
+int ga_pool_set_launch(ga_pool* pool, uint32_t islands_per_wave, uint32_t waves_per_group);
+int ga_pool_set_class_launch(ga_pool* pool, uint32_t log2n, uint32_t words,
+                             uint32_t islands_per_wave);
 /* Generations still owed to a run (host mirror). GA_EINVAL for an unknown ticket. */
 int ga_pool_remaining(const ga_pool* pool, uint64_t ticket, uint64_t* left);
 /* Tickets of the runs whose budget is spent: up to cap of them in tickets

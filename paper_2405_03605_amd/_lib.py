@@ -103,6 +103,8 @@ SIGNATURES = {
     "ga_pool_admit": (i32, [P, P, u64, ctypes.POINTER(u64)]),
     "ga_pool_step": (i32, [P, u64]),
     "ga_pool_set_graph_block": (i32, [P, u32]),
+    "ga_pool_set_launch": (i32, [P, u32, u32]),
+    "ga_pool_set_class_launch": (i32, [P, u32, u32, u32]),
     "ga_pool_remaining": (i32, [P, u64, ctypes.POINTER(u64)]),
     "ga_pool_poll": (i32, [P, P, sz, ctypes.POINTER(sz)]),
     "ga_pool_poll_settled": (i32, [P, P, sz, ctypes.POINTER(sz), i32]),

@@ -170,8 +170,15 @@ def autotune_batch(batch: GABatch, cfgs: list, gens: int = 100, use_cache: bool 
             r.close()
         _batch_cache[key] = chosen
     chosen = _batch_cache[key]
-    batch.set_launch(0, chosen["waves_per_group"])
+    apply_shapes(batch, chosen)
+    return dict(chosen)
+
+
+def apply_shapes(target, chosen: dict):
+    """Apply autotune_batch's choice to a GABatch or a GAPool (whose runs fall
+    in the same classes): the group size, then each class's islands per
+    wavefront."""
+    target.set_launch(0, chosen["waves_per_group"])
     for k, ipw in chosen.items():
         if k != "waves_per_group":
-            batch.set_class_launch(k[0], k[1], ipw)
-    return dict(chosen)
+            target.set_class_launch(k[0], k[1], ipw)

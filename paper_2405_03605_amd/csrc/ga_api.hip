@@ -1466,6 +1466,17 @@ int ga_pool_set_graph_block(ga_pool* p, uint32_t gens_per_block) {
   return ga_batch_set_graph_block(p->batch, gens_per_block);
 }
 
+int ga_pool_set_launch(ga_pool* p, uint32_t islands_per_wave, uint32_t waves_per_group) {
+  if (!p) return fail(GA_EINVAL, "pool is NULL");
+  return ga_batch_set_launch(p->batch, islands_per_wave, waves_per_group);
+}
+
+int ga_pool_set_class_launch(ga_pool* p, uint32_t log2n, uint32_t words,
+                             uint32_t islands_per_wave) {
+  if (!p) return fail(GA_EINVAL, "pool is NULL");
+  return ga_batch_set_class_launch(p->batch, log2n, words, islands_per_wave);
+}
+
 int ga_pool_remaining(const ga_pool* p, uint64_t ticket, uint64_t* left) {
   if (!p || !left) return fail(GA_EINVAL, "pool or left is NULL");
   auto it = p->members.find(ticket);

@@ -313,6 +313,14 @@ class GAPool:
     def set_graph_block(self, gens: int):
         check(load().ga_pool_set_graph_block(self._h, int(gens)))
 
+    def set_launch(self, islands_per_wave: int = 0, waves_per_group: int = 0):
+        check(load().ga_pool_set_launch(self._h, int(islands_per_wave), int(waves_per_group)))
+
+    def set_class_launch(self, log2n: int, words: int, islands_per_wave: int = 0):
+        """Islands per wavefront of one class (log2 N, surface words) of the pool's batch."""
+        check(load().ga_pool_set_class_launch(self._h, int(log2n), int(words),
+                                              int(islands_per_wave)))
+
     def remaining(self, ticket: int) -> int:
         left = ctypes.c_uint64()
         check(load().ga_pool_remaining(self._h, int(ticket), ctypes.byref(left)))

@@ -43,7 +43,7 @@ class Request:
 
 class Server:
     def __init__(self, budget_bytes: int, max_slots: int = 64, block: int = 100,
-                 make_pool=None, state_bytes=None, clock=time.perf_counter):
+                 make_pool=None, state_bytes=None, clock=time.perf_counter, shapes=None):
         if make_pool is None or state_bytes is None:
             from .run import GAPool, state_bytes as sb
             make_pool = make_pool or GAPool
@@ -54,6 +54,10 @@ class Server:
         self._state_bytes = state_bytes
         self.pool = make_pool(self.budget, self.max_slots)
         self.pool.set_graph_block(self.block)
+        if shapes:
+            # the launch shape the autotuner chose for a batch of this mix
+            from .autotune import apply_shapes
+            apply_shapes(self.pool, shapes)
         self.clock = clock
         self.waiting: deque[Request] = deque()
         self.live: dict[int, tuple[Request, int]] = {}   # ticket -> (request, ticket)

@@ -200,7 +200,10 @@ def test_settled_with_many_step_calls_enqueued():
         r.close()
 
 
-def test_served_results_equal_alone_and_oracle():
+@pytest.mark.parametrize("shapes", [None, {"waves_per_group": 2, (3, 1): 16, (3, 2): 64,
+                                             (4, 1): 4, (4, 2): 32, (5, 1): 2, (5, 2): 16}])
+def test_served_results_equal_alone_and_oracle(shapes):
+    # also with a launch shape applied to the pool as the autotuner would
     rng = np.random.default_rng(5)
     stream = []
     for i in range(10):
@@ -211,7 +214,7 @@ def test_served_results_equal_alone_and_oracle():
         stream.append((0.002 * i, cfg, int(rng.integers(50, 400))))
     import paper_2405_03605_amd as ga
     biggest = max(ga.state_bytes(c) for _, c, _ in stream)
-    srv = Server(budget_bytes=3 * biggest, max_slots=4, block=64)
+    srv = Server(budget_bytes=3 * biggest, max_slots=4, block=64, shapes=shapes)
     done = srv.drain(stream)
     srv.close()
     assert len(done) == len(stream)

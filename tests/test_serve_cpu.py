@@ -22,6 +22,13 @@ class FakePool:
     def set_graph_block(self, n):
         self.block = n
 
+    def set_launch(self, ipw=0, wpg=0):
+        self.launch = (ipw, wpg)
+
+    def set_class_launch(self, log2n, words, ipw=0):
+        self.classes = getattr(self, "classes", {})
+        self.classes[(log2n, words)] = ipw
+
     @property
     def used(self):
         return sum(self.size.values())
@@ -81,6 +88,16 @@ def sb(c):
 def make_server(budget, slots=8, block=10):
     return Server(budget, max_slots=slots, block=block, make_pool=FakePool, state_bytes=sb,
                   clock=Clock())
+
+
+def test_autotuned_shapes_reach_the_pool():
+    shapes = {"waves_per_group": 8, (3, 1): 32, (5, 2): 8}
+    srv = Server(10_000, max_slots=2, block=10, make_pool=FakePool, state_bytes=sb,
+                 clock=Clock(), shapes=shapes)
+    assert srv.pool.launch == (0, 8)
+    assert srv.pool.classes == {(3, 1): 32, (5, 2): 8}
+    plain = make_server(10_000)
+    assert not hasattr(plain.pool, "launch")
 
 
 def test_admission_respects_memory_and_order():
