@@ -20,13 +20,16 @@
 //                 outside the tile, to the HBM outbox;
 //   iterations    lanes are agent slots, 64/N islands per wavefront
 //                 iteration, tournament / copy / mutation / deposit (`breed`)
-//                 in registers, children written back in place;
+//                 in registers, children written back in place; iterations
+//                 are handed out one at a time from an LDS counter, so the
+//                 wavefronts finish together whatever the SIMDs favour;
 //   publish       after its first iteration each wavefront drains its HBM
 //                 stores and arrives on an LDS counter; the last one sets the
 //                 tile's progress word to t+1: its emissions of t are readable
 //                 and it has finished reading its neighbours' emissions of t-1;
-//   halo          wavefront 0, halfway through its iterations, polls the four
-//                 neighbouring tiles' progress words and, once they read t+1,
+//   halo          wavefront 0, once the tile is halfway through its
+//                 iterations, polls the four neighbouring tiles' progress
+//                 words and, once they read t+1,
 //                 loads their edge emissions of t (the halo of generation t+1)
 //                 into registers, staged in LDS after its last iteration (a
 //                 bounded wait there if they are late).
@@ -51,7 +54,8 @@ extern __shared__ uint32_t tile_lds[];
 // records), the island-id and packed (x, y) tables of TA / N islands, the outbox for
 // both parities (TI entries of ob_stride words each), the halo staging (one
 // entry per edge island and outward direction, at most 2 (tile_w + tile_h)),
-// the neighbour island each such pair reads, and one arrival counter.
+// the neighbour island each such pair reads, an arrival counter and two iteration
+// counters (one per generation parity).
 __host__ __device__ inline uint32_t tile_agents_padded(uint32_t ti_full, uint32_t log2n) {
   return ((ti_full << log2n) + 63u) & ~63u;
 }
@@ -134,6 +138,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
   uint32_t* halo = lob + 2u * TI * obs;                    // [pair * obs + k]
   uint32_t* halo_isl = halo + 2u * (v.tile_w + v.tile_h) * obs;  // [pair]: neighbour island
   uint32_t* arrivals = halo_isl + 2u * (v.tile_w + v.tile_h);
+  uint32_t* grab = arrivals + 1;  // [g & 1]: iterations handed out in generation g
   const uint32_t n_pairs = edges.count;
   // the HBM outbox entry (of plane `ob`) that edge pair p reads
   auto halo_src = [&](const uint32_t* ob, uint32_t p) {
@@ -153,7 +158,11 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
     torus_xy(x0 + lx, y0 + ly, q, W, H, &nx, &ny);
     halo_isl[p] = ny * W + nx;
   }
-  if (tid == 0u) *arrivals = 0u;
+  if (tid == 0u) {
+    *arrivals = 0u;
+    grab[0] = 0u;
+    grab[1] = 0u;
+  }
   __syncthreads();
   const uint64_t t0 = *v.gen;
   {
@@ -192,9 +201,6 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
   }
   const bool waits_on = lane < 4u && nb_tile != tile;
   uint32_t gave_up = 0u;
-  // this wavefront's iterations per generation (at least one: the launch
-  // has no more wavefronts than iterations)
-  const uint32_t my_iters = (n_iter - wave + nwaves - 1u) / nwaves;
 
   for (uint64_t g = 0; g < n_gens; ++g) {
     const uint64_t t = t0 + g;
@@ -204,6 +210,9 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
     uint32_t* __restrict__ out_ob = v.ob[p_out];
 
     // ---- island pass: one thread per island ---------------------------------
+    // (generation g - 1, the last user of the other counter, has passed its
+    // closing barrier; generation g + 1 reads it after this one's)
+    if (tid == 0u) grab[(g + 1u) & 1u] = 0u;
     for (uint32_t li = tid; li < ti; li += nthreads) {
       const uint32_t xy = lxy[li];
       const uint32_t x = xy & 0xFFFFu, y = xy >> 16;
@@ -278,10 +287,33 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
     uint32_t pf[obs];
     bool fetching = false;
     uint32_t polled = 0u, flag = 0u;
-    const uint32_t poll_at = my_iters / 2u;
     const BreedLane bl = breed_lane<LC>(v, t);
+    // Iterations are handed out from an LDS counter, one at a time: a
+    // wavefront the SIMD favours takes more of them, so the tile's wavefronts
+    // finish together instead of in age order (with a fixed share the
+    // youngest ran last, alone on their SIMDs). Each grab is issued an
+    // iteration ahead. Which wavefront computes an iteration does not change
+    // its children.
+    uint32_t* ctr = grab + (g & 1u);
+    auto take = [&]() {
+      uint32_t x = 0u;
+      if (lane == 0u)
+        x = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return x;
+    };
+    auto publish = [&]() {
+      drain_memory();
+      if (lane == 0u) {
+        const uint32_t before = __hip_atomic_fetch_add(arrivals, 1u, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (before == (uint32_t)(g + 1u) * nwaves - 1u) store_agent(v.prog + tile, due);
+      }
+    };
+    const uint32_t poll_from = n_iter / 2u;
     uint32_t k = 0;
-    for (uint32_t it = wave; it < n_iter; it += nwaves, ++k) {
+    uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane(take());
+    while (it < n_iter) {
+      const uint32_t next_it = take();
       const uint32_t la = (it << 6) + lane;
       const uint32_t li = la >> L;
       const uint32_t island = lisl[li];
@@ -301,15 +333,9 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
         pop[la] = make_uint4(__float_as_uint(c.f), c.T, c.D0, c.D1);
         if (kStr) pstr[la] = make_uint2(c.P0, c.P1);
       }
-      if (k == 0u) {
-        drain_memory();
-        if (lane == 0u) {
-          const uint32_t before = __hip_atomic_fetch_add(arrivals, 1u, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
-          if (before == (uint32_t)(g + 1u) * nwaves - 1u) store_agent(v.prog + tile, due);
-        }
-      }
-      if (wave == 0u && next && !fetching && k >= poll_at) {
+      if (k == 0u) publish();
+      ++k;
+      if (wave == 0u && next && !fetching && it >= poll_from) {
         // a poll issued one iteration ago is read now; a fresh one goes out
         if (polled) {
           drain_memory();
@@ -331,7 +357,11 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
           polled = 1u;
         }
       }
+      it = (uint32_t)__builtin_amdgcn_readfirstlane(next_it);
     }
+    // a wavefront that got no iteration still drains its island-pass stores
+    // and counts its arrival
+    if (k == 0u) publish();
 
     // ---- wavefront 0: finish the wait and stage the halo of t + 1 ------------
     if (wave == 0u && next) {
@@ -417,7 +447,7 @@ size_t tile_lds_bytes(uint32_t tile_w, uint32_t tile_h, uint32_t log2n, uint32_t
   const uint32_t TA = tile_agents_padded(TI, log2n);
   return 4u * ((size_t)tile_agent_words(model_has_string(model)) * TA +
                2u * tile_table_words(TA, log2n) + 2u * (size_t)TI * ob_stride +
-               2u * (size_t)(tile_w + tile_h) * (ob_stride + 1u) + 1u);
+               2u * (size_t)(tile_w + tile_h) * (ob_stride + 1u) + 3u);
 }
 
 uint32_t tile_threads(uint32_t tile_w, uint32_t tile_h, uint32_t log2n) {
