@@ -51,7 +51,7 @@ def tile_lds_estimate(tw: int, th: int, cfg: dict) -> int:
     words = cfg["sites"] * cfg.get("dbits", 1) // 32
     strings = cfg.get("model", 0) != 0
     ob = 4 if words == 1 and not strings else 8
-    agents = -(-tw * th * cfg["pop"] // 64) * 64
+    agents = -(-tw * th * cfg["pop"] // 64) * 64 + 2   # and two scratch records
     return agents * (24 if strings else 16) + 8 * tw * th + 8 * tw * th * ob + 8 * (tw + th) * (ob + 1) + 16
 
 

@@ -50,8 +50,9 @@ namespace {
 
 extern __shared__ uint32_t tile_lds[];
 
-// LDS words of a tile: the population as TA agent records (and TA string
-// records), the island-id and packed (x, y) tables of TA / N islands, the outbox for
+// LDS words of a tile: the population as TA agent records and two scratch
+// records (the same for strings; the scratch one takes arrivals that are not
+// taken, so the island pass writes without a branch), the island-id and packed (x, y) tables of TA / N islands, the outbox for
 // both parities (TI entries of ob_stride words each), the halo staging (one
 // entry per edge island and outward direction, at most 2 (tile_w + tile_h)),
 // the neighbour island each such pair reads, an arrival counter and two iteration
@@ -126,13 +127,14 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
   const uint32_t ti = w * h;
   const uint32_t TI = v.tile_w * v.tile_h;
   const uint32_t TA = tile_agents_padded(TI, L);
+  const uint32_t TR = TA + 2u;   // records: TA agents, scratch at TA (a pair keeps 16-byte alignment)
   const uint32_t TIP = TA >> L;  // islands covered by whole iterations
   const uint32_t n_iter = TA >> 6;
   const EdgePairs edges(w, h, W, H);
 
   uint4* pop = reinterpret_cast<uint4*>(tile_lds);         // [a]: f, T, D0, D1
-  uint2* pstr = reinterpret_cast<uint2*>(pop + TA);        // [a]: P0, P1 (strings)
-  uint32_t* lisl = tile_lds + TA * tile_agent_words(kStr);  // [li]: island id
+  uint2* pstr = reinterpret_cast<uint2*>(pop + TR);        // [a]: P0, P1 (strings)
+  uint32_t* lisl = tile_lds + TR * tile_agent_words(kStr);  // [li]: island id
   uint32_t* lxy = lisl + tile_table_words(TA, L);          // [li]: x | y << 16
   uint32_t* lob = lxy + tile_table_words(TA, L);           // [(p * TI + li) * obs + k]
   uint32_t* halo = lob + 2u * TI * obs;                    // [pair * obs + k]
@@ -201,6 +203,9 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
   }
   const bool waits_on = lane < 4u && nb_tile != tile;
   uint32_t gave_up = 0u;
+  // this thread's first island of the island pass (its coordinates never
+  // change; most tiles have no more islands than threads)
+  const uint32_t my_xy = tid < ti ? lxy[tid] : 0u;
 
   for (uint64_t g = 0; g < n_gens; ++g) {
     const uint64_t t = t0 + g;
@@ -214,53 +219,77 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
     // closing barrier; generation g + 1 reads it after this one's)
     if (tid == 0u) grab[(g + 1u) & 1u] = 0u;
     for (uint32_t li = tid; li < ti; li += nthreads) {
-      const uint32_t xy = lxy[li];
+      const uint32_t xy = li == tid ? my_xy : lxy[li];
       const uint32_t x = xy & 0xFFFFu, y = xy >> 16;
       const uint32_t lx = x - x0, ly = y - y0;
       const uint32_t island = y * W + x;
       const Block mig = philox10(0u, island, t_lo, t_hi4 | kStreamMigrate, v.seed, v.run_id);
       const uint32_t emig = L ? (mig.x >> (32u - L)) : 0u;
+      // The four neighbours' entries: a neighbour in the tile gives its LDS
+      // outbox entry of parity (t-1)&1, one outside the staged copy of its HBM
+      // outbox entry. All four are read before any arrival is written (the
+      // reads then go out together instead of each waiting on the previous
+      // write), and every entry is written, an arrival to its drawn slot and
+      // anything else to the scratch record, so there is no branch. Later
+      // directions overwrite earlier ones.
       bool edge = false;
+      uint32_t e[4][obs];
 #pragma unroll
       for (uint32_t q = 0; q < 4; ++q) {
         uint32_t nx, ny;
         torus_xy(x, y, q, W, H, &nx, &ny);
         const bool inside = nx - x0 < w && ny - y0 < h;
         edge |= !inside;
-        // a neighbour in the tile: its LDS outbox entry of parity (t-1)&1; one
-        // outside: the staged copy of its HBM outbox entry
         const uint32_t* src = inside ? lob + (p_in * TI + (ny - y0) * w + (nx - x0)) * obs
                                      : halo + edges.index(lx, ly, q) * obs;
-        uint32_t e[obs];
 #pragma unroll
         for (uint32_t k = 0; k < obs; k += 4) {
           const uint4 u = *reinterpret_cast<const uint4*>(src + k);
-          e[k] = u.x;
-          e[k + 1] = u.y;
-          e[k + 2] = u.z;
-          e[k + 3] = u.w;
-        }
-        if (e[ob_hdr] == (kMetaValid | (q ^ 2u))) {
-          const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
-          const uint32_t a = (li << L) + slot;
-          pop[a] = make_uint4(e[0], e[1], e[2], SW > 1 ? e[3] : 0u);
-          if (kStr) pstr[a] = make_uint2(e[4], e[5]);
+          e[q][k] = u.x;
+          e[q][k + 1] = u.y;
+          e[q][k + 2] = u.z;
+          e[q][k + 3] = u.w;
         }
       }
-      // the emission: the drawn member after immigration
+      // The emission is the drawn member after immigration: the last arrival
+      // drawn into its slot, else the member there before the pass (read
+      // now, ahead of the writes, so no read waits on them).
+      const uint32_t a_em = (li << L) + emig;
+      const uint4 pre = pop[a_em];
+      uint32_t em[6] = {pre.x, pre.y, pre.z, pre.w, 0u, 0u};
+      if (kStr) {
+        const uint2 ps = pstr[a_em];
+        em[4] = ps.x;
+        em[5] = ps.y;
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t slot = ((mig.z >> (8u * q)) & 0xFFu) >> (8u - L);
+        const bool hit = e[q][ob_hdr] == (kMetaValid | (q ^ 2u));
+        const uint32_t a = hit ? (li << L) + slot : TA;
+        const uint32_t w3 = SW > 1 ? e[q][3] : 0u;
+        pop[a] = make_uint4(e[q][0], e[q][1], e[q][2], w3);
+        if (kStr) pstr[a] = make_uint2(e[q][4], e[q][5]);
+        const bool takes = hit && slot == emig;
+        em[0] = takes ? e[q][0] : em[0];
+        em[1] = takes ? e[q][1] : em[1];
+        em[2] = takes ? e[q][2] : em[2];
+        em[3] = takes ? w3 : em[3];
+        if (kStr) {
+          em[4] = takes ? e[q][4] : em[4];
+          em[5] = takes ? e[q][5] : em[5];
+        }
+      }
       uint32_t o[obs];
 #pragma unroll
       for (uint32_t k = 0; k < obs; ++k) o[k] = 0u;
-      const uint32_t a = (li << L) + emig;
-      const uint4 em = pop[a];
-      o[0] = em.x;
-      o[1] = em.y;
-      o[2] = em.z;
-      if (SW > 1) o[3] = em.w;
+      o[0] = em[0];
+      o[1] = em[1];
+      o[2] = em[2];
+      if (SW > 1) o[3] = em[3];
       if (kStr) {
-        const uint2 es = pstr[a];
-        o[4] = es.x;
-        o[5] = es.y;
+        o[4] = em[4];
+        o[5] = em[5];
       }
       o[ob_hdr] = v.migration ? (kMetaValid | (mig.y >> 30)) : 0u;
       uint4* dst = reinterpret_cast<uint4*>(lob + (p_out * TI + li) * obs);
@@ -445,7 +474,7 @@ size_t tile_lds_bytes(uint32_t tile_w, uint32_t tile_h, uint32_t log2n, uint32_t
   (void)words;  // one 16-byte record per agent whatever the surface words
   const uint32_t TI = tile_w * tile_h;
   const uint32_t TA = tile_agents_padded(TI, log2n);
-  return 4u * ((size_t)tile_agent_words(model_has_string(model)) * TA +
+  return 4u * ((size_t)tile_agent_words(model_has_string(model)) * (TA + 2u) +
                2u * tile_table_words(TA, log2n) + 2u * (size_t)TI * ob_stride +
                2u * (size_t)(tile_w + tile_h) * (ob_stride + 1u) + 3u);
 }
