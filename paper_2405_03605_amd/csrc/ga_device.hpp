@@ -235,7 +235,17 @@ struct BreedLane {
   uint32_t lane0_addr;
   uint32_t t_lo, t_hi4;
   SelectStream sel, mut;
+  // the mutation thresholds, compared lane by lane: held in vector registers
+  // so that the loops do not keep (or reload) them in scalar ones
+  uint32_t p32, p_ben, p_any;
 };
+
+// A copy of a wavefront-uniform value in a vector register.
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
+  uint32_t r;
+  asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
 
 template <int LC>
 __device__ __forceinline__ BreedLane breed_lane(const RunView& v, uint64_t t) {
@@ -248,6 +258,9 @@ __device__ __forceinline__ BreedLane breed_lane(const RunView& v, uint64_t t) {
   b.t_hi4 = (uint32_t)(t >> 32) << 2;
   b.sel.init(b.slot, b.t_lo, b.t_hi4, v.seed, v.run_id, kStreamSelect);
   if (v.law) b.mut.init(b.slot, b.t_lo, b.t_hi4, v.seed, v.run_id, kStreamMutate);
+  b.p32 = in_vgpr(v.p32);
+  b.p_ben = in_vgpr(v.p_ben);
+  b.p_any = in_vgpr(v.p_any);
   return b;
 }
 
@@ -310,7 +323,7 @@ __device__ __forceinline__ Genome breed(const RunView& v, const BreedLane& b, co
   c.f = fbest;
 
   // 6. mutation, by the genome model
-  MutateArgs ma{v.p32, v.law, v.p_ben, v.p_any, &b.mut, island};
+  MutateArgs ma{b.p32, v.law, b.p_ben, b.p_any, &b.mut, island};
   Model::mutate(c, r, ma);
 
   // 7. stratum deposit at rank T, then T + 1. The hybrid policy sends even
