@@ -17,6 +17,10 @@ SOURCES = [os.path.join(_HERE, "csrc", n)
 BUILD_DIR = os.path.join(_HERE, "_build")
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per source: the tile kernel's LDS counters are bumped by one lane at a time;
+# the compiler's atomic optimizer would turn each such bump into a wavefront
+# scan that waits for its result on the spot.
+EXTRA_FLAGS = {"ga_tile.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_ESTATE = 0, -1, -2, -3, -4
 FORM_AUTO, FORM_STREAMING, FORM_RESIDENT = 0, 1, 2
@@ -41,7 +45,9 @@ def build(hipcc: str = "hipcc") -> str:
 
     def compile_one(src_obj):
         src, obj = src_obj
-        subprocess.run([hipcc] + HIPCC_FLAGS + ["-c", src, "-o", obj], check=True, stderr=quiet)
+        extra = EXTRA_FLAGS.get(os.path.basename(src), [])
+        subprocess.run([hipcc] + HIPCC_FLAGS + extra + ["-c", src, "-o", obj], check=True,
+                       stderr=quiet)
 
     with ThreadPoolExecutor(len(SOURCES)) as pool:
         list(pool.map(compile_one, zip(SOURCES, objs)))
