@@ -66,16 +66,21 @@ def algorithmic_lane_ops_per_agent_generation(cfg: dict) -> float:
     return child + island / cfg["pop"]
 
 
-def counter_record(mode: str):
+def counter_record(mode: str, tiles=None):
     """The committed counter record of a kernel, or None if its sources have
-    changed since the counters were taken."""
+    changed since the counters were taken (or, for a tile kernel, they were
+    taken on another tiling)."""
     from paper_2405_03605_amd.counters import source_hash
     try:
         with open(COUNTER_FILES[mode]) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    return rec if rec.get("kernel_source_sha256") == source_hash(mode) else None
+    if rec.get("kernel_source_sha256") != source_hash(mode):
+        return None
+    if tiles is not None and rec.get("tiles") != f"{tiles[0]}x{tiles[1]}":
+        return None
+    return rec
 
 
 def progress(msg: str):
@@ -165,9 +170,13 @@ def bench_resident(gens: int, torch):
     agents = MID["width"] * MID["height"] * MID["pop"]
     out = {"workload": "256x256 islands x 32 agents (2.1M), 32-site surface, tournament 2",
            "generations": gens}
+    from paper_2405_03605_amd.autotune import autotune
+    choice = autotune(MID, forms=(FORM_RESIDENT,))
     for name, form in (("resident", FORM_RESIDENT), ("streaming", FORM_STREAMING)):
         run = GARun(MID)
         run.set_launch(form=form)
+        if form == FORM_RESIDENT:
+            run.set_tiles(choice[0], choice[1])      # the autotuner's tiling
         tiles = run.tiles()
         wall, ev_ms = _timed(run, gens, 100, torch)
         run.close()
@@ -175,7 +184,7 @@ def bench_resident(gens: int, torch):
         out[f"{name}_agent_gens_per_s"] = agents * gens / wall
         out[f"{name}_us_per_generation"] = round(us, 3)
         if name == "resident":
-            out["roofline"] = roofline_tiles(MID, us, counter_record("mid-tiles"), tiles)
+            out["roofline"] = roofline_tiles(MID, us, counter_record("mid-tiles", tiles), tiles)
         else:
             out["streaming_hbm_frac"] = round(
                 algorithmic_bytes_per_generation(MID) / (us * 1e-6) / 1e9 / PEAK_HBM_GBPS, 4)
@@ -367,7 +376,8 @@ def main():
                          "launch_us": None, "us_per_generation": round(us_per_gen, 2)})
     elif tiles[2]:
         mode = "mid-tiles" if args.workload == "shard" else None
-        roofline = roofline_tiles(cfg, us_per_gen, counter_record(mode) if mode else None, tiles)
+        roofline = roofline_tiles(cfg, us_per_gen, counter_record(mode, tiles) if mode else None,
+                                  tiles)
     else:
         mode = "paper-streaming" if args.workload == "paper" else None
         roofline = roofline_streaming(cfg, us_per_gen, counter_record(mode) if mode else None)

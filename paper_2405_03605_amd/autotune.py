@@ -39,7 +39,16 @@ def candidates(cfg: dict) -> list[tuple]:
         ipw *= 2
     out.append((0, 0, FORM_RESIDENT))
     W, H = cfg["width"], cfg["height"]
-    for tw, th in ((W, H), (max(1, W // 2), max(1, H // 2)), (max(1, W // 4), max(1, H // 4))):
+    shapes = [(W, H), (max(1, W // 2), max(1, H // 2)), (max(1, W // 4), max(1, H // 4))]
+    # one tile per CU (256), square and at half and twice, four times the width
+    area = -(-W * H // 256)
+    side = 1
+    while side * side < area:
+        side *= 2
+    for tw in (side // 4, side // 2, side, side * 2, side * 4):
+        if tw >= 1:
+            shapes.append((min(tw, W), min(-(-area // tw), H)))
+    for tw, th in shapes:
         if tile_lds_estimate(tw, th, cfg) <= 160 * 1024 and (tw, th, FORM_RESIDENT) not in out:
             out.append((tw, th, FORM_RESIDENT))
     return out
@@ -74,11 +83,12 @@ def time_candidate(run: GARun, cand, gens: int, torch) -> float:
     return (time.perf_counter() - t0) / gens
 
 
-def autotune(cfg: dict, gens: int | None = None, use_cache: bool = True):
-    """Fastest candidate for cfg's shape (candidates that do not fit are skipped)."""
+def autotune(cfg: dict, gens: int | None = None, use_cache: bool = True, forms=None):
+    """Fastest candidate for cfg's shape (candidates that do not fit are
+    skipped), among those of the given forms (None: all)."""
     import torch
     from ._lib import GAError
-    key = shape_key(cfg)
+    key = (shape_key(cfg), tuple(forms) if forms else None)
     if use_cache and key in _cache:
         return _cache[key]
     agents = cfg["width"] * cfg["height"] * cfg["pop"]
@@ -87,6 +97,8 @@ def autotune(cfg: dict, gens: int | None = None, use_cache: bool = True):
     scratch = GARun(dict(cfg, seed=0x5eed, run_id=0xA070))
     best, best_t = None, float("inf")
     for cand in candidates(cfg):
+        if forms and cand[2] not in forms:
+            continue
         try:
             t = time_candidate(scratch, cand, gens, torch)
         except GAError:

@@ -44,8 +44,8 @@ KERNELS = {
     "mid-tiles": {"kernel": "tile_kernel", "sources": ["ga_tile.hip"] + COMMON,
                   "name": "tile_kernel<5,1,FitnessModel,false>",
                   "workload": "256x256 islands x 32 agents, 32-site surface, tournament 2, "
-                              "256 tiles of 16x16 islands",
-                  "gens_per_dispatch": 200},
+                              "the autotuner's tiling (one tile per CU)",
+                  "gens_per_dispatch": 200, "autotuned_tiles": True},
     "batch": {"kernel": "batch_all_kernel", "sources": ["ga_kernels.hip"] + COMMON,
               "name": "batch_all_kernel",
               "workload": "64 uneven runs, 8,597,368 agents, one launch per generation",
@@ -95,10 +95,30 @@ def _mean(dispatches, name, skip_first=True):
     return sum(vals) / len(vals)
 
 
+def autotuned_tiles() -> str:
+    """The tile shape the autotuner picks for the 256 x 256 x 32 workload in
+    the LDS-resident form, found in a child process outside the profiler."""
+    code = ("import torch; torch.cuda.set_device(0); "
+            "from paper_2405_03605_amd.autotune import autotune; "
+            "from paper_2405_03605_amd.workloads import MID; "
+            "from paper_2405_03605_amd import FORM_RESIDENT, GARun; "
+            "c = autotune(MID, forms=(FORM_RESIDENT,)); r = GARun(MID); "
+            "r.set_launch(form=FORM_RESIDENT); r.set_tiles(c[0], c[1]); "
+            "w, h, n = r.tiles(); print(f'{w}x{h}')")
+    out = subprocess.run([sys.executable, "-c", code], check=True, capture_output=True, text=True,
+                         timeout=300, cwd=ROOT)
+    return out.stdout.strip().splitlines()[-1]
+
+
 def collect(mode: str) -> dict:
     spec = KERNELS[mode]
     py = sys.executable
     cmd = [py, "-m", "paper_2405_03605_amd.profile_run", mode]
+    tiles = None
+    if spec.get("autotuned_tiles"):
+        tiles = autotuned_tiles()
+        print(f"[counters] autotuned tiles {tiles}", flush=True)
+        cmd += ["--tiles", tiles]
     calib = [py, "-m", "paper_2405_03605_amd.roofs", "--only", "inplace", "--reps", "2"]
     tmp = tempfile.mkdtemp(prefix="counters_", dir=os.environ.get("TMPDIR", "/tmp"))
     try:
@@ -124,6 +144,7 @@ def collect(mode: str) -> dict:
     rec = {
         "kernel": spec["name"], "workload": spec["workload"], "mode": mode,
         "kernel_source_sha256": source_hash(mode),
+        "tiles": tiles,
         "generations_per_dispatch": gens, "dispatches": len(sq),
         "fetch_scale": round(fetch_scale, 4), "write_scale": round(write_scale, 4),
         "fetch_kib_per_dispatch": round(fetch_kib, 1), "write_kib_per_dispatch": round(write_kib, 1),

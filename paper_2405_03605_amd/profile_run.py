@@ -9,7 +9,8 @@ profiler's per-dispatch counters compare across dispatches (graphs off).
   python -m paper_2405_03605_amd.profile_run batch-classes     # per class: one run plain, then batched
 
 --gens is the generations per dispatch for mid-tiles (default 200) and the
-dispatch count otherwise (default 12); --launches the tile launches (default 4).
+dispatch count otherwise (default 12); --launches the tile launches (default 4);
+--tiles WxH the tile shape of mid-tiles.
 """
 from __future__ import annotations
 
@@ -56,6 +57,7 @@ def main():
     ap.add_argument("mode", choices=MODES)
     ap.add_argument("--gens", type=int, default=None)
     ap.add_argument("--launches", type=int, default=4)
+    ap.add_argument("--tiles", default=None, help="mid-tiles: tile shape WxH (default: the library's)")
     args = ap.parse_args()
     import torch
     if not torch.cuda.is_available():
@@ -71,6 +73,9 @@ def main():
         gens = args.gens or 200
         run = GARun(MID)
         run.set_launch(form=FORM_RESIDENT)
+        if args.tiles:
+            tw, th = (int(x) for x in args.tiles.split("x"))
+            run.set_tiles(tw, th)
         assert run.tiles()[2] > 0
         for _ in range(args.launches):
             run.step(gens)          # one tile launch of `gens` generations each
