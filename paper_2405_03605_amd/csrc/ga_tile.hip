@@ -203,9 +203,36 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
   }
   const bool waits_on = lane < 4u && nb_tile != tile;
   uint32_t gave_up = 0u;
-  // this thread's first island of the island pass (its coordinates never
-  // change; most tiles have no more islands than threads)
-  const uint32_t my_xy = tid < ti ? lxy[tid] : 0u;
+  // An island's place in the pass: its id, its place in the tile, and for
+  // each direction the word offset in LDS of the entry it reads (the LDS
+  // outbox entry of parity 0 for a neighbour in the tile, add TI * obs for
+  // parity 1; the halo entry for one outside, whose bit in `inside` is 0).
+  struct IslandGeom {
+    uint32_t island, lx, ly, inside;
+    uint32_t src[4];
+  };
+  auto geom = [&](uint32_t li) {
+    const uint32_t xy = lxy[li];
+    const uint32_t x = xy & 0xFFFFu, y = xy >> 16;
+    IslandGeom gm;
+    gm.island = y * W + x;
+    gm.lx = x - x0;
+    gm.ly = y - y0;
+    gm.inside = 0u;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      uint32_t nx, ny;
+      torus_xy(x, y, q, W, H, &nx, &ny);
+      const bool in = nx - x0 < w && ny - y0 < h;
+      gm.inside |= (in ? 1u : 0u) << q;
+      gm.src[q] = in ? (uint32_t)(lob - tile_lds) + ((ny - y0) * w + (nx - x0)) * obs
+                     : (uint32_t)(halo - tile_lds) + edges.index(gm.lx, gm.ly, q) * obs;
+    }
+    return gm;
+  };
+  // this thread's first island of the pass, fixed for the launch (most tiles
+  // have no more islands than threads)
+  const IslandGeom my_geom = geom(tid < ti ? tid : 0u);
 
   for (uint64_t g = 0; g < n_gens; ++g) {
     const uint64_t t = t0 + g;
@@ -218,11 +245,8 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
     // (generation g - 1, the last user of the other counter, has passed its
     // closing barrier; generation g + 1 reads it after this one's)
     if (tid == 0u) grab[(g + 1u) & 1u] = 0u;
-    for (uint32_t li = tid; li < ti; li += nthreads) {
-      const uint32_t xy = li == tid ? my_xy : lxy[li];
-      const uint32_t x = xy & 0xFFFFu, y = xy >> 16;
-      const uint32_t lx = x - x0, ly = y - y0;
-      const uint32_t island = y * W + x;
+    auto island_pass = [&](const IslandGeom& gm, uint32_t li) {
+      const uint32_t island = gm.island;
       const Block mig = philox10(0u, island, t_lo, t_hi4 | kStreamMigrate, v.seed, v.run_id);
       const uint32_t emig = L ? (mig.x >> (32u - L)) : 0u;
       // The four neighbours' entries: a neighbour in the tile gives its LDS
@@ -232,16 +256,12 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
       // write), and every entry is written, an arrival to its drawn slot and
       // anything else to the scratch record, so there is no branch. Later
       // directions overwrite earlier ones.
-      bool edge = false;
+      const bool edge = gm.inside != 15u;
       uint32_t e[4][obs];
 #pragma unroll
       for (uint32_t q = 0; q < 4; ++q) {
-        uint32_t nx, ny;
-        torus_xy(x, y, q, W, H, &nx, &ny);
-        const bool inside = nx - x0 < w && ny - y0 < h;
-        edge |= !inside;
-        const uint32_t* src = inside ? lob + (p_in * TI + (ny - y0) * w + (nx - x0)) * obs
-                                     : halo + edges.index(lx, ly, q) * obs;
+        const uint32_t* src =
+            tile_lds + gm.src[q] + (((gm.inside >> q) & 1u) ? p_in * TI * obs : 0u);
 #pragma unroll
         for (uint32_t k = 0; k < obs; k += 4) {
           const uint4 u = *reinterpret_cast<const uint4*>(src + k);
@@ -301,7 +321,9 @@ __global__ __launch_bounds__(1024) void tile_kernel(RunView v, uint64_t n_gens) 
 #pragma unroll
         for (uint32_t k = 0; k < obs; k += 2) store_agent2(gdst + k, o[k], o[k + 1]);
       }
-    }
+    };
+    if (tid < ti) island_pass(my_geom, tid);
+    for (uint32_t li = tid + nthreads; li < ti; li += nthreads) island_pass(geom(li), li);
     __syncthreads();
 
     // ---- iterations: lanes are agent slots ----------------------------------
