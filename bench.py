@@ -237,9 +237,7 @@ def bench_batched(gens: int, torch, tune: bool = True):
     bytes_gen = sum(algorithmic_bytes_per_generation(c) for c in cfgs)
     achieved = bytes_gen * gens / batched / 1e9
     counters = counter_record("batch")
-    shapes = {"waves_per_group": chosen["waves_per_group"]}
-    shapes.update({f"N={1 << k[0]},words={k[1]}": {"islands_per_wave": v}
-                   for k, v in sorted((k, v) for k, v in chosen.items() if k != "waves_per_group")})
+    shapes = shape_names(chosen)
     return chosen, {"runs": len(cfgs), "agents": agents, "generations": gens,
             "plain_form": "each run alone in the library's default form (LDS-resident tiles "
                           "where it fits, else streaming)",
@@ -255,11 +253,19 @@ def bench_batched(gens: int, torch, tune: bool = True):
                          "kernel": "batch_all_kernel"}}
 
 
-def bench_served(n_requests: int, capacity: float, torch, shapes=None):
+def shape_names(chosen: dict) -> dict:
+    """autotune_batch's choice with readable class names."""
+    out = {"waves_per_group": chosen["waves_per_group"]}
+    out.update({f"N={1 << k[0]},words={k[1]}": {"islands_per_wave": v}
+                for k, v in sorted((k, v) for k, v in chosen.items() if k != "waves_per_group")})
+    return out
+
+
+def bench_served(n_requests: int, capacity: float, torch, tune: bool = True):
     """The served workload's Poisson stream (its first n_requests requests) at
     80% of the measured batched capacity, full free HBM as budget, the pool's
-    launch shape the one the autotuner chose for the batched workload (same
-    run mix)."""
+    launch shape chosen by the autotuner on a batch of the stream's first 64
+    requests (the served mix, not the batched one)."""
     import numpy as np
 
     from paper_2405_03605_amd.serve import Server
@@ -271,6 +277,18 @@ def bench_served(n_requests: int, capacity: float, torch, shapes=None):
     arrivals = [(t / rate, c, g) for t, c, g in reqs]
     free, _ = torch.cuda.mem_get_info()
     budget = int(free - 8e9)
+    shapes = None
+    if tune:
+        from paper_2405_03605_amd.autotune import autotune_batch
+
+        class _Keep:      # collects the choice; the server applies it to its pool
+            def set_launch(self, ipw, wpg):
+                pass
+
+            def set_class_launch(self, log2n, words, ipw):
+                pass
+        shapes = autotune_batch(_Keep(), [c for _, c, _ in reqs[:64]])
+        progress(f"served leg: shapes {shapes}")
     srv = Server(budget, max_slots=256, block=100, shapes=shapes)
     progress(f"served leg: {n_requests} requests at {rate:.2f}/s")
 
@@ -286,6 +304,8 @@ def bench_served(n_requests: int, capacity: float, torch, shapes=None):
     srv.close()
     rep.update({"requests": n_requests, "rate_per_s": rate, "budget_bytes": budget,
                 "mean_work_agent_gens": mean_work})
+    if shapes:
+        rep["autotuned_shapes"] = shape_names(shapes)
     return rep
 
 
@@ -403,12 +423,12 @@ def main():
         progress("resident leg: 256x256x32, tiles and streaming")
         out["resident"] = bench_resident(args.resident_gens, torch)
     if not args.no_batched:
-        shapes, out["batched"] = bench_batched(args.batched_gens, torch,
-                                               tune=not args.no_batch_autotune)
+        _, out["batched"] = bench_batched(args.batched_gens, torch,
+                                          tune=not args.no_batch_autotune)
         if args.served_requests > 0:
             out["served"] = bench_served(args.served_requests,
                                          out["batched"]["batched_agent_gens_per_s"], torch,
-                                         shapes=shapes)
+                                         tune=not args.no_batch_autotune)
     if not args.no_cpu_baseline:
         progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cfg)
