@@ -225,7 +225,7 @@ struct ga_batch {
   std::vector<ga_run*> members;
   std::vector<uint64_t> remaining;
   std::vector<uint64_t> finished_step;  // step call at which the member's budget ran out
-  // device tables: [views: view_cap RunViews][tiles: tile_cap][tile count, member count]
+  // device tables: [views: view_cap RunViews][tiles: tile_cap slots][tile count, member count]
   uint8_t* d_tab = nullptr;
   uint32_t view_cap = 0, tile_cap = 0;
   // pinned staging for the table uploads, two buffers used in turn, each free
@@ -1200,6 +1200,48 @@ uint32_t pow2_at_least(uint32_t v) {
   return p;
 }
 
+// Algorithmic bytes a tile moves in one generation: each agent's fitness,
+// lineage counter and surface read and written, each island's outbox entry
+// read and written.
+uint64_t tile_bytes(const ga::RunView& v, uint32_t islands) {
+  const uint64_t agent = 2u * (8u + 4u * v.words), island = 2u * (12u + 4u * v.words);
+  return (uint64_t)islands * (((uint64_t)1 << v.log2n) * agent + island);
+}
+
+// Place the tiles (in class order) in the launch's wavefront slots. The
+// dispatcher hands workgroup g to XCD g mod 8, each XCD with its own L2: the
+// tiles are cut into eight contiguous stretches of about equal bytes
+// (wavefronts of different classes move different amounts), stretch x fills
+// XCD x's workgroups x, x + 8, x + 16, ... wpg tiles each, in order, so a
+// member's neighbouring tiles share an L2 and no XCD is left with a heavier
+// share to finish alone. Returns the slots the placement spans (a multiple of
+// 8 wpg); slot[i] is tile i's slot.
+uint32_t place_tiles(const std::vector<ga::RunView>& views, const std::vector<ga::Tile>& tiles,
+                     uint32_t wpg, std::vector<uint32_t>& slot) {
+  slot.assign(tiles.size(), 0u);
+  if (tiles.empty()) return 0;
+  std::vector<uint64_t> w(tiles.size());
+  uint64_t total = 0;
+  for (size_t i = 0; i < tiles.size(); ++i) {
+    const ga::RunView& v = views[tiles[i].run];
+    w[i] = tile_bytes(v, std::min(v.ipw, v.islands - tiles[i].first));
+    total += w[i];
+  }
+  // tile i goes to the XCD whose eighth of the bytes holds its midpoint
+  uint32_t count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint64_t before = 0;
+  uint32_t groups = 0;
+  for (size_t i = 0; i < tiles.size(); ++i) {
+    const uint64_t mid2 = 2 * before + w[i];  // twice the midpoint
+    const uint32_t x = (uint32_t)std::min<uint64_t>(7, mid2 * 8 / (2 * total));
+    const uint32_t k = count[x]++;
+    slot[i] = ((k / wpg) * 8u + x) * wpg + k % wpg;
+    groups = std::max(groups, k / wpg + 1);
+    before += w[i];
+  }
+  return groups * 8u * wpg;
+}
+
 // Rebuild the device tables for the current members and upload them in the
 // batch's stream order (no wait: a kernel already enqueued keeps reading the
 // old contents until the copy runs after it). Capacities grow (with a wait
@@ -1214,21 +1256,30 @@ int rebuild_tables(ga_batch* b) {
     v.ipw = class_ipw(b, class_of(v));
     max_ipw = std::max(max_ipw, v.ipw);
     views.push_back(v);
-    for (uint32_t first = 0; first < v.islands; first += v.ipw) tiles.push_back({m, first});
+    for (uint32_t first = 0; first < v.islands; first += v.ipw)
+      tiles.push_back({m, first, class_of(v), 0u});
   }
   // wavefronts of one class side by side: neighbouring wavefronts on a CU
   // then run the same shape and share instruction-cache lines
-  std::stable_sort(tiles.begin(), tiles.end(), [&](const ga::Tile& a, const ga::Tile& c) {
-    return class_of(views[a.run]) < class_of(views[c.run]);
-  });
+  std::stable_sort(tiles.begin(), tiles.end(),
+                   [](const ga::Tile& a, const ga::Tile& c) { return a.cls < c.cls; });
   for (BatchClass& k : b->cls) k.n_tiles = 0;
-  for (const ga::Tile& t : tiles) b->cls[class_of(views[t.run])].n_tiles += 1;
-  if (views.size() > b->view_cap || tiles.size() > b->tile_cap || !b->d_tab) {
+  for (const ga::Tile& t : tiles) b->cls[t.cls].n_tiles += 1;
+  std::vector<uint32_t> slot;
+  const uint32_t span = place_tiles(views, tiles, b->wpg, slot);
+  // the graph's grid covers the placement with headroom; it is captured
+  // again only when a placement outgrows it or the launch shape changes (the
+  // largest islands per wavefront sizes each wavefront's LDS)
+  const uint32_t unit = 8u * b->wpg;  // whole groups on every XCD
+  uint32_t grid = b->grid_waves;
+  if (span > grid || b->wpg != b->use_wpg)
+    grid = ceil_div(std::max(grid, pow2_at_least(span)), unit) * unit;
+  if (views.size() > b->view_cap || grid > b->tile_cap || !b->d_tab) {
     GA_HIP(hipStreamSynchronize(b->stream), "stream sync");
     if (b->d_tab) GA_HIP(hipFree(b->d_tab), "free tables");
     b->d_tab = nullptr;
     b->view_cap = std::max<uint32_t>({64u, b->view_cap, (uint32_t)views.size() * 2});
-    b->tile_cap = std::max<uint32_t>({4096u, b->tile_cap, (uint32_t)tiles.size() * 2});
+    b->tile_cap = std::max<uint32_t>({4096u, b->tile_cap, grid * 2});
     GA_HIP(hipMalloc(&b->d_tab, tab_bytes(b)), "alloc tables");
     for (int i = 0; i < 2; ++i) {
       if (b->h_stage[i]) GA_HIP(hipHostFree(b->h_stage[i]), "free staging");
@@ -1246,18 +1297,14 @@ int rebuild_tables(ga_batch* b) {
   std::memset(st, 0, b->stage_bytes);
   for (ga::RunView& v : views) to_table(v, b->d_tab);
   if (!views.empty()) std::memcpy(st, views.data(), views.size() * sizeof(ga::RunView));
-  if (!tiles.empty())
-    std::memcpy(st + tab_tiles_off(b), tiles.data(), tiles.size() * sizeof(ga::Tile));
+  ga::Tile* tab = reinterpret_cast<ga::Tile*>(st + tab_tiles_off(b));
+  for (uint32_t i = 0; i < b->tile_cap; ++i) tab[i] = {0u, 0u, ga::kNoTile, 0u};
+  for (size_t i = 0; i < tiles.size(); ++i) tab[slot[i]] = tiles[i];
   uint32_t* counts = reinterpret_cast<uint32_t*>(st + tab_counts_off(b));
   counts[0] = (uint32_t)tiles.size();
   counts[1] = (uint32_t)views.size();
-  // the graph covers the tiles with headroom; it is captured again only when
-  // they outgrow it or the launch shape changes (the largest islands per
-  // wavefront sizes each wavefront's LDS)
-  if (tiles.size() > b->grid_waves) {
-    b->grid_waves = pow2_at_least((uint32_t)tiles.size());
-    b->graph_stale = true;
-  }
+  if (grid != b->grid_waves) b->graph_stale = true;
+  b->grid_waves = grid;
   if (max_ipw != b->use_max_ipw || b->wpg != b->use_wpg) b->graph_stale = true;
   b->use_max_ipw = max_ipw;
   b->use_wpg = b->wpg;
@@ -1280,8 +1327,8 @@ const uint32_t* tab_count(const ga_batch* b, uint32_t i) {
 }
 
 hipError_t launch_gen(ga_batch* b, uint32_t gen_offset, hipStream_t s) {
-  return ga::launch_batch_all(tab_views(b), tab_tiles(b), tab_count(b, 0), b->grid_waves,
-                              gen_offset, b->use_max_ipw, b->use_wpg, s);
+  return ga::launch_batch_all(tab_views(b), tab_tiles(b), b->grid_waves, gen_offset,
+                              b->use_max_ipw, b->use_wpg, s);
 }
 
 int batch_direct(ga_batch* b, uint64_t n) {

@@ -24,7 +24,8 @@ struct RunView {
   uint32_t* pop_D;
   uint32_t* ob[2];
   unsigned long long* gen;   // generation counter t (device)
-  unsigned long long* left;  // generations still owed in the current batch block (batch only)
+  unsigned long long* left;  // generations still owed in the current batch block (batch
+                             // only); always the word after *gen
   uint32_t width, height, islands, agents;
   uint32_t island_stride, agent_stride;
   uint32_t log2n, words, k, selection;
@@ -76,12 +77,19 @@ constexpr uint32_t kPaceSpins = 2048;
 // milliseconds (first touches of a multi-GB mail plane).
 constexpr uint32_t kLockSpins = 32768;
 
-// One wavefront's share of a batched launch: islands [first, first + ipw) of run `run`.
+// One wavefront's share of a batched launch: islands [first, first + ipw) of
+// member `run`, whose class is `cls` (read with the tile, so the wavefront
+// branches to its body before it reads anything of the member). The table
+// has one slot per wavefront of the launch; a slot no tile takes has class
+// kNoTile.
 // Batch classes: one per (log2 N, surface words), index log2 N * 2 + words - 1.
 constexpr uint32_t kBatchClasses = 14;
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 struct Tile {
   uint32_t run;
   uint32_t first;
+  uint32_t cls;
+  uint32_t pad;
 };
 
 constexpr uint32_t kMetaValid = 4u;
@@ -123,11 +131,12 @@ hipError_t launch_fill(uint32_t* p, uint32_t value, size_t words, hipStream_t st
 hipError_t launch_sample(const RunView& v, uint32_t* ids, hipStream_t stream);
 hipError_t launch_gather(const RunView& v, const uint32_t* ids, uint32_t n, uint32_t* T_out,
                          uint32_t* D_out, hipStream_t stream);
-// One generation of a batch: grid_waves wavefronts over the members' tiles,
-// of which *n_tiles (device memory) are live; LDS sized for max_ipw.
-hipError_t launch_batch_all(const RunView* views, const Tile* tiles, const uint32_t* n_tiles,
-                            uint32_t grid_waves, uint32_t gen_offset, uint32_t max_ipw,
-                            uint32_t waves_per_group, hipStream_t stream);
+// One generation of a batch: grid_waves wavefronts, wavefront w running
+// tiles[w] (the table holds grid_waves slots; an empty one has class
+// kNoTile); LDS sized for max_ipw.
+hipError_t launch_batch_all(const RunView* views, const Tile* tiles, uint32_t grid_waves,
+                            uint32_t gen_offset, uint32_t max_ipw, uint32_t waves_per_group,
+                            hipStream_t stream);
 hipError_t launch_store_u64(unsigned long long* p, unsigned long long value, hipStream_t stream);
 // Close a block of a batch: *n_runs members (device count), a grid for cap.
 hipError_t launch_batch_advance(const RunView* views, const uint32_t* n_runs, uint32_t cap,

@@ -649,36 +649,71 @@ __device__ __forceinline__ void from_table(RunView& v, const RunView* table) {
   v.left = table_ptr(table, v.left);
 }
 
+// Memory that stays unchanged for a whole launch (the member table, a
+// member's counters) is read through the constant address space, which the
+// compiler issues as scalar loads straight into scalar registers: the batched
+// form's member pointers then stay scalar (and global) through the
+// generation's loop, as a plain launch's kernel arguments do, and a
+// wavefront's start waits on no vector memory round trip for them.
+typedef __attribute__((address_space(4))) const uint32_t ConstWord;
+__device__ __forceinline__ uint32_t const_word(const void* p) {
+  return *(ConstWord*)p;
+}
+__device__ __forceinline__ uint64_t const_u64(const void* p) {
+  return (uint64_t)const_word(p) | ((uint64_t)const_word((const char*)p + 4) << 32);
+}
+// Member `run` of the table, one word at a time (an aggregate copy would be
+// turned back into vector loads).
+__device__ __forceinline__ RunView load_member(const RunView* table, uint32_t run) {
+  RunView v;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(table + run);
+#pragma unroll
+  for (uint32_t i = 0; i < sizeof(RunView) / 4; ++i) dst[i] = const_word(src + i);
+  from_table(v, table);
+  return v;
+}
+
+// Every view word a synchronous body reads, requested before the member's
+// counters are read (and both counters before they are tested): left to
+// itself the compiler issues them after that test, a few at a time, and a
+// starting wavefront waits on one scalar round trip after another before its
+// first genome load.
+__device__ __forceinline__ void view_ready(const RunView& v) {
+  asm volatile("" ::"s"(v.pop_f), "s"(v.pop_T), "s"(v.pop_D), "s"(v.ob[0]), "s"(v.ob[1]),
+               "s"(v.width), "s"(v.height), "s"(v.islands), "s"(v.agent_stride), "s"(v.ipw),
+               "s"(v.seed), "s"(v.run_id), "s"(v.migration), "s"(v.k), "s"(v.selection),
+               "s"(v.p32), "s"(v.law), "s"(v.p_ben), "s"(v.p_any), "s"(v.s_log), "s"(v.dlog),
+               "s"(v.policy));
+}
+
 // Batched form, one launch per generation over every member's tiles (sorted by
-// class, so neighbouring wavefronts run the same shape). The grid has headroom
-// past the live tiles (*n_tiles, device memory, so a captured launch follows
-// membership changes): only its first live_groups groups work, renumbered
-// over that count so that all eight XCDs share them. Each wavefront branches
-// (uniformly) to the body compiled for its member's log2 N and surface words.
+// class, so neighbouring wavefronts run the same shape). Wavefront w runs the
+// tile in slot w of the table, which the host lays out so that each XCD's
+// workgroups (the dispatcher hands workgroup g to XCD g mod 8) take a
+// contiguous stretch of tiles of about equal bytes; slots past the live tiles
+// are empty, so a captured launch follows membership changes. Each wavefront
+// branches (uniformly) to the body compiled for its member's log2 N and
+// surface words.
 __global__ __launch_bounds__(1024) void batch_all_kernel(const RunView* __restrict__ views,
                                                          const Tile* __restrict__ tiles,
-                                                         const uint32_t* __restrict__ n_tiles,
                                                          uint32_t gen_offset, uint32_t max_ipw) {
   const uint32_t wig = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t wpg = blockDim.x >> 6;
-  const uint32_t n = *n_tiles;
-  const uint32_t live_groups = (n + wpg - 1) / wpg;
-  if (blockIdx.x >= live_groups) return;
-  const uint32_t wave = xcd_band(blockIdx.x, live_groups) * wpg + wig;
-  if (wave >= n) return;
-  const Tile tile = tiles[wave];
-  const RunView* vp = views + tile.run;
+  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wig;
+  const uint32_t run = const_word(&tiles[wave].run), first = const_word(&tiles[wave].first);
   uint4* lds = wave_lds(wig, max_ipw, 1u);
-  // only the class is read before the branch; each body loads the rest of
-  // the view itself, so nothing of it stays live across the branch
-  const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane(vp->log2n * 2u + vp->words - 1u);
-  switch (c) {
+  // only the tile is read before the branch; each body loads the member's
+  // view itself (nothing of it stays live across the branch), then its two
+  // counters side by side (the budget left follows the generation counter)
+  switch (const_word(&tiles[wave].cls)) {
 #define GA_BATCH_CASE(L, S)                                  \
   case L * 2 + S - 1: {                                      \
-    RunView v = *vp;                                         \
-    from_table(v, views);                                    \
-    if (*v.left <= gen_offset) return;                       \
-    chunk_generation<L, S>(v, tile.first, *v.gen + gen_offset, lds); \
+    const RunView v = load_member(views, run);               \
+    view_ready(v);                                           \
+    const uint64_t t0 = const_u64(v.gen), left = const_u64(v.gen + 1); \
+    asm volatile("" ::"s"(t0), "s"(left));                   \
+    if (left <= gen_offset) return;                          \
+    chunk_generation<L, S>(v, first, t0 + gen_offset, lds);  \
     break;                                                   \
   }
     GA_BATCH_CASE(0, 1) GA_BATCH_CASE(0, 2) GA_BATCH_CASE(1, 1) GA_BATCH_CASE(1, 2)
@@ -686,7 +721,7 @@ __global__ __launch_bounds__(1024) void batch_all_kernel(const RunView* __restri
     GA_BATCH_CASE(4, 1) GA_BATCH_CASE(4, 2) GA_BATCH_CASE(5, 1) GA_BATCH_CASE(5, 2)
     GA_BATCH_CASE(6, 1) GA_BATCH_CASE(6, 2)
 #undef GA_BATCH_CASE
-    default: break;  // no such class: members are validated on admission
+    default: break;  // an empty slot (members' classes are validated on admission)
   }
 }
 
@@ -819,14 +854,15 @@ hipError_t launch_gather(const RunView& v, const uint32_t* ids, uint32_t n, uint
   return hipGetLastError();
 }
 
-hipError_t launch_batch_all(const RunView* views, const Tile* tiles, const uint32_t* n_tiles,
-                            uint32_t grid_waves, uint32_t gen_offset, uint32_t max_ipw,
-                            uint32_t waves_per_group, hipStream_t stream) {
+hipError_t launch_batch_all(const RunView* views, const Tile* tiles, uint32_t grid_waves,
+                            uint32_t gen_offset, uint32_t max_ipw, uint32_t waves_per_group,
+                            hipStream_t stream) {
   if (grid_waves == 0) return hipSuccess;
-  const uint32_t groups = (grid_waves + waves_per_group - 1) / waves_per_group;
+  if (waves_per_group == 0 || grid_waves % waves_per_group) return hipErrorInvalidValue;
+  const uint32_t groups = grid_waves / waves_per_group;
   const size_t lds = lds_bytes(max_ipw, waves_per_group, 0u);
   batch_all_kernel<<<dim3(groups), dim3(64 * waves_per_group), lds, stream>>>(
-      views, tiles, n_tiles, gen_offset, max_ipw);
+      views, tiles, gen_offset, max_ipw);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 // launched and not synchronised, or a table a launch would misread, aborts.
 // Test infrastructure only; nothing here computes a generation.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdio>
 #include <new>
 #include "ga_internal.hpp"
@@ -68,17 +69,33 @@ hipError_t launch_gather(const RunView& v, const uint32_t* ids, uint32_t n, uint
   for (uint32_t j = 0; j < n; ++j) { T[j] = v.pop_T[ids[j]]; for (uint32_t w = 0; w < v.words; ++w) D[(size_t)w * n + j] = v.pop_D[(size_t)w * v.agent_stride + ids[j]]; }
   return hipSuccess;
 }
-hipError_t launch_batch_all(const RunView* views, const Tile* tiles, const uint32_t* n, uint32_t grid, uint32_t, uint32_t max_ipw, uint32_t wpg, hipStream_t) {
+hipError_t launch_batch_all(const RunView* views, const Tile* tiles, uint32_t grid, uint32_t, uint32_t max_ipw, uint32_t wpg, hipStream_t) {
   if (wpg == 0 || wpg > 16) { fprintf(stderr, "bad wpg\n"); abort(); }
-  if (*n > grid) { fprintf(stderr, "grid below tile count\n"); abort(); }
-  for (uint32_t i = 0; i < *n; ++i) {
-    const Tile t = tiles[i];
-    if (t.run >= n[1]) { fprintf(stderr, "tile names no member\n"); abort(); }
-    const RunView& v = views[t.run];
-    if (v.ipw > max_ipw) { fprintf(stderr, "member ipw %u above launch %u\n", v.ipw, max_ipw); abort(); }
-    if (t.first % v.ipw || t.first >= v.islands) { fprintf(stderr, "bad tile start\n"); abort(); }
-    if (i && v.log2n * 2 + v.words < views[tiles[i - 1].run].log2n * 2 + views[tiles[i - 1].run].words) { fprintf(stderr, "tiles not sorted by class\n"); abort(); }
+  if (grid % (8 * wpg)) { fprintf(stderr, "grid %u not whole groups on every XCD\n", grid); abort(); }
+  // walk each XCD's slots in dispatch order: tiles in class order within an
+  // XCD and from one XCD to the next, bytes spread evenly
+  uint64_t bytes[8] = {0}, total = 0, heaviest = 0;
+  uint32_t last_cls = 0;
+  for (uint32_t x = 0; x < 8; ++x) {
+    for (uint32_t g = x; g < grid / wpg; g += 8) {
+      for (uint32_t w = 0; w < wpg; ++w) {
+        const Tile t = tiles[g * wpg + w];
+        if (t.cls == kNoTile) continue;
+        const RunView& v = views[t.run];
+        if (v.ipw > max_ipw) { fprintf(stderr, "member ipw %u above launch %u\n", v.ipw, max_ipw); abort(); }
+        if (t.first % v.ipw || t.first >= v.islands) { fprintf(stderr, "bad tile start\n"); abort(); }
+        if (t.cls != v.log2n * 2 + v.words - 1) { fprintf(stderr, "tile class differs from its member's\n"); abort(); }
+        if (v.left != v.gen + 1) { fprintf(stderr, "budget word not after the generation counter\n"); abort(); }
+        if (t.cls < last_cls) { fprintf(stderr, "tiles not in class order\n"); abort(); }
+        last_cls = t.cls;
+        const uint32_t isl = std::min(v.ipw, v.islands - t.first);
+        const uint64_t b = (uint64_t)isl * (((uint64_t)1 << v.log2n) * 2 * (8 + 4 * v.words) + 2 * (12 + 4 * v.words));
+        bytes[x] += b; total += b; heaviest = std::max(heaviest, b);
+      }
+    }
   }
+  for (uint32_t x = 0; x < 8; ++x)
+    if (bytes[x] > total / 8 + heaviest) { fprintf(stderr, "XCD %u holds %llu of %llu bytes\n", x, (unsigned long long)bytes[x], (unsigned long long)total); abort(); }
   return hipSuccess;
 }
 hipError_t launch_store_u64(unsigned long long* p, unsigned long long v, hipStream_t) { *p = v; return hipSuccess; }
