@@ -1210,8 +1210,9 @@ uint64_t tile_bytes(const ga::RunView& v, uint32_t islands) {
 
 // Place the tiles (in class order) in the launch's wavefront slots. The
 // dispatcher hands workgroup g to XCD g mod 8, each XCD with its own L2: the
-// tiles are cut into eight contiguous stretches of about equal bytes
-// (wavefronts of different classes move different amounts), stretch x fills
+// tiles are cut into eight contiguous stretches of about equal weight, a
+// tile's bytes plus a wavefront's fixed cost (wavefronts of different classes
+// move different amounts), stretch x fills
 // XCD x's workgroups x, x + 8, x + 16, ... wpg tiles each, in order, so a
 // member's neighbouring tiles share an L2 and no XCD is left with a heavier
 // share to finish alone. Returns the slots the placement spans (a multiple of
@@ -1224,7 +1225,7 @@ uint32_t place_tiles(const std::vector<ga::RunView>& views, const std::vector<ga
   uint64_t total = 0;
   for (size_t i = 0; i < tiles.size(); ++i) {
     const ga::RunView& v = views[tiles[i].run];
-    w[i] = tile_bytes(v, std::min(v.ipw, v.islands - tiles[i].first));
+    w[i] = tile_bytes(v, std::min(v.ipw, v.islands - tiles[i].first)) + ga::kWaveFixedBytes;
     total += w[i];
   }
   // tile i goes to the XCD whose eighth of the bytes holds its midpoint

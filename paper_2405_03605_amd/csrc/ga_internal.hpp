@@ -85,6 +85,10 @@ constexpr uint32_t kLockSpins = 32768;
 // Batch classes: one per (log2 N, surface words), index log2 N * 2 + words - 1.
 constexpr uint32_t kBatchClasses = 14;
 constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+// A batched wavefront's fixed cost (its start, the island pass) in the units
+// the tiles are balanced over the XCDs in, algorithmic bytes: measured on the
+// 64-run workload, weights of 2 to 8 KiB per wavefront balance best.
+constexpr uint64_t kWaveFixedBytes = 4096;
 struct Tile {
   uint32_t run;
   uint32_t first;

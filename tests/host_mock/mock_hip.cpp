@@ -89,13 +89,13 @@ hipError_t launch_batch_all(const RunView* views, const Tile* tiles, uint32_t gr
         if (t.cls < last_cls) { fprintf(stderr, "tiles not in class order\n"); abort(); }
         last_cls = t.cls;
         const uint32_t isl = std::min(v.ipw, v.islands - t.first);
-        const uint64_t b = (uint64_t)isl * (((uint64_t)1 << v.log2n) * 2 * (8 + 4 * v.words) + 2 * (12 + 4 * v.words));
+        const uint64_t b = (uint64_t)isl * (((uint64_t)1 << v.log2n) * 2 * (8 + 4 * v.words) + 2 * (12 + 4 * v.words)) + kWaveFixedBytes;
         bytes[x] += b; total += b; heaviest = std::max(heaviest, b);
       }
     }
   }
   for (uint32_t x = 0; x < 8; ++x)
-    if (bytes[x] > total / 8 + heaviest) { fprintf(stderr, "XCD %u holds %llu of %llu bytes\n", x, (unsigned long long)bytes[x], (unsigned long long)total); abort(); }
+    if (bytes[x] > total / 8 + heaviest) { fprintf(stderr, "XCD %u holds %llu of %llu (bytes plus a fixed cost per wavefront)\n", x, (unsigned long long)bytes[x], (unsigned long long)total); abort(); }
   return hipSuccess;
 }
 hipError_t launch_store_u64(unsigned long long* p, unsigned long long v, hipStream_t) { *p = v; return hipSuccess; }
