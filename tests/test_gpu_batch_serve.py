@@ -77,6 +77,36 @@ def test_membership_changes_between_blocks():
     assert_same_state(c.read(), oracle_after(UNEVEN[2], 80), "c")
 
 
+def test_placement_with_odd_group_sizes_and_grid_growth():
+    """The launch's slots are laid out per XCD in whole rounds of eight
+    groups: group sizes that are no power of two, and a member whose tiles
+    outgrow the captured grid (new tables, a new graph) mid-run, must leave
+    every member's bits as the oracle's."""
+    small = UNEVEN[:4]
+    big = run_config(width=256, height=64, pop=8, sites=32, k=3, selection=1, run_id=21)
+    runs = [GARun(c) for c in small]
+    batch = GABatch()
+    batch.set_launch(0, 3)
+    for r in runs:
+        batch.add(r, 400)
+    say("odd group sizes: 3 waves per group, small members")
+    batch.step(100)
+    rb = GARun(big)
+    batch.add(rb, 150)       # 256 more tiles: past the first grid
+    say("odd group sizes: a large member joins")
+    batch.step(100)
+    batch.set_launch(0, 5)
+    say("odd group sizes: 5 waves per group")
+    batch.step(100)
+    batch.step(100)
+    for r in runs + [rb]:
+        assert batch.remaining(r) == 0
+    batch.close()
+    for r, c in zip(runs, small):
+        assert_same_state(r.read(), oracle_after(c, 400), f"member {c['run_id']}")
+    assert_same_state(rb.read(), oracle_after(big, 150), "large member")
+
+
 def test_batched_workload_equals_alone():
     cfgs = batched_configs()
     gens = 130
