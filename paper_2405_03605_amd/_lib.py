@@ -21,6 +21,8 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 # the compiler's atomic optimizer would turn each such bump into a wavefront
 # scan that waits for its result on the spot.
 EXTRA_FLAGS = {"ga_tile.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+# roctx ranges around the host calls that submit generations
+ROCTX = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
 
 GA_OK, GA_EINVAL, GA_ENOMEM, GA_EDEVICE, GA_ESTATE = 0, -1, -2, -3, -4
 FORM_AUTO, FORM_STREAMING, FORM_RESIDENT = 0, 1, 2
@@ -52,7 +54,7 @@ def build(hipcc: str = "hipcc") -> str:
     with ThreadPoolExecutor(len(SOURCES)) as pool:
         list(pool.map(compile_one, zip(SOURCES, objs)))
     tmp = LIB_PATH + ".tmp"
-    subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs,
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ROCTX,
                    check=True, stderr=quiet)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH

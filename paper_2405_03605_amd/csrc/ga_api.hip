@@ -2,9 +2,11 @@
 // HIP-graph capture of generation blocks, state I/O and the batched form.
 // Declarations and semantics: include/ga.h.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cstddef>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <new>
@@ -17,6 +19,20 @@
 namespace {
 
 thread_local std::string g_last_error;
+
+// A roctx range (recorded by rocprofv3 --marker-trace) over host work that
+// submits generations: a step call, and inside it each graph block. Ranges
+// time the submission on the host thread; the kernels run after it.
+struct Range {
+  Range(const char* what, uint64_t gens) {
+    char name[64];
+    std::snprintf(name, sizeof name, "%s %llu", what, (unsigned long long)gens);
+    roctxRangePushA(name);
+  }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
@@ -777,6 +793,7 @@ int ga_step(ga_run* r, uint64_t n) {
   if (!r) return fail(GA_EINVAL, "run is NULL");
   if (r->batch) return fail(GA_ESTATE, "run is a batch member; advance it with ga_batch_step");
   if (n == 0) return GA_OK;
+  const Range range("ga_step", n);
   if (r->cfg.schedule == GA_SCHEDULE_ASYNC) return step_async(r, n);
   bool tiles = false;
   int rc0 = use_tiles(r, &tiles);
@@ -787,6 +804,7 @@ int ga_step(ga_run* r, uint64_t n) {
     int rc = ensure_graph(r);
     if (rc != GA_OK) return rc;
     while (left >= r->graph_block) {
+      const Range block("block", r->graph_block);
       GA_HIP(hipGraphLaunch(r->graph, r->stream), "graph launch");
       left -= r->graph_block;
     }
@@ -1399,6 +1417,7 @@ int ga_batch_class_launch(ga_batch* b, uint32_t log2n, uint32_t words, uint32_t*
 int ga_batch_step(ga_batch* b, uint64_t n) {
   if (!b) return fail(GA_EINVAL, "batch is NULL");
   if (n == 0 || b->members.empty()) return GA_OK;
+  const Range range("ga_batch_step", n);
   if (b->dirty) {
     int rc = rebuild_tables(b);
     if (rc != GA_OK) return rc;
@@ -1408,6 +1427,7 @@ int ga_batch_step(ga_batch* b, uint64_t n) {
     int rc = batch_graph(b);
     if (rc != GA_OK) return rc;
     while (left >= b->graph_block) {
+      const Range block("batch block", b->graph_block);
       GA_HIP(hipGraphLaunch(b->graph, b->stream), "graph launch");
       left -= b->graph_block;
     }

@@ -30,7 +30,7 @@ def test_host_logic_under_sanitizers(tmp_path):
     build = ["g++", "-std=c++17", "-g", "-O1", "-fsanitize=address,undefined",
              "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-fPIC", "-shared",
              "-I" + MOCK, "-I" + os.path.join(ROOT, "paper_2405_03605_amd", "csrc"),
-             "-I" + os.path.join(ROOT, "include"),
+             "-I" + os.path.join(ROOT, "include"), "-I/opt/rocm/include",
              "-x", "c++", os.path.join(ROOT, "paper_2405_03605_amd", "csrc", "ga_api.hip"),
              "-x", "c++", os.path.join(MOCK, "mock_hip.cpp"), "-o", so]
     subprocess.run(build, check=True, capture_output=True, timeout=600)
