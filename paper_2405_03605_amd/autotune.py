@@ -73,14 +73,20 @@ def apply(run: GARun, choice):
         run.set_launch(a, b, form)
 
 
-def time_candidate(run: GARun, cand, gens: int, torch) -> float:
+def time_candidate(run: GARun, cand, gens: int, torch, reps: int = 3) -> float:
+    """Seconds per generation of one candidate, the best of reps timings (the
+    candidates of a shape differ by a percent or so, about what one timing
+    varies by)."""
     apply(run, cand)
     run.step(2)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run.step(gens)
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / gens
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        run.step(gens)
+        torch.cuda.synchronize()
+        best = min(best, (time.perf_counter() - t0) / gens)
+    return best
 
 
 def autotune(cfg: dict, gens: int | None = None, use_cache: bool = True, forms=None):
@@ -92,8 +98,8 @@ def autotune(cfg: dict, gens: int | None = None, use_cache: bool = True, forms=N
     if use_cache and key in _cache:
         return _cache[key]
     agents = cfg["width"] * cfg["height"] * cfg["pop"]
-    if gens is None:
-        gens = max(4, min(200, int(2e8 // max(agents, 1))))
+    if gens is None:            # a few milliseconds per timing
+        gens = max(4, min(400, int(8e8 // max(agents, 1))))
     scratch = GARun(dict(cfg, seed=0x5eed, run_id=0xA070))
     best, best_t = None, float("inf")
     for cand in candidates(cfg):
