@@ -258,11 +258,12 @@ void ga_destroy(ga_run* run);
  * or about 2^34 agent-generations each). Needs a tiling whose tiles fit the
  * LDS of a CU (160 KiB: per agent 4 bytes each of fitness, T, the surface
  * words and any string words; per island two outbox entries) with every
- * workgroup resident at once. The launch needs the GPU's CUs to itself: kernels of
- * other processes running at the same time hold CUs, tiles then wait for
- * neighbours that are not scheduled until their bounded waits give up, and
- * reading the state reports GA_EDEVICE. Choose GA_FORM_STREAMING on a GPU
- * shared with other work.
+ * workgroup resident at once. The launch needs the GPU's CUs to itself: kernels
+ * running at the same time (another stream's, another process's) hold CUs,
+ * tiles then wait for neighbours that are not scheduled until their bounded
+ * waits give up, and reading the state reports GA_EDEVICE. Runs stepped on one
+ * stream are safe; choose GA_FORM_STREAMING for runs stepped on streams that
+ * run concurrently or on a GPU shared with other work.
  * GA_FORM_AUTO (default): the resident form when such a tiling exists, else
  * streaming. Results do not depend on the form. */
 #define GA_FORM_AUTO 0
