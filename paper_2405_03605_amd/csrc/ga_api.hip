@@ -547,13 +547,15 @@ int step_async(ga_run* r, uint64_t n) {
   const bool lockstep = r->async_lead == 0u && r->async_skew == 0u;
   uint32_t cap = 0;
   GA_HIP(ga::async_capacity(v, r->wpg, lockstep, &cap), "occupancy query");
-  // Lockstep with the default chunk size: while each resident wavefront
-  // would run more than two chunks in turn (waiting out each one's exchange),
-  // take chunks twice as large. Measured at 1024 x 512 x 32: four 16-island
-  // chunks per wavefront 127 us per generation, two 32-island ones 123 us,
-  // one 64-island one 130 us. Lockstep results do not depend on it.
-  while (lockstep && !r->ipw_set && waves_for(r, v.ipw) > 2u * cap && v.ipw * 2u <= 64u &&
-         ga::lds_bytes(v.ipw * 2u, r->wpg, v.model) <= kMaxGroupLds) {
+  // With the default chunk size (and no skew, whose one-wavefront
+  // interleavings name their chunks): while each resident wavefront would run
+  // more than two chunks in turn (waiting out each one's exchange), take
+  // chunks twice as large. Measured at 1024 x 512 x 32, four 16-island chunks
+  // per wavefront against two 32-island ones: lockstep 127 against 123 us per
+  // generation (one 64-island chunk, at lower occupancy: 130), max_lead 2 158
+  // against 142, unpaced 150 against 136. Lockstep results do not depend on it.
+  while (r->async_skew == 0u && !r->ipw_set && waves_for(r, v.ipw) > 2u * cap &&
+         v.ipw * 2u <= 64u && ga::lds_bytes(v.ipw * 2u, r->wpg, v.model) <= kMaxGroupLds) {
     v.ipw *= 2u;
     GA_HIP(ga::async_capacity(v, r->wpg, lockstep, &cap), "occupancy query");
   }
